@@ -1,0 +1,207 @@
+"""Benchmark of the generalized-SpMSpV hot path on one MI355X.
+
+One step = one pass of every program of the full-size single-source workload
+on RMAT scale 22 (4,194,304 vertices, edge factor 16, a/b/c = .57/.19/.19,
+self-loops and duplicates removed):
+  BFS from vertex 0 on the symmetrised graph (int32 levels),
+  SSSP from vertex 0 on the directed graph, uint32 weights in [1, 255],
+  PageRank, 20 supersteps, FP32 (r = 0.15).
+Each program's property array is re-initialised inside the step.
+
+value = edges traversed by the step / step time, in GTEPS, where "edges
+traversed" counts, per superstep, the out-edges of every vertex that sent a
+message (Alg. 1's column walk): BFS and SSSP report it from the library's
+counters, PageRank traverses all m edges per superstep.
+
+Prints one JSON line. Inputs are generated and loaded before the timed region
+(graph loading is excluded, as in the paper's measurements).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GTEPS per generalized-SpMV iteration + % HBM peak; batched/adjoint vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def ensure_built():
+    from paper_1503_07241_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    ensure_built()
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import paper_1503_07241_amd as gm
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    scale = args.scale
+    t0 = time.time()
+    n, s, d = gg.rmat(scale)
+    w = gg.weights_u32(s, d)
+    log("generated RMAT scale %d in %.1fs" % (scale, time.time() - t0))
+    g_sym = gm.Graph.from_coo(n, s, d, prep=gm.GM_PREP_DROP_SELF_LOOPS | gm.GM_PREP_SYMMETRIZE,
+                              layouts=gm.GM_LAYOUT_OUT)
+    g_dir = gm.Graph.from_coo(n, s, d, w=w, prep=gm.GM_PREP_DROP_SELF_LOOPS,
+                              layouts=gm.GM_LAYOUT_OUT | gm.GM_LAYOUT_IN)
+    m_dir, m_sym = g_dir.m, g_sym.m
+    log("graphs loaded: m_dir=%d m_sym=%d (%.1fs)" % (m_dir, m_sym, time.time() - t0))
+
+    level = torch.empty(n, dtype=torch.int32, device=dev)
+    dist = torch.empty(n, dtype=torch.int32, device=dev)
+    rank = torch.empty(n, dtype=torch.float32, device=dev)
+    root = torch.zeros(1, dtype=torch.int32, device=dev)
+    T_PR = 20
+    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for k in ("bfs", "sssp", "pr")}
+    acc = {k: 0.0 for k in ev}
+    edges = {}
+
+    def step(record: bool):
+        e = ev["bfs"]
+        if record:
+            e[0].record()
+        level.fill_(gm.INF_LEVEL)
+        level[0] = 0
+        gm.run_vertex_program(g_sym, gm.GM_PROG_BFS, root, -1, level)
+        if record:
+            e[1].record()
+        edges["bfs"] = g_sym.last_run_stats().edges_scanned
+        e = ev["sssp"]
+        if record:
+            e[0].record()
+        dist.fill_(-1)
+        dist[0] = 0
+        gm.run_vertex_program(g_dir, gm.GM_PROG_SSSP, root, -1, dist)
+        if record:
+            e[1].record()
+        edges["sssp"] = g_dir.last_run_stats().edges_scanned
+        e = ev["pr"]
+        if record:
+            e[0].record()
+        rank.fill_(1.0)
+        gm.run_vertex_program(g_dir, gm.GM_PROG_PAGERANK, None, T_PR, rank)
+        if record:
+            e[1].record()
+        edges["pr"] = T_PR * m_dir
+        if record:
+            torch.cuda.synchronize()
+            for k, (a, b) in ev.items():
+                acc[k] += a.elapsed_time(b)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_step = 1e3 * wall / args.steps
+    edges_step = sum(edges.values())
+    gteps = edges_step / (wall / args.steps) / 1e9
+
+    # Dominant kernel: the PageRank pull superstep (one launch per superstep).
+    pr_ms_launch = acc["pr"] / args.steps / T_PR
+    pr_bytes = 4 * m_dir + 16 * n  # idx + offsets + gathered msg + 1/outdeg + msg write
+    achieved = pr_bytes / (pr_ms_launch * 1e-3) / 1e9
+    programs = {}
+    for k in ev:
+        ms = acc[k] / args.steps
+        programs[k] = {"ms": round(ms, 4), "edges": int(edges[k]),
+                       "gteps": round(edges[k] / (ms * 1e-3) / 1e9, 2)}
+    log("programs: %s" % json.dumps(programs))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(n, s, d, w)
+
+    out = {
+        "metric": METRIC,
+        "value": round(gteps, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32/u32 (BFS, SSSP), f32 (PageRank)",
+        "data": "synthetic",
+        "config": {"workload": "RMAT scale %d: BFS + SSSP + PageRank x20, single source 0" % scale,
+                   "scale": scale, "n": n, "m_dir": m_dir, "m_sym": m_sym,
+                   "edges_per_step": int(edges_step)},
+        "programs": programs,
+        "roofline": {"kernel": "pr_pull (PageRank superstep)", "bound": "hbm",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": int(pr_bytes),
+                     "launch_ms": round(pr_ms_launch, 5)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(n, s, d, w):
+    """The oracle (single-threaded C) on a bounded sample of the same workload:
+    BFS + Dijkstra SSSP + 2 PageRank supersteps on the same scale-22 graph,
+    reported as traversed edges per second (GTEPS)."""
+    import numpy as np
+
+    import oracle
+    t0 = time.time()
+    gs = oracle.prepare(n, s, d, mode="symmetric")
+    gd = oracle.prepare(n, s, d, w=w)
+    gin = oracle.Graph(gd.n, gd.off, gd.idx).transpose()
+    log("oracle graphs prepared in %.1fs" % (time.time() - t0))
+    t = time.perf_counter()
+    lv = oracle.bfs(gs, 0)
+    t_bfs = time.perf_counter() - t
+    e_bfs = int(gs.degree()[lv != oracle.INF_I32].sum())
+    t = time.perf_counter()
+    dist = oracle.sssp(gd, 0)
+    t_sssp = time.perf_counter() - t
+    e_sssp = int(gd.degree()[dist != oracle.INF_U32].sum())  # Dijkstra scans each once
+    t = time.perf_counter()
+    oracle.pagerank(gd, 0.15, 2, g_in=gin)
+    t_pr = time.perf_counter() - t
+    e_pr = 2 * gd.m
+    tot = t_bfs + t_sssp + t_pr
+    return {"value": round((e_bfs + e_sssp + e_pr) / tot / 1e9, 4), "unit": "GTEPS", "cores": 1,
+            "kind": "oracle",
+            "sample": "scale-22 graph: queue BFS (%.2fs) + Dijkstra SSSP (%.2fs) + 2 PageRank "
+                      "supersteps in FP64 (%.2fs)" % (t_bfs, t_sssp, t_pr)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * gm.h -- C ABI of the GraphMat generalized-SpMSpV library for AMD MI355X
+ * (gfx950).
+ *
+ * The library runs GraphMat vertex programs (Sundaram et al., "GraphMat:
+ * High performance graph analytics made productive", VLDB 2015) as
+ * generalized sparse-matrix x sparse-vector products on one GPU. Every
+ * superstep of a program is Alg. 2 of the paper: active vertices send a
+ * message (SEND_MESSAGE), every edge out of an active vertex processes it
+ * (PROCESS_MESSAGE), the processed messages arriving at a vertex are
+ * combined (REDUCE) and the vertex updates its property (APPLY); vertices
+ * whose property changed are active in the next superstep (Sec. 4.1,
+ * Sec. 4.3). The product itself is Alg. 1 (Sec. 4.2).
+ *
+ * Conventions for every call:
+ *  - Every call returns a gm_status. Nothing throws or aborts across the
+ *    ABI. On failure gm_last_error() returns a message for the calling
+ *    thread, output buffers are unspecified and the graph stays valid.
+ *  - Arguments are validated before any device work is enqueued.
+ *  - "device" pointers are GPU memory owned by the caller, who keeps them
+ *    alive until the enqueued work has finished. "host" pointers are read
+ *    or written before the call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it; calls documented as synchronising wait for it.
+ *  - A gm_graph is used by one stream at a time (its workspace is shared).
+ *  - Vertex ids are int32 in [0, n). Edge counts are limited to 2^32 - 1
+ *    stored edges per graph (32-bit offsets); larger graphs give
+ *    GM_EUNSUPPORTED.
+ */
+#ifndef GM_H_
+#define GM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gm_status {
+  GM_OK = 0,
+  GM_EINVAL = 1,       /* bad argument: null pointer, size, id, enum, dtype */
+  GM_ENOMEM = 2,       /* device or host allocation failed */
+  GM_EHIP = 3,         /* a HIP runtime call failed */
+  GM_EUNSUPPORTED = 4, /* valid but unsupported combination */
+  GM_ESTATE = 5        /* handle not live (destroyed or never created) */
+} gm_status;
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* gm_last_error(void);
+
+/* Library version string. */
+const char* gm_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Graphs                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Opaque handle; owns device memory from creation until gm_graph_destroy. */
+typedef struct gm_graph_s* gm_graph;
+
+/* Preprocessing applied while loading (Sec. 5.1: self-loops are removed;
+ * PageRank and SSSP use the directed graph; BFS replicates edges to make
+ * the graph symmetric; triangle counting symmetrises and keeps only the
+ * upper triangle, i.e. edges u -> v with u < v). Duplicate edges are
+ * always merged; a merged edge keeps the smallest weight. */
+enum {
+  GM_PREP_DROP_SELF_LOOPS = 1,
+  GM_PREP_SYMMETRIZE = 2,
+  GM_PREP_UPPER_DAG = 4 /* implies symmetrise, then keep u < v */
+};
+
+/* Edge value types (the edge value of Alg. 1). */
+enum { GM_W_NONE = 0, GM_W_U32 = 1, GM_W_F32 = 2 };
+
+/* Device layouts to build. The paper stores G^T column-compressed (DCSC,
+ * Sec. 4.4.1); its columns are the out-edge lists of the vertices, i.e. a
+ * row-compressed out-adjacency (CSR) of G, used by the push direction.
+ * The in-adjacency (CSC of G) serves the pull direction. Both keep the
+ * neighbour lists sorted. */
+enum { GM_LAYOUT_OUT = 1, GM_LAYOUT_IN = 2 };
+
+/*
+ * Build a graph on the current HIP device from a host edge list
+ * (src[e] -> dst[e], e < m), with optional per-edge values w (host,
+ * wtype GM_W_U32 or GM_W_F32; NULL with GM_W_NONE). Mirrors the paper's
+ * graph loading (App. A, ReadMTX) followed by the preprocessing of
+ * Sec. 5.1 selected by `prep`. Canonical edge order is sorted by
+ * (src, dst); every per-edge array exchanged with the library (weights,
+ * edge gradients) uses it.
+ * Errors: GM_EINVAL if n <= 0 or n > 2^31-1, m < 0, src/dst/out NULL
+ * (m > 0), an id is outside [0, n), wtype unknown or w NULL/non-NULL
+ * against wtype, layouts == 0 or unknown bits; GM_EUNSUPPORTED if more
+ * than 2^32 - 1 edges remain; GM_ENOMEM, GM_EHIP.
+ * Synchronises `stream`.
+ */
+gm_status gm_graph_from_coo(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                            const void* w, int32_t wtype, uint32_t prep, uint32_t layouts,
+                            void* stream, gm_graph* out);
+
+typedef struct gm_graph_info {
+  int64_t n;          /* vertices */
+  int64_t m;          /* stored directed edges after preprocessing */
+  int64_t max_out;    /* largest out-degree */
+  int64_t max_in;     /* largest in-degree (0 if the in-layout is absent) */
+  int32_t wtype;      /* GM_W_* */
+  uint32_t prep;      /* GM_PREP_* used */
+  uint32_t layouts;   /* GM_LAYOUT_* built */
+  int32_t device;     /* HIP device ordinal */
+  int64_t device_bytes; /* device memory held by the graph (not the workspace) */
+} gm_graph_info;
+
+/* Fill *info (host). Errors: GM_ESTATE, GM_EINVAL (info NULL). */
+gm_status gm_graph_get_info(gm_graph g, gm_graph_info* info);
+
+/*
+ * Copy the canonical edge list to host arrays of length m: src, dst
+ * (either may be NULL) and values w (NULL, or uint32/float per wtype).
+ * Errors: GM_ESTATE, GM_EINVAL (w non-NULL on an unweighted graph),
+ * GM_EHIP. Synchronous.
+ */
+gm_status gm_graph_edges(gm_graph g, int32_t* src, int32_t* dst, void* w);
+
+/* Free the graph and its workspace. Errors: GM_ESTATE if not live. */
+gm_status gm_graph_destroy(gm_graph g);
+
+/* ------------------------------------------------------------------------ */
+/* Vertex programs                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Programs of Sec. 3, each a (SEND, PROCESS, REDUCE, APPLY) tuple. */
+enum {
+  /* Sec. 3 II, Eq. (2). Property int32 level, INT32_MAX = unreached.
+   * SEND level(u); PROCESS msg + 1; REDUCE min; APPLY min.
+   * Needs GM_LAYOUT_OUT; uses GM_LAYOUT_IN too (pull supersteps) when
+   * built. */
+  GM_PROG_BFS = 1,
+  /* Sec. 3 V, Eq. (8) and App. A. Property uint32 distance,
+   * UINT32_MAX = unreached. SEND dist(u); PROCESS msg + w_uv saturating
+   * at UINT32_MAX; REDUCE min; APPLY min. Needs GM_W_U32 and
+   * GM_LAYOUT_OUT. */
+  GM_PROG_SSSP = 2,
+  /* Sec. 3 I, Eq. (1). Property float rank. Every vertex is active in
+   * every superstep; SEND rank(u)/outdeg(u) (none if outdeg = 0);
+   * PROCESS msg (times w_uv for GM_W_F32 graphs); REDUCE +;
+   * APPLY r + (1 - r) * y for every vertex. Runs exactly max_iters
+   * supersteps. Needs GM_LAYOUT_IN. */
+  GM_PROG_PAGERANK = 3,
+  /* Personalised PageRank with one seed s (the first frontier id):
+   * APPLY r * [v == s] + (1 - r) * y. Otherwise as GM_PROG_PAGERANK. */
+  GM_PROG_PPR = 4
+};
+
+/* Edge direction messages travel along (App. A, `order`). */
+enum { GM_ORDER_OUT = 1, GM_ORDER_IN = 2, GM_ORDER_ALL = 3 };
+
+typedef struct gm_program {
+  int32_t kind;   /* GM_PROG_* */
+  int32_t order;  /* GM_ORDER_*; only GM_ORDER_OUT is supported */
+  float r;        /* PageRank random-surf probability (Eq. (1)); 0.15 */
+  uint32_t flags; /* reserved, must be 0 */
+} gm_program;
+
+/* Initially active vertices: `count` distinct ids in device memory. */
+typedef struct gm_frontier {
+  const int32_t* ids;
+  int64_t count;
+} gm_frontier;
+
+/*
+ * Run a vertex program (Alg. 2) on graph g. The caller initialises the
+ * property array `vprop` (device, n entries of the program's type) and
+ * names the initially active vertices, as App. A does
+ * (setAllVertexproperty, then vertexproperty[s] = 0, active[s] = true).
+ * BFS and SSSP run until no vertex is active when max_iters <= 0, else at
+ * most max_iters supersteps; PageRank runs exactly max_iters (> 0)
+ * supersteps with every vertex active (frontier may be NULL); PPR takes
+ * its seed from frontier->ids[0].
+ * On return *iters_done (host, may be NULL) holds the number of
+ * supersteps that started with at least one active vertex, and
+ * active_out (device int32 of n entries, may be NULL) marks, with 1, the
+ * vertices still active afterwards, so a later call can resume from
+ * (vprop, active) exactly.
+ * Errors: GM_ESTATE; GM_EINVAL (prog/vprop NULL, unknown kind, order not
+ * OUT, flags != 0, frontier missing or count < 0 or ids NULL with
+ * count > 0, an id out of range, PageRank with max_iters <= 0, r outside
+ * [0, 1]); GM_EUNSUPPORTED (program needs a layout or weight type the
+ * graph lacks); GM_ENOMEM; GM_EHIP.
+ * BFS and SSSP synchronise `stream` once per superstep; PageRank is
+ * asynchronous.
+ */
+gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_frontier* frontier,
+                                int32_t max_iters, void* vprop, int32_t* active_out,
+                                int32_t* iters_done, void* stream);
+
+/* Counters of the last gm_run_vertex_program call on a graph. */
+typedef struct gm_run_stats {
+  int32_t supersteps;      /* supersteps run (as *iters_done) */
+  int32_t push_supersteps; /* supersteps that walked out-edges of active vertices */
+  int32_t pull_supersteps; /* supersteps that scanned in-edges of all vertices */
+  int64_t edges_scanned;   /* sum over supersteps of the out-degrees of the
+                              vertices that sent a message (the edges Alg. 1
+                              traverses) */
+} gm_run_stats;
+
+/* Copy the counters of g's last run to *out (host).
+ * Errors: GM_ESTATE, GM_EINVAL (out NULL). */
+gm_status gm_last_run_stats(gm_graph g, gm_run_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GM_H_ */

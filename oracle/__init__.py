@@ -140,12 +140,14 @@ def prepare(n: int, src: np.ndarray, dst: np.ndarray, w: np.ndarray | None = Non
         key = np.unique(key)
         wout = None
     else:
-        order = np.lexsort((ww, key))  # by key, then weight
+        order = np.argsort(key, kind="stable")
         key_s = key[order]
         first = np.ones(len(key_s), dtype=bool)
         first[1:] = key_s[1:] != key_s[:-1]
-        key = key_s[first]
-        wout = np.ascontiguousarray(ww[order][first])
+        heads = np.flatnonzero(first)
+        key = key_s[heads]
+        w_s = ww[order]
+        wout = np.ascontiguousarray(np.minimum.reduceat(w_s, heads) if len(heads) else w_s[:0])
     rows = key // n
     off = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(np.bincount(rows, minlength=n), out=off[1:])

@@ -1,0 +1,152 @@
+"""GraphMat generalized SpMSpV on AMD MI355X: Python binding of libgm.so.
+
+Thin marshalling over the C ABI of ``include/gm.h``: every step of every
+program runs in the library's HIP kernels. Device buffers are torch tensors
+(``data_ptr()``); work is enqueued on ``torch.cuda.current_stream()``.
+
+    import paper_1503_07241_amd as gm
+    g = gm.Graph.from_coo(n, src, dst, prep=gm.GM_PREP_DROP_SELF_LOOPS | gm.GM_PREP_SYMMETRIZE)
+    level = torch.full((n,), 2**31 - 1, dtype=torch.int32, device="cuda"); level[0] = 0
+    iters = gm.run_vertex_program(g, gm.GM_PROG_BFS, torch.tensor([0], ...), -1, level)
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (GM_LAYOUT_IN, GM_LAYOUT_OUT, GM_ORDER_ALL, GM_ORDER_IN, GM_ORDER_OUT,  # noqa: F401
+                   GM_PREP_DROP_SELF_LOOPS, GM_PREP_SYMMETRIZE, GM_PREP_UPPER_DAG, GM_PROG_BFS,
+                   GM_PROG_PAGERANK, GM_PROG_PPR, GM_PROG_SSSP, GM_W_F32, GM_W_NONE, GM_W_U32,
+                   GmError)
+
+INF_LEVEL = 2**31 - 1
+INF_DIST = 2**32 - 1
+
+
+def _stream(stream=None) -> int:
+    if stream is not None:
+        return int(stream)
+    import torch
+    if not torch.cuda.is_available():
+        return 0  # the library reports the missing device itself
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous")
+    return int(t.data_ptr())
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data
+
+
+def version() -> str:
+    return _lib.load().gm_version().decode()
+
+
+class Graph:
+    """A device graph (gm_graph handle); freed by close() or garbage collection."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise GmError(_lib.GM_ESTATE, "Graph", "graph was closed")
+        return self._h
+
+    @classmethod
+    def from_coo(cls, n: int, src, dst, w=None, prep: int = GM_PREP_DROP_SELF_LOOPS,
+                 layouts: int = GM_LAYOUT_OUT | GM_LAYOUT_IN, stream=None) -> "Graph":
+        """gm_graph_from_coo on host arrays src, dst (int32) and optional w
+        (uint32 or float32)."""
+        lib = _lib.load()
+        s, sp = _host(src, np.int32)
+        d, dp = _host(dst, np.int32)
+        if len(s) != len(d):
+            raise ValueError("src and dst differ in length")
+        wtype, wp = GM_W_NONE, None
+        if w is not None:
+            w = np.asarray(w)
+            if w.dtype == np.uint32:
+                wtype = GM_W_U32
+            elif w.dtype == np.float32:
+                wtype = GM_W_F32
+            else:
+                raise ValueError("w must be uint32 or float32")
+            w, wp = _host(w, w.dtype)
+            if len(w) != len(s):
+                raise ValueError("w differs in length from src")
+        out = ctypes.c_void_p()
+        _lib.check(lib.gm_graph_from_coo(n, len(s), sp, dp, wp, wtype, prep, layouts,
+                                         _stream(stream), ctypes.byref(out)), "gm_graph_from_coo")
+        return cls(out.value)
+
+    def info(self) -> _lib.gm_graph_info:
+        info = _lib.gm_graph_info()
+        _lib.check(_lib.load().gm_graph_get_info(self.handle, ctypes.byref(info)),
+                   "gm_graph_get_info")
+        return info
+
+    @property
+    def n(self) -> int:
+        return self.info().n
+
+    @property
+    def m(self) -> int:
+        return self.info().m
+
+    def edges(self, with_weights: bool = False):
+        """Canonical (src, dst[, w]) host arrays, sorted by (src, dst)."""
+        info = self.info()
+        src = np.empty(info.m, dtype=np.int32)
+        dst = np.empty(info.m, dtype=np.int32)
+        w = None
+        if with_weights:
+            w = np.empty(info.m, dtype=np.uint32 if info.wtype == GM_W_U32 else np.float32)
+        _lib.check(_lib.load().gm_graph_edges(self.handle, src.ctypes.data, dst.ctypes.data,
+                                              None if w is None else w.ctypes.data),
+                   "gm_graph_edges")
+        return (src, dst, w) if with_weights else (src, dst)
+
+    def last_run_stats(self) -> _lib.gm_run_stats:
+        st = _lib.gm_run_stats()
+        _lib.check(_lib.load().gm_last_run_stats(self.handle, ctypes.byref(st)),
+                   "gm_last_run_stats")
+        return st
+
+    def close(self) -> None:
+        if self._h is not None:
+            _lib.check(_lib.load().gm_graph_destroy(self._h), "gm_graph_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_vertex_program(g: Graph, kind: int, frontier, max_iters: int, vprop, active_out=None,
+                       r: float = 0.15, stream=None) -> int:
+    """gm_run_vertex_program. frontier: device int32 tensor of active ids (or
+    None for PageRank); vprop: device property tensor (int32 levels, uint32
+    distances as int32 storage, float32 ranks). Returns supersteps done."""
+    prog = _lib.gm_program(kind, GM_ORDER_OUT, r, 0)
+    fr = None
+    if frontier is not None:
+        fr = _lib.gm_frontier(_ptr(frontier), frontier.numel())
+    it = ctypes.c_int32(0)
+    _lib.check(_lib.load().gm_run_vertex_program(
+        g.handle, ctypes.byref(prog), None if fr is None else ctypes.byref(fr), max_iters,
+        _ptr(vprop), _ptr(active_out), ctypes.byref(it), _stream(stream)),
+        "gm_run_vertex_program")
+    return it.value

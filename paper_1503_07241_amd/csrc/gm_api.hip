@@ -1,0 +1,275 @@
+// Exported C ABI: argument validation, handle registry, error reporting and
+// dispatch to the kernels. No device work is enqueued before a call's
+// arguments have been checked.
+#include <cmath>
+#include <cstdarg>
+#include <cstdlib>
+#include <mutex>
+#include <new>
+#include <unordered_set>
+
+#include "gm_internal.h"
+
+namespace gm {
+
+namespace {
+thread_local char g_msg[512] = "";
+std::mutex g_reg_mu;
+std::unordered_set<gm_graph>* g_reg = nullptr;
+std::mutex g_fault_mu;
+long g_alloc_count = 0;
+long g_fault_at = -2;  // -2: not read yet, -1: disabled
+}  // namespace
+
+gm_status fail(gm_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+gm_status ok() {
+  g_msg[0] = '\0';
+  return GM_OK;
+}
+
+// Device allocations go through here. GM_FAULT_ALLOC=k makes the k-th
+// allocation of the process fail (fault injection for the error paths).
+void* dmalloc(size_t bytes) {
+  {
+    std::lock_guard<std::mutex> lk(g_fault_mu);
+    if (g_fault_at == -2) {
+      const char* e = getenv("GM_FAULT_ALLOC");
+      g_fault_at = e ? atol(e) : -1;
+    }
+    ++g_alloc_count;
+    if (g_fault_at > 0 && g_alloc_count == g_fault_at) throw OutOfMemory{bytes};
+  }
+  void* p = nullptr;
+  const hipError_t e = hipMalloc(&p, bytes ? bytes : 16);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    throw OutOfMemory{bytes};
+  }
+  if (e != hipSuccess) throw HipError{e, "hipMalloc", __LINE__};
+  return p;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+bool graph_live(gm_graph g) {
+  std::lock_guard<std::mutex> lk(g_reg_mu);
+  return g && g_reg && g_reg->count(g) && g->magic == kGraphMagic;
+}
+
+void graph_register(gm_graph g) {
+  std::lock_guard<std::mutex> lk(g_reg_mu);
+  if (!g_reg) g_reg = new std::unordered_set<gm_graph>();
+  g_reg->insert(g);
+}
+
+void graph_unregister(gm_graph g) {
+  std::lock_guard<std::mutex> lk(g_reg_mu);
+  if (g_reg) g_reg->erase(g);
+}
+
+template <class F>
+gm_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const OutOfMemory& e) {
+    return fail(GM_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
+  } catch (const Unsupported& e) {
+    return fail(GM_EUNSUPPORTED, "%s", e.what);
+  } catch (const HipError& e) {
+    return fail(GM_EHIP, "%s: %s (%s:%d)", e.what, hipGetErrorString(e.err), __FILE__, e.line);
+  } catch (const std::bad_alloc&) {
+    return fail(GM_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(GM_EHIP, "unexpected internal error");
+  }
+}
+
+}  // namespace gm
+
+using namespace gm;
+
+extern "C" {
+
+const char* gm_last_error(void) { return g_msg; }
+
+const char* gm_version(void) { return "graphmat-mi355x 0.1 (gfx950)"; }
+
+gm_status gm_graph_from_coo(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                            const void* w, int32_t wtype, uint32_t prep, uint32_t layouts,
+                            void* stream, gm_graph* out) {
+  if (!out) return fail(GM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n <= 0 || n > INT32_MAX) return fail(GM_EINVAL, "n = %lld outside [1, 2^31-1]", (long long)n);
+  if (m < 0) return fail(GM_EINVAL, "m = %lld is negative", (long long)m);
+  if (m > 0 && (!src || !dst)) return fail(GM_EINVAL, "src/dst is NULL");
+  if (wtype != GM_W_NONE && wtype != GM_W_U32 && wtype != GM_W_F32)
+    return fail(GM_EINVAL, "unknown wtype %d", wtype);
+  if ((wtype == GM_W_NONE) != (w == nullptr) && m > 0)
+    return fail(GM_EINVAL, "w must be NULL exactly when wtype is GM_W_NONE");
+  if (prep & ~(uint32_t)(GM_PREP_DROP_SELF_LOOPS | GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG))
+    return fail(GM_EINVAL, "unknown prep bits 0x%x", prep);
+  if (layouts == 0 || (layouts & ~(uint32_t)(GM_LAYOUT_OUT | GM_LAYOUT_IN)))
+    return fail(GM_EINVAL, "layouts 0x%x: need GM_LAYOUT_OUT and/or GM_LAYOUT_IN", layouts);
+  for (int64_t e = 0; e < m; ++e) {
+    if ((uint32_t)src[e] >= (uint64_t)n || (uint32_t)dst[e] >= (uint64_t)n)
+      return fail(GM_EINVAL, "edge %lld (%d -> %d) has an id outside [0, %lld)", (long long)e,
+                  src[e], dst[e], (long long)n);
+  }
+  if (wtype == GM_W_F32) {
+    const float* wf = static_cast<const float*>(w);
+    for (int64_t e = 0; e < m; ++e)
+      if (!std::isfinite(wf[e]))
+        return fail(GM_EINVAL, "weight of edge %lld is not finite", (long long)e);
+  }
+  gm_graph g = nullptr;
+  return guarded([&]() -> gm_status {
+    int dev = 0;
+    GM_HIP(hipGetDevice(&dev));
+    g = new gm_graph_s();
+    g->magic = kGraphMagic;
+    g->n = n;
+    g->wtype = wtype;
+    g->prep = prep;
+    g->layouts = layouts | GM_LAYOUT_OUT;
+    g->device = dev;
+    try {
+      build_graph(g, src, dst, w, m, static_cast<hipStream_t>(stream));
+    } catch (...) {
+      free_graph_memory(g);
+      delete g;
+      throw;
+    }
+    graph_register(g);
+    *out = g;
+    return ok();
+  });
+}
+
+gm_status gm_graph_get_info(gm_graph g, gm_graph_info* info) {
+  if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
+  if (!info) return fail(GM_EINVAL, "info is NULL");
+  info->n = g->n;
+  info->m = g->m;
+  info->max_out = g->max_out;
+  info->max_in = g->max_in;
+  info->wtype = g->wtype;
+  info->prep = g->prep;
+  info->layouts = g->layouts;
+  info->device = g->device;
+  info->device_bytes = g->device_bytes;
+  return ok();
+}
+
+gm_status gm_graph_edges(gm_graph g, int32_t* src, int32_t* dst, void* w) {
+  if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
+  if (w && g->wtype == GM_W_NONE) return fail(GM_EINVAL, "graph has no edge values");
+  return guarded([&]() -> gm_status {
+    const int64_t n = g->n, m = g->m;
+    if (dst && m > 0) GM_HIP(hipMemcpy(dst, g->out_idx, m * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (w && m > 0) GM_HIP(hipMemcpy(w, g->out_w, m * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (src && m > 0) {
+      uint32_t* off = new uint32_t[n + 1];
+      const hipError_t e = hipMemcpy(off, g->out_off, (n + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) {
+        delete[] off;
+        throw HipError{e, "hipMemcpy", __LINE__};
+      }
+      for (int64_t v = 0; v < n; ++v)
+        for (uint32_t i = off[v]; i < off[v + 1]; ++i) src[i] = (int32_t)v;
+      delete[] off;
+    }
+    return ok();
+  });
+}
+
+gm_status gm_graph_destroy(gm_graph g) {
+  if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
+  graph_unregister(g);
+  free_min_workspace(g);
+  free_pull_schedule(g);
+  free_graph_memory(g);
+  g->magic = 0;
+  delete g;
+  return ok();
+}
+
+gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_frontier* frontier,
+                                int32_t max_iters, void* vprop, int32_t* active_out,
+                                int32_t* iters_done, void* stream) {
+  if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
+  if (!prog) return fail(GM_EINVAL, "prog is NULL");
+  if (!vprop) return fail(GM_EINVAL, "vprop is NULL");
+  const int kind = prog->kind;
+  if (kind != GM_PROG_BFS && kind != GM_PROG_SSSP && kind != GM_PROG_PAGERANK && kind != GM_PROG_PPR)
+    return fail(GM_EINVAL, "unknown program kind %d", kind);
+  if (prog->order != GM_ORDER_OUT)
+    return fail(GM_EINVAL, "order %d: only GM_ORDER_OUT is supported", prog->order);
+  if (prog->flags != 0) return fail(GM_EINVAL, "flags must be 0");
+  const bool dense = kind == GM_PROG_PAGERANK || kind == GM_PROG_PPR;
+  if (dense) {
+    if (max_iters <= 0) return fail(GM_EINVAL, "PageRank needs max_iters > 0");
+    if (!(prog->r >= 0.0f && prog->r <= 1.0f)) return fail(GM_EINVAL, "r outside [0, 1]");
+    if (!(g->layouts & GM_LAYOUT_IN)) return fail(GM_EUNSUPPORTED, "PageRank needs GM_LAYOUT_IN");
+  }
+  if (kind == GM_PROG_SSSP && g->wtype != GM_W_U32)
+    return fail(GM_EUNSUPPORTED, "SSSP needs uint32 edge weights");
+  if (!dense || kind == GM_PROG_PPR) {
+    if (!frontier) return fail(GM_EINVAL, "frontier is NULL");
+    if (frontier->count < 0 || frontier->count > g->n)
+      return fail(GM_EINVAL, "frontier count %lld outside [0, n]", (long long)frontier->count);
+    if (frontier->count > 0 && !frontier->ids) return fail(GM_EINVAL, "frontier ids NULL");
+    if (kind == GM_PROG_PPR && frontier->count < 1) return fail(GM_EINVAL, "PPR needs a seed");
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return guarded([&]() -> gm_status {
+    int dev = 0;
+    GM_HIP(hipGetDevice(&dev));
+    if (dev != g->device) return fail(GM_EINVAL, "graph lives on device %d, current is %d", g->device, dev);
+    if (frontier && frontier->count > 0 && !ids_in_range(frontier->ids, frontier->count, g->n, s))
+      return fail(GM_EINVAL, "frontier id outside [0, n)");
+    int32_t it = 0;
+    if (dense) {
+      int32_t seed = -1;
+      if (kind == GM_PROG_PPR) {
+        GM_HIP(hipMemcpyAsync(&seed, frontier->ids, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        GM_HIP(hipStreamSynchronize(s));
+      }
+      run_pagerank(g, prog->r, max_iters, static_cast<float*>(vprop), seed, s);
+      if (active_out) {
+        // every vertex stays active in a dense program
+        fill_u32(reinterpret_cast<uint32_t*>(active_out), g->n, 1u, s);
+      }
+      it = max_iters;
+      g->last_stats = RunStats{};
+      g->last_stats.supersteps = it;
+      g->last_stats.pull_supersteps = it;
+      g->last_stats.edges_scanned = (unsigned long long)g->m * it;
+    } else {
+      it = run_min_program(g, kind, frontier->ids, frontier->count, max_iters,
+                           static_cast<uint32_t*>(vprop), active_out, s, &g->last_stats);
+    }
+    if (iters_done) *iters_done = it;
+    return ok();
+  });
+}
+
+gm_status gm_last_run_stats(gm_graph g, gm_run_stats* out) {
+  if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
+  if (!out) return fail(GM_EINVAL, "out is NULL");
+  out->supersteps = g->last_stats.supersteps;
+  out->push_supersteps = g->last_stats.push_supersteps;
+  out->pull_supersteps = g->last_stats.pull_supersteps;
+  out->edges_scanned = (int64_t)g->last_stats.edges_scanned;
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "gm.h"
+
+namespace gm {
+
+// ---------------------------------------------------------------------------
+// Errors. Every exported function returns through these helpers so the
+// thread-local message always matches the status.
+// ---------------------------------------------------------------------------
+gm_status fail(gm_status st, const char* fmt, ...);
+gm_status ok();
+
+struct HipError {
+  hipError_t err;
+  const char* what;
+  int line;
+};
+
+#define GM_HIP(expr)                                                          \
+  do {                                                                        \
+    hipError_t _e = (expr);                                                   \
+    if (_e != hipSuccess) throw ::gm::HipError{_e, #expr, __LINE__};          \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Device buffers
+// ---------------------------------------------------------------------------
+struct OutOfMemory {
+  size_t bytes;
+};
+
+// A valid request the library cannot serve (reported as GM_EUNSUPPORTED).
+struct Unsupported {
+  const char* what;
+};
+
+// Device allocation that throws OutOfMemory / HipError.
+void* dmalloc(size_t bytes);
+void dfree(void* p);
+
+template <class T>
+T* dalloc(size_t count) {
+  return static_cast<T*>(dmalloc(count * sizeof(T) + (count == 0 ? 16 : 0)));
+}
+
+// Counters of the last frontier-program run.
+struct RunStats {
+  int32_t supersteps = 0;
+  int32_t push_supersteps = 0;
+  int32_t pull_supersteps = 0;
+  unsigned long long edges_scanned = 0;  // out-edges of the vertices that sent
+};
+
+struct Tuning {
+  // BFS: pull superstep when the frontier holds more than n / pull_div vertices
+  uint32_t pull_div = 20;
+  // supersteps launched between two host checks of the frontier size
+  uint32_t superstep_batch = 4;
+};
+
+}  // namespace gm
+
+struct gm_graph_s {
+  uint64_t magic;
+  int64_t n = 0;
+  int64_t m = 0;
+  int32_t wtype = GM_W_NONE;
+  uint32_t prep = 0;
+  uint32_t layouts = 0;
+  int device = 0;
+  int64_t max_out = 0, max_in = 0;
+  // out-adjacency (CSR of G; the columns of G^T in the paper's terms)
+  uint32_t* out_off = nullptr;
+  int32_t* out_idx = nullptr;
+  void* out_w = nullptr;
+  // in-adjacency (CSC of G)
+  uint32_t* in_off = nullptr;
+  int32_t* in_idx = nullptr;
+  void* in_w = nullptr;
+  uint32_t* in_eid = nullptr;  // canonical (CSR) edge id of each in-edge
+  float* inv_outdeg = nullptr; // 1/outdeg, 0 for dangling vertices
+  int64_t device_bytes = 0;
+  void* min_ws = nullptr;    // frontier workspace of the min programs (minprog.hip)
+  void* pr_sched = nullptr;  // pull schedule of the dense programs (pagerank.hip)
+  gm::RunStats last_stats;
+  gm::Tuning tune;
+};
+
+namespace gm {
+
+constexpr uint64_t kGraphMagic = 0x4752'4150'484d'4154ull;  // "GRAPHMAT"
+
+// Handle registry (graph handles are validated on every call).
+bool graph_live(gm_graph g);
+void graph_register(gm_graph g);
+void graph_unregister(gm_graph g);
+
+// Device-side graph construction (graph_build.hip).
+void build_graph(gm_graph g, const int32_t* src, const int32_t* dst, const void* w, int64_t m_in,
+                 hipStream_t s);
+void free_graph_memory(gm_graph g);
+
+// PageRank family (pagerank.hip).
+void ensure_pull_schedule(gm_graph g, hipStream_t s);
+void run_pagerank(gm_graph g, float r, int32_t iters, float* rank, int32_t seed, hipStream_t s);
+
+// Min programs (minprog.hip). Returns supersteps done.
+int32_t run_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count,
+                        int32_t max_iters, uint32_t* prop, int32_t* active_out, hipStream_t s,
+                        RunStats* stats);
+void free_min_workspace(gm_graph g);
+void free_pull_schedule(gm_graph g);
+
+// Fill n uint32 words with v on stream s (a kernel, safe under graph capture).
+void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+
+// Validate device ids in [0, n): returns false if any is out of range.
+bool ids_in_range(const int32_t* ids, int64_t count, int64_t n, hipStream_t s);
+
+}  // namespace gm

@@ -1,0 +1,476 @@
+// BFS (Sec. 3 II, Eq. (2)) and SSSP (Sec. 3 V, Eq. (8)): vertex programs whose
+// REDUCE is min, run as supersteps of Alg. 2 on a sparse frontier.
+//
+// The frontier is a bitvector over the vertices (the sparse-vector layout the
+// paper adopts, Sec. 4.4.2). Superstep t:
+//   send_kernel   compacts the frontier bitvector into a queue of active
+//                 vertices and snapshots each one's message x_u = prop(u)
+//                 (SEND_MESSAGE), its first out-edge, and the exclusive
+//                 prefix sum of out-degrees over the queue. Counts, edge
+//                 totals and the smallest/largest message go to a small
+//                 per-superstep control record.
+//   push_kernel   walks the out-edges of the queued vertices (the columns of
+//                 G^T present in x, Alg. 1). The concatenated edge lists are
+//                 cut into equal ranges, one per wavefront, so hubs and
+//                 low-degree vertices cost the same per edge; a wavefront
+//                 finds its first vertex by a 64-ary search of the prefix sum.
+//                 Each edge (u, v, w) forms PROCESS(x_u, w) and REDUCEs it
+//                 into prop(v) with an atomic min, which is also APPLY
+//                 (min(prop, y)); a vertex whose value dropped gets its bit in
+//                 the next frontier.
+//   pull_kernel   (BFS, large frontier, all frontier levels equal) instead
+//                 lets every vertex whose level exceeds the frontier level + 1
+//                 look for an in-neighbour in the frontier. Levels are
+//                 unique, so the result is the same as pushing.
+// The push and pull kernels of a superstep are both launched; each reads the
+// control record written by send_kernel and only the selected one works.
+// Messages are snapshotted before the product and min is exact and
+// order-free, so every superstep leaves exactly the state of Alg. 2. Only
+// non-returning atomics are used on the hot path.
+#include <cstring>
+
+#include "gm_internal.h"
+
+namespace gm {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kPushBlocks = 2048;
+constexpr int kUnroll = 4;  // edge rounds in flight per wavefront
+constexpr uint32_t kInfBfs = 0x7FFFFFFFu;
+constexpr int kMaxCtl = 64;  // control records per launch batch
+
+struct Ctl {
+  unsigned long long packed;  // (queued vertices << 32) | their out-edges
+  unsigned int msg_min;       // smallest message of the frontier
+  unsigned int msg_max;       // largest message of the frontier
+};
+
+struct Workspace {
+  int64_t n = 0;
+  int32_t* q = nullptr;       // active vertices
+  uint32_t* qmsg = nullptr;   // their messages
+  uint32_t* qbeg = nullptr;   // their first out-edge
+  uint32_t* qest = nullptr;   // exclusive prefix sum of out-degrees
+  uint32_t* bits[2] = {nullptr, nullptr};
+  Ctl* ctl = nullptr;         // kMaxCtl records
+  Ctl* host_ctl = nullptr;    // pinned mirror
+};
+
+__device__ inline bool use_pull(const Ctl& c, int kind, bool pull_ok, int64_t n,
+                                uint32_t pull_div) {
+  const uint64_t count = c.packed >> 32;
+  return kind == GM_PROG_BFS && pull_ok && count > 0 && c.msg_min == c.msg_max &&
+         count > (uint64_t)(n / (int64_t)pull_div);
+}
+
+template <int kKind>
+__device__ inline uint32_t process(uint32_t msg, uint32_t w) {
+  if constexpr (kKind == GM_PROG_SSSP) {
+    const uint32_t s = msg + w;
+    return s < msg ? 0xFFFFFFFFu : s;  // saturating add
+  } else {
+    return msg >= kInfBfs ? kInfBfs : msg + 1;
+  }
+}
+
+__device__ inline uint32_t wave_incl_scan(uint32_t x, int lane) {
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(x, o, 64);
+    if (lane >= o) x += t;
+  }
+  return x;
+}
+
+// Block-wide exclusive scan of one value per thread; returns the exclusive
+// prefix and writes the block total to *total.
+__device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t* sh, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t incl = wave_incl_scan(x, lane);
+  if (lane == 63) sh[wave] = incl;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+  for (int i = 0; i < kWaves; ++i) {
+    if (i < wave) base += sh[i];
+    tot += sh[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + incl - x;
+}
+
+__global__ __launch_bounds__(kThreads) void seed_bits(const int32_t* __restrict__ ids,
+                                                      int64_t count, uint32_t* bits) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = ids[i];
+    atomicOr(&bits[v >> 5], 1u << (v & 31));
+  }
+}
+
+// SEND: frontier bitvector -> queue (vertex, message, first edge, edge prefix).
+__global__ __launch_bounds__(kThreads) void send_kernel(
+    const uint32_t* __restrict__ bits, int64_t words, const uint32_t* __restrict__ prop,
+    const uint32_t* __restrict__ off, int32_t* __restrict__ q, uint32_t* __restrict__ qmsg,
+    uint32_t* __restrict__ qbeg, uint32_t* __restrict__ qest, Ctl* __restrict__ ctl) {
+  __shared__ uint32_t sh[2 * kWaves];
+  __shared__ unsigned long long base_packed;
+  uint32_t mn = 0xFFFFFFFFu, mx = 0;
+  for (int64_t w0 = (int64_t)blockIdx.x * kThreads; w0 < words;
+       w0 += (int64_t)gridDim.x * kThreads) {
+    const int64_t wi = w0 + threadIdx.x;
+    const uint32_t word = wi < words ? bits[wi] : 0u;
+    const uint32_t cnt = __popc(word);
+    uint32_t edges = 0;
+    for (uint32_t b = word; b; b &= b - 1) {
+      const uint32_t v = (uint32_t)(wi * 32) + (__ffs(b) - 1);
+      edges += off[v + 1] - off[v];
+    }
+    uint32_t ctot, etot;
+    const uint32_t cex = block_excl_scan(cnt, sh, &ctot);
+    const uint32_t eex = block_excl_scan(edges, sh + kWaves, &etot);
+    if (ctot == 0) continue;  // block-uniform
+    if (threadIdx.x == 0)
+      base_packed = atomicAdd(&ctl->packed, ((unsigned long long)ctot << 32) | etot);
+    __syncthreads();
+    const unsigned long long bp = base_packed;
+    __syncthreads();
+    uint32_t slot = (uint32_t)(bp >> 32) + cex;
+    uint32_t est = (uint32_t)bp + eex;
+    for (uint32_t b = word; b; b &= b - 1) {
+      const uint32_t v = (uint32_t)(wi * 32) + (__ffs(b) - 1);
+      const uint32_t msg = prop[v];
+      const uint32_t ob = off[v];
+      q[slot] = (int32_t)v;
+      qmsg[slot] = msg;
+      qbeg[slot] = ob;
+      qest[slot] = est;
+      est += off[v + 1] - ob;
+      ++slot;
+      mn = msg < mn ? msg : mn;
+      mx = msg > mx ? msg : mx;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  if ((threadIdx.x & 63) == 0 && mn <= mx) {
+    atomicMin(&ctl->msg_min, mn);
+    atomicMax(&ctl->msg_max, mx);
+  }
+}
+
+// PROCESS + REDUCE(min) + APPLY(min) of one edge; non-returning atomics only.
+// The value of v drops this superstep iff cand < (any value of v read during
+// the superstep), so marking v after such a read is exactly "v changed".
+__device__ inline void relax(uint32_t cand, int32_t v, uint32_t* prop, uint32_t* next) {
+  if (cand < __hip_atomic_load(&prop[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    __hip_atomic_fetch_min(&prop[v], cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t bit = 1u << (v & 31);
+    if (!(__hip_atomic_load(&next[v >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit))
+      __hip_atomic_fetch_or(&next[v >> 5], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <int kKind>
+__global__ __launch_bounds__(kThreads) void push_kernel(
+    const Ctl* __restrict__ ctlp, int64_t n, bool pull_ok, uint32_t pull_div,
+    const uint32_t* __restrict__ qmsg, const uint32_t* __restrict__ qbeg,
+    const uint32_t* __restrict__ qest, const int32_t* __restrict__ idx,
+    const uint32_t* __restrict__ w, uint32_t* prop, uint32_t* next) {
+  const Ctl c = *ctlp;
+  if (use_pull(c, kKind, pull_ok, n, pull_div)) return;
+  const uint32_t count = (uint32_t)(c.packed >> 32);
+  const uint64_t E = (uint32_t)c.packed;
+  if (count == 0 || E == 0) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t nw = (uint64_t)gridDim.x * kWaves;
+  const uint64_t wid = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const uint32_t e_begin = (uint32_t)(E * wid / nw);
+  const uint32_t e_end = (uint32_t)(E * (wid + 1) / nw);
+  if (e_begin >= e_end) return;
+  // 64-ary search for the last slot whose edge prefix is <= e_begin (slot 0
+  // has prefix 0, so lane 0's sample always qualifies).
+  uint32_t lo = 0, hi = count;  // answer in [lo, hi)
+  while (hi - lo > 64) {
+    const uint32_t span = hi - lo;
+    const uint32_t p = lo + (uint32_t)((uint64_t)span * lane / 64);
+    const unsigned long long m = __ballot(qest[p] <= e_begin);
+    const int last = 63 - __clzll(m);
+    const uint32_t nlo = lo + (uint32_t)((uint64_t)span * last / 64);
+    hi = last == 63 ? hi : lo + (uint32_t)((uint64_t)span * (last + 1) / 64);
+    lo = nlo;
+  }
+  {
+    const uint32_t p = lo + lane;
+    lo += 63 - __clzll(__ballot(p < hi && qest[p] <= e_begin));
+  }
+  // Walk windows of 64 queue slots; lane j of a window holds slot s0 + j.
+  uint32_t e = e_begin;
+  for (uint32_t s0 = lo; e < e_end; s0 += 64) {
+    const uint32_t s = s0 + lane;
+    const bool valid = s < count;
+    const uint32_t est = valid ? qest[s] : (uint32_t)E;
+    const uint32_t beg = valid ? qbeg[s] : 0u;
+    const uint32_t msg = valid ? qmsg[s] : 0u;
+    const uint32_t win_end = s0 + 64 < count ? qest[s0 + 64] : (uint32_t)E;
+    const uint32_t stop = win_end < e_end ? win_end : e_end;
+    for (; e < stop; e += 64 * kUnroll) {
+      uint32_t cand[kUnroll];
+      uint32_t eidx[kUnroll];
+      int32_t dst[kUnroll];
+      bool act[kUnroll];
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k) {
+        const uint32_t ee = e + k * 64 + lane;
+        act[k] = ee < stop;
+        int j = 0;  // owner: the last lane whose prefix is <= ee
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+          const uint32_t ex = __shfl(est, j + step, 64);
+          if (ex <= ee) j += step;
+        }
+        const uint32_t ej = __shfl(est, j, 64);
+        const uint32_t bj = __shfl(beg, j, 64);
+        cand[k] = __shfl(msg, j, 64);
+        eidx[k] = bj + (ee - ej);
+      }
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k) dst[k] = act[k] ? idx[eidx[k]] : 0;
+      if constexpr (kKind == GM_PROG_SSSP) {
+        uint32_t ww[kUnroll];
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) ww[k] = act[k] ? w[eidx[k]] : 0u;
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) cand[k] = process<kKind>(cand[k], ww[k]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) cand[k] = process<kKind>(cand[k], 0u);
+      }
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k)
+        if (act[k]) relax(cand[k], dst[k], prop, next);
+    }
+    e = stop;
+  }
+}
+
+// BFS pull superstep over all vertices (frontier levels uniform).
+__global__ __launch_bounds__(kThreads) void pull_kernel(
+    const Ctl* __restrict__ ctlp, int64_t n, bool pull_ok, uint32_t pull_div,
+    const uint32_t* __restrict__ off, const int32_t* __restrict__ idx,
+    const uint32_t* __restrict__ cur, uint32_t* prop, uint32_t* next) {
+  const Ctl c = *ctlp;
+  if (!use_pull(c, GM_PROG_BFS, pull_ok, n, pull_div)) return;
+  const uint32_t cand = c.msg_min >= kInfBfs ? kInfBfs : c.msg_min + 1;
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += stride) {
+    const int64_t v = base + threadIdx.x;
+    bool hit = false;
+    if (v < n && cand < prop[v]) {
+      const uint32_t e1 = off[v + 1];
+      for (uint32_t e = off[v]; e < e1; ++e) {
+        const int32_t u = idx[e];
+        if (cur[u >> 5] & (1u << (u & 31))) {
+          hit = true;
+          break;
+        }
+      }
+      if (hit) prop[v] = cand;
+    }
+    // 64 consecutive vertices = two whole words owned by this wavefront
+    const unsigned long long m = __ballot(hit);
+    const int64_t word0 = (base + (threadIdx.x & ~63)) >> 5;
+    if (lane == 0 && (uint32_t)m) atomicOr(&next[word0], (uint32_t)m);
+    if (lane == 32 && (uint32_t)(m >> 32)) atomicOr(&next[word0 + 1], (uint32_t)(m >> 32));
+  }
+}
+
+__global__ void reset_ctl(Ctl* ctl) {
+  ctl->packed = 0;
+  ctl->msg_min = 0xFFFFFFFFu;
+  ctl->msg_max = 0;
+}
+
+__global__ void fill_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// active_out[v] = bit v of the frontier; then clear the frontier.
+__global__ void bits_epilogue(uint32_t* bits, int64_t words, int64_t n, int32_t* active_out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t word = bits[i];
+    if (active_out)
+      for (int k = 0; k < 32 && i * 32 + k < n; ++k) active_out[i * 32 + k] = (word >> k) & 1u;
+    if (word) bits[i] = 0;
+  }
+}
+
+__global__ void id_range(const int32_t* __restrict__ ids, int64_t count, int64_t n,
+                         unsigned int* __restrict__ bad) {
+  unsigned int b = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    b |= (ids[i] < 0 || (int64_t)ids[i] >= n) ? 1u : 0u;
+  for (int o = 32; o > 0; o >>= 1) b |= __shfl_xor(b, o, 64);
+  if (b && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
+}
+
+inline unsigned blocks_for(int64_t n, int64_t cap = 8192) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+Workspace* ensure_ws(gm_graph g, hipStream_t s) {
+  Workspace* ws = static_cast<Workspace*>(g->min_ws);
+  if (ws) return ws;
+  ws = new Workspace();
+  g->min_ws = ws;
+  const int64_t n = g->n;
+  const int64_t words = (n + 31) / 32;
+  ws->n = n;
+  ws->q = dalloc<int32_t>(n);
+  ws->qmsg = dalloc<uint32_t>(n);
+  ws->qbeg = dalloc<uint32_t>(n);
+  ws->qest = dalloc<uint32_t>(n);
+  ws->bits[0] = dalloc<uint32_t>(words);
+  ws->bits[1] = dalloc<uint32_t>(words);
+  ws->ctl = dalloc<Ctl>(kMaxCtl);
+  void* h = nullptr;
+  GM_HIP(hipHostMalloc(&h, kMaxCtl * sizeof(Ctl), hipHostMallocDefault));
+  ws->host_ctl = static_cast<Ctl*>(h);
+  fill_kernel<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[0], words, 0);
+  fill_kernel<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[1], words, 0);
+  GM_HIP(hipGetLastError());
+  return ws;
+}
+
+}  // namespace
+
+void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
+  if (n <= 0) return;
+  fill_kernel<<<blocks_for(n), kThreads, 0, s>>>(p, n, v);
+  GM_HIP(hipGetLastError());
+}
+
+void free_min_workspace(gm_graph g) {
+  Workspace* ws = static_cast<Workspace*>(g->min_ws);
+  if (!ws) return;
+  dfree(ws->q);
+  dfree(ws->qmsg);
+  dfree(ws->qbeg);
+  dfree(ws->qest);
+  dfree(ws->bits[0]);
+  dfree(ws->bits[1]);
+  dfree(ws->ctl);
+  if (ws->host_ctl) (void)hipHostFree(ws->host_ctl);
+  delete ws;
+  g->min_ws = nullptr;
+}
+
+bool ids_in_range(const int32_t* ids, int64_t count, int64_t n, hipStream_t s) {
+  if (count <= 0) return true;
+  unsigned int* bad = dalloc<unsigned int>(1);
+  unsigned int h = 0;
+  try {
+    fill_u32(bad, 1, 0u, s);
+    id_range<<<blocks_for(count), kThreads, 0, s>>>(ids, count, n, bad);
+    GM_HIP(hipGetLastError());
+    GM_HIP(hipMemcpyAsync(&h, bad, sizeof(h), hipMemcpyDeviceToHost, s));
+    GM_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    dfree(bad);
+    throw;
+  }
+  dfree(bad);
+  return h == 0;
+}
+
+int32_t run_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count,
+                        int32_t max_iters, uint32_t* prop, int32_t* active_out, hipStream_t s,
+                        RunStats* stats) {
+  Workspace* ws = ensure_ws(g, s);
+  const int64_t n = g->n;
+  const int64_t words = (n + 31) / 32;
+  const bool sym = (g->prep & (GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG)) == GM_PREP_SYMMETRIZE;
+  const uint32_t* pull_off = sym ? g->out_off : g->in_off;
+  const int32_t* pull_idx = sym ? g->out_idx : g->in_idx;
+  const bool pull_ok = kind == GM_PROG_BFS && pull_off != nullptr;
+  const uint32_t pull_div = g->tune.pull_div;
+  int32_t batch = (int32_t)g->tune.superstep_batch;
+  if (batch < 1) batch = 1;
+  const uint32_t* w = static_cast<const uint32_t*>(g->out_w);
+  int cur = 0;
+  if (count > 0) {
+    seed_bits<<<blocks_for(count), kThreads, 0, s>>>(ids, count, ws->bits[0]);
+    GM_HIP(hipGetLastError());
+  }
+  int32_t iters = 0;
+  RunStats st{};
+  bool done = count == 0;
+  const unsigned send_blocks = blocks_for(words, 4096);
+  const unsigned pull_blocks = blocks_for(n, 8192);
+  while (!done) {
+    int32_t nb = batch;
+    if (max_iters > 0 && max_iters - iters < nb) nb = max_iters - iters;
+    if (nb > kMaxCtl) nb = kMaxCtl;
+    for (int32_t b = 0; b < nb; ++b) {
+      Ctl* c = ws->ctl + b;
+      reset_ctl<<<1, 1, 0, s>>>(c);
+      send_kernel<<<send_blocks, kThreads, 0, s>>>(ws->bits[cur], words, prop, g->out_off, ws->q,
+                                                   ws->qmsg, ws->qbeg, ws->qest, c);
+      if (kind == GM_PROG_SSSP)
+        push_kernel<GM_PROG_SSSP><<<kPushBlocks, kThreads, 0, s>>>(
+            c, n, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, g->out_idx, w, prop,
+            ws->bits[cur ^ 1]);
+      else
+        push_kernel<GM_PROG_BFS><<<kPushBlocks, kThreads, 0, s>>>(
+            c, n, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, g->out_idx, nullptr, prop,
+            ws->bits[cur ^ 1]);
+      if (pull_ok)
+        pull_kernel<<<pull_blocks, kThreads, 0, s>>>(c, n, pull_ok, pull_div, pull_off, pull_idx,
+                                                     ws->bits[cur], prop, ws->bits[cur ^ 1]);
+      fill_kernel<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[cur], words, 0);
+      GM_HIP(hipGetLastError());
+      cur ^= 1;
+    }
+    GM_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, nb * sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    GM_HIP(hipStreamSynchronize(s));
+    for (int32_t b = 0; b < nb; ++b) {
+      const Ctl& c = ws->host_ctl[b];
+      const uint64_t cnt = c.packed >> 32;
+      if (cnt == 0) {
+        done = true;
+        break;
+      }
+      ++iters;
+      st.edges_scanned += (uint32_t)c.packed;
+      const bool pulled = kind == GM_PROG_BFS && pull_ok && c.msg_min == c.msg_max &&
+                          (int64_t)cnt > n / (int64_t)pull_div;
+      if (pulled)
+        ++st.pull_supersteps;
+      else
+        ++st.push_supersteps;
+    }
+    if (max_iters > 0 && iters >= max_iters) done = true;
+  }
+  // bits[cur] holds the frontier left after the last superstep (empty when
+  // the program converged); report it and leave the workspace cleared.
+  bits_epilogue<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[cur], words, n, active_out);
+  GM_HIP(hipGetLastError());
+  GM_HIP(hipStreamSynchronize(s));
+  st.supersteps = iters;
+  if (stats) *stats = st;
+  return iters;
+}
+
+}  // namespace gm

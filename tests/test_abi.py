@@ -1,0 +1,110 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/*.h declares, and rejects bad arguments before touching the device."""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1503_07241_amd as gm
+from paper_1503_07241_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1503_07241_amd import build
+        build.build()
+    return _lib.load()
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(gm_\w+)\s*\(", text, re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "gm_run_vertex_program" in names and "gm_graph_from_coo" in names
+    for name in sorted(names):
+        assert hasattr(lib, name), "libgm.so does not export %s" % name
+
+
+def test_version_and_clean_error(lib):
+    assert b"gfx950" in lib.gm_version()
+
+
+def status(lib, fn, *args):
+    st = getattr(lib, fn)(*args)
+    return st, lib.gm_last_error().decode()
+
+
+def test_from_coo_argument_errors(lib):
+    src = np.array([0, 1, 2], dtype=np.int32)
+    dst = np.array([1, 2, 5], dtype=np.int32)
+    out = ctypes.c_void_p()
+    P = src.ctypes.data
+    Q = dst.ctypes.data
+    # out NULL
+    assert status(lib, "gm_graph_from_coo", 4, 3, P, Q, None, 0, 1, 1, None, None)[0] == _lib.GM_EINVAL
+    # n <= 0, n too large
+    for n in (0, -3, 2**31):
+        st, msg = status(lib, "gm_graph_from_coo", n, 3, P, Q, None, 0, 1, 1, None, ctypes.byref(out))
+        assert st == _lib.GM_EINVAL and "n =" in msg
+    # m < 0
+    assert status(lib, "gm_graph_from_coo", 8, -1, P, Q, None, 0, 1, 1, None, ctypes.byref(out))[0] == _lib.GM_EINVAL
+    # src NULL with m > 0
+    assert status(lib, "gm_graph_from_coo", 8, 3, None, Q, None, 0, 1, 1, None, ctypes.byref(out))[0] == _lib.GM_EINVAL
+    # id out of range (dst 5 with n = 4)
+    st, msg = status(lib, "gm_graph_from_coo", 4, 3, P, Q, None, 0, 1, 1, None, ctypes.byref(out))
+    assert st == _lib.GM_EINVAL and "outside" in msg
+    # negative id
+    neg = np.array([0, -1, 2], dtype=np.int32)
+    assert status(lib, "gm_graph_from_coo", 8, 3, neg.ctypes.data, Q, None, 0, 1, 1, None, ctypes.byref(out))[0] == _lib.GM_EINVAL
+    # unknown wtype, weights vs wtype mismatch
+    assert status(lib, "gm_graph_from_coo", 8, 3, P, Q, None, 7, 1, 1, None, ctypes.byref(out))[0] == _lib.GM_EINVAL
+    assert status(lib, "gm_graph_from_coo", 8, 3, P, Q, None, _lib.GM_W_U32, 1, 1, None, ctypes.byref(out))[0] == _lib.GM_EINVAL
+    w = np.ones(3, dtype=np.uint32)
+    assert status(lib, "gm_graph_from_coo", 8, 3, P, Q, w.ctypes.data, 0, 1, 1, None, ctypes.byref(out))[0] == _lib.GM_EINVAL
+    # non-finite float weight
+    wf = np.array([1.0, np.nan, 2.0], dtype=np.float32)
+    assert status(lib, "gm_graph_from_coo", 8, 3, P, Q, wf.ctypes.data, _lib.GM_W_F32, 1, 1, None, ctypes.byref(out))[0] == _lib.GM_EINVAL
+    # unknown prep / layout bits
+    assert status(lib, "gm_graph_from_coo", 8, 3, P, Q, None, 0, 64, 1, None, ctypes.byref(out))[0] == _lib.GM_EINVAL
+    assert status(lib, "gm_graph_from_coo", 8, 3, P, Q, None, 0, 1, 0, None, ctypes.byref(out))[0] == _lib.GM_EINVAL
+    assert status(lib, "gm_graph_from_coo", 8, 3, P, Q, None, 0, 1, 8, None, ctypes.byref(out))[0] == _lib.GM_EINVAL
+    assert out.value is None
+
+
+def test_dead_handles_are_estate(lib):
+    bogus = ctypes.c_void_p(0x1234)
+    info = _lib.gm_graph_info()
+    assert lib.gm_graph_get_info(None, ctypes.byref(info)) == _lib.GM_ESTATE
+    assert lib.gm_graph_get_info(bogus, ctypes.byref(info)) == _lib.GM_ESTATE
+    assert lib.gm_graph_destroy(None) == _lib.GM_ESTATE
+    assert lib.gm_graph_destroy(bogus) == _lib.GM_ESTATE
+    assert "not live" in lib.gm_last_error().decode()
+    prog = _lib.gm_program(_lib.GM_PROG_BFS, _lib.GM_ORDER_OUT, 0.15, 0)
+    it = ctypes.c_int32()
+    assert lib.gm_run_vertex_program(bogus, ctypes.byref(prog), None, -1, None, None,
+                                     ctypes.byref(it), None) == _lib.GM_ESTATE
+    st = _lib.gm_run_stats()
+    assert lib.gm_last_run_stats(bogus, ctypes.byref(st)) == _lib.GM_ESTATE
+    assert lib.gm_graph_edges(bogus, None, None, None) == _lib.GM_ESTATE
+
+
+def test_python_binding_raises(lib):
+    with pytest.raises(gm.GmError) as ei:
+        gm.Graph.from_coo(4, [0, 1], [1, 9])
+    assert ei.value.status == _lib.GM_EINVAL
+    with pytest.raises(ValueError):
+        gm.Graph.from_coo(4, [0, 1], [1])

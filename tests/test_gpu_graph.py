@@ -1,0 +1,90 @@
+"""GPU graph construction (gm_graph_from_coo) against the oracle's preprocessing
+(Sec. 5.1): canonical edge lists must be identical, values included."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+import paper_1503_07241_amd as gm
+from tests import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+P_DIR = gm.GM_PREP_DROP_SELF_LOOPS
+P_SYM = gm.GM_PREP_DROP_SELF_LOOPS | gm.GM_PREP_SYMMETRIZE
+P_DAG = gm.GM_PREP_UPPER_DAG
+MODES = {"directed": P_DIR, "symmetric": P_SYM, "dag": P_DAG}
+
+
+def check_same(g: gm.Graph, og: oracle.Graph, weighted=False):
+    info = g.info()
+    assert info.n == og.n and info.m == og.m
+    if weighted:
+        s, d, w = g.edges(with_weights=True)
+        assert np.array_equal(w, og.w)
+    else:
+        s, d = g.edges()
+    assert np.array_equal(s.astype(np.int64), og.rows())
+    assert np.array_equal(d, og.idx)
+    deg = np.diff(og.off)
+    assert info.max_out == (deg.max() if og.m else 0)
+
+
+@pytest.mark.parametrize("mode", ["directed", "symmetric", "dag"])
+def test_rmat_small_build(mode):
+    n, s, d = W.raw(W.SMALL_SCALE)
+    g = gm.Graph.from_coo(n, s, d, prep=MODES[mode])
+    check_same(g, W.ograph(W.SMALL_SCALE, mode))
+    if mode == "directed":
+        assert g.info().max_in == np.bincount(W.ograph(W.SMALL_SCALE, mode).idx).max()
+
+
+def test_weighted_build_min_of_duplicates():
+    n = 1000  # not a power of two: ragged id range
+    rng = np.random.default_rng(4)
+    s = rng.integers(0, n, 30000).astype(np.int32)
+    d = rng.integers(0, n, 30000).astype(np.int32)
+    s[:50] = d[:50]  # self-loops
+    s[100:400] = 7  # many duplicates of (7, 3) with distinct weights
+    d[100:400] = 3
+    w = rng.integers(1, 10**6, 30000).astype(np.uint32)
+    g = gm.Graph.from_coo(n, s, d, w=w, prep=P_DIR)
+    og = oracle.prepare(n, s, d, w=w)
+    check_same(g, og, weighted=True)
+    wf = rng.uniform(0.5, 1.5, 30000).astype(np.float32)
+    gf = gm.Graph.from_coo(n, s, d, w=wf, prep=P_DIR)
+    check_same(gf, oracle.prepare(n, s, d, w=wf), weighted=True)
+
+
+def test_self_loops_kept_without_drop_flag():
+    s = np.array([0, 1, 1, 2], dtype=np.int32)
+    d = np.array([0, 1, 2, 2], dtype=np.int32)
+    g = gm.Graph.from_coo(3, s, d, prep=0)
+    gs, gd = g.edges()
+    assert gs.tolist() == [0, 1, 1, 2] and gd.tolist() == [0, 1, 2, 2]
+    g2 = gm.Graph.from_coo(3, s, d, prep=gm.GM_PREP_SYMMETRIZE)
+    gs, gd = g2.edges()
+    assert list(zip(gs.tolist(), gd.tolist())) == [(0, 0), (1, 1), (1, 2), (2, 1), (2, 2)]
+
+
+def test_empty_and_single_vertex():
+    g = gm.Graph.from_coo(5, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    info = g.info()
+    assert info.n == 5 and info.m == 0 and info.max_out == 0
+    g1 = gm.Graph.from_coo(1, [0], [0])
+    assert g1.info().m == 0
+
+
+def test_full_size_build_counts():
+    n, s, d = W.raw(W.FULL_SCALE)
+    g = gm.Graph.from_coo(n, s, d, w=W.weights(W.FULL_SCALE), prep=P_DIR)
+    og = W.ograph(W.FULL_SCALE, "directed", True)
+    check_same(g, og, weighted=True)
+
+
+def test_destroy_then_estate():
+    g = gm.Graph.from_coo(4, [0, 1], [1, 2])
+    h = g.handle
+    g.close()
+    st = gm._lib.load().gm_graph_destroy(h)
+    assert st == gm._lib.GM_ESTATE

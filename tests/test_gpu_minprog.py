@@ -1,0 +1,152 @@
+"""GPU BFS (Sec. 3 II) and SSSP (Sec. 3 V) against the oracle: bit-exact
+properties and the superstep counts of Alg. 2."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+import paper_1503_07241_amd as gm
+from tests import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+P_DIR = gm.GM_PREP_DROP_SELF_LOOPS
+P_SYM = gm.GM_PREP_DROP_SELF_LOOPS | gm.GM_PREP_SYMMETRIZE
+
+
+def ids(*v):
+    return torch.tensor(list(v), dtype=torch.int32, device=DEV)
+
+
+def run_bfs(g, n, roots, max_iters=-1):
+    level = torch.full((n,), gm.INF_LEVEL, dtype=torch.int32, device=DEV)
+    level[torch.as_tensor(roots, dtype=torch.long)] = 0
+    active = torch.zeros(n, dtype=torch.int32, device=DEV)
+    it = gm.run_vertex_program(g, gm.GM_PROG_BFS, ids(*roots), max_iters, level, active)
+    return level.cpu().numpy(), it, active.cpu().numpy()
+
+
+def run_sssp(g, n, source, max_iters=-1, prop=None, frontier=None):
+    if prop is None:
+        prop = torch.full((n,), -1, dtype=torch.int32, device=DEV)  # UINT32_MAX bits
+        prop[source] = 0
+        frontier = ids(source)
+    active = torch.zeros(n, dtype=torch.int32, device=DEV)
+    it = gm.run_vertex_program(g, gm.GM_PROG_SSSP, frontier, max_iters, prop, active)
+    return prop.cpu().numpy().view(np.uint32), it, active.cpu().numpy()
+
+
+@pytest.mark.parametrize("scale", [W.SMALL_SCALE, W.FULL_SCALE])
+def test_bfs_rmat(scale):
+    n, s, d = W.raw(scale)
+    g = gm.Graph.from_coo(n, s, d, prep=P_SYM)
+    level, it, active = run_bfs(g, n, [0])
+    ref = W.bfs_levels(scale)
+    assert np.array_equal(level, ref)
+    assert it == int(ref[ref != oracle.INF_I32].max()) + 1
+    assert not active.any()
+    st = g.last_run_stats()
+    # Alg. 1 traverses the out-edges of every vertex that sends: all reached ones
+    og = W.ograph(scale, "symmetric")
+    assert st.edges_scanned == int(og.degree()[ref != oracle.INF_I32].sum())
+
+
+@pytest.mark.parametrize("scale", [W.SMALL_SCALE, W.FULL_SCALE])
+def test_sssp_rmat(scale):
+    n, s, d = W.raw(scale)
+    g = gm.Graph.from_coo(n, s, d, w=W.weights(scale), prep=P_DIR)
+    dist, it, active = run_sssp(g, n, 0)
+    assert np.array_equal(dist, W.sssp_dist(scale))
+    assert it == W.sssp_supersteps(scale)
+    assert not active.any()
+
+
+def test_sssp_resume_equals_uninterrupted():
+    scale = 12
+    n, s, d = W.raw(scale)
+    g = gm.Graph.from_coo(n, s, d, w=W.weights(scale), prep=P_DIR)
+    full, it_full, _ = run_sssp(g, n, 0)
+    prop = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+    prop[0] = 0
+    d1, it1, act1 = run_sssp(g, n, 0, max_iters=3, prop=prop, frontier=ids(0))
+    assert it1 == 3 and act1.any()
+    fr = torch.tensor(np.flatnonzero(act1), dtype=torch.int32, device=DEV)
+    d2, it2, _ = run_sssp(g, n, 0, prop=prop, frontier=fr)
+    assert np.array_equal(d2, full) and it1 + it2 == it_full
+    # the oracle's Alg. 2 agrees on the intermediate state after 3 supersteps
+    og = W.ograph(scale, "directed", True)
+    p0 = np.full(n, oracle.INF_U32, dtype=np.uint32)
+    p0[0] = 0
+    a0 = np.zeros(n, dtype=bool)
+    a0[0] = True
+    po, ao, _ = oracle.run_min_program(og, p0, a0, weighted=True, max_iters=3)
+    assert np.array_equal(d1, po) and np.array_equal(act1.astype(bool), ao)
+
+
+def test_bfs_multi_root_empty_and_isolated():
+    n = 50
+    s = np.arange(0, 20, dtype=np.int32)
+    d = np.arange(1, 21, dtype=np.int32)  # path 0..20, vertices 21..49 isolated
+    g = gm.Graph.from_coo(n, s, d, prep=P_SYM)
+    og = oracle.prepare(n, s, d, mode="symmetric")
+    level, it, _ = run_bfs(g, n, [0, 20])
+    assert np.array_equal(level, oracle.bfs(og, [0, 20]))
+    assert it == 11
+    level, it, _ = run_bfs(g, n, [30])
+    assert it == 1 and level[30] == 0 and (np.delete(level, 30) == gm.INF_LEVEL).all()
+    # empty frontier: nothing runs, nothing changes
+    lv = torch.full((n,), 5, dtype=torch.int32, device=DEV)
+    assert gm.run_vertex_program(g, gm.GM_PROG_BFS, ids(), -1, lv) == 0
+    assert (lv.cpu().numpy() == 5).all()
+
+
+def test_hub_chunks_and_long_path():
+    """A star whose centre has far more out-edges than the hub chunk, plus a
+    long path (many supersteps, one vertex each)."""
+    leaves = 20000
+    n = leaves + 1 + 3000
+    s = np.concatenate([np.zeros(leaves, np.int32), np.arange(leaves + 1, n - 1, dtype=np.int32),
+                        np.array([5], np.int32)])
+    d = np.concatenate([np.arange(1, leaves + 1, dtype=np.int32),
+                        np.arange(leaves + 2, n, dtype=np.int32), np.array([leaves + 1], np.int32)])
+    w = gg.weights_u32(s, d)
+    g = gm.Graph.from_coo(n, s, d, w=w, prep=P_DIR)
+    og = oracle.prepare(n, s, d, w=w)
+    dist, it, _ = run_sssp(g, n, 0)
+    assert np.array_equal(dist, oracle.sssp(og, 0))
+    gs = gm.Graph.from_coo(n, s, d, prep=P_SYM)
+    level, it, _ = run_bfs(gs, n, [0])
+    ref = oracle.bfs(oracle.prepare(n, s, d, mode="symmetric"), 0)
+    assert np.array_equal(level, ref) and it == ref[ref != oracle.INF_I32].max() + 1
+
+
+def test_bfs_deterministic_repeats():
+    n, s, d = W.raw(16)
+    g = gm.Graph.from_coo(n, s, d, prep=P_SYM)
+    first = run_bfs(g, n, [0])[0]
+    for _ in range(3):
+        assert np.array_equal(run_bfs(g, n, [0])[0], first)
+
+
+def test_sssp_unit_weights_equal_directed_bfs():
+    n, s, d = W.raw(12)
+    g = gm.Graph.from_coo(n, s, d, w=np.ones(len(s), np.uint32), prep=P_DIR)
+    dist, _, _ = run_sssp(g, n, 0)
+    lvl = oracle.bfs(oracle.prepare(n, s, d), 0)
+    assert np.array_equal(dist, np.where(lvl == oracle.INF_I32, oracle.INF_U32, lvl).astype(np.uint32))
+
+
+def test_argument_errors_on_device():
+    n, s, d = W.raw(10)
+    g = gm.Graph.from_coo(n, s, d, prep=P_DIR)
+    lv = torch.zeros(n, dtype=torch.int32, device=DEV)
+    with pytest.raises(gm.GmError) as e:
+        gm.run_vertex_program(g, gm.GM_PROG_BFS, ids(n + 5), -1, lv)
+    assert e.value.status == gm._lib.GM_EINVAL
+    with pytest.raises(gm.GmError) as e:  # SSSP on an unweighted graph
+        gm.run_vertex_program(g, gm.GM_PROG_SSSP, ids(0), -1, lv)
+    assert e.value.status == gm._lib.GM_EUNSUPPORTED
+    with pytest.raises(gm.GmError) as e:  # PageRank needs max_iters > 0
+        gm.run_vertex_program(g, gm.GM_PROG_PAGERANK, None, 0, lv.float())
+    assert e.value.status == gm._lib.GM_EINVAL
