@@ -131,8 +131,12 @@ def main():
     gteps = edges_step / (wall / args.steps) / 1e9
 
     # Dominant kernel: the PageRank pull superstep (one launch per superstep).
+    # Algorithmic bytes per superstep: every in-edge index (4 m), per row with
+    # in-edges its offset, 1/outdeg and new message (12 n_dst), and every
+    # message that is sent read once (4 n_src).
     pr_ms_launch = acc["pr"] / args.steps / T_PR
-    pr_bytes = 4 * m_dir + 16 * n  # idx + offsets + gathered msg + 1/outdeg + msg write
+    info = g_dir.info()
+    pr_bytes = 4 * m_dir + 12 * info.n_dst + 4 * info.n_src
     achieved = pr_bytes / (pr_ms_launch * 1e-3) / 1e9
     programs = {}
     for k in ev:

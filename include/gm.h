@@ -107,6 +107,8 @@ typedef struct gm_graph_info {
   uint32_t layouts;   /* GM_LAYOUT_* built */
   int32_t device;     /* HIP device ordinal */
   int64_t device_bytes; /* device memory held by the graph (not the workspace) */
+  int64_t n_src;      /* vertices with out-degree > 0 */
+  int64_t n_dst;      /* vertices with in-degree > 0 (0 if the in-layout is absent) */
 } gm_graph_info;
 
 /* Fill *info (host). Errors: GM_ESTATE, GM_EINVAL (info NULL). */

@@ -33,7 +33,8 @@ class gm_graph_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("max_out", ctypes.c_int64),
                 ("max_in", ctypes.c_int64), ("wtype", ctypes.c_int32), ("prep", ctypes.c_uint32),
                 ("layouts", ctypes.c_uint32), ("device", ctypes.c_int32),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("n_src", ctypes.c_int64),
+                ("n_dst", ctypes.c_int64)]
 
 
 class gm_program(ctypes.Structure):

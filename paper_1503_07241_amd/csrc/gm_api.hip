@@ -166,6 +166,8 @@ gm_status gm_graph_get_info(gm_graph g, gm_graph_info* info) {
   info->layouts = g->layouts;
   info->device = g->device;
   info->device_bytes = g->device_bytes;
+  info->n_src = g->n_src;
+  info->n_dst = g->n_dst;
   return ok();
 }
 

@@ -77,6 +77,8 @@ struct gm_graph_s {
   uint32_t layouts = 0;
   int device = 0;
   int64_t max_out = 0, max_in = 0;
+  int64_t n_src = 0;  // vertices with out-degree > 0
+  int64_t n_dst = 0;  // vertices with in-degree > 0 (0 without the in-layout)
   // out-adjacency (CSR of G; the columns of G^T in the paper's terms)
   uint32_t* out_off = nullptr;
   int32_t* out_idx = nullptr;

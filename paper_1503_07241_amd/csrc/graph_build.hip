@@ -146,20 +146,27 @@ __global__ void gather_u32(const uint32_t* __restrict__ src, const uint32_t* __r
     out[i] = src[idx[i]];
 }
 
+// Per-vertex 1/degree, plus the largest degree (stats[0]) and the number of
+// vertices with nonzero degree (stats[1]).
 __global__ void degree_stats(const uint32_t* __restrict__ off, int64_t n,
-                             float* __restrict__ inv_deg, unsigned int* __restrict__ maxdeg) {
-  unsigned int local = 0;
+                             float* __restrict__ inv_deg, unsigned int* __restrict__ stats) {
+  unsigned int local = 0, nz = 0;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t d = off[v + 1] - off[v];
     if (inv_deg) inv_deg[v] = d ? 1.0f / (float)d : 0.0f;
     local = d > local ? d : local;
+    nz += d != 0;
   }
   for (int o = 32; o > 0; o >>= 1) {
     const unsigned int t = __shfl_xor(local, o, 64);
     local = t > local ? t : local;
+    nz += __shfl_xor(nz, o, 64);
   }
-  if ((threadIdx.x & 63) == 0 && local) atomicMax(maxdeg, local);
+  if ((threadIdx.x & 63) == 0 && local) {
+    atomicMax(&stats[0], local);
+    atomicAdd(&stats[1], nz);
+  }
 }
 
 struct Scratch {
@@ -278,7 +285,7 @@ void build_graph(gm_graph g, const int32_t* src, const int32_t* dst, const void*
     std::swap(v2.p, valt.p);
   }
 
-  DevBuf<unsigned int> maxdeg(1);
+  DevBuf<unsigned int> maxdeg(2);
   // Out-adjacency (always built: it fixes the canonical edge order).
   {
     DevBuf<uint32_t> off(n + 1);
@@ -287,13 +294,14 @@ void build_graph(gm_graph g, const int32_t* src, const int32_t* dst, const void*
     if (m > 0) low_ids<<<grid_for(m), kThreads, 0, s>>>(ukeys.p, m, b, idx.p);
     GM_HIP(hipGetLastError());
     DevBuf<float> inv(n);
-    GM_HIP(hipMemsetAsync(maxdeg.p, 0, sizeof(unsigned int), s));
+    GM_HIP(hipMemsetAsync(maxdeg.p, 0, 2 * sizeof(unsigned int), s));
     degree_stats<<<grid_for(n), kThreads, 0, s>>>(off.p, n, inv.p, maxdeg.p);
     GM_HIP(hipGetLastError());
-    unsigned int mx = 0;
-    GM_HIP(hipMemcpyAsync(&mx, maxdeg.p, sizeof(mx), hipMemcpyDeviceToHost, s));
+    unsigned int mx[2] = {0, 0};
+    GM_HIP(hipMemcpyAsync(mx, maxdeg.p, sizeof(mx), hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
-    g->max_out = mx;
+    g->max_out = mx[0];
+    g->n_src = mx[1];
     g->out_off = off.release();
     g->out_idx = idx.release();
     g->inv_outdeg = inv.release();
@@ -329,13 +337,14 @@ void build_graph(gm_graph g, const int32_t* src, const int32_t* dst, const void*
       g->in_w = iw.release();
       g->device_bytes += m * 4;
     }
-    GM_HIP(hipMemsetAsync(maxdeg.p, 0, sizeof(unsigned int), s));
+    GM_HIP(hipMemsetAsync(maxdeg.p, 0, 2 * sizeof(unsigned int), s));
     degree_stats<<<grid_for(n), kThreads, 0, s>>>(off.p, n, nullptr, maxdeg.p);
     GM_HIP(hipGetLastError());
-    unsigned int mx = 0;
-    GM_HIP(hipMemcpyAsync(&mx, maxdeg.p, sizeof(mx), hipMemcpyDeviceToHost, s));
+    unsigned int mx[2] = {0, 0};
+    GM_HIP(hipMemcpyAsync(mx, maxdeg.p, sizeof(mx), hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
-    g->max_in = mx;
+    g->max_in = mx[0];
+    g->n_dst = mx[1];
     g->in_off = off.release();
     g->in_idx = idx.release();
     g->in_eid = eid.release();

@@ -2,22 +2,29 @@
 // generalized SpMV over the in-adjacency, with APPLY and the next SEND fused
 // into the same kernel.
 //
-// One superstep = one launch of pr_pull:
+// One superstep = one launch of pr_dense (+ pr_finish for split rows):
 //   y_v   = sum_{u -> v} x_u (* w_uv)          PROCESS = msg (* w), REDUCE = +
 //   PR_v  = r * tele(v) + (1 - r) * y_v        APPLY, for every vertex
 //   x'_v  = PR_v / outdeg(v)                   SEND for the next superstep
 // where x_u = PR_u / outdeg(u) is the message (0 for dangling vertices, which
-// send nothing). Row sums are accumulated in double, in a fixed order, so the
+// send nothing). Row sums are accumulated in double in a fixed order, so the
 // result does not depend on scheduling.
 //
-// Work decomposition (static, built once per graph): consecutive destination
-// rows are grouped into tasks of at most kBlockEdges in-edges and kMaxRows
-// rows; a row with more in-edges is split into chunks of kBlockEdges edges
-// whose partial sums are combined, in chunk order, by a small second kernel
-// (pr_finish) after the launch. A task's edges are streamed once, coalesced, and their
-// messages gathered into LDS; rows are then reduced from LDS by one thread
-// (short rows) or one wavefront (rows longer than kLaneRow).
+// Dense layout (built once per graph, on first use): vertices are relabelled
+// in decreasing in-degree order and the in-adjacency is rebuilt in the new
+// labels. Rows of similar length are then contiguous, so each degree class
+// gets its own number of lanes per row (from 1 up to a whole workgroup, so
+// that every lane gathers at most eight messages, all in flight at once; the
+// longest rows are cut into chunks reduced by separate workgroups), every
+// access to per-row data is a coalesced stream, and the most frequently
+// gathered messages (high-degree vertices) sit together at low labels where
+// they stay cache resident. The caller's rank vector is mapped into the new
+// labels by the first SEND and back after the last APPLY.
+#include <algorithm>
+#include <cstring>
 #include <vector>
+
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "gm_internal.h"
 
@@ -26,296 +33,467 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kMaxRows = 1024;
-constexpr int kBlockEdges = 2048;          // in-edges per work item
-constexpr int kPer = kBlockEdges / kThreads;  // edges per thread, loaded together
-constexpr uint32_t kLaneRow = 32;
-constexpr uint32_t kNoLong = 0xFFFFFFFFu;
+constexpr int kUnroll = 8;  // most edges per lane; all of a lane's loads are in flight at once
+constexpr uint32_t kChunk = kThreads * kUnroll;  // edges per chunk of a split row
 
-struct Task {
-  uint32_t row_begin, row_end, edge_begin, edge_end;
-  uint32_t long_id;  // split row id, or kNoLong
-  uint32_t chunk;    // partial-sum slot of this chunk
+// Degree classes c = 0..kClasses-1: in-degree in (kClassMax[c-1],
+// kClassMax[c]] (class 0: in-degree 0), each row taken by kClassLanes[c]
+// lanes with kClassUnroll[c] edges per lane. Degree ranges double from class
+// to class, so at most half of a lane's load slots are padding. The last
+// class is a workgroup per row; rows longer than kChunk are split.
+constexpr int kClasses = 13;
+constexpr uint32_t kClassMax[kClasses] = {0, 1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048};
+constexpr int kClassLanes[kClasses] = {1, 1, 1, 1, 1, 2, 4, 8, 16, 32, 64, 256, 256};
+constexpr int kClassUnroll[kClasses] = {1, 1, 2, 4, 8, 8, 8, 8, 8, 8, 8, 4, 8};
+
+struct SplitChunk {
+  uint32_t row;  // new label
+  uint32_t edge_begin;
+  uint32_t edge_end;
+  uint32_t pad;
 };
 
-struct LongRow {
+struct SplitRow {
   uint32_t row;
   uint32_t first_chunk;
   uint32_t nchunks;
   uint32_t pad;
 };
 
-__device__ inline double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
+// Block layout of one pr_dense launch: chunk blocks first, then the classes
+// from the longest rows (c = kClasses - 1) down to in-degree 0 (c = 0).
+struct Bins {
+  int64_t nchunks;
+  int64_t class_begin[kClasses];  // first row (new label)
+  int64_t class_rows[kClasses];
+  int64_t class_block0[kClasses];  // first block; decreases with c
+};
 
-// Messages of the in-edges [e0 + tid + k * kThreads] for k < kPer: all index
-// loads are issued before any gather so each thread keeps kPer loads in flight.
-template <bool kWeighted>
-__device__ inline void gather_edges(const int32_t* __restrict__ idx, const float* __restrict__ w,
-                                    const float* __restrict__ x, uint32_t e0, uint32_t ne,
-                                    float (&val)[kPer]) {
-  int32_t src[kPer];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const uint32_t i = threadIdx.x + k * kThreads;
-    src[k] = i < ne ? idx[e0 + i] : -1;
-  }
-  float wv[kPer];
-  if constexpr (kWeighted) {
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const uint32_t i = threadIdx.x + k * kThreads;
-      wv[k] = i < ne ? w[e0 + i] : 0.0f;
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) val[k] = src[k] >= 0 ? x[src[k]] : 0.0f;
-  if constexpr (kWeighted) {
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) val[k] *= wv[k];
-  }
+struct Dense {
+  int64_t n = 0, m = 0;
+  int32_t* new_of = nullptr;    // old label -> new label
+  int32_t* old_of = nullptr;    // new label -> old label
+  uint32_t* off = nullptr;      // relabelled in-adjacency
+  int32_t* idx = nullptr;
+  float* w = nullptr;           // edge values in the relabelled order (weighted graphs)
+  float* inv_outdeg = nullptr;  // new labels
+  float* x[2] = {nullptr, nullptr};
+  float* pr = nullptr;          // PR in new labels (last superstep)
+  SplitChunk* chunks = nullptr;
+  SplitRow* splits = nullptr;
+  double* partial = nullptr;
+  int64_t nsplit = 0;
+  int64_t nblocks = 0;
+  Bins bins{};
+};
+
+__device__ inline double group_sum(double v, int width) {
+  for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
 
 template <bool kPersonal>
 __device__ inline void apply_row(uint32_t v, double y, float r, int32_t seed,
                                  const float* __restrict__ inv_outdeg, float* __restrict__ x_out,
-                                 float* __restrict__ rank_out) {
+                                 float* __restrict__ pr_out) {
   double tele = 1.0;
   if constexpr (kPersonal) tele = (int32_t)v == seed ? 1.0 : 0.0;
   const float pr = (float)((double)r * tele + (1.0 - (double)r) * y);
   x_out[v] = pr * inv_outdeg[v];
-  if (rank_out) rank_out[v] = pr;
+  if (pr_out) pr_out[v] = pr;
+}
+
+// Sum of the messages of in-edges [b, e) taken by `lanes` lanes with stride
+// `lanes` (this lane starts at b + sub), kU loads in flight per lane.
+// Positions past the end are clamped to the last edge and their values
+// dropped by a select, so every load is unconditional and all of a lane's
+// index loads, then all of its gathers, are issued back to back.
+template <int kU, bool kWeighted>
+__device__ inline double row_partial(const int32_t* __restrict__ idx, const float* __restrict__ w,
+                                     const float* __restrict__ x, uint32_t b, uint32_t e,
+                                     int sub, int lanes) {
+  double acc = 0.0;
+  for (uint32_t k0 = b + sub; k0 < e; k0 += kU * lanes) {
+    uint32_t k[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t kk = k0 + u * lanes;
+      k[u] = kk < e ? kk : e - 1;
+    }
+    int32_t src[kU];
+    float wv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      src[u] = idx[k[u]];
+      if constexpr (kWeighted) wv[u] = w[k[u]];
+    }
+    float val[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) val[u] = x[src[u]];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if constexpr (kWeighted) val[u] *= wv[u];
+      acc += k0 + u * lanes < e ? (double)val[u] : 0.0;
+    }
+  }
+  return acc;
+}
+
+template <bool kWeighted>
+__device__ inline double row_partial_u(int unroll, const int32_t* __restrict__ idx,
+                                       const float* __restrict__ w, const float* __restrict__ x,
+                                       uint32_t b, uint32_t e, int sub, int lanes) {
+  switch (unroll) {
+    case 1:
+      return row_partial<1, kWeighted>(idx, w, x, b, e, sub, lanes);
+    case 2:
+      return row_partial<2, kWeighted>(idx, w, x, b, e, sub, lanes);
+    case 4:
+      return row_partial<4, kWeighted>(idx, w, x, b, e, sub, lanes);
+    default:
+      return row_partial<8, kWeighted>(idx, w, x, b, e, sub, lanes);
+  }
 }
 
 template <bool kWeighted, bool kPersonal>
-__global__ __launch_bounds__(kThreads) void pr_pull(
-    const Task* __restrict__ tasks, const LongRow* __restrict__ longs,
-    const uint32_t* __restrict__ in_off, const int32_t* __restrict__ in_idx,
-    const float* __restrict__ in_w, const float* __restrict__ x_in,
+__global__ __launch_bounds__(kThreads) void pr_dense(
+    const uint32_t* __restrict__ off, const int32_t* __restrict__ idx,
+    const float* __restrict__ w, const float* __restrict__ x_in,
     const float* __restrict__ inv_outdeg, float r, int32_t seed, float* __restrict__ x_out,
-    float* __restrict__ rank_out, double* __restrict__ partial) {
-  __shared__ float vals[kBlockEdges];
-  __shared__ uint32_t offs[kMaxRows + 1];
+    float* __restrict__ pr_out, const SplitChunk* __restrict__ chunks,
+    double* __restrict__ partial, Bins bins) {
   __shared__ double wsum[kWaves];
-
-  const Task t = tasks[blockIdx.x];
+  const int64_t blk = blockIdx.x;
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-
-  if (t.long_id != kNoLong) {
-    // One chunk of a split row.
-    float val[kPer];
-    gather_edges<kWeighted>(in_idx, in_w, x_in, t.edge_begin, t.edge_end - t.edge_begin, val);
-    double acc = 0.0;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) acc += (double)val[k];
-    acc = wave_sum(acc);
-    if (lane == 0) wsum[wave] = acc;
+  if (blk < bins.nchunks) {
+    // One chunk of a split row: partial sum, combined by pr_finish.
+    const SplitChunk c = chunks[blk];
+    double acc =
+        row_partial<kUnroll, kWeighted>(idx, w, x_in, c.edge_begin, c.edge_end, tid, kThreads);
+    acc = group_sum(acc, 64);
+    if ((tid & 63) == 0) wsum[tid >> 6] = acc;
     __syncthreads();
-    if (tid == 0) {
-      double s = 0.0;
-      for (int i = 0; i < kWaves; ++i) s += wsum[i];
-      partial[t.chunk] = s;  // combined by pr_finish after this launch
-    }
+    if (tid == 0) partial[blk] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
     return;
   }
-
-  const uint32_t nrows = t.row_end - t.row_begin;
-  const uint32_t e0 = t.edge_begin;
-  for (uint32_t i = tid; i <= nrows; i += kThreads) offs[i] = in_off[t.row_begin + i] - e0;
-  const uint32_t ne = t.edge_end - e0;
-  {
-    float val[kPer];
-    gather_edges<kWeighted>(in_idx, in_w, x_in, e0, ne, val);
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const uint32_t i = tid + k * kThreads;
-      if (i < ne) vals[i] = val[k];
-    }
+  // Degree class of this block: the class with the largest first block <= blk.
+  int cls = 0;
+  while (blk < bins.class_block0[cls]) ++cls;
+  const int lanes = kClassLanes[cls];
+  if (lanes == kThreads) {
+    // A whole workgroup per row.
+    const uint32_t row = (uint32_t)(bins.class_begin[cls] + (blk - bins.class_block0[cls]));
+    double acc = row_partial_u<kWeighted>(kClassUnroll[cls], idx, w, x_in, off[row], off[row + 1],
+                                          tid, kThreads);
+    acc = group_sum(acc, 64);
+    if ((tid & 63) == 0) wsum[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0)
+      apply_row<kPersonal>(row, (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]), r, seed, inv_outdeg,
+                           x_out, pr_out);
+    return;
   }
-  __syncthreads();
-
-  // Short rows: one thread each, sequential sum from LDS.
-  for (uint32_t i = tid; i < nrows; i += kThreads) {
-    const uint32_t b = offs[i], e = offs[i + 1];
-    if (e - b > kLaneRow) continue;
-    double y = 0.0;
-    for (uint32_t j = b; j < e; ++j) y += (double)vals[j];
-    apply_row<kPersonal>(t.row_begin + i, y, r, seed, inv_outdeg, x_out, rank_out);
-  }
-  // Longer rows: one wavefront each.
-  for (uint32_t base = wave * 64; base < nrows; base += kThreads) {
-    const uint32_t i = base + lane;
-    const bool longrow = i < nrows && offs[i + 1] - offs[i] > kLaneRow;
-    unsigned long long mask = __ballot(longrow);
-    while (mask) {
-      const int j = __ffsll((long long)mask) - 1;
-      mask &= mask - 1;
-      const uint32_t row = base + j;
-      const uint32_t b = offs[row], e = offs[row + 1];
-      double y = 0.0;
-      for (uint32_t k = b + lane; k < e; k += 64) y += (double)vals[k];
-      y = wave_sum(y);
-      if (lane == 0) apply_row<kPersonal>(t.row_begin + row, y, r, seed, inv_outdeg, x_out, rank_out);
-    }
-  }
+  const int64_t rows_per_block = kThreads / lanes;
+  const int64_t local = (blk - bins.class_block0[cls]) * rows_per_block + tid / lanes;
+  const bool valid = local < bins.class_rows[cls];
+  const uint32_t row = (uint32_t)(bins.class_begin[cls] + (valid ? local : 0));
+  const int sub = tid % lanes;
+  double y = 0.0;
+  if (valid && cls > 0)
+    y = row_partial_u<kWeighted>(kClassUnroll[cls], idx, w, x_in, off[row], off[row + 1], sub,
+                                 lanes);
+  y = group_sum(y, lanes);
+  if (valid && sub == 0) apply_row<kPersonal>(row, y, r, seed, inv_outdeg, x_out, pr_out);
 }
 
-// Rows split into chunks: sum the chunk partials in chunk order, then APPLY.
 template <bool kPersonal>
-__global__ void pr_finish(const LongRow* __restrict__ longs, int64_t nlong,
+__global__ void pr_finish(const SplitRow* __restrict__ splits, int64_t nsplit,
                           const double* __restrict__ partial, const float* __restrict__ inv_outdeg,
                           float r, int32_t seed, float* __restrict__ x_out,
-                          float* __restrict__ rank_out) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nlong;
+                          float* __restrict__ pr_out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nsplit;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const LongRow lr = longs[i];
+    const SplitRow sr = splits[i];
     double y = 0.0;
-    for (uint32_t c = 0; c < lr.nchunks; ++c) y += partial[lr.first_chunk + c];
-    apply_row<kPersonal>(lr.row, y, r, seed, inv_outdeg, x_out, rank_out);
+    for (uint32_t c = 0; c < sr.nchunks; ++c) y += partial[sr.first_chunk + c];
+    apply_row<kPersonal>(sr.row, y, r, seed, inv_outdeg, x_out, pr_out);
   }
 }
 
-// x_v = PR_v / outdeg(v): the first SEND of a run.
-__global__ void pr_send(const float* __restrict__ rank, const float* __restrict__ inv_outdeg,
-                        int64_t n, float* __restrict__ x) {
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * blockDim.x)
-    x[v] = rank[v] * inv_outdeg[v];
+// Rows without in-edges: PR = r * tele(v) in every superstep after the first,
+// so their APPLY and next SEND are written once per run instead of per
+// superstep.
+template <bool kPersonal>
+__global__ void pr_const_rows(int64_t row_begin, int64_t nrows, float r, int32_t seed,
+                              const float* __restrict__ inv_outdeg, float* __restrict__ x_out,
+                              float* __restrict__ pr_out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nrows;
+       i += (int64_t)gridDim.x * blockDim.x)
+    apply_row<kPersonal>((uint32_t)(row_begin + i), 0.0, r, seed, inv_outdeg, x_out, pr_out);
 }
 
-struct Schedule {
-  Task* tasks = nullptr;
-  LongRow* longs = nullptr;
-  double* partial = nullptr;
-  int64_t ntasks = 0, nlong = 0;
-  float* x[2] = {nullptr, nullptr};
-  int block_edges = 0;
-};
+// First SEND in new labels: x[i] = rank[old(i)] / outdeg.
+__global__ void pr_send0(const float* __restrict__ rank, const int32_t* __restrict__ old_of,
+                         const float* __restrict__ inv_outdeg, int64_t n, float* __restrict__ x) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = rank[old_of[i]] * inv_outdeg[i];
+}
 
-Schedule* sched(gm_graph g) { return static_cast<Schedule*>(g->pr_sched); }
+// rank[v] = pr[new(v)]: back to the caller's labels.
+__global__ void pr_unpermute(const float* __restrict__ pr, const int32_t* __restrict__ new_of,
+                             int64_t n, float* __restrict__ rank) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    rank[v] = pr[new_of[v]];
+}
+
+// Relabelled in-adjacency keys: (new row << b | new source), value = in-edge id.
+__global__ void relabel_keys(const uint32_t* __restrict__ in_off, const int32_t* __restrict__ in_idx,
+                             const int32_t* __restrict__ new_of, int64_t n, int b,
+                             unsigned long long* __restrict__ keys, uint32_t* __restrict__ eid) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long row = (unsigned long long)(uint32_t)new_of[v] << b;
+    for (uint32_t e = in_off[v]; e < in_off[v + 1]; ++e) {
+      keys[e] = row | (uint32_t)new_of[in_idx[e]];
+      eid[e] = e;
+    }
+  }
+}
+
+__global__ void relabel_finish(const unsigned long long* __restrict__ keys,
+                               const uint32_t* __restrict__ eid, int64_t m, int b,
+                               const float* __restrict__ in_w, int32_t* __restrict__ idx,
+                               float* __restrict__ w) {
+  const unsigned long long mask = (1ull << b) - 1;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    idx[i] = (int32_t)(keys[i] & mask);
+    if (w) w[i] = in_w[eid[i]];
+  }
+}
+
+__global__ void gather_f32(const float* __restrict__ src, const int32_t* __restrict__ index,
+                           int64_t n, float* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = src[index[i]];
+}
+
+inline unsigned blocks_for(int64_t n) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  if (b < 1) b = 1;
+  if (b > 65536) b = 65536;
+  return (unsigned)b;
+}
+
+Dense* dense(gm_graph g) { return static_cast<Dense*>(g->pr_sched); }
+
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  explicit DevBuf(size_t n) : p(dalloc<T>(n)) {}
+  ~DevBuf() { dfree(p); }
+};
 
 }  // namespace
 
 void free_pull_schedule(gm_graph g) {
-  Schedule* s = sched(g);
-  if (!s) return;
-  dfree(s->tasks);
-  dfree(s->longs);
-  dfree(s->partial);
-  dfree(s->x[0]);
-  dfree(s->x[1]);
-  delete s;
+  Dense* d = dense(g);
+  if (!d) return;
+  dfree(d->new_of);
+  dfree(d->old_of);
+  dfree(d->off);
+  dfree(d->idx);
+  dfree(d->w);
+  dfree(d->inv_outdeg);
+  dfree(d->x[0]);
+  dfree(d->x[1]);
+  dfree(d->pr);
+  dfree(d->chunks);
+  dfree(d->splits);
+  dfree(d->partial);
+  delete d;
   g->pr_sched = nullptr;
 }
 
 void ensure_pull_schedule(gm_graph g, hipStream_t st) {
-  const int block_edges = kBlockEdges;
-  if (sched(g)) return;
-  free_pull_schedule(g);
-  const int64_t n = g->n;
+  if (dense(g)) return;
+  const int64_t n = g->n, m = g->m;
+  // Counting sort of the vertices by decreasing in-degree (ties by label).
   std::vector<uint32_t> off(n + 1);
   GM_HIP(hipMemcpyAsync(off.data(), g->in_off, (n + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost,
                         st));
   GM_HIP(hipStreamSynchronize(st));
-  std::vector<Task> tasks;
-  std::vector<LongRow> longs;
-  uint32_t nchunk_total = 0;
-  const uint32_t B = (uint32_t)block_edges;
-  int64_t r = 0;
-  while (r < n) {
-    const uint32_t deg = off[r + 1] - off[r];
-    if (deg > B) {
-      const uint32_t nch = (deg + B - 1) / B;
-      const uint32_t id = (uint32_t)longs.size();
-      longs.push_back({(uint32_t)r, nchunk_total, nch, 0});
-      for (uint32_t c = 0; c < nch; ++c) {
-        const uint32_t eb = off[r] + c * B;
-        const uint32_t ee = eb + B < off[r + 1] ? eb + B : off[r + 1];
-        tasks.push_back({(uint32_t)r, (uint32_t)r + 1, eb, ee, id, nchunk_total + c});
-      }
-      nchunk_total += nch;
-      ++r;
-      continue;
-    }
-    const int64_t r0 = r;
-    uint32_t edges = 0;
-    while (r < n && r - r0 < kMaxRows) {
-      const uint32_t d = off[r + 1] - off[r];
-      if (d > B || edges + d > B) break;
-      edges += d;
-      ++r;
-    }
-    tasks.push_back({(uint32_t)r0, (uint32_t)r, off[r0], off[r], kNoLong, 0});
+  const uint32_t maxd = (uint32_t)g->max_in;
+  std::vector<int64_t> cnt((size_t)maxd + 2, 0);
+  for (int64_t v = 0; v < n; ++v) ++cnt[maxd - (off[v + 1] - off[v])];
+  int64_t acc = 0;
+  for (size_t i = 0; i < cnt.size(); ++i) {
+    const int64_t c = cnt[i];
+    cnt[i] = acc;
+    acc += c;
   }
-  Schedule* s = new Schedule();
+  std::vector<int32_t> old_of(n), new_of(n);
+  for (int64_t v = 0; v < n; ++v) {
+    const int64_t pos = cnt[maxd - (off[v + 1] - off[v])]++;
+    old_of[pos] = (int32_t)v;
+    new_of[v] = (int32_t)pos;
+  }
+  std::vector<uint32_t> noff(n + 1);
+  noff[0] = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t v = old_of[i];
+    noff[i + 1] = noff[i] + (off[v + 1] - off[v]);
+  }
+  Dense* d = new Dense();
+  g->pr_sched = d;
   try {
-    s->block_edges = block_edges;
-    s->ntasks = (int64_t)tasks.size();
-    s->nlong = (int64_t)longs.size();
-    s->tasks = dalloc<Task>(tasks.size());
-    s->longs = dalloc<LongRow>(longs.size());
-    s->partial = dalloc<double>(nchunk_total);
-    s->x[0] = dalloc<float>(n);
-    s->x[1] = dalloc<float>(n);
-    GM_HIP(hipMemcpyAsync(s->tasks, tasks.data(), tasks.size() * sizeof(Task),
-                          hipMemcpyHostToDevice, st));
-    if (!longs.empty())
-      GM_HIP(hipMemcpyAsync(s->longs, longs.data(), longs.size() * sizeof(LongRow),
+    d->n = n;
+    d->m = m;
+    // Split rows first, then the degree classes from long to empty rows.
+    std::vector<SplitChunk> chunks;
+    std::vector<SplitRow> splits;
+    int64_t i = 0;
+    while (i < n && noff[i + 1] - noff[i] > kChunk) {
+      const uint32_t deg = noff[i + 1] - noff[i];
+      const uint32_t nch = (deg + kChunk - 1) / kChunk;
+      splits.push_back({(uint32_t)i, (uint32_t)chunks.size(), nch, 0});
+      for (uint32_t c = 0; c < nch; ++c) {
+        const uint32_t eb = noff[i] + c * kChunk;
+        chunks.push_back({(uint32_t)i, eb, std::min(eb + kChunk, noff[i + 1]), 0});
+      }
+      ++i;
+    }
+    Bins& bins = d->bins;
+    bins.nchunks = (int64_t)chunks.size();
+    d->nsplit = (int64_t)splits.size();
+    int64_t block = bins.nchunks;
+    for (int c = kClasses - 1; c >= 0; --c) {
+      const int64_t r0 = i;
+      if (c == 0)
+        i = n;  // the rest has in-degree 0
+      else
+        while (i < n && noff[i + 1] - noff[i] > kClassMax[c - 1]) ++i;
+      bins.class_begin[c] = r0;
+      bins.class_rows[c] = i - r0;
+      bins.class_block0[c] = block;
+      const int64_t rpb = kThreads / kClassLanes[c];
+      block += (bins.class_rows[c] + rpb - 1) / rpb;
+    }
+    d->nblocks = block;
+    d->new_of = dalloc<int32_t>(n);
+    d->old_of = dalloc<int32_t>(n);
+    d->off = dalloc<uint32_t>(n + 1);
+    d->idx = dalloc<int32_t>(m);
+    d->inv_outdeg = dalloc<float>(n);
+    d->x[0] = dalloc<float>(n);
+    d->x[1] = dalloc<float>(n);
+    d->pr = dalloc<float>(n);
+    d->chunks = dalloc<SplitChunk>(chunks.size());
+    d->splits = dalloc<SplitRow>(splits.size());
+    d->partial = dalloc<double>(chunks.size());
+    GM_HIP(hipMemcpyAsync(d->new_of, new_of.data(), n * 4, hipMemcpyHostToDevice, st));
+    GM_HIP(hipMemcpyAsync(d->old_of, old_of.data(), n * 4, hipMemcpyHostToDevice, st));
+    GM_HIP(hipMemcpyAsync(d->off, noff.data(), (n + 1) * 4, hipMemcpyHostToDevice, st));
+    if (!chunks.empty())
+      GM_HIP(hipMemcpyAsync(d->chunks, chunks.data(), chunks.size() * sizeof(SplitChunk),
                             hipMemcpyHostToDevice, st));
+    if (!splits.empty())
+      GM_HIP(hipMemcpyAsync(d->splits, splits.data(), splits.size() * sizeof(SplitRow),
+                            hipMemcpyHostToDevice, st));
+    gather_f32<<<blocks_for(n), kThreads, 0, st>>>(g->inv_outdeg, d->old_of, n, d->inv_outdeg);
+    GM_HIP(hipGetLastError());
+    if (m > 0) {
+      int b = 1;
+      while ((1ll << b) < n) ++b;
+      DevBuf<unsigned long long> k1(m), k2(m);
+      DevBuf<uint32_t> e1(m), e2(m);
+      relabel_keys<<<blocks_for(n), kThreads, 0, st>>>(g->in_off, g->in_idx, d->new_of, n, b, k1.p,
+                                                       e1.p);
+      GM_HIP(hipGetLastError());
+      rocprim::double_buffer<unsigned long long> kb(k1.p, k2.p);
+      rocprim::double_buffer<uint32_t> vb(e1.p, e2.p);
+      size_t bytes = 0;
+      GM_HIP(rocprim::radix_sort_pairs(nullptr, bytes, kb, vb, (size_t)m, 0, 2 * b, st));
+      void* tmp = dmalloc(bytes);
+      const hipError_t err = rocprim::radix_sort_pairs(tmp, bytes, kb, vb, (size_t)m, 0, 2 * b, st);
+      if (err == hipSuccess) (void)hipStreamSynchronize(st);
+      dfree(tmp);
+      GM_HIP(err);
+      if (g->wtype == GM_W_F32) d->w = dalloc<float>(m);
+      relabel_finish<<<blocks_for(m), kThreads, 0, st>>>(kb.current(), vb.current(), m, b,
+                                                         static_cast<const float*>(g->in_w),
+                                                         d->idx, d->w);
+      GM_HIP(hipGetLastError());
+    }
     GM_HIP(hipStreamSynchronize(st));
   } catch (...) {
-    g->pr_sched = s;
     free_pull_schedule(g);
     throw;
   }
-  g->pr_sched = s;
 }
 
 void run_pagerank(gm_graph g, float r, int32_t iters, float* rank, int32_t seed, hipStream_t st) {
   ensure_pull_schedule(g, st);
-  Schedule* s = sched(g);
+  Dense* d = dense(g);
   const int64_t n = g->n;
-  {
-    int64_t blocks = (n + kThreads - 1) / kThreads;
-    if (blocks > 65536) blocks = 65536;
-    pr_send<<<(unsigned)(blocks < 1 ? 1 : blocks), kThreads, 0, st>>>(rank, g->inv_outdeg, n,
-                                                                        s->x[0]);
-    GM_HIP(hipGetLastError());
-  }
   const bool weighted = g->wtype == GM_W_F32;
   const bool personal = seed >= 0;
-  const float* w = static_cast<const float*>(g->in_w);
+  int32_t seed_new = -1;
+  if (personal) {
+    GM_HIP(hipMemcpyAsync(&seed_new, d->new_of + seed, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GM_HIP(hipStreamSynchronize(st));
+  }
+  pr_send0<<<blocks_for(n), kThreads, 0, st>>>(rank, d->old_of, d->inv_outdeg, n, d->x[0]);
+  GM_HIP(hipGetLastError());
+  const int64_t c0 = d->bins.class_begin[0], n0 = d->bins.class_rows[0];
+  auto const_rows = [&](float* xo, float* po) {
+    if (n0 == 0) return;
+    if (personal)
+      pr_const_rows<true><<<blocks_for(n0), kThreads, 0, st>>>(c0, n0, r, seed_new, d->inv_outdeg,
+                                                                xo, po);
+    else
+      pr_const_rows<false><<<blocks_for(n0), kThreads, 0, st>>>(c0, n0, r, seed_new,
+                                                                 d->inv_outdeg, xo, po);
+    GM_HIP(hipGetLastError());
+  };
+  // The blocks of the in-degree-0 class come last; the per-superstep launch
+  // stops before them.
+  const unsigned grid = (unsigned)d->bins.class_block0[0];
+  const_rows(d->x[1], d->pr);
   for (int32_t it = 0; it < iters; ++it) {
-    const float* xin = s->x[it & 1];
-    float* xout = s->x[(it + 1) & 1];
-    float* rout = it == iters - 1 ? rank : nullptr;
+    const float* xin = d->x[it & 1];
+    float* xout = d->x[(it + 1) & 1];
+    float* pout = it == iters - 1 ? d->pr : nullptr;
     auto launch = [&](auto kern) {
-      kern<<<(unsigned)s->ntasks, kThreads, 0, st>>>(s->tasks, s->longs, g->in_off, g->in_idx, w,
-                                                     xin, g->inv_outdeg, r, seed, xout, rout,
-                                                     s->partial);
+      if (grid > 0)
+        kern<<<grid, kThreads, 0, st>>>(d->off, d->idx, d->w, xin, d->inv_outdeg, r, seed_new,
+                                        xout, pout, d->chunks, d->partial, d->bins);
     };
     if (weighted && personal)
-      launch(pr_pull<true, true>);
+      launch(pr_dense<true, true>);
     else if (weighted)
-      launch(pr_pull<true, false>);
+      launch(pr_dense<true, false>);
     else if (personal)
-      launch(pr_pull<false, true>);
+      launch(pr_dense<false, true>);
     else
-      launch(pr_pull<false, false>);
-    if (s->nlong > 0) {
-      const unsigned fb = (unsigned)((s->nlong + kThreads - 1) / kThreads);
+      launch(pr_dense<false, false>);
+    if (d->nsplit > 0) {
+      const unsigned fb = (unsigned)((d->nsplit + kThreads - 1) / kThreads);
       if (personal)
-        pr_finish<true><<<fb, kThreads, 0, st>>>(s->longs, s->nlong, s->partial, g->inv_outdeg, r,
-                                                  seed, xout, rout);
+        pr_finish<true><<<fb, kThreads, 0, st>>>(d->splits, d->nsplit, d->partial, d->inv_outdeg,
+                                                  r, seed_new, xout, pout);
       else
-        pr_finish<false><<<fb, kThreads, 0, st>>>(s->longs, s->nlong, s->partial, g->inv_outdeg,
-                                                   r, seed, xout, rout);
+        pr_finish<false><<<fb, kThreads, 0, st>>>(d->splits, d->nsplit, d->partial, d->inv_outdeg,
+                                                   r, seed_new, xout, pout);
     }
     GM_HIP(hipGetLastError());
+    if (it == 0) const_rows(d->x[0], nullptr);  // x[0] held PR^0 messages until now
   }
+  pr_unpermute<<<blocks_for(n), kThreads, 0, st>>>(d->pr, d->new_of, n, rank);
+  GM_HIP(hipGetLastError());
 }
 
 }  // namespace gm
