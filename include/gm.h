@@ -149,7 +149,13 @@ enum {
   GM_PROG_PAGERANK = 3,
   /* Personalised PageRank with one seed s (the first frontier id):
    * APPLY r * [v == s] + (1 - r) * y. Otherwise as GM_PROG_PAGERANK. */
-  GM_PROG_PPR = 4
+  GM_PROG_PPR = 4,
+  /* Triangle counting, program 2 of Sec. 4.2 (Eq. (7)). Needs a graph
+   * loaded with GM_PREP_UPPER_DAG and GM_LAYOUT_IN, whose in-lists are
+   * program 1's output. Property uint64 count; every vertex u sends its
+   * in-neighbour list along its out-edges; PROCESS |in(u) ∩ in(v)|;
+   * REDUCE +; APPLY count(v) += y. One superstep; frontier must be NULL. */
+  GM_PROG_TC = 5
 };
 
 /* Edge direction messages travel along (App. A, `order`). */
@@ -193,6 +199,17 @@ typedef struct gm_frontier {
 gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_frontier* frontier,
                                 int32_t max_iters, void* vprop, int32_t* active_out,
                                 int32_t* iters_done, void* stream);
+
+/*
+ * Triangle count of Eq. (7) (Sec. 3 IV) via the two-program form of
+ * Sec. 4.2 on g, which must be loaded with GM_PREP_UPPER_DAG and
+ * GM_LAYOUT_IN. counts (device, n uint64, may be NULL) receives, per
+ * vertex v, the triangles whose largest vertex is v; *total (host, may be
+ * NULL) their sum, exact. Errors: GM_ESTATE; GM_EUNSUPPORTED (graph not an
+ * upper-triangle DAG with in-lists); GM_ENOMEM; GM_EHIP. Synchronises
+ * `stream`.
+ */
+gm_status gm_triangle_count(gm_graph g, uint64_t* counts, uint64_t* total, void* stream);
 
 /* Counters of the last gm_run_vertex_program call on a graph. */
 typedef struct gm_run_stats {

@@ -18,7 +18,8 @@ import numpy as np
 from . import _lib
 from ._lib import (GM_LAYOUT_IN, GM_LAYOUT_OUT, GM_ORDER_ALL, GM_ORDER_IN, GM_ORDER_OUT,  # noqa: F401
                    GM_PREP_DROP_SELF_LOOPS, GM_PREP_SYMMETRIZE, GM_PREP_UPPER_DAG, GM_PROG_BFS,
-                   GM_PROG_PAGERANK, GM_PROG_PPR, GM_PROG_SSSP, GM_W_F32, GM_W_NONE, GM_W_U32,
+                   GM_PROG_PAGERANK, GM_PROG_PPR, GM_PROG_SSSP, GM_PROG_TC, GM_W_F32, GM_W_NONE,
+                   GM_W_U32,
                    GmError)
 
 INF_LEVEL = 2**31 - 1
@@ -150,3 +151,12 @@ def run_vertex_program(g: Graph, kind: int, frontier, max_iters: int, vprop, act
         _ptr(vprop), _ptr(active_out), ctypes.byref(it), _stream(stream)),
         "gm_run_vertex_program")
     return it.value
+
+
+def triangle_count(g: Graph, counts=None, stream=None) -> int:
+    """gm_triangle_count: exact triangle total; per-vertex counts (device
+    uint64 stored in an int64 tensor) are written to `counts` when given."""
+    total = ctypes.c_uint64(0)
+    _lib.check(_lib.load().gm_triangle_count(g.handle, _ptr(counts), ctypes.byref(total),
+                                             _stream(stream)), "gm_triangle_count")
+    return int(total.value)

@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "GM_OK", 1: "GM_EINVAL", 2: "GM_ENOMEM", 3: "GM_EHIP", 4: "GM
 GM_PREP_DROP_SELF_LOOPS, GM_PREP_SYMMETRIZE, GM_PREP_UPPER_DAG = 1, 2, 4
 GM_W_NONE, GM_W_U32, GM_W_F32 = 0, 1, 2
 GM_LAYOUT_OUT, GM_LAYOUT_IN = 1, 2
-GM_PROG_BFS, GM_PROG_SSSP, GM_PROG_PAGERANK, GM_PROG_PPR = 1, 2, 3, 4
+GM_PROG_BFS, GM_PROG_SSSP, GM_PROG_PAGERANK, GM_PROG_PPR, GM_PROG_TC = 1, 2, 3, 4, 5
 GM_ORDER_OUT, GM_ORDER_IN, GM_ORDER_ALL = 1, 2, 3
 
 
@@ -73,6 +73,7 @@ def load():
         "gm_run_vertex_program": ([vp, ctypes.POINTER(gm_program), ctypes.POINTER(gm_frontier), i32,
                                    vp, vp, ctypes.POINTER(i32), vp], i32),
         "gm_last_run_stats": ([vp, ctypes.POINTER(gm_run_stats)], i32),
+        "gm_triangle_count": ([vp, vp, ctypes.POINTER(ctypes.c_uint64), vp], i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)

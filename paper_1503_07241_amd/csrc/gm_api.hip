@@ -198,6 +198,7 @@ gm_status gm_graph_destroy(gm_graph g) {
   graph_unregister(g);
   free_min_workspace(g);
   free_pull_schedule(g);
+  free_tc_plan(g);
   free_graph_memory(g);
   g->magic = 0;
   delete g;
@@ -211,11 +212,29 @@ gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_fro
   if (!prog) return fail(GM_EINVAL, "prog is NULL");
   if (!vprop) return fail(GM_EINVAL, "vprop is NULL");
   const int kind = prog->kind;
-  if (kind != GM_PROG_BFS && kind != GM_PROG_SSSP && kind != GM_PROG_PAGERANK && kind != GM_PROG_PPR)
+  if (kind != GM_PROG_BFS && kind != GM_PROG_SSSP && kind != GM_PROG_PAGERANK &&
+      kind != GM_PROG_PPR && kind != GM_PROG_TC)
     return fail(GM_EINVAL, "unknown program kind %d", kind);
   if (prog->order != GM_ORDER_OUT)
     return fail(GM_EINVAL, "order %d: only GM_ORDER_OUT is supported", prog->order);
   if (prog->flags != 0) return fail(GM_EINVAL, "flags must be 0");
+  if (kind == GM_PROG_TC) {
+    if (frontier) return fail(GM_EINVAL, "triangle counting takes no frontier (all vertices send)");
+    if (!(g->prep & GM_PREP_UPPER_DAG) || !(g->layouts & GM_LAYOUT_IN))
+      return fail(GM_EUNSUPPORTED, "triangle counting needs GM_PREP_UPPER_DAG and GM_LAYOUT_IN");
+    return guarded([&]() -> gm_status {
+      run_triangle_count(g, static_cast<unsigned long long*>(vprop), nullptr,
+                         static_cast<hipStream_t>(stream));
+      if (active_out) fill_u32(reinterpret_cast<uint32_t*>(active_out), g->n, 0u,
+                               static_cast<hipStream_t>(stream));
+      g->last_stats = RunStats{};
+      g->last_stats.supersteps = 1;
+      g->last_stats.push_supersteps = 1;
+      g->last_stats.edges_scanned = (unsigned long long)g->m;
+      if (iters_done) *iters_done = 1;
+      return ok();
+    });
+  }
   const bool dense = kind == GM_PROG_PAGERANK || kind == GM_PROG_PPR;
   if (dense) {
     if (max_iters <= 0) return fail(GM_EINVAL, "PageRank needs max_iters > 0");
@@ -260,6 +279,32 @@ gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_fro
                            static_cast<uint32_t*>(vprop), active_out, s, &g->last_stats);
     }
     if (iters_done) *iters_done = it;
+    return ok();
+  });
+}
+
+gm_status gm_triangle_count(gm_graph g, uint64_t* counts, uint64_t* total, void* stream) {
+  if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
+  if (!(g->prep & GM_PREP_UPPER_DAG) || !(g->layouts & GM_LAYOUT_IN))
+    return fail(GM_EUNSUPPORTED, "triangle counting needs GM_PREP_UPPER_DAG and GM_LAYOUT_IN");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return guarded([&]() -> gm_status {
+    unsigned long long* c = reinterpret_cast<unsigned long long*>(counts);
+    unsigned long long* own = nullptr;
+    if (!c) own = c = dalloc<unsigned long long>(g->n);
+    try {
+      zero_counts(c, g->n, s);
+      unsigned long long t = 0;
+      run_triangle_count(g, c, &t, s);
+      if (total) *total = t;
+    } catch (...) {
+      dfree(own);
+      throw;
+    }
+    if (own) {
+      GM_HIP(hipStreamSynchronize(s));
+      dfree(own);
+    }
     return ok();
   });
 }

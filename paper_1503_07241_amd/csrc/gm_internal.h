@@ -92,6 +92,7 @@ struct gm_graph_s {
   int64_t device_bytes = 0;
   void* min_ws = nullptr;    // frontier workspace of the min programs (minprog.hip)
   void* pr_sched = nullptr;  // pull schedule of the dense programs (pagerank.hip)
+  void* tc_plan = nullptr;   // receiver lists of the triangle count (tc.hip)
   gm::RunStats last_stats;
   gm::Tuning tune;
 };
@@ -120,6 +121,13 @@ int32_t run_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count,
                         RunStats* stats);
 void free_min_workspace(gm_graph g);
 void free_pull_schedule(gm_graph g);
+
+// Triangle counting (tc.hip): counts[v] += triangles whose largest vertex is
+// v; *total_host (optional) = sum of counts after the call (synchronises).
+void run_triangle_count(gm_graph g, unsigned long long* counts, unsigned long long* total_host,
+                        hipStream_t s);
+void zero_counts(unsigned long long* a, int64_t n, hipStream_t s);
+void free_tc_plan(gm_graph g);
 
 // Fill n uint32 words with v on stream s (a kernel, safe under graph capture).
 void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);

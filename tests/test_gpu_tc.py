@@ -1,0 +1,107 @@
+"""GPU triangle counting (Sec. 3 IV, Eq. (7); two-program form of Sec. 4.2) against
+the oracle: exact totals and exact per-vertex counts (APPLY output)."""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1503_07241_amd as gm
+from tests import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def gpu_tc(n, s, d):
+    g = gm.Graph.from_coo(n, np.asarray(s, np.int32), np.asarray(d, np.int32),
+                          prep=gm.GM_PREP_UPPER_DAG, layouts=gm.GM_LAYOUT_OUT | gm.GM_LAYOUT_IN)
+    counts = torch.zeros(n, dtype=torch.int64, device=DEV)
+    total = gm.triangle_count(g, counts)
+    return g, total, counts.cpu().numpy().view(np.uint64)
+
+
+def pairs(lst):
+    a = np.asarray(lst, dtype=np.int64).reshape(-1, 2)
+    return a[:, 0], a[:, 1]
+
+
+def test_closed_forms():
+    for n in (3, 4, 7, 40):
+        s, d = pairs(list(itertools.combinations(range(n), 2)))
+        assert gpu_tc(n, s, d)[1] == n * (n - 1) * (n - 2) // 6
+    for n in (5, 9):
+        s, d = pairs([(i, (i + 1) % n) for i in range(n)])
+        assert gpu_tc(n, s, d)[1] == 0
+    n = 12
+    s, d = pairs([(0, i) for i in range(1, n)] + [(i, i % (n - 1) + 1) for i in range(1, n)])
+    assert gpu_tc(n, s, d)[1] == n - 1
+    s, d = pairs([(i, j) for i in range(5) for j in range(5, 12)])
+    assert gpu_tc(12, s, d)[1] == 0
+
+
+@pytest.mark.parametrize("scale", [W.SMALL_SCALE, 16])
+def test_rmat_total_and_per_vertex(scale):
+    n, s, d = W.raw(scale)
+    _, total, counts = gpu_tc(n, s, d)
+    dag = W.ograph(scale, "dag")
+    dag_in = oracle.dag_in_lists(dag)
+    assert total == oracle.triangle_count(dag, dag_in)
+    assert np.array_equal(counts, oracle.triangles_at(dag_in, np.arange(n)))
+    assert int(counts.sum()) == total
+
+
+def test_hub_receivers_large_lists():
+    """Receivers whose in-list exceeds one wavefront's and the LDS limit:
+    a dense core of 2000 vertices plus a sparse fringe."""
+    rng = np.random.default_rng(7)
+    core = 2000
+    n = core + 30000
+    s = rng.integers(0, core, 800_000)
+    d = rng.integers(0, core, 800_000)
+    s2 = rng.integers(0, n, 200_000)
+    d2 = rng.integers(0, core, 200_000)
+    s3 = rng.choice(n - 1, 17000, replace=False)  # in-list longer than the LDS stage
+    d3 = np.full(17000, n - 1)
+    S = np.concatenate([s, s2, np.arange(core - 1), s3])
+    D = np.concatenate([d, d2, np.arange(1, core), d3])
+    _, total, counts = gpu_tc(n, S, D)
+    dag = oracle.prepare(n, S, D, mode="dag")
+    dag_in = oracle.dag_in_lists(dag)
+    assert total == oracle.triangle_count(dag, dag_in)
+    assert np.array_equal(counts, oracle.triangles_at(dag_in, np.arange(n)))
+
+
+def test_full_size_sampled_vertices():
+    """RMAT scale 22: per-vertex counts of sampled receivers, computed one by
+    one by the oracle; the total equals the sum of the per-vertex counts."""
+    n, s, d = W.raw(W.FULL_SCALE)
+    _, total, counts = gpu_tc(n, s, d)
+    assert int(counts.sum()) == total
+    dag_in = oracle.dag_in_lists(W.ograph(W.FULL_SCALE, "dag"))
+    indeg = np.diff(dag_in.off)
+    rng = np.random.default_rng(11)
+    cand = np.flatnonzero(indeg > 0)
+    sample = rng.choice(cand, 300, replace=False)
+    mid = np.flatnonzero((indeg > 1500) & (indeg < 2500))[:4]  # workgroup-path receivers
+    verts = np.concatenate([sample, mid]).astype(np.int32)
+    assert np.array_equal(counts[verts], oracle.triangles_at(dag_in, verts))
+
+
+def test_run_vertex_program_tc_apply_accumulates():
+    n, s, d = W.raw(10)
+    g = gm.Graph.from_coo(n, s, d, prep=gm.GM_PREP_UPPER_DAG, layouts=3)
+    counts = torch.full((n,), 5, dtype=torch.int64, device=DEV)
+    it = gm.run_vertex_program(g, gm.GM_PROG_TC, None, 1, counts)
+    assert it == 1
+    ref = oracle.triangles_at(oracle.dag_in_lists(W.ograph(10, "dag")), np.arange(n))
+    assert np.array_equal(counts.cpu().numpy().view(np.uint64), ref + 5)
+
+
+def test_tc_needs_dag():
+    n, s, d = W.raw(8)
+    g = gm.Graph.from_coo(n, s, d, prep=gm.GM_PREP_DROP_SELF_LOOPS | gm.GM_PREP_SYMMETRIZE)
+    with pytest.raises(gm.GmError) as e:
+        gm.triangle_count(g)
+    assert e.value.status == gm._lib.GM_EUNSUPPORTED
