@@ -201,6 +201,31 @@ gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_fro
                                 int32_t* iters_done, void* stream);
 
 /*
+ * Batched run: k sources (BFS, SSSP) or personalised-PageRank seeds (PPR)
+ * processed together, one matrix pass serving all k frontiers (the
+ * generalized SpMV of Alg. 1 with a dense n x k frontier block). Column s
+ * of the result equals gm_run_vertex_program from sources[s] alone.
+ * sources: device int32[k], ids in [0, n). vprop_block: device, n x k,
+ * vertex-major (entry (v, s) at v * k + s), initialised by the call:
+ *   BFS  (k <= 64)  int32 levels, INT32_MAX unreached; needs a symmetrised
+ *                   graph or GM_LAYOUT_IN (pull supersteps over in-edges);
+ *   SSSP (k <= 64)  uint32 distances, UINT32_MAX unreached; GM_W_U32;
+ *   PPR  (k <= 256) float ranks after exactly max_iters (> 0) supersteps,
+ *                   PPR_s^0 = e_s, teleport r to the seed only; GM_LAYOUT_IN.
+ * max_iters <= 0 runs BFS/SSSP to convergence. *iters_done (host, may be
+ * NULL): supersteps run (for BFS/SSSP the largest count of any source's
+ * plain run; SSSP supersteps may end earlier than the slowest plain run
+ * because a source reads distances other sources lowered in the same
+ * superstep only through its own column - the final values are exact).
+ * Errors: GM_ESTATE; GM_EINVAL (NULL pointers, k out of range, order or
+ * flags, r, max_iters for PPR, a source out of range, unknown kind);
+ * GM_EUNSUPPORTED (layout or weight type missing, n * k > 2^40); GM_ENOMEM;
+ * GM_EHIP. Synchronises `stream`.
+ */
+gm_status gm_run_batched(gm_graph g, const gm_program* prog, const int32_t* sources, int32_t k,
+                         int32_t max_iters, void* vprop_block, int32_t* iters_done, void* stream);
+
+/*
  * Triangle count of Eq. (7) (Sec. 3 IV) via the two-program form of
  * Sec. 4.2 on g, which must be loaded with GM_PREP_UPPER_DAG and
  * GM_LAYOUT_IN. counts (device, n uint64, may be NULL) receives, per

@@ -160,3 +160,16 @@ def triangle_count(g: Graph, counts=None, stream=None) -> int:
     _lib.check(_lib.load().gm_triangle_count(g.handle, _ptr(counts), ctypes.byref(total),
                                              _stream(stream)), "gm_triangle_count")
     return int(total.value)
+
+
+def run_batched(g: Graph, kind: int, sources, max_iters: int, vprop_block, r: float = 0.15,
+                stream=None) -> int:
+    """gm_run_batched: sources is a device int32 tensor of k ids; vprop_block a
+    device (n, k) tensor (int32 levels, int32-stored uint32 distances, float32
+    ranks) that the call initialises. Returns supersteps run."""
+    prog = _lib.gm_program(kind, GM_ORDER_OUT, r, 0)
+    it = ctypes.c_int32(0)
+    _lib.check(_lib.load().gm_run_batched(g.handle, ctypes.byref(prog), _ptr(sources),
+                                          sources.numel(), max_iters, _ptr(vprop_block),
+                                          ctypes.byref(it), _stream(stream)), "gm_run_batched")
+    return it.value

@@ -74,6 +74,8 @@ def load():
                                    vp, vp, ctypes.POINTER(i32), vp], i32),
         "gm_last_run_stats": ([vp, ctypes.POINTER(gm_run_stats)], i32),
         "gm_triangle_count": ([vp, vp, ctypes.POINTER(ctypes.c_uint64), vp], i32),
+        "gm_run_batched": ([vp, ctypes.POINTER(gm_program), vp, i32, i32, vp, ctypes.POINTER(i32),
+                            vp], i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)

@@ -199,6 +199,7 @@ gm_status gm_graph_destroy(gm_graph g) {
   free_min_workspace(g);
   free_pull_schedule(g);
   free_tc_plan(g);
+  free_batch(g);
   free_graph_memory(g);
   g->magic = 0;
   delete g;
@@ -305,6 +306,46 @@ gm_status gm_triangle_count(gm_graph g, uint64_t* counts, uint64_t* total, void*
       GM_HIP(hipStreamSynchronize(s));
       dfree(own);
     }
+    return ok();
+  });
+}
+
+gm_status gm_run_batched(gm_graph g, const gm_program* prog, const int32_t* sources, int32_t k,
+                         int32_t max_iters, void* vprop_block, int32_t* iters_done, void* stream) {
+  if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
+  if (!prog || !sources || !vprop_block) return fail(GM_EINVAL, "prog/sources/vprop_block is NULL");
+  const int kind = prog->kind;
+  if (prog->order != GM_ORDER_OUT) return fail(GM_EINVAL, "only GM_ORDER_OUT is supported");
+  if (prog->flags != 0) return fail(GM_EINVAL, "flags must be 0");
+  if (kind == GM_PROG_BFS || kind == GM_PROG_SSSP) {
+    if (k < 1 || k > 64) return fail(GM_EINVAL, "k = %d outside [1, 64]", k);
+  } else if (kind == GM_PROG_PPR) {
+    if (k < 1 || k > 256) return fail(GM_EINVAL, "k = %d outside [1, 256]", k);
+    if (max_iters <= 0) return fail(GM_EINVAL, "PPR needs max_iters > 0");
+    if (!(prog->r >= 0.0f && prog->r <= 1.0f)) return fail(GM_EINVAL, "r outside [0, 1]");
+    if (!(g->layouts & GM_LAYOUT_IN)) return fail(GM_EUNSUPPORTED, "PPR needs GM_LAYOUT_IN");
+  } else {
+    return fail(GM_EINVAL, "batched runs support BFS, SSSP and PPR (kind %d)", kind);
+  }
+  if ((int64_t)k * g->n > ((int64_t)1 << 40)) return fail(GM_EUNSUPPORTED, "n * k too large");
+  if (kind == GM_PROG_SSSP && g->wtype != GM_W_U32)
+    return fail(GM_EUNSUPPORTED, "SSSP needs uint32 edge weights");
+  const bool sym = (g->prep & (GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG)) == GM_PREP_SYMMETRIZE;
+  if (kind == GM_PROG_BFS && !sym && !(g->layouts & GM_LAYOUT_IN))
+    return fail(GM_EUNSUPPORTED, "batched BFS on a directed graph needs GM_LAYOUT_IN");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return guarded([&]() -> gm_status {
+    if (!ids_in_range(sources, k, g->n, s)) return fail(GM_EINVAL, "source id outside [0, n)");
+    int32_t it = 0;
+    if (kind == GM_PROG_BFS)
+      it = run_batched_bfs(g, sources, k, max_iters, static_cast<int32_t*>(vprop_block), s);
+    else if (kind == GM_PROG_SSSP)
+      it = run_batched_sssp(g, sources, k, max_iters, static_cast<uint32_t*>(vprop_block), s);
+    else {
+      run_batched_ppr(g, sources, k, prog->r, max_iters, static_cast<float*>(vprop_block), s);
+      it = max_iters;
+    }
+    if (iters_done) *iters_done = it;
     return ok();
   });
 }

@@ -93,6 +93,7 @@ struct gm_graph_s {
   void* min_ws = nullptr;    // frontier workspace of the min programs (minprog.hip)
   void* pr_sched = nullptr;  // pull schedule of the dense programs (pagerank.hip)
   void* tc_plan = nullptr;   // receiver lists of the triangle count (tc.hip)
+  void* batch_ws = nullptr;  // workspace of the batched programs (batched.hip)
   gm::RunStats last_stats;
   gm::Tuning tune;
 };
@@ -128,6 +129,15 @@ void run_triangle_count(gm_graph g, unsigned long long* counts, unsigned long lo
                         hipStream_t s);
 void zero_counts(unsigned long long* a, int64_t n, hipStream_t s);
 void free_tc_plan(gm_graph g);
+
+// Batched programs (batched.hip); return supersteps run.
+int32_t run_batched_bfs(gm_graph g, const int32_t* sources, int k, int32_t max_iters,
+                        int32_t* level, hipStream_t s);
+int32_t run_batched_sssp(gm_graph g, const int32_t* sources, int k, int32_t max_iters,
+                         uint32_t* dist, hipStream_t s);
+void run_batched_ppr(gm_graph g, const int32_t* seeds, int k, float r, int32_t iters, float* out,
+                     hipStream_t s);
+void free_batch(gm_graph g);
 
 // Fill n uint32 words with v on stream s (a kernel, safe under graph capture).
 void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
