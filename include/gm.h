@@ -236,6 +236,71 @@ gm_status gm_run_batched(gm_graph g, const gm_program* prog, const int32_t* sour
  */
 gm_status gm_triangle_count(gm_graph g, uint64_t* counts, uint64_t* total, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Differentiation: adjoint (transpose-direction) products                  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Build a rating graph for collaborative filtering (Sec. 3 III): an
+ * n_rows x n_cols matrix G (rows = users, columns = items) with m ratings
+ * G[row[e]][col[e]] = val[e] (host arrays; uint8 ratings). Pairs must be
+ * distinct. The library keeps it compressed by row and by column. Only the
+ * gm_cf_* calls (and gm_graph_get_info / gm_graph_destroy) accept it.
+ * Errors: GM_EINVAL (sizes, NULL arrays, ids outside the matrix);
+ * GM_EUNSUPPORTED (repeated (row, col) pair, m > 2^32 - 1); GM_ENOMEM;
+ * GM_EHIP. Synchronises `stream`.
+ */
+gm_status gm_bipartite_from_coo(int64_t n_rows, int64_t n_cols, int64_t m, const int32_t* row,
+                                const int32_t* col, const uint8_t* val, void* stream,
+                                gm_graph* out);
+
+/*
+ * CF loss of Eq. (3): L = sum_(u,v) e_uv^2 + lambda sum_u |p_u|^2
+ * + lambda sum_v |p_v|^2 with e_uv = G_uv - p_u . p_v (Eq. (4)).
+ * PU (n_rows x K) and PV (n_cols x K) are row-major float factors (device);
+ * *loss is a device double written on `stream` (asynchronous).
+ * Errors: GM_ESTATE; GM_EUNSUPPORTED (not a rating graph); GM_EINVAL
+ * (K outside [1, 64], NULL pointers, lambda < 0); GM_ENOMEM; GM_EHIP.
+ */
+gm_status gm_cf_forward(gm_graph g, int32_t K, const float* PU, const float* PV, float lambda,
+                        double* loss, void* stream);
+
+/*
+ * Gradients of the CF loss, scaled by `scale` (the upstream gradient):
+ *   gPU[u] = scale * (-2 sum_v e_uv p_v + 2 lambda p_u)   (row pass)
+ *   gPV[v] = scale * (-2 sum_u e_uv p_u + 2 lambda p_v)   (transpose pass)
+ * so a GD step of Eqs. (5)-(6) is p -= (gamma / 2) * g with scale = 1.
+ * gPU / gPV are device arrays shaped like PU / PV; either may be NULL (not
+ * both). Deterministic. Errors as gm_cf_forward, plus GM_EINVAL if both
+ * outputs are NULL or scale is not finite. Asynchronous.
+ */
+gm_status gm_cf_backward(gm_graph g, int32_t K, const float* PU, const float* PV, float lambda,
+                         float scale, float* gPU, float* gPV, void* stream);
+
+/*
+ * Weighted PageRank with history: PR^{t+1}(v) = r + (1 - r) *
+ * sum_{u -> v} w_uv PR^t(u) / outdeg(u) (Eq. (1) with edge weights w in
+ * canonical edge order, device float[m]; outdeg is the unweighted count).
+ * hist is a device float (T + 1) x n array whose row 0 the caller fills
+ * with PR^0; the call writes rows 1..T. Needs GM_LAYOUT_IN.
+ * Errors: GM_ESTATE; GM_EINVAL (NULL pointers, T < 1, r outside [0, 1]);
+ * GM_EUNSUPPORTED (no in-layout, rating graph); GM_ENOMEM; GM_EHIP.
+ * Asynchronous.
+ */
+gm_status gm_pagerank_forward_w(gm_graph g, const float* w, float r, int32_t T, float* hist,
+                                void* stream);
+
+/*
+ * Vector-Jacobian product of PR^T with respect to the edge weights: given
+ * grad_out = dL/dPR^T (device float[n]) and the history from
+ * gm_pagerank_forward_w, writes grad_w = dL/dw (device float[m], canonical
+ * edge order) by T reverse steps, each one pass over the out-edges (the
+ * product with the transposed matrix). Errors as gm_pagerank_forward_w.
+ * Asynchronous.
+ */
+gm_status gm_pagerank_vjp_w(gm_graph g, const float* w, float r, int32_t T, const float* hist,
+                            const float* grad_out, float* grad_w, void* stream);
+
 /* Counters of the last gm_run_vertex_program call on a graph. */
 typedef struct gm_run_stats {
   int32_t supersteps;      /* supersteps run (as *iters_done) */

@@ -173,3 +173,108 @@ def run_batched(g: Graph, kind: int, sources, max_iters: int, vprop_block, r: fl
                                           sources.numel(), max_iters, _ptr(vprop_block),
                                           ctypes.byref(it), _stream(stream)), "gm_run_batched")
     return it.value
+
+
+# --------------------------------------------------------------------------
+# Differentiation (adjoint products) and torch.autograd wrappers
+# --------------------------------------------------------------------------
+class RatingGraph(Graph):
+    """Rating matrix for collaborative filtering (gm_bipartite_from_coo)."""
+
+    @classmethod
+    def from_coo(cls, n_rows: int, n_cols: int, row, col, val, stream=None) -> "RatingGraph":
+        r, rp = _host(row, np.int32)
+        c, cp = _host(col, np.int32)
+        v, vpp = _host(val, np.uint8)
+        if not (len(r) == len(c) == len(v)):
+            raise ValueError("row, col and val differ in length")
+        out = ctypes.c_void_p()
+        _lib.check(_lib.load().gm_bipartite_from_coo(n_rows, n_cols, len(r), rp, cp, vpp,
+                                                     _stream(stream), ctypes.byref(out)),
+                   "gm_bipartite_from_coo")
+        return cls(out.value)
+
+
+def cf_forward(g: RatingGraph, PU, PV, lam: float, loss_out, stream=None) -> None:
+    """gm_cf_forward: writes the Eq. (3) loss into loss_out (device float64[1])."""
+    _lib.check(_lib.load().gm_cf_forward(g.handle, PU.shape[1], _ptr(PU), _ptr(PV), lam,
+                                         _ptr(loss_out), _stream(stream)), "gm_cf_forward")
+
+
+def cf_backward(g: RatingGraph, PU, PV, lam: float, scale: float, gPU=None, gPV=None,
+                stream=None) -> None:
+    """gm_cf_backward: scale * dL/dP_U into gPU, scale * dL/dP_V into gPV."""
+    _lib.check(_lib.load().gm_cf_backward(g.handle, PU.shape[1], _ptr(PU), _ptr(PV), lam, scale,
+                                          _ptr(gPU), _ptr(gPV), _stream(stream)),
+               "gm_cf_backward")
+
+
+def pagerank_forward_w(g: Graph, w, r: float, T: int, hist, stream=None) -> None:
+    """gm_pagerank_forward_w: hist[0] holds PR^0; rows 1..T are written."""
+    _lib.check(_lib.load().gm_pagerank_forward_w(g.handle, _ptr(w), r, T, _ptr(hist),
+                                                 _stream(stream)), "gm_pagerank_forward_w")
+
+
+def pagerank_vjp_w(g: Graph, w, r: float, T: int, hist, grad_out, grad_w, stream=None) -> None:
+    """gm_pagerank_vjp_w: grad_w = dL/dw given grad_out = dL/dPR^T."""
+    _lib.check(_lib.load().gm_pagerank_vjp_w(g.handle, _ptr(w), r, T, _ptr(hist), _ptr(grad_out),
+                                             _ptr(grad_w), _stream(stream)), "gm_pagerank_vjp_w")
+
+
+def _autograd():
+    import torch
+
+    class CFLoss(torch.autograd.Function):
+        """L(P_U, P_V) of Eq. (3) on a RatingGraph; backward runs the row pass
+        and the transpose (column) pass of the library."""
+
+        @staticmethod
+        def forward(ctx, PU, PV, g, lam):
+            PU = PU.contiguous()
+            PV = PV.contiguous()
+            loss = torch.empty(1, dtype=torch.float64, device=PU.device)
+            cf_forward(g, PU, PV, lam, loss)
+            ctx.save_for_backward(PU, PV)
+            ctx.g, ctx.lam = g, lam
+            return loss[0]
+
+        @staticmethod
+        def backward(ctx, grad):
+            PU, PV = ctx.saved_tensors
+            gPU = torch.empty_like(PU) if ctx.needs_input_grad[0] else None
+            gPV = torch.empty_like(PV) if ctx.needs_input_grad[1] else None
+            if gPU is not None or gPV is not None:
+                cf_backward(ctx.g, PU, PV, ctx.lam, float(grad), gPU, gPV)
+            return gPU, gPV, None, None
+
+    class PageRankW(torch.autograd.Function):
+        """PR^T of the edge-weighted Eq. (1) (PR^0 = 1) as a function of the
+        edge weights w (canonical order); backward is the adjoint SpMV."""
+
+        @staticmethod
+        def forward(ctx, w, g, r, T):
+            w = w.contiguous()
+            n = g.n
+            hist = torch.empty((T + 1, n), dtype=torch.float32, device=w.device)
+            hist[0].fill_(1.0)
+            pagerank_forward_w(g, w, r, T, hist)
+            ctx.save_for_backward(w, hist)
+            ctx.g, ctx.r, ctx.T = g, r, T
+            return hist[T].clone()
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            w, hist = ctx.saved_tensors
+            gw = torch.empty_like(w)
+            pagerank_vjp_w(ctx.g, w, ctx.r, ctx.T, hist, grad_out.contiguous().float(), gw)
+            return gw, None, None, None
+
+    return CFLoss, PageRankW
+
+
+def __getattr__(name):
+    if name in ("CFLoss", "PageRankW"):
+        CFLoss, PageRankW = _autograd()
+        globals()["CFLoss"], globals()["PageRankW"] = CFLoss, PageRankW
+        return globals()[name]
+    raise AttributeError(name)

@@ -76,6 +76,11 @@ def load():
         "gm_triangle_count": ([vp, vp, ctypes.POINTER(ctypes.c_uint64), vp], i32),
         "gm_run_batched": ([vp, ctypes.POINTER(gm_program), vp, i32, i32, vp, ctypes.POINTER(i32),
                             vp], i32),
+        "gm_bipartite_from_coo": ([i64, i64, i64, vp, vp, vp, vp, ctypes.POINTER(vp)], i32),
+        "gm_cf_forward": ([vp, i32, vp, vp, ctypes.c_float, vp, vp], i32),
+        "gm_cf_backward": ([vp, i32, vp, vp, ctypes.c_float, ctypes.c_float, vp, vp, vp], i32),
+        "gm_pagerank_forward_w": ([vp, vp, ctypes.c_float, i32, vp, vp], i32),
+        "gm_pagerank_vjp_w": ([vp, vp, ctypes.c_float, i32, vp, vp, vp, vp], i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)

@@ -200,6 +200,8 @@ gm_status gm_graph_destroy(gm_graph g) {
   free_pull_schedule(g);
   free_tc_plan(g);
   free_batch(g);
+  free_cf_plan(g);
+  free_vjp_plan(g);
   free_graph_memory(g);
   g->magic = 0;
   delete g;
@@ -212,6 +214,7 @@ gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_fro
   if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
   if (!prog) return fail(GM_EINVAL, "prog is NULL");
   if (!vprop) return fail(GM_EINVAL, "vprop is NULL");
+  if (g->bipartite) return fail(GM_EUNSUPPORTED, "rating graphs take the CF calls only");
   const int kind = prog->kind;
   if (kind != GM_PROG_BFS && kind != GM_PROG_SSSP && kind != GM_PROG_PAGERANK &&
       kind != GM_PROG_PPR && kind != GM_PROG_TC)
@@ -286,6 +289,7 @@ gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_fro
 
 gm_status gm_triangle_count(gm_graph g, uint64_t* counts, uint64_t* total, void* stream) {
   if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
+  if (g->bipartite) return fail(GM_EUNSUPPORTED, "rating graphs take the CF calls only");
   if (!(g->prep & GM_PREP_UPPER_DAG) || !(g->layouts & GM_LAYOUT_IN))
     return fail(GM_EUNSUPPORTED, "triangle counting needs GM_PREP_UPPER_DAG and GM_LAYOUT_IN");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -314,6 +318,7 @@ gm_status gm_run_batched(gm_graph g, const gm_program* prog, const int32_t* sour
                          int32_t max_iters, void* vprop_block, int32_t* iters_done, void* stream) {
   if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
   if (!prog || !sources || !vprop_block) return fail(GM_EINVAL, "prog/sources/vprop_block is NULL");
+  if (g->bipartite) return fail(GM_EUNSUPPORTED, "rating graphs take the CF calls only");
   const int kind = prog->kind;
   if (prog->order != GM_ORDER_OUT) return fail(GM_EINVAL, "only GM_ORDER_OUT is supported");
   if (prog->flags != 0) return fail(GM_EINVAL, "flags must be 0");
@@ -346,6 +351,107 @@ gm_status gm_run_batched(gm_graph g, const gm_program* prog, const int32_t* sour
       it = max_iters;
     }
     if (iters_done) *iters_done = it;
+    return ok();
+  });
+}
+
+gm_status gm_bipartite_from_coo(int64_t n_rows, int64_t n_cols, int64_t m, const int32_t* row,
+                                const int32_t* col, const uint8_t* val, void* stream,
+                                gm_graph* out) {
+  if (!out) return fail(GM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_rows <= 0 || n_cols <= 0 || n_rows > INT32_MAX || n_cols > INT32_MAX)
+    return fail(GM_EINVAL, "n_rows/n_cols outside [1, 2^31-1]");
+  if (m < 0) return fail(GM_EINVAL, "m is negative");
+  if (m > (int64_t)UINT32_MAX) return fail(GM_EUNSUPPORTED, "more than 2^32-1 ratings");
+  if (m > 0 && (!row || !col || !val)) return fail(GM_EINVAL, "row/col/val is NULL");
+  for (int64_t e = 0; e < m; ++e)
+    if ((uint32_t)row[e] >= (uint64_t)n_rows || (uint32_t)col[e] >= (uint64_t)n_cols)
+      return fail(GM_EINVAL, "rating %lld (%d, %d) outside the matrix", (long long)e, row[e], col[e]);
+  return guarded([&]() -> gm_status {
+    int dev = 0;
+    GM_HIP(hipGetDevice(&dev));
+    gm_graph g = new gm_graph_s();
+    g->magic = kGraphMagic;
+    g->bipartite = true;
+    g->n_rows = n_rows;
+    g->n_cols = n_cols;
+    g->n = n_rows + n_cols;
+    g->layouts = GM_LAYOUT_OUT | GM_LAYOUT_IN;
+    g->device = dev;
+    try {
+      build_bipartite(g, row, col, val, m, static_cast<hipStream_t>(stream));
+    } catch (...) {
+      free_graph_memory(g);
+      delete g;
+      throw;
+    }
+    graph_register(g);
+    *out = g;
+    return ok();
+  });
+}
+
+static gm_status check_cf(gm_graph g, int32_t K, const float* PU, const float* PV, float lambda) {
+  if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
+  if (!g->bipartite) return fail(GM_EUNSUPPORTED, "CF needs a rating graph (gm_bipartite_from_coo)");
+  if (K < 1 || K > 64) return fail(GM_EINVAL, "K = %d outside [1, 64]", K);
+  if (!PU || !PV) return fail(GM_EINVAL, "PU/PV is NULL");
+  if (!(lambda >= 0.0f) || !std::isfinite(lambda)) return fail(GM_EINVAL, "lambda must be >= 0");
+  return GM_OK;
+}
+
+gm_status gm_cf_forward(gm_graph g, int32_t K, const float* PU, const float* PV, float lambda,
+                        double* loss, void* stream) {
+  const gm_status st = check_cf(g, K, PU, PV, lambda);
+  if (st != GM_OK) return st;
+  if (!loss) return fail(GM_EINVAL, "loss is NULL");
+  return guarded([&]() -> gm_status {
+    run_cf_forward(g, K, PU, PV, lambda, loss, static_cast<hipStream_t>(stream));
+    return ok();
+  });
+}
+
+gm_status gm_cf_backward(gm_graph g, int32_t K, const float* PU, const float* PV, float lambda,
+                         float scale, float* gPU, float* gPV, void* stream) {
+  const gm_status st = check_cf(g, K, PU, PV, lambda);
+  if (st != GM_OK) return st;
+  if (!gPU && !gPV) return fail(GM_EINVAL, "gPU and gPV are both NULL");
+  if (!std::isfinite(scale)) return fail(GM_EINVAL, "scale is not finite");
+  return guarded([&]() -> gm_status {
+    run_cf_backward(g, K, PU, PV, lambda, scale, gPU, gPV, static_cast<hipStream_t>(stream));
+    return ok();
+  });
+}
+
+static gm_status check_prw(gm_graph g, const float* w, float r, int32_t T) {
+  if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
+  if (g->bipartite) return fail(GM_EUNSUPPORTED, "rating graphs take the CF calls only");
+  if (!(g->layouts & GM_LAYOUT_IN)) return fail(GM_EUNSUPPORTED, "needs GM_LAYOUT_IN");
+  if (!w) return fail(GM_EINVAL, "w is NULL");
+  if (!(r >= 0.0f && r <= 1.0f)) return fail(GM_EINVAL, "r outside [0, 1]");
+  if (T < 1) return fail(GM_EINVAL, "T must be >= 1");
+  return GM_OK;
+}
+
+gm_status gm_pagerank_forward_w(gm_graph g, const float* w, float r, int32_t T, float* hist,
+                                void* stream) {
+  const gm_status st = check_prw(g, w, r, T);
+  if (st != GM_OK) return st;
+  if (!hist) return fail(GM_EINVAL, "hist is NULL");
+  return guarded([&]() -> gm_status {
+    run_pagerank_history(g, w, r, T, hist, static_cast<hipStream_t>(stream));
+    return ok();
+  });
+}
+
+gm_status gm_pagerank_vjp_w(gm_graph g, const float* w, float r, int32_t T, const float* hist,
+                            const float* grad_out, float* grad_w, void* stream) {
+  const gm_status st = check_prw(g, w, r, T);
+  if (st != GM_OK) return st;
+  if (!hist || !grad_out || !grad_w) return fail(GM_EINVAL, "hist/grad_out/grad_w is NULL");
+  return guarded([&]() -> gm_status {
+    run_pagerank_vjp(g, w, r, T, hist, grad_out, grad_w, static_cast<hipStream_t>(stream));
     return ok();
   });
 }

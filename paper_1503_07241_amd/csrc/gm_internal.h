@@ -94,6 +94,14 @@ struct gm_graph_s {
   void* pr_sched = nullptr;  // pull schedule of the dense programs (pagerank.hip)
   void* tc_plan = nullptr;   // receiver lists of the triangle count (tc.hip)
   void* batch_ws = nullptr;  // workspace of the batched programs (batched.hip)
+  void* cf_plan = nullptr;   // work items of the rating passes (cf.hip)
+  void* vjp_plan = nullptr;  // row schedule of the PageRank adjoint (prgrad.hip)
+  // bipartite rating graphs (gm_bipartite_from_coo): rows = users, cols = items;
+  // out_* is the CSR by row, in_* the CSC by column, ratings in *_val.
+  bool bipartite = false;
+  int64_t n_rows = 0, n_cols = 0;
+  uint8_t* out_val = nullptr;
+  uint8_t* in_val = nullptr;
   gm::RunStats last_stats;
   gm::Tuning tune;
 };
@@ -138,6 +146,23 @@ int32_t run_batched_sssp(gm_graph g, const int32_t* sources, int k, int32_t max_
 void run_batched_ppr(gm_graph g, const int32_t* seeds, int k, float r, int32_t iters, float* out,
                      hipStream_t s);
 void free_batch(gm_graph g);
+
+// Collaborative filtering (cf.hip).
+void build_bipartite(gm_graph g, const int32_t* row, const int32_t* col, const uint8_t* val,
+                     int64_t m, hipStream_t s);
+void run_cf_forward(gm_graph g, int K, const float* PU, const float* PV, float lambda,
+                    double* loss_dev, hipStream_t s);
+void run_cf_backward(gm_graph g, int K, const float* PU, const float* PV, float lambda, float scale,
+                     float* gPU, float* gPV, hipStream_t s);
+void free_cf_plan(gm_graph g);
+
+// Weighted PageRank with history and its edge-weight VJP (pagerank.hip,
+// prgrad.hip). hist is (T + 1) x n in the caller's labels.
+void run_pagerank_history(gm_graph g, const float* w, float r, int32_t T, float* hist,
+                          hipStream_t s);
+void run_pagerank_vjp(gm_graph g, const float* w, float r, int32_t T, const float* hist,
+                      const float* grad_out, float* grad_w, hipStream_t s);
+void free_vjp_plan(gm_graph g);
 
 // Fill n uint32 words with v on stream s (a kernel, safe under graph capture).
 void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);

@@ -361,6 +361,9 @@ void free_graph_memory(gm_graph g) {
   dfree(g->in_w);
   dfree(g->in_eid);
   dfree(g->inv_outdeg);
+  dfree(g->out_val);
+  dfree(g->in_val);
+  g->out_val = g->in_val = nullptr;
   g->out_off = g->in_off = g->in_eid = nullptr;
   g->out_idx = g->in_idx = nullptr;
   g->out_w = g->in_w = nullptr;

@@ -76,6 +76,8 @@ struct Dense {
   uint32_t* off = nullptr;      // relabelled in-adjacency
   int32_t* idx = nullptr;
   float* w = nullptr;           // edge values in the relabelled order (weighted graphs)
+  uint32_t* ceid = nullptr;     // canonical (CSR) edge id of each relabelled in-edge
+  float* wdyn = nullptr;        // caller-supplied edge values, relabelled per call
   float* inv_outdeg = nullptr;  // new labels
   float* x[2] = {nullptr, nullptr};
   float* pr = nullptr;          // PR in new labels (last superstep)
@@ -264,14 +266,24 @@ __global__ void relabel_keys(const uint32_t* __restrict__ in_off, const int32_t*
 
 __global__ void relabel_finish(const unsigned long long* __restrict__ keys,
                                const uint32_t* __restrict__ eid, int64_t m, int b,
-                               const float* __restrict__ in_w, int32_t* __restrict__ idx,
-                               float* __restrict__ w) {
+                               const float* __restrict__ in_w, const uint32_t* __restrict__ in_eid,
+                               int32_t* __restrict__ idx, float* __restrict__ w,
+                               uint32_t* __restrict__ ceid) {
   const unsigned long long mask = (1ull << b) - 1;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
        i += (int64_t)gridDim.x * blockDim.x) {
     idx[i] = (int32_t)(keys[i] & mask);
     if (w) w[i] = in_w[eid[i]];
+    ceid[i] = in_eid[eid[i]];
   }
+}
+
+// Caller-supplied edge values (canonical order) -> relabelled order.
+__global__ void gather_w(const float* __restrict__ w, const uint32_t* __restrict__ ceid, int64_t m,
+                         float* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = w[ceid[i]];
 }
 
 __global__ void gather_f32(const float* __restrict__ src, const int32_t* __restrict__ index,
@@ -307,6 +319,8 @@ void free_pull_schedule(gm_graph g) {
   dfree(d->off);
   dfree(d->idx);
   dfree(d->w);
+  dfree(d->ceid);
+  dfree(d->wdyn);
   dfree(d->inv_outdeg);
   dfree(d->x[0]);
   dfree(d->x[1]);
@@ -423,9 +437,10 @@ void ensure_pull_schedule(gm_graph g, hipStream_t st) {
       dfree(tmp);
       GM_HIP(err);
       if (g->wtype == GM_W_F32) d->w = dalloc<float>(m);
+      d->ceid = dalloc<uint32_t>(m);
       relabel_finish<<<blocks_for(m), kThreads, 0, st>>>(kb.current(), vb.current(), m, b,
                                                          static_cast<const float*>(g->in_w),
-                                                         d->idx, d->w);
+                                                         g->in_eid, d->idx, d->w, d->ceid);
       GM_HIP(hipGetLastError());
     }
     GM_HIP(hipStreamSynchronize(st));
@@ -435,18 +450,17 @@ void ensure_pull_schedule(gm_graph g, hipStream_t st) {
   }
 }
 
-void run_pagerank(gm_graph g, float r, int32_t iters, float* rank, int32_t seed, hipStream_t st) {
-  ensure_pull_schedule(g, st);
-  Dense* d = dense(g);
+// Supersteps of (personalised, optionally weighted) PageRank from the rank
+// vector `rank0` (caller labels). w: relabelled edge values or NULL. After
+// the last superstep the ranks go to `rank_out`; with `hist` (T + 1 rows),
+// PR^t is also written to row t for t = 1..iters.
+static void pagerank_driver(gm_graph g, Dense* d, float r, int32_t iters, const float* rank0,
+                            int32_t seed_new, const float* w, float* hist, float* rank_out,
+                            hipStream_t st) {
   const int64_t n = g->n;
-  const bool weighted = g->wtype == GM_W_F32;
-  const bool personal = seed >= 0;
-  int32_t seed_new = -1;
-  if (personal) {
-    GM_HIP(hipMemcpyAsync(&seed_new, d->new_of + seed, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    GM_HIP(hipStreamSynchronize(st));
-  }
-  pr_send0<<<blocks_for(n), kThreads, 0, st>>>(rank, d->old_of, d->inv_outdeg, n, d->x[0]);
+  const bool weighted = w != nullptr;
+  const bool personal = seed_new >= 0;
+  pr_send0<<<blocks_for(n), kThreads, 0, st>>>(rank0, d->old_of, d->inv_outdeg, n, d->x[0]);
   GM_HIP(hipGetLastError());
   const int64_t c0 = d->bins.class_begin[0], n0 = d->bins.class_rows[0];
   auto const_rows = [&](float* xo, float* po) {
@@ -466,11 +480,11 @@ void run_pagerank(gm_graph g, float r, int32_t iters, float* rank, int32_t seed,
   for (int32_t it = 0; it < iters; ++it) {
     const float* xin = d->x[it & 1];
     float* xout = d->x[(it + 1) & 1];
-    float* pout = it == iters - 1 ? d->pr : nullptr;
+    float* pout = (hist || it == iters - 1) ? d->pr : nullptr;
     auto launch = [&](auto kern) {
       if (grid > 0)
-        kern<<<grid, kThreads, 0, st>>>(d->off, d->idx, d->w, xin, d->inv_outdeg, r, seed_new,
-                                        xout, pout, d->chunks, d->partial, d->bins);
+        kern<<<grid, kThreads, 0, st>>>(d->off, d->idx, w, xin, d->inv_outdeg, r, seed_new, xout,
+                                        pout, d->chunks, d->partial, d->bins);
     };
     if (weighted && personal)
       launch(pr_dense<true, true>);
@@ -491,9 +505,39 @@ void run_pagerank(gm_graph g, float r, int32_t iters, float* rank, int32_t seed,
     }
     GM_HIP(hipGetLastError());
     if (it == 0) const_rows(d->x[0], nullptr);  // x[0] held PR^0 messages until now
+    if (hist) {
+      pr_unpermute<<<blocks_for(n), kThreads, 0, st>>>(d->pr, d->new_of, n, hist + (it + 1) * n);
+      GM_HIP(hipGetLastError());
+    }
   }
-  pr_unpermute<<<blocks_for(n), kThreads, 0, st>>>(d->pr, d->new_of, n, rank);
-  GM_HIP(hipGetLastError());
+  if (rank_out) {
+    pr_unpermute<<<blocks_for(n), kThreads, 0, st>>>(d->pr, d->new_of, n, rank_out);
+    GM_HIP(hipGetLastError());
+  }
+}
+
+void run_pagerank(gm_graph g, float r, int32_t iters, float* rank, int32_t seed, hipStream_t st) {
+  ensure_pull_schedule(g, st);
+  Dense* d = dense(g);
+  int32_t seed_new = -1;
+  if (seed >= 0) {
+    GM_HIP(hipMemcpyAsync(&seed_new, d->new_of + seed, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GM_HIP(hipStreamSynchronize(st));
+  }
+  pagerank_driver(g, d, r, iters, rank, seed_new, g->wtype == GM_W_F32 ? d->w : nullptr, nullptr,
+                  rank, st);
+}
+
+void run_pagerank_history(gm_graph g, const float* w, float r, int32_t T, float* hist,
+                          hipStream_t st) {
+  ensure_pull_schedule(g, st);
+  Dense* d = dense(g);
+  if (!d->wdyn) d->wdyn = dalloc<float>(g->m);
+  if (g->m > 0) {
+    gather_w<<<blocks_for(g->m), kThreads, 0, st>>>(w, d->ceid, g->m, d->wdyn);
+    GM_HIP(hipGetLastError());
+  }
+  pagerank_driver(g, d, r, T, hist, -1, d->wdyn, hist, nullptr, st);
 }
 
 }  // namespace gm

@@ -1,0 +1,191 @@
+"""Adjoint (transpose-direction) products on the GPU against the FP64 oracle:
+collaborative-filtering loss and factor gradients (Sec. 3 III, Eqs. (3)-(6))
+and the edge-weight gradient of PageRank (Eq. (1) with weights).
+
+Tolerances: loss relative error <= 1e-5; gradients ||g - g_ref|| / ||g_ref||
+<= 1e-5 (Frobenius / 2-norm)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import graphgen as gg
+import oracle
+import paper_1503_07241_amd as gm
+from tests import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+HERE = os.path.dirname(os.path.abspath(__file__))
+LAM = 0.05
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def cf_setup(n_users, n_items, total, K=32, seed=gg.SEED_CF_POINT, dmin=gg.CF_DMIN):
+    R = gg.cf_ratings(n_users=n_users, n_items=n_items, total=total, dmin=dmin)
+    PU, PV = gg.cf_point(R.n_users, R.n_items, K, seed)
+    g = gm.RatingGraph.from_coo(R.n_users, R.n_items, R.user, R.item, R.rating)
+    return R, PU, PV, g
+
+
+def gpu_cf(g, PU, PV, lam=LAM, scale=1.0):
+    pu = torch.tensor(PU, device=DEV)
+    pv = torch.tensor(PV, device=DEV)
+    loss = torch.empty(1, dtype=torch.float64, device=DEV)
+    gm.cf_forward(g, pu, pv, lam, loss)
+    gu, gv = torch.empty_like(pu), torch.empty_like(pv)
+    gm.cf_backward(g, pu, pv, lam, scale, gu, gv)
+    return float(loss.item()), gu.cpu().numpy(), gv.cpu().numpy()
+
+
+def test_cf_hand_example():
+    kv = {}
+    for line in open(os.path.join(HERE, "golden", "cf_hand_example.txt")):
+        if line.startswith("#") or not line.strip() or line.startswith("key"):
+            continue
+        k, v = line.split()
+        kv[k] = float(v)
+    g = gm.RatingGraph.from_coo(1, 1, [0], [0], [int(kv["G"])])
+    L, gu, gv = gpu_cf(g, np.array([[kv["p_u"]]], np.float32), np.array([[kv["p_v"]]], np.float32),
+                       kv["lambda"])
+    # lambda crosses the ABI as float32 (0.05f = 0.05 + 7.5e-10), hence 1e-7
+    assert abs(L - kv["L"]) < 1e-7
+    assert abs(gu[0, 0] - kv["g_u"]) < 1e-6 and abs(gv[0, 0] - kv["g_v"]) < 1e-6
+
+
+@pytest.mark.parametrize("shape,K", [((3000, 500, 120_000), 32), ((3000, 3000, 600_000), 32),
+                                     ((2000, 20, 30_000), 16), ((500, 400, 20_000), 7)])
+def test_cf_loss_and_gradients(shape, K):
+    """Includes long rows and columns (more than one work item) and K not a
+    power of two."""
+    nu, ni, tot = shape
+    R, PU, PV, g = cf_setup(nu, ni, tot, K, dmin=min(gg.CF_DMIN, ni))
+    L, gu, gv = gpu_cf(g, PU, PV)
+    Lr, gur, gvr = oracle.cf_loss_grad(R.n_users, R.n_items, R.user, R.item, R.rating, PU, PV, LAM)
+    assert abs(L - Lr) <= 1e-5 * abs(Lr)
+    assert rel(gu, gur) <= 1e-5 and rel(gv, gvr) <= 1e-5
+
+
+def test_cf_full_size():
+    """The 480,189 x 17,770 rating graph with 100M ratings, K = 32."""
+    R, PU, PV, g = cf_setup(gg.NETFLIX_USERS, gg.NETFLIX_ITEMS, gg.NETFLIX_RATINGS)
+    L, gu, gv = gpu_cf(g, PU, PV)
+    Lr, gur, gvr = oracle.cf_loss_grad(R.n_users, R.n_items, R.user, R.item, R.rating, PU, PV, LAM)
+    assert abs(L - Lr) <= 1e-5 * abs(Lr)
+    assert rel(gu, gur) <= 1e-5 and rel(gv, gvr) <= 1e-5
+    # per-row maxima, reported for information
+    print("cf full: loss rel %.2e, gU rel %.2e, gV rel %.2e" % (
+        abs(L - Lr) / Lr, rel(gu, gur), rel(gv, gvr)))
+
+
+def test_cf_autograd_and_finite_difference():
+    R, PU, PV, g = cf_setup(2000, 300, 60_000)
+    pu = torch.tensor(PU, device=DEV, requires_grad=True)
+    pv = torch.tensor(PV, device=DEV, requires_grad=True)
+    loss = gm.CFLoss.apply(pu, pv, g, LAM)
+    (3.0 * loss).backward()
+    Lr, gur, gvr = oracle.cf_loss_grad(R.n_users, R.n_items, R.user, R.item, R.rating, PU, PV, LAM)
+    assert rel(pu.grad.cpu().numpy(), 3.0 * gur) <= 1e-5
+    assert rel(pv.grad.cpu().numpy(), 3.0 * gvr) <= 1e-5
+    # central difference of the GPU loss along a random direction; the
+    # direction is taken from the float32-rounded perturbed points
+    rng = np.random.default_rng(3)
+    du, dv = rng.normal(size=PU.shape), rng.normal(size=PV.shape)
+    h = 1e-3
+    Up, Um = (PU + h * du).astype(np.float32), (PU - h * du).astype(np.float32)
+    Vp, Vm = (PV + h * dv).astype(np.float32), (PV - h * dv).astype(np.float32)
+    Lp = gpu_cf(g, Up, Vp)[0]
+    Lm = gpu_cf(g, Um, Vm)[0]
+    fd = (Lp - Lm) / (2 * h)
+    du_eff = (Up.astype(np.float64) - Um) / (2 * h)
+    dv_eff = (Vp.astype(np.float64) - Vm) / (2 * h)
+    _, gu0, gv0 = oracle.cf_loss_grad(R.n_users, R.n_items, R.user, R.item, R.rating,
+                                      (Up.astype(np.float64) + Um) / 2, (Vp.astype(np.float64) + Vm) / 2,
+                                      LAM)
+    ana = (gu0 * du_eff).sum() + (gv0 * dv_eff).sum()
+    assert abs(fd - ana) <= 1e-5 * abs(ana)
+
+
+def test_cf_rejects_plain_graph_and_bad_k():
+    n, s, d = W.raw(8)
+    g = gm.Graph.from_coo(n, s, d)
+    x = torch.zeros((n, 4), device=DEV)
+    loss = torch.empty(1, dtype=torch.float64, device=DEV)
+    with pytest.raises(gm.GmError) as e:
+        gm.cf_forward(g, x, x, LAM, loss)
+    assert e.value.status == gm._lib.GM_EUNSUPPORTED
+    R, PU, PV, rg = cf_setup(200, 50, 3000)
+    big = torch.zeros((200, 65), device=DEV)
+    with pytest.raises(gm.GmError) as e:
+        gm.cf_forward(rg, big, torch.zeros((50, 65), device=DEV), LAM, loss)
+    assert e.value.status == gm._lib.GM_EINVAL
+
+
+# --- PageRank edge-weight gradient ------------------------------------------
+def pr_setup(n, s, d, seed=11):
+    og = oracle.prepare(n, s, d)
+    w = gg.weights_f32(og.rows().astype(np.int32), og.idx, seed, 0.5, 1.5)
+    c = gg.uniform_f32(n, gg.SEED_PR_UPSTREAM)
+    g = gm.Graph.from_coo(n, s, d)
+    return og, w, c, g
+
+
+def gpu_pr_grad(g, n, w, c, T, r=0.15):
+    wt = torch.tensor(w, device=DEV)
+    hist = torch.empty((T + 1, n), dtype=torch.float32, device=DEV)
+    hist[0].fill_(1.0)
+    gm.pagerank_forward_w(g, wt, r, T, hist)
+    gw = torch.empty_like(wt)
+    gm.pagerank_vjp_w(g, wt, r, T, hist, torch.tensor(c, device=DEV), gw)
+    return hist.cpu().numpy(), gw.cpu().numpy()
+
+
+@pytest.mark.parametrize("scale,T", [(12, 20), (W.SMALL_SCALE, 20), (10, 1), (W.SMALL_SCALE, 3)])
+def test_pagerank_weight_gradient(scale, T):
+    n, s, d = W.raw(scale)
+    og, w, c, g = pr_setup(n, s, d)
+    hist, gw = gpu_pr_grad(g, n, w, c, T)
+    ref_hist = oracle.pagerank_history(og, 0.15, T, w=w.astype(np.float64))
+    assert W.max_rel_err(hist[T], ref_hist[T]) <= 1e-5
+    ref = oracle.pagerank_vjp_w(og, w, c, 0.15, T, hist=ref_hist)
+    assert rel(gw, ref) <= 1e-5
+    if T == 1:  # closed form: 0.85 * c_v / outdeg(u)
+        deg = og.degree()[og.rows()]
+        assert rel(gw, 0.85 * c[og.idx].astype(np.float64) / deg) <= 1e-6
+
+
+def test_pagerank_weight_gradient_long_rows():
+    """Out-degree and in-degree far above one work item (split rows)."""
+    hub = 0
+    n = 12000
+    s = np.concatenate([np.zeros(n - 1), np.arange(1, n), np.arange(1, n - 1)]).astype(np.int32)
+    d = np.concatenate([np.arange(1, n), np.zeros(n - 1), np.arange(2, n)]).astype(np.int32)
+    og, w, c, g = pr_setup(n, s, d)
+    hist, gw = gpu_pr_grad(g, n, w, c, 20)
+    ref_hist = oracle.pagerank_history(og, 0.15, 20, w=w.astype(np.float64))
+    assert W.max_rel_err(hist[20], ref_hist[20]) <= 1e-5
+    assert rel(gw, oracle.pagerank_vjp_w(og, w, c, 0.15, 20, hist=ref_hist)) <= 1e-5
+
+
+def test_pagerank_weight_gradient_autograd_fd():
+    n, s, d = W.raw(10)
+    og, w, c, g = pr_setup(n, s, d)
+    wt = torch.tensor(w, device=DEV, requires_grad=True)
+    out = gm.PageRankW.apply(wt, g, 0.15, 20)
+    (out * torch.tensor(c, device=DEV)).sum().backward()
+    ref = oracle.pagerank_vjp_w(og, w, c, 0.15, 20)
+    assert rel(wt.grad.cpu().numpy(), ref) <= 1e-5
+    # FP64 central difference of the oracle along a random direction
+    rng = np.random.default_rng(5)
+    dirv = rng.normal(size=og.m)
+    h = 1e-6
+    Lp = c @ oracle.pagerank(og, 0.15, 20, w=w + h * dirv)
+    Lm = c @ oracle.pagerank(og, 0.15, 20, w=w - h * dirv)
+    fd = (Lp - Lm) / (2 * h)
+    assert abs(wt.grad.cpu().numpy().astype(np.float64) @ dirv - fd) <= 1e-5 * abs(fd)
