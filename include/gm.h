@@ -301,6 +301,132 @@ gm_status gm_pagerank_forward_w(gm_graph g, const float* w, float r, int32_t T, 
 gm_status gm_pagerank_vjp_w(gm_graph g, const float* w, float r, int32_t T, const float* hist,
                             const float* grad_out, float* grad_w, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Mixed batches and captured runs                                          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Block-diagonal union of `count` graphs (host array of live handles with
+ * equal prep, wtype and layouts; no rating graphs): vertex v of parts[i]
+ * becomes base_i + v with base_i = n_0 + ... + n_{i-1}, and the edges keep
+ * their order part by part, so the union's canonical edge order is the
+ * parts' canonical orders one after another. No edge joins two parts, so the
+ * adjacency matrix is block diagonal and every program run on the union
+ * gives, on part i's vertex range, exactly the run on part i alone: graphs of
+ * uneven sizes then share each generalized SpMV of Alg. 1. The parts stay
+ * valid and independent of the union.
+ * Errors: GM_EINVAL (parts/out NULL, count < 1, differing prep, wtype or
+ * layouts); GM_ESTATE (a handle not live); GM_EUNSUPPORTED (a rating graph,
+ * more than 2^31 - 1 vertices or 2^32 - 1 edges in total); GM_ENOMEM;
+ * GM_EHIP. Synchronises `stream`.
+ */
+gm_status gm_graph_union(const gm_graph* parts, int32_t count, void* stream, gm_graph* out);
+
+/* One run recorded in a plan. */
+typedef struct gm_plan_run {
+  gm_graph g;
+  gm_program prog;
+  int32_t batched;     /* 0: a run as gm_run_vertex_program; 1: as gm_run_batched */
+  int32_t max_iters;   /* supersteps recorded. PageRank and PPR run exactly this
+                          many; BFS and SSSP at most this many (1..64): the
+                          supersteps after the frontier empties do nothing */
+  const int32_t* ids;  /* device: frontier ids (BFS, SSSP) or the k sources /
+                          seeds of a batched run; NULL for PageRank and TC */
+  int64_t count;       /* number of ids (k of a batched run) */
+  void* vprop;         /* device output: n entries, or n x k for a batched run */
+} gm_plan_run;
+
+/* Outcome of one recorded run after a launch. */
+typedef struct gm_plan_result {
+  int32_t iters_done;    /* as *iters_done of the corresponding call */
+  int32_t converged;     /* 0 if vertices were still active after max_iters
+                            supersteps (BFS, SSSP); 1 otherwise */
+  int64_t edges_scanned; /* out-edges of the vertices that sent (0 for batched BFS) */
+} gm_plan_result;
+
+typedef struct gm_plan_s* gm_plan;
+
+/*
+ * Record `nruns` runs, in order, as one HIP graph (supersteps of Alg. 2
+ * with the frontier test on the device, so nothing returns to the host
+ * between supersteps); gm_plan_launch replays it with one launch. Each run
+ * initialises its own output: BFS levels INT32_MAX with 0 at the ids, SSSP
+ * distances UINT32_MAX with 0 at the ids, PageRank PR^0 = 1, TC counts 0,
+ * batched runs as gm_run_batched. The ids and outputs must stay allocated
+ * while the plan lives; ids are read at every launch, so new sources may be
+ * written between launches. Plain PPR is not recorded (use a batched run
+ * with k = 1).
+ * A plan holds device addresses of its graphs' workspaces: destroying a
+ * graph, gm_graph_set_tuning, gm_autotune or a call that needs a larger
+ * workspace (a batched run with a larger k) makes it stale, and
+ * gm_plan_launch then fails with GM_ESTATE.
+ * Errors: as the corresponding calls for each run; GM_EINVAL (runs/out
+ * NULL, nruns < 1, max_iters outside [1, 64] for BFS or SSSP, ids NULL
+ * where needed, an id out of range); GM_EUNSUPPORTED (plain PPR); GM_ENOMEM;
+ * GM_EHIP. Synchronises `stream` (capture runs on a library stream).
+ */
+gm_status gm_plan_create(const gm_plan_run* runs, int32_t nruns, void* stream, gm_plan* out);
+
+/* Replay every recorded run on `stream` (one graph launch, asynchronous).
+ * Errors: GM_ESTATE (plan not live, a graph destroyed or its workspace
+ * changed since the plan was created); GM_EHIP. */
+gm_status gm_plan_launch(gm_plan p, void* stream);
+
+/* Copy the outcome of the last launch, one entry per run, to out (host).
+ * Errors: GM_ESTATE, GM_EINVAL (out NULL), GM_EHIP. Synchronises `stream`. */
+gm_status gm_plan_results(gm_plan p, gm_plan_result* out, void* stream);
+
+/* Free the plan. Errors: GM_ESTATE if not live. */
+gm_status gm_plan_destroy(gm_plan p);
+
+/* ------------------------------------------------------------------------ */
+/* Tuning                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Per-graph schedule parameters. None changes any result, only time. */
+typedef struct gm_tuning {
+  uint32_t pull_div;        /* BFS: pull superstep when more than n / pull_div
+                               vertices are active (1..65536; 20) */
+  uint32_t superstep_batch; /* BFS/SSSP: supersteps enqueued between two host
+                               checks of the frontier (1..64; 4) */
+  uint32_t push_blocks;     /* workgroups of the push kernels, plain and batched
+                               SSSP (64..65536; 2048) */
+  uint32_t ppr_chunk;       /* batched PPR: in-edges per work item (64..65536; 512) */
+  uint32_t tc_wave_max;     /* TC: owners with at most this many in-neighbours
+                               use a per-wavefront table (64..1024; 1024) */
+  uint32_t tc_wave_work;    /* TC: partner elements per wavefront work item
+                               (256..2^24; 2^14) */
+  uint32_t tc_block_work;   /* TC: partner elements per workgroup work item
+                               (256..2^26; 2^18) */
+} gm_tuning;
+
+/* Read g's parameters. Errors: GM_ESTATE, GM_EINVAL (out NULL). */
+gm_status gm_graph_get_tuning(gm_graph g, gm_tuning* out);
+
+/* Set g's parameters; workspaces built with other values are rebuilt on
+ * next use. Errors: GM_ESTATE, GM_EINVAL (NULL, a value out of range). */
+gm_status gm_graph_set_tuning(gm_graph g, const gm_tuning* t);
+
+/*
+ * Autotuner: times `prog` on g for candidate values of the parameters that
+ * schedule it and keeps the fastest, one parameter at a time (coordinate
+ * descent; median of `trials` timed runs per candidate after a warm-up run):
+ *   BFS: pull_div, superstep_batch, push_blocks; SSSP: superstep_batch,
+ *   push_blocks; batched SSSP: push_blocks; batched PPR: ppr_chunk;
+ *   TC: tc_wave_max, tc_wave_work, tc_block_work; PageRank and batched BFS
+ *   have no parameters (the current values are returned).
+ * batched selects gm_run_batched semantics with `count` = k sources; ids are
+ * device sources / frontier ids as for the corresponding call (NULL for
+ * PageRank and TC); max_iters as for that call (> 0 for PageRank and PPR).
+ * The library allocates the outputs of the trial runs. chosen (host, may be
+ * NULL) receives the parameters kept, which stay set on g.
+ * Errors: as the corresponding call; GM_EINVAL (trials outside [1, 100]);
+ * GM_ENOMEM; GM_EHIP. Synchronises `stream`.
+ */
+gm_status gm_autotune(gm_graph g, const gm_program* prog, int32_t batched, const int32_t* ids,
+                      int64_t count, int32_t max_iters, int32_t trials, gm_tuning* chosen,
+                      void* stream);
+
 /* Counters of the last gm_run_vertex_program call on a graph. */
 typedef struct gm_run_stats {
   int32_t supersteps;      /* supersteps run (as *iters_done) */

@@ -118,6 +118,33 @@ class Graph:
                    "gm_graph_edges")
         return (src, dst, w) if with_weights else (src, dst)
 
+    @classmethod
+    def union(cls, parts, stream=None) -> "Graph":
+        """gm_graph_union: block-diagonal union; part i's vertex v becomes
+        base_i + v (see ``union_bases``)."""
+        arr = (ctypes.c_void_p * len(parts))(*[p.handle.value for p in parts])
+        out = ctypes.c_void_p()
+        _lib.check(_lib.load().gm_graph_union(arr, len(parts), _stream(stream), ctypes.byref(out)),
+                   "gm_graph_union")
+        return cls(out.value)
+
+    def tuning(self) -> dict:
+        t = _lib.gm_tuning()
+        _lib.check(_lib.load().gm_graph_get_tuning(self.handle, ctypes.byref(t)),
+                   "gm_graph_get_tuning")
+        return {f: int(getattr(t, f)) for f in _lib.TUNING_FIELDS}
+
+    def set_tuning(self, **values) -> None:
+        """gm_graph_set_tuning with the given fields changed."""
+        cur = self.tuning()
+        unknown = set(values) - set(cur)
+        if unknown:
+            raise ValueError("unknown tuning fields: %s" % sorted(unknown))
+        cur.update(values)
+        t = _lib.gm_tuning(*[cur[f] for f in _lib.TUNING_FIELDS])
+        _lib.check(_lib.load().gm_graph_set_tuning(self.handle, ctypes.byref(t)),
+                   "gm_graph_set_tuning")
+
     def last_run_stats(self) -> _lib.gm_run_stats:
         st = _lib.gm_run_stats()
         _lib.check(_lib.load().gm_last_run_stats(self.handle, ctypes.byref(st)),
@@ -173,6 +200,75 @@ def run_batched(g: Graph, kind: int, sources, max_iters: int, vprop_block, r: fl
                                           sources.numel(), max_iters, _ptr(vprop_block),
                                           ctypes.byref(it), _stream(stream)), "gm_run_batched")
     return it.value
+
+
+def union_bases(parts) -> np.ndarray:
+    """First vertex of each part in their union (plus the total at the end)."""
+    return np.concatenate([[0], np.cumsum([p.n for p in parts])]).astype(np.int64)
+
+
+def autotune(g: Graph, kind: int, ids=None, batched: bool = False, max_iters: int = -1,
+             trials: int = 3, r: float = 0.15, stream=None) -> dict:
+    """gm_autotune: times the program for candidate schedule parameters and
+    keeps the fastest on g; returns the parameters kept."""
+    prog = _lib.gm_program(kind, GM_ORDER_OUT, r, 0)
+    t = _lib.gm_tuning()
+    count = 0 if ids is None else ids.numel()
+    _lib.check(_lib.load().gm_autotune(g.handle, ctypes.byref(prog), 1 if batched else 0,
+                                       _ptr(ids), count, max_iters, trials, ctypes.byref(t),
+                                       _stream(stream)), "gm_autotune")
+    return {f: int(getattr(t, f)) for f in _lib.TUNING_FIELDS}
+
+
+class PlanRun:
+    """One run of a Plan: `vprop` is the output tensor the plan initialises;
+    `ids` the device int32 frontier / sources (None for PageRank and TC)."""
+
+    def __init__(self, g: Graph, kind: int, vprop, ids=None, max_iters: int = 64,
+                 batched: bool = False, r: float = 0.15):
+        self.g, self.kind, self.vprop, self.ids = g, kind, vprop, ids
+        self.max_iters, self.batched, self.r = max_iters, batched, r
+
+
+class Plan:
+    """gm_plan_*: runs recorded once as a HIP graph, replayed by launch().
+    Keeps references to its graphs and tensors so they outlive it."""
+
+    def __init__(self, runs, stream=None):
+        self._keep = list(runs)
+        arr = (_lib.gm_plan_run * len(runs))()
+        for i, r in enumerate(runs):
+            arr[i].g = r.g.handle.value
+            arr[i].prog = _lib.gm_program(r.kind, GM_ORDER_OUT, r.r, 0)
+            arr[i].batched = 1 if r.batched else 0
+            arr[i].max_iters = r.max_iters
+            arr[i].ids = _ptr(r.ids)
+            arr[i].count = 0 if r.ids is None else r.ids.numel()
+            arr[i].vprop = _ptr(r.vprop)
+        out = ctypes.c_void_p()
+        _lib.check(_lib.load().gm_plan_create(arr, len(runs), _stream(stream), ctypes.byref(out)),
+                   "gm_plan_create")
+        self._h = out
+
+    def launch(self, stream=None) -> None:
+        _lib.check(_lib.load().gm_plan_launch(self._h, _stream(stream)), "gm_plan_launch")
+
+    def results(self, stream=None):
+        """[(iters_done, converged, edges_scanned)] of the last launch."""
+        res = (_lib.gm_plan_result * len(self._keep))()
+        _lib.check(_lib.load().gm_plan_results(self._h, res, _stream(stream)), "gm_plan_results")
+        return [(r.iters_done, r.converged, r.edges_scanned) for r in res]
+
+    def close(self) -> None:
+        if self._h is not None:
+            _lib.check(_lib.load().gm_plan_destroy(self._h), "gm_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # --------------------------------------------------------------------------

@@ -51,6 +51,25 @@ class gm_run_stats(ctypes.Structure):
                 ("pull_supersteps", ctypes.c_int32), ("edges_scanned", ctypes.c_int64)]
 
 
+class gm_plan_run(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_void_p), ("prog", gm_program), ("batched", ctypes.c_int32),
+                ("max_iters", ctypes.c_int32), ("ids", ctypes.c_void_p), ("count", ctypes.c_int64),
+                ("vprop", ctypes.c_void_p)]
+
+
+class gm_plan_result(ctypes.Structure):
+    _fields_ = [("iters_done", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("edges_scanned", ctypes.c_int64)]
+
+
+TUNING_FIELDS = ("pull_div", "superstep_batch", "push_blocks", "ppr_chunk", "tc_wave_max",
+                 "tc_wave_work", "tc_block_work")
+
+
+class gm_tuning(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint32) for f in TUNING_FIELDS]
+
+
 _lib = None
 
 
@@ -81,6 +100,15 @@ def load():
         "gm_cf_backward": ([vp, i32, vp, vp, ctypes.c_float, ctypes.c_float, vp, vp, vp], i32),
         "gm_pagerank_forward_w": ([vp, vp, ctypes.c_float, i32, vp, vp], i32),
         "gm_pagerank_vjp_w": ([vp, vp, ctypes.c_float, i32, vp, vp, vp, vp], i32),
+        "gm_graph_union": ([vp, i32, vp, ctypes.POINTER(vp)], i32),
+        "gm_plan_create": ([ctypes.POINTER(gm_plan_run), i32, vp, ctypes.POINTER(vp)], i32),
+        "gm_plan_launch": ([vp, vp], i32),
+        "gm_plan_results": ([vp, ctypes.POINTER(gm_plan_result), vp], i32),
+        "gm_plan_destroy": ([vp], i32),
+        "gm_graph_get_tuning": ([vp, ctypes.POINTER(gm_tuning)], i32),
+        "gm_graph_set_tuning": ([vp, ctypes.POINTER(gm_tuning)], i32),
+        "gm_autotune": ([vp, ctypes.POINTER(gm_program), i32, vp, i64, i32, i32,
+                         ctypes.POINTER(gm_tuning), vp], i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)

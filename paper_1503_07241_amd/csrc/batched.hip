@@ -14,7 +14,7 @@
 //    sources that improved v are or-ed into v's next active mask.
 //  - Personalised PageRank (k <= 256): messages are an n x k float block;
 //    one wavefront reduces one destination row (all k seeds at once, lane
-//    l holding seeds l, l + 64, ...), rows longer than kChunk are split
+//    l holding seeds l, l + 64, ...), rows longer than the chunk size are split
 //    into chunks combined by a second kernel, sums in double.
 // Blocks are vertex-major: entry (v, s) at v * k + s.
 #include <algorithm>
@@ -29,7 +29,6 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr uint32_t kInfBfs = 0x7FFFFFFFu;
 constexpr uint32_t kInfDist = 0xFFFFFFFFu;
-constexpr uint32_t kChunk = 512;   // PPR: in-edges per work item
 constexpr int kEdgeUnroll = 4;     // rows in flight per wavefront
 
 inline unsigned blocks_for(int64_t n, int64_t cap = 8192) {
@@ -71,7 +70,9 @@ __global__ __launch_bounds__(kThreads) void bbfs_pull(
     int64_t n, int k, int32_t t, const uint32_t* __restrict__ off, const int32_t* __restrict__ idx,
     const unsigned long long* __restrict__ fr, unsigned long long* __restrict__ vis,
     unsigned long long* __restrict__ fnext, int32_t* __restrict__ level,
-    unsigned int* __restrict__ changed) {
+    const unsigned int* __restrict__ prev, unsigned int* __restrict__ changed) {
+  // a recorded superstep after the one that found nothing new does nothing
+  if (prev && !*prev) return;
   const unsigned long long full = full_mask(k);
   int any = 0;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
@@ -366,7 +367,7 @@ struct Batch {
   // BFS
   unsigned long long* vis = nullptr;
   unsigned long long* fr[2] = {nullptr, nullptr};
-  unsigned int* flag = nullptr;
+  unsigned int* flags = nullptr;  // kMaxPlanSteps "changed" words
   unsigned int* host_flag = nullptr;
   // SSSP
   unsigned long long* act[2] = {nullptr, nullptr};
@@ -375,7 +376,7 @@ struct Batch {
   uint32_t* qest = nullptr;
   uint32_t* qrow = nullptr;
   int64_t qrow_k = 0;
-  BCtl* ctl = nullptr;
+  BCtl* ctl = nullptr;  // kMaxPlanSteps records
   BCtl* host_ctl = nullptr;
   // PPR
   PprItem* items = nullptr;
@@ -383,6 +384,7 @@ struct Batch {
   PprSplit* splits = nullptr;
   int64_t nsplit = 0;
   int64_t npartial = 0;
+  uint32_t items_chunk = 0;  // ppr chunk the items were built with
   double* partial = nullptr;
   int64_t partial_k = 0;
   float* xb[2] = {nullptr, nullptr};
@@ -396,8 +398,21 @@ Batch* ensure_batch(gm_graph g) {
   return batch(g);
 }
 
+void free_ppr_items(gm_graph g, Batch* b) {
+  dfree(b->items);
+  dfree(b->splits);
+  dfree(b->partial);
+  b->items = nullptr;
+  b->splits = nullptr;
+  b->partial = nullptr;
+  b->nitems = b->nsplit = b->npartial = b->partial_k = 0;
+  ++g->ws_gen;
+}
+
 void ensure_ppr_items(gm_graph g, Batch* b, hipStream_t s) {
-  if (b->items) return;
+  const uint32_t chunk = g->tune.ppr_chunk;
+  if (b->items && b->items_chunk == chunk) return;
+  if (b->items) free_ppr_items(g, b);
   const int64_t n = g->n;
   std::vector<uint32_t> off(n + 1);
   GM_HIP(hipMemcpyAsync(off.data(), g->in_off, (n + 1) * 4, hipMemcpyDeviceToHost, s));
@@ -408,17 +423,17 @@ void ensure_ppr_items(gm_graph g, Batch* b, hipStream_t s) {
   // long rows first so they start early
   std::vector<int64_t> order;
   for (int64_t v = 0; v < n; ++v)
-    if (off[v + 1] - off[v] > kChunk) order.push_back(v);
+    if (off[v + 1] - off[v] > chunk) order.push_back(v);
   std::sort(order.begin(), order.end(),
             [&](int64_t a, int64_t c) { return off[a + 1] - off[a] > off[c + 1] - off[c]; });
   std::vector<uint8_t> split(n, 0);
   for (int64_t v : order) {
     split[v] = 1;
-    const uint32_t nch = (off[v + 1] - off[v] + kChunk - 1) / kChunk;
+    const uint32_t nch = (off[v + 1] - off[v] + chunk - 1) / chunk;
     splits.push_back({(uint32_t)v, (uint32_t)np, nch, 0});
     for (uint32_t c = 0; c < nch; ++c) {
-      const uint32_t eb = off[v] + c * kChunk;
-      items.push_back({(uint32_t)v, eb, std::min(eb + kChunk, off[v + 1]), np++});
+      const uint32_t eb = off[v] + c * chunk;
+      items.push_back({(uint32_t)v, eb, std::min(eb + chunk, off[v + 1]), np++});
     }
   }
   for (int64_t v = 0; v < n; ++v)
@@ -426,6 +441,7 @@ void ensure_ppr_items(gm_graph g, Batch* b, hipStream_t s) {
   b->nitems = (int64_t)items.size();
   b->nsplit = (int64_t)splits.size();
   b->npartial = np;
+  b->items_chunk = chunk;
   b->items = dalloc<PprItem>(items.size());
   b->splits = dalloc<PprSplit>(splits.size());
   GM_HIP(hipMemcpyAsync(b->items, items.data(), items.size() * sizeof(PprItem),
@@ -436,6 +452,181 @@ void ensure_ppr_items(gm_graph g, Batch* b, hipStream_t s) {
   GM_HIP(hipStreamSynchronize(s));
 }
 
+void ensure_bfs_ws(Batch* b, int64_t n) {
+  if (b->vis) return;
+  b->vis = dalloc<unsigned long long>(n);
+  b->fr[0] = dalloc<unsigned long long>(n);
+  b->fr[1] = dalloc<unsigned long long>(n);
+  b->flags = dalloc<unsigned int>(kMaxPlanSteps);
+  void* h = nullptr;
+  GM_HIP(hipHostMalloc(&h, sizeof(unsigned int), hipHostMallocDefault));
+  b->host_flag = static_cast<unsigned int*>(h);
+}
+
+void ensure_sssp_ws(gm_graph g, Batch* b, int k) {
+  const int64_t n = g->n;
+  if (!b->act[0]) {
+    b->act[0] = dalloc<unsigned long long>(2 * n);  // both masks in one buffer
+    b->act[1] = b->act[0] + n;
+    b->q = dalloc<int32_t>(n);
+    b->qbeg = dalloc<uint32_t>(n);
+    b->qest = dalloc<uint32_t>(n);
+    b->ctl = dalloc<BCtl>(kMaxPlanSteps);
+    void* h = nullptr;
+    GM_HIP(hipHostMalloc(&h, sizeof(BCtl), hipHostMallocDefault));
+    b->host_ctl = static_cast<BCtl*>(h);
+  }
+  if (b->qrow_k < k) {
+    dfree(b->qrow);
+    b->qrow = nullptr;
+    ++g->ws_gen;
+    b->qrow = dalloc<uint32_t>((size_t)n * k);
+    b->qrow_k = k;
+  }
+}
+
+void ensure_ppr_ws(gm_graph g, Batch* b, int k, hipStream_t s) {
+  const int64_t n = g->n;
+  ensure_ppr_items(g, b, s);
+  if (b->xb_k < k) {
+    dfree(b->xb[0]);
+    dfree(b->xb[1]);
+    b->xb[0] = b->xb[1] = nullptr;
+    ++g->ws_gen;
+    b->xb[0] = dalloc<float>((size_t)n * k);
+    b->xb[1] = dalloc<float>((size_t)n * k);
+    b->xb_k = k;
+  }
+  if (b->partial_k < k) {
+    dfree(b->partial);
+    b->partial = nullptr;
+    ++g->ws_gen;
+    b->partial = dalloc<double>((size_t)b->npartial * k);
+    b->partial_k = k;
+  }
+}
+
+// Pull adjacency of batched BFS: the out-lists of a symmetrised graph, else
+// the in-lists.
+void bfs_adjacency(gm_graph g, const uint32_t** off, const int32_t** idx) {
+  const bool sym = (g->prep & (GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG)) == GM_PREP_SYMMETRIZE;
+  *off = sym ? g->out_off : g->in_off;
+  *idx = sym ? g->out_idx : g->in_idx;
+}
+
+void bfs_init(gm_graph g, Batch* b, const int32_t* sources, int k, int32_t* level, hipStream_t s) {
+  const int64_t n = g->n;
+  bbfs_init<<<blocks_for(n * k), kThreads, 0, s>>>(n, k, sources, level, b->vis, b->fr[0]);
+  bbfs_seed<<<1, 64, 0, s>>>(k, sources, level, b->vis, b->fr[0]);
+  GM_HIP(hipGetLastError());
+}
+
+void bfs_superstep(gm_graph g, Batch* b, int k, int32_t t, int cur, int32_t* level,
+                   const unsigned int* prev, unsigned int* changed, hipStream_t s) {
+  const uint32_t* off;
+  const int32_t* idx;
+  bfs_adjacency(g, &off, &idx);
+  bbfs_pull<<<blocks_for(g->n), kThreads, 0, s>>>(g->n, k, t, off, idx, b->fr[cur], b->vis,
+                                                  b->fr[cur ^ 1], level, prev, changed);
+  GM_HIP(hipGetLastError());
+}
+
+void sssp_init(gm_graph g, Batch* b, const int32_t* sources, int k, uint32_t* dist,
+               hipStream_t s) {
+  const int64_t n = g->n;
+  bsssp_init<<<blocks_for(n * k), kThreads, 0, s>>>(n, k, dist, b->act[0], b->act[1]);
+  bsssp_seed<<<1, 64, 0, s>>>(k, sources, dist, b->act[0]);
+  GM_HIP(hipGetLastError());
+}
+
+void sssp_superstep(gm_graph g, Batch* b, int k, int cur, BCtl* ctl, uint32_t* dist,
+                    hipStream_t s) {
+  const int64_t n = g->n;
+  reset_bctl<<<1, 1, 0, s>>>(ctl);
+  bsssp_send<<<blocks_for(n, 4096), kThreads, 0, s>>>(n, k, b->act[cur], dist, g->out_off, b->q,
+                                                      b->qbeg, b->qest, b->qrow, ctl);
+  bsssp_push<<<g->tune.push_blocks, kThreads, 0, s>>>(
+      k, ctl, b->qbeg, b->qest, b->qrow, g->out_idx, static_cast<const uint32_t*>(g->out_w), dist,
+      b->act[cur ^ 1]);
+  GM_HIP(hipGetLastError());
+}
+
+void ppr_supersteps(gm_graph g, Batch* b, const int32_t* seeds, int k, float r, int32_t iters,
+                    float* out, hipStream_t s) {
+  const int64_t n = g->n;
+  bppr_init<<<blocks_for(n * k, 65536), kThreads, 0, s>>>(n, k, seeds, g->inv_outdeg, b->xb[0]);
+  GM_HIP(hipGetLastError());
+  const unsigned gi = (unsigned)((b->nitems + kWaves - 1) / kWaves);
+  const unsigned gs = (unsigned)((b->nsplit + kWaves - 1) / kWaves);
+  for (int32_t it = 0; it < iters; ++it) {
+    const float* xin = b->xb[it & 1];
+    float* xo = b->xb[(it + 1) & 1];
+    float* po = it == iters - 1 ? out : nullptr;
+    auto launch = [&](auto pull, auto finish) {
+      if (gi > 0)
+        pull<<<gi, kThreads, 0, s>>>(k, b->items, b->nitems, g->in_idx, xin, g->inv_outdeg, seeds,
+                                     r, xo, po, b->partial);
+      if (b->nsplit > 0)
+        finish<<<gs, kThreads, 0, s>>>(k, b->splits, b->nsplit, b->partial, g->inv_outdeg, seeds,
+                                       r, xo, po);
+    };
+    if (k <= 64)
+      launch(bppr_pull<1>, bppr_finish<1>);
+    else if (k <= 128)
+      launch(bppr_pull<2>, bppr_finish<2>);
+    else
+      launch(bppr_pull<4>, bppr_finish<4>);
+    GM_HIP(hipGetLastError());
+  }
+}
+
+// Outcome of recorded batched BFS supersteps: superstep t found nothing new
+// iff changed[t] == 0 (that superstep still counts, as in the plain run).
+__global__ void bbfs_summary(const unsigned int* __restrict__ changed, int32_t steps,
+                             PlanResult* res) {
+  int32_t it = steps, conv = 0;
+  for (int32_t t = 0; t < steps; ++t)
+    if (!changed[t]) {
+      it = t + 1;
+      conv = 1;
+      break;
+    }
+  res->iters = it;
+  res->converged = conv;
+  res->edges = 0;
+}
+
+// Outcome of recorded batched SSSP supersteps: the first superstep with no
+// active vertex ends the run.
+__global__ void bsssp_summary(const BCtl* __restrict__ ctl, int32_t steps, PlanResult* res) {
+  int32_t it = steps;
+  unsigned long long e = 0;
+  for (int32_t t = 0; t < steps; ++t) {
+    if ((ctl[t].packed >> 32) == 0) {
+      it = t;
+      break;
+    }
+    e += (uint32_t)ctl[t].packed;
+  }
+  res->iters = it;
+  res->converged = 1;  // cleared by bsssp_finish if a vertex is still active
+  res->edges = e;
+}
+
+// The run converged iff no vertex is left active; both masks are cleared for
+// the next run. Every writer stores 0.
+__global__ void bsssp_finish(unsigned long long* act, int64_t words, int32_t* converged) {
+  bool any = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (act[i]) {
+      any = true;
+      act[i] = 0;
+    }
+  }
+  if (any) *converged = 0;
+}
+
 }  // namespace
 
 void free_batch(gm_graph g) {
@@ -444,10 +635,9 @@ void free_batch(gm_graph g) {
   dfree(b->vis);
   dfree(b->fr[0]);
   dfree(b->fr[1]);
-  dfree(b->flag);
+  dfree(b->flags);
   if (b->host_flag) (void)hipHostFree(b->host_flag);
   dfree(b->act[0]);
-  dfree(b->act[1]);
   dfree(b->q);
   dfree(b->qbeg);
   dfree(b->qest);
@@ -461,36 +651,21 @@ void free_batch(gm_graph g) {
   dfree(b->xb[1]);
   delete b;
   g->batch_ws = nullptr;
+  ++g->ws_gen;
 }
 
 int32_t run_batched_bfs(gm_graph g, const int32_t* sources, int k, int32_t max_iters,
                         int32_t* level, hipStream_t s) {
   Batch* b = ensure_batch(g);
-  const int64_t n = g->n;
-  if (!b->vis) {
-    b->vis = dalloc<unsigned long long>(n);
-    b->fr[0] = dalloc<unsigned long long>(n);
-    b->fr[1] = dalloc<unsigned long long>(n);
-    b->flag = dalloc<unsigned int>(1);
-    void* h = nullptr;
-    GM_HIP(hipHostMalloc(&h, sizeof(unsigned int), hipHostMallocDefault));
-    b->host_flag = static_cast<unsigned int*>(h);
-  }
-  const bool sym = (g->prep & (GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG)) == GM_PREP_SYMMETRIZE;
-  const uint32_t* off = sym ? g->out_off : g->in_off;
-  const int32_t* idx = sym ? g->out_idx : g->in_idx;
-  bbfs_init<<<blocks_for(n * k), kThreads, 0, s>>>(n, k, sources, level, b->vis, b->fr[0]);
-  bbfs_seed<<<1, 64, 0, s>>>(k, sources, level, b->vis, b->fr[0]);
-  GM_HIP(hipGetLastError());
+  ensure_bfs_ws(b, g->n);
+  bfs_init(g, b, sources, k, level, s);
   int cur = 0;
   int32_t t = 0;
   for (;; ++t) {
     if (max_iters > 0 && t >= max_iters) break;
-    fill_u32(b->flag, 1, 0u, s);
-    bbfs_pull<<<blocks_for(n), kThreads, 0, s>>>(n, k, t, off, idx, b->fr[cur], b->vis,
-                                                 b->fr[cur ^ 1], level, b->flag);
-    GM_HIP(hipGetLastError());
-    GM_HIP(hipMemcpyAsync(b->host_flag, b->flag, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    fill_u32(b->flags, 1, 0u, s);
+    bfs_superstep(g, b, k, t, cur, level, nullptr, b->flags, s);
+    GM_HIP(hipMemcpyAsync(b->host_flag, b->flags, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
     cur ^= 1;
     if (!*b->host_flag) {
@@ -504,45 +679,20 @@ int32_t run_batched_bfs(gm_graph g, const int32_t* sources, int k, int32_t max_i
 int32_t run_batched_sssp(gm_graph g, const int32_t* sources, int k, int32_t max_iters,
                          uint32_t* dist, hipStream_t s) {
   Batch* b = ensure_batch(g);
-  const int64_t n = g->n;
-  if (!b->act[0]) {
-    b->act[0] = dalloc<unsigned long long>(n);
-    b->act[1] = dalloc<unsigned long long>(n);
-    b->q = dalloc<int32_t>(n);
-    b->qbeg = dalloc<uint32_t>(n);
-    b->qest = dalloc<uint32_t>(n);
-    b->ctl = dalloc<BCtl>(1);
-    void* h = nullptr;
-    GM_HIP(hipHostMalloc(&h, sizeof(BCtl), hipHostMallocDefault));
-    b->host_ctl = static_cast<BCtl*>(h);
-  }
-  if (b->qrow_k < k) {
-    dfree(b->qrow);
-    b->qrow = nullptr;
-    b->qrow = dalloc<uint32_t>((size_t)n * k);
-    b->qrow_k = k;
-  }
-  bsssp_init<<<blocks_for(n * k), kThreads, 0, s>>>(n, k, dist, b->act[0], b->act[1]);
-  bsssp_seed<<<1, 64, 0, s>>>(k, sources, dist, b->act[0]);
-  GM_HIP(hipGetLastError());
+  ensure_sssp_ws(g, b, k);
+  sssp_init(g, b, sources, k, dist, s);
   int cur = 0;
   int32_t t = 0;
-  const uint32_t* w = static_cast<const uint32_t*>(g->out_w);
   for (;; ++t) {
     if (max_iters > 0 && t >= max_iters) break;
-    reset_bctl<<<1, 1, 0, s>>>(b->ctl);
-    bsssp_send<<<blocks_for(n, 4096), kThreads, 0, s>>>(n, k, b->act[cur], dist, g->out_off, b->q,
-                                                        b->qbeg, b->qest, b->qrow, b->ctl);
-    bsssp_push<<<2048, kThreads, 0, s>>>(k, b->ctl, b->qbeg, b->qest, b->qrow, g->out_idx, w, dist,
-                                         b->act[cur ^ 1]);
-    GM_HIP(hipGetLastError());
+    sssp_superstep(g, b, k, cur, b->ctl, dist, s);
     GM_HIP(hipMemcpyAsync(b->host_ctl, b->ctl, sizeof(BCtl), hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
     cur ^= 1;
     if ((b->host_ctl->packed >> 32) == 0) break;  // no vertex was active
   }
   // leave the workspace cleared for the next run
-  fill_u32(reinterpret_cast<uint32_t*>(b->act[cur]), 2 * n, 0u, s);
+  fill_u32(reinterpret_cast<uint32_t*>(b->act[0]), 4 * g->n, 0u, s);
   GM_HIP(hipStreamSynchronize(s));
   return t;
 }
@@ -550,45 +700,55 @@ int32_t run_batched_sssp(gm_graph g, const int32_t* sources, int k, int32_t max_
 void run_batched_ppr(gm_graph g, const int32_t* seeds, int k, float r, int32_t iters, float* out,
                      hipStream_t s) {
   Batch* b = ensure_batch(g);
-  const int64_t n = g->n;
-  ensure_ppr_items(g, b, s);
-  if (b->xb_k < k) {
-    dfree(b->xb[0]);
-    dfree(b->xb[1]);
-    b->xb[0] = b->xb[1] = nullptr;
-    b->xb[0] = dalloc<float>((size_t)n * k);
-    b->xb[1] = dalloc<float>((size_t)n * k);
-    b->xb_k = k;
+  ensure_ppr_ws(g, b, k, s);
+  ppr_supersteps(g, b, seeds, k, r, iters, out, s);
+}
+
+void prepare_batched(gm_graph g, int kind, int k, hipStream_t s) {
+  Batch* b = ensure_batch(g);
+  if (kind == GM_PROG_BFS)
+    ensure_bfs_ws(b, g->n);
+  else if (kind == GM_PROG_SSSP)
+    ensure_sssp_ws(g, b, k);
+  else
+    ensure_ppr_ws(g, b, k, s);
+  GM_HIP(hipStreamSynchronize(s));
+}
+
+void enqueue_batched(gm_graph g, int kind, const int32_t* sources, int k, int32_t steps, float r,
+                     void* block, PlanResult* res, hipStream_t s) {
+  Batch* b = batch(g);
+  if (!b || steps < 1) throw Unsupported{"captured run not prepared"};
+  if (kind == GM_PROG_BFS) {
+    if (!b->vis || steps > kMaxPlanSteps) throw Unsupported{"captured run not prepared"};
+    int32_t* level = static_cast<int32_t*>(block);
+    bfs_init(g, b, sources, k, level, s);
+    fill_u32(b->flags, steps, 0u, s);
+    int cur = 0;
+    for (int32_t t = 0; t < steps; ++t) {
+      bfs_superstep(g, b, k, t, cur, level, t > 0 ? b->flags + t - 1 : nullptr, b->flags + t, s);
+      cur ^= 1;
+    }
+    bbfs_summary<<<1, 1, 0, s>>>(b->flags, steps, res);
+  } else if (kind == GM_PROG_SSSP) {
+    if (!b->act[0] || b->qrow_k < k || steps > kMaxPlanSteps)
+      throw Unsupported{"captured run not prepared"};
+    uint32_t* dist = static_cast<uint32_t*>(block);
+    sssp_init(g, b, sources, k, dist, s);
+    int cur = 0;
+    for (int32_t t = 0; t < steps; ++t) {
+      sssp_superstep(g, b, k, cur, b->ctl + t, dist, s);
+      cur ^= 1;
+    }
+    bsssp_summary<<<1, 1, 0, s>>>(b->ctl, steps, res);
+    // all supersteps used: converged only if nothing is left active
+    bsssp_finish<<<blocks_for(2 * g->n), kThreads, 0, s>>>(b->act[0], 2 * g->n, &res->converged);
+  } else {
+    if (!b->items || b->xb_k < k || b->partial_k < k) throw Unsupported{"captured run not prepared"};
+    ppr_supersteps(g, b, sources, k, r, steps, static_cast<float*>(block), s);
+    set_plan_result(res, steps, (unsigned long long)g->m * steps, s);
   }
-  if (b->partial_k < k) {
-    dfree(b->partial);
-    b->partial = nullptr;
-    b->partial = dalloc<double>((size_t)b->npartial * k);
-    b->partial_k = k;
-  }
-  bppr_init<<<blocks_for(n * k, 65536), kThreads, 0, s>>>(n, k, seeds, g->inv_outdeg, b->xb[0]);
   GM_HIP(hipGetLastError());
-  const unsigned gi = (unsigned)((b->nitems + kWaves - 1) / kWaves);
-  const unsigned gs = (unsigned)((b->nsplit + kWaves - 1) / kWaves);
-  for (int32_t it = 0; it < iters; ++it) {
-    const float* xin = b->xb[it & 1];
-    float* xo = b->xb[(it + 1) & 1];
-    float* po = it == iters - 1 ? out : nullptr;
-    auto launch = [&](auto pull, auto finish) {
-      pull<<<gi, kThreads, 0, s>>>(k, b->items, b->nitems, g->in_idx, xin, g->inv_outdeg, seeds, r,
-                                   xo, po, b->partial);
-      if (b->nsplit > 0)
-        finish<<<gs, kThreads, 0, s>>>(k, b->splits, b->nsplit, b->partial, g->inv_outdeg, seeds,
-                                       r, xo, po);
-    };
-    if (k <= 64)
-      launch(bppr_pull<1>, bppr_finish<1>);
-    else if (k <= 128)
-      launch(bppr_pull<2>, bppr_finish<2>);
-    else
-      launch(bppr_pull<4>, bppr_finish<4>);
-    GM_HIP(hipGetLastError());
-  }
 }
 
 }  // namespace gm

@@ -322,6 +322,7 @@ void free_cf_plan(gm_graph g) {
   dfree(p->loss_part);
   delete p;
   g->cf_plan = nullptr;
+  ++g->ws_gen;
 }
 
 void build_bipartite(gm_graph g, const int32_t* row, const int32_t* col, const uint8_t* val,

@@ -76,23 +76,6 @@ void graph_unregister(gm_graph g) {
   if (g_reg) g_reg->erase(g);
 }
 
-template <class F>
-gm_status guarded(F&& f) {
-  try {
-    return f();
-  } catch (const OutOfMemory& e) {
-    return fail(GM_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
-  } catch (const Unsupported& e) {
-    return fail(GM_EUNSUPPORTED, "%s", e.what);
-  } catch (const HipError& e) {
-    return fail(GM_EHIP, "%s: %s (%s:%d)", e.what, hipGetErrorString(e.err), __FILE__, e.line);
-  } catch (const std::bad_alloc&) {
-    return fail(GM_ENOMEM, "host allocation failed");
-  } catch (...) {
-    return fail(GM_EHIP, "unexpected internal error");
-  }
-}
-
 }  // namespace gm
 
 using namespace gm;

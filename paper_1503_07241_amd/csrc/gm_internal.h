@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <new>
 #include <string>
 
 #include "gm.h"
@@ -64,7 +65,26 @@ struct Tuning {
   uint32_t pull_div = 20;
   // supersteps launched between two host checks of the frontier size
   uint32_t superstep_batch = 4;
+  // workgroups of the push kernels (plain and batched SSSP)
+  uint32_t push_blocks = 2048;
+  // batched PPR: in-edges per work item
+  uint32_t ppr_chunk = 512;
+  // TC: owners whose in-list is at most this long use a per-wavefront table
+  uint32_t tc_wave_max = 1024;
+  // TC: partner-list elements per wavefront / workgroup work item
+  uint32_t tc_wave_work = 1u << 14;
+  uint32_t tc_block_work = 1u << 18;
 };
+
+// Per-run outcome recorded on the device by a captured plan.
+struct PlanResult {
+  int32_t iters;       // supersteps that started with an active vertex
+  int32_t converged;   // 1 if no vertex was left active
+  unsigned long long edges;  // out-edges of the vertices that sent
+};
+
+// Most supersteps a captured BFS/SSSP run records.
+constexpr int kMaxPlanSteps = 64;
 
 }  // namespace gm
 
@@ -104,11 +124,33 @@ struct gm_graph_s {
   uint8_t* in_val = nullptr;
   gm::RunStats last_stats;
   gm::Tuning tune;
+  // Bumped whenever a workspace buffer is freed or replaced, so that captured
+  // plans holding its address can tell they are stale.
+  uint64_t ws_gen = 0;
 };
 
 namespace gm {
 
 constexpr uint64_t kGraphMagic = 0x4752'4150'484d'4154ull;  // "GRAPHMAT"
+
+// Runs f, turning the library's exceptions into a status and message.
+template <class F>
+gm_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const OutOfMemory& e) {
+    return fail(GM_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
+  } catch (const Unsupported& e) {
+    return fail(GM_EUNSUPPORTED, "%s", e.what);
+  } catch (const HipError& e) {
+    return fail(GM_EHIP, "%s: %s (%s:%d)", e.what, hipGetErrorString(e.err), __FILE__, e.line);
+  } catch (const std::bad_alloc&) {
+    return fail(GM_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(GM_EHIP, "unexpected internal error");
+  }
+}
+
 
 // Handle registry (graph handles are validated on every call).
 bool graph_live(gm_graph g);
@@ -163,6 +205,28 @@ void run_pagerank_history(gm_graph g, const float* w, float r, int32_t T, float*
 void run_pagerank_vjp(gm_graph g, const float* w, float r, int32_t T, const float* hist,
                       const float* grad_out, float* grad_w, hipStream_t s);
 void free_vjp_plan(gm_graph g);
+
+// Captured-run building blocks (no allocation, no host synchronisation once
+// the prepare_* call for the same graph and shape has run).
+void prepare_min_program(gm_graph g, hipStream_t s);
+void enqueue_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count, int32_t steps,
+                         uint32_t* prop, PlanResult* res, hipStream_t s);
+void prepare_batched(gm_graph g, int kind, int k, hipStream_t s);
+void enqueue_batched(gm_graph g, int kind, const int32_t* sources, int k, int32_t steps, float r,
+                     void* block, PlanResult* res, hipStream_t s);
+void prepare_triangle_count(gm_graph g, hipStream_t s);
+void enqueue_pagerank(gm_graph g, float r, int32_t iters, float* rank, hipStream_t s);
+// res <- {iters, 1, edges}
+void set_plan_result(PlanResult* res, int32_t iters, unsigned long long edges, hipStream_t s);
+void fill_f32(float* p, int64_t n, float v, hipStream_t s);
+
+// Tuning checks and the scratch-output runs of the autotuner (plan.hip,
+// minprog.hip).
+void init_min_prop(gm_graph g, int kind, const int32_t* ids, int64_t count, uint32_t* prop,
+                   hipStream_t s);
+
+// Block-diagonal union of graphs (union.hip).
+void build_union(gm_graph u, const gm_graph* parts, int32_t count, hipStream_t s);
 
 // Fill n uint32 words with v on stream s (a kernel, safe under graph capture).
 void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);

@@ -36,7 +36,6 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kPushBlocks = 2048;
 constexpr int kUnroll = 4;  // edge rounds in flight per wavefront
 constexpr uint32_t kInfBfs = 0x7FFFFFFFu;
 constexpr int kMaxCtl = 64;  // control records per launch batch
@@ -375,6 +374,7 @@ void free_min_workspace(gm_graph g) {
   if (ws->host_ctl) (void)hipHostFree(ws->host_ctl);
   delete ws;
   g->min_ws = nullptr;
+  ++g->ws_gen;
 }
 
 bool ids_in_range(const int32_t* ids, int64_t count, int64_t n, hipStream_t s) {
@@ -395,10 +395,12 @@ bool ids_in_range(const int32_t* ids, int64_t count, int64_t n, hipStream_t s) {
   return h == 0;
 }
 
-int32_t run_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count,
-                        int32_t max_iters, uint32_t* prop, int32_t* active_out, hipStream_t s,
-                        RunStats* stats) {
-  Workspace* ws = ensure_ws(g, s);
+namespace {
+
+// One superstep on control record c: SEND from bits[cur], then the push or
+// the pull product into bits[cur ^ 1]; bits[cur] is cleared afterwards.
+void enqueue_superstep(gm_graph g, Workspace* ws, int kind, Ctl* c, int cur, uint32_t* prop,
+                       hipStream_t s) {
   const int64_t n = g->n;
   const int64_t words = (n + 31) / 32;
   const bool sym = (g->prep & (GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG)) == GM_PREP_SYMMETRIZE;
@@ -406,9 +408,118 @@ int32_t run_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count,
   const int32_t* pull_idx = sym ? g->out_idx : g->in_idx;
   const bool pull_ok = kind == GM_PROG_BFS && pull_off != nullptr;
   const uint32_t pull_div = g->tune.pull_div;
+  const unsigned push_blocks = g->tune.push_blocks;
+  reset_ctl<<<1, 1, 0, s>>>(c);
+  send_kernel<<<blocks_for(words, 4096), kThreads, 0, s>>>(ws->bits[cur], words, prop, g->out_off,
+                                                           ws->q, ws->qmsg, ws->qbeg, ws->qest, c);
+  if (kind == GM_PROG_SSSP)
+    push_kernel<GM_PROG_SSSP><<<push_blocks, kThreads, 0, s>>>(
+        c, n, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, g->out_idx,
+        static_cast<const uint32_t*>(g->out_w), prop, ws->bits[cur ^ 1]);
+  else
+    push_kernel<GM_PROG_BFS><<<push_blocks, kThreads, 0, s>>>(
+        c, n, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, g->out_idx, nullptr, prop,
+        ws->bits[cur ^ 1]);
+  if (pull_ok)
+    pull_kernel<<<blocks_for(n, 8192), kThreads, 0, s>>>(c, n, pull_ok, pull_div, pull_off, pull_idx,
+                                                         ws->bits[cur], prop, ws->bits[cur ^ 1]);
+  fill_kernel<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[cur], words, 0);
+  GM_HIP(hipGetLastError());
+}
+
+// prop[v] = 0 and v active, for every id.
+__global__ void seed_sources(const int32_t* __restrict__ ids, int64_t count, uint32_t* prop,
+                             uint32_t* bits) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = ids[i];
+    prop[v] = 0;
+    atomicOr(&bits[v >> 5], 1u << (v & 31));
+  }
+}
+
+__global__ void set_zero(const int32_t* __restrict__ ids, int64_t count, uint32_t* prop) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    prop[ids[i]] = 0;
+}
+
+// Outcome of `steps` recorded supersteps (one thread).
+__global__ void min_summary(const Ctl* __restrict__ ctl, int32_t steps, PlanResult* res) {
+  int32_t it = 0;
+  unsigned long long e = 0;
+  for (int32_t b = 0; b < steps; ++b) {
+    if ((ctl[b].packed >> 32) == 0) break;
+    ++it;
+    e += (uint32_t)ctl[b].packed;
+  }
+  res->iters = it;
+  res->converged = 1;
+  res->edges = e;
+}
+
+// A frontier left after the last recorded superstep means the run did not
+// converge; the frontier is cleared either way. Every writer stores 0.
+__global__ void bits_finish(uint32_t* bits, int64_t words, int32_t* converged) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (bits[i]) {
+      *converged = 0;
+      bits[i] = 0;
+    }
+  }
+}
+
+}  // namespace
+
+void prepare_min_program(gm_graph g, hipStream_t s) {
+  ensure_ws(g, s);
+  GM_HIP(hipStreamSynchronize(s));
+}
+
+void enqueue_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count, int32_t steps,
+                         uint32_t* prop, PlanResult* res, hipStream_t s) {
+  Workspace* ws = static_cast<Workspace*>(g->min_ws);
+  if (!ws || steps < 1 || steps > kMaxCtl) throw Unsupported{"captured run not prepared"};
+  const int64_t n = g->n;
+  const int64_t words = (n + 31) / 32;
+  fill_kernel<<<blocks_for(n), kThreads, 0, s>>>(prop, n,
+                                                 kind == GM_PROG_SSSP ? 0xFFFFFFFFu : kInfBfs);
+  if (count > 0)
+    seed_sources<<<blocks_for(count), kThreads, 0, s>>>(ids, count, prop, ws->bits[0]);
+  GM_HIP(hipGetLastError());
+  int cur = 0;
+  for (int32_t b = 0; b < steps; ++b) {
+    enqueue_superstep(g, ws, kind, ws->ctl + b, cur, prop, s);
+    cur ^= 1;
+  }
+  min_summary<<<1, 1, 0, s>>>(ws->ctl, steps, res);
+  bits_finish<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[cur], words, &res->converged);
+  GM_HIP(hipGetLastError());
+}
+
+// Property array of a fresh run: unreached everywhere, 0 at the ids (their
+// frontier bits are set by the run itself).
+void init_min_prop(gm_graph g, int kind, const int32_t* ids, int64_t count, uint32_t* prop,
+                   hipStream_t s) {
+  const int64_t n = g->n;
+  fill_kernel<<<blocks_for(n), kThreads, 0, s>>>(prop, n,
+                                                 kind == GM_PROG_SSSP ? 0xFFFFFFFFu : kInfBfs);
+  if (count > 0) set_zero<<<blocks_for(count), kThreads, 0, s>>>(ids, count, prop);
+  GM_HIP(hipGetLastError());
+}
+
+int32_t run_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count,
+                        int32_t max_iters, uint32_t* prop, int32_t* active_out, hipStream_t s,
+                        RunStats* stats) {
+  Workspace* ws = ensure_ws(g, s);
+  const int64_t n = g->n;
+  const int64_t words = (n + 31) / 32;
+  const bool sym = (g->prep & (GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG)) == GM_PREP_SYMMETRIZE;
+  const bool pull_ok = kind == GM_PROG_BFS && (sym ? g->out_off : g->in_off) != nullptr;
+  const uint32_t pull_div = g->tune.pull_div;
   int32_t batch = (int32_t)g->tune.superstep_batch;
   if (batch < 1) batch = 1;
-  const uint32_t* w = static_cast<const uint32_t*>(g->out_w);
   int cur = 0;
   if (count > 0) {
     seed_bits<<<blocks_for(count), kThreads, 0, s>>>(ids, count, ws->bits[0]);
@@ -417,30 +528,12 @@ int32_t run_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count,
   int32_t iters = 0;
   RunStats st{};
   bool done = count == 0;
-  const unsigned send_blocks = blocks_for(words, 4096);
-  const unsigned pull_blocks = blocks_for(n, 8192);
   while (!done) {
     int32_t nb = batch;
     if (max_iters > 0 && max_iters - iters < nb) nb = max_iters - iters;
     if (nb > kMaxCtl) nb = kMaxCtl;
     for (int32_t b = 0; b < nb; ++b) {
-      Ctl* c = ws->ctl + b;
-      reset_ctl<<<1, 1, 0, s>>>(c);
-      send_kernel<<<send_blocks, kThreads, 0, s>>>(ws->bits[cur], words, prop, g->out_off, ws->q,
-                                                   ws->qmsg, ws->qbeg, ws->qest, c);
-      if (kind == GM_PROG_SSSP)
-        push_kernel<GM_PROG_SSSP><<<kPushBlocks, kThreads, 0, s>>>(
-            c, n, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, g->out_idx, w, prop,
-            ws->bits[cur ^ 1]);
-      else
-        push_kernel<GM_PROG_BFS><<<kPushBlocks, kThreads, 0, s>>>(
-            c, n, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, g->out_idx, nullptr, prop,
-            ws->bits[cur ^ 1]);
-      if (pull_ok)
-        pull_kernel<<<pull_blocks, kThreads, 0, s>>>(c, n, pull_ok, pull_div, pull_off, pull_idx,
-                                                     ws->bits[cur], prop, ws->bits[cur ^ 1]);
-      fill_kernel<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[cur], words, 0);
-      GM_HIP(hipGetLastError());
+      enqueue_superstep(g, ws, kind, ws->ctl + b, cur, prop, s);
       cur ^= 1;
     }
     GM_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, nb * sizeof(Ctl), hipMemcpyDeviceToHost, s));

@@ -330,6 +330,7 @@ void free_pull_schedule(gm_graph g) {
   dfree(d->partial);
   delete d;
   g->pr_sched = nullptr;
+  ++g->ws_gen;
 }
 
 void ensure_pull_schedule(gm_graph g, hipStream_t st) {
@@ -526,6 +527,16 @@ void run_pagerank(gm_graph g, float r, int32_t iters, float* rank, int32_t seed,
   }
   pagerank_driver(g, d, r, iters, rank, seed_new, g->wtype == GM_W_F32 ? d->w : nullptr, nullptr,
                   rank, st);
+}
+
+// PR^0 = 1 for every vertex, then `iters` supersteps (no allocation and no
+// host synchronisation once the pull schedule exists).
+void enqueue_pagerank(gm_graph g, float r, int32_t iters, float* rank, hipStream_t st) {
+  Dense* d = dense(g);
+  if (!d) throw Unsupported{"captured run not prepared"};
+  fill_f32(rank, g->n, 1.0f, st);
+  pagerank_driver(g, d, r, iters, rank, -1, g->wtype == GM_W_F32 ? d->w : nullptr, nullptr, rank,
+                  st);
 }
 
 void run_pagerank_history(gm_graph g, const float* w, float r, int32_t T, float* hist,

@@ -285,6 +285,7 @@ void free_vjp_plan(gm_graph g) {
   dfree(p->abar[1]);
   delete p;
   g->vjp_plan = nullptr;
+  ++g->ws_gen;
 }
 
 void run_pagerank_vjp(gm_graph g, const float* w, float r, int32_t T, const float* hist,

@@ -32,8 +32,6 @@ constexpr uint32_t kWaveMax = 1024;          // owners with |in(x)| <= this: LDS
 constexpr uint32_t kBlockMax = 8192;         // owners up to this: LDS table per workgroup
 constexpr uint32_t kWaveSlots = 2048;
 constexpr uint32_t kBlockSlots = 16384;      // 64 KB
-constexpr uint32_t kWaveWork = 1u << 14;     // partner elements per wavefront work item
-constexpr uint32_t kBlockWork = 1u << 18;    // per workgroup work item
 constexpr uint32_t kCreditPartner = 0x80000000u;  // partner entry flag: credit goes to it
 constexpr int32_t kEmpty = -1;
 constexpr int kRounds = 4;                   // element loads in flight per lane
@@ -58,6 +56,8 @@ struct TcPlan {
   int32_t* gtable_owner = nullptr;
   int64_t ntables = 0;
   unsigned long long* total = nullptr;
+  // tuning the plan was built with
+  uint32_t wave_max = 0, wave_work = 0, block_work = 0;
 };
 
 // 32-bit integer mixer (xor-shift-multiply rounds); every output bit depends
@@ -300,6 +300,8 @@ TcPlan* plan(gm_graph g) { return static_cast<TcPlan*>(g->tc_plan); }
 
 }  // namespace
 
+static TcPlan* ensure_plan(gm_graph g, hipStream_t s);
+
 void free_tc_plan(gm_graph g) {
   TcPlan* p = plan(g);
   if (!p) return;
@@ -312,10 +314,22 @@ void free_tc_plan(gm_graph g) {
   dfree(p->total);
   delete p;
   g->tc_plan = nullptr;
+  ++g->ws_gen;
+}
+
+void prepare_triangle_count(gm_graph g, hipStream_t s) {
+  ensure_plan(g, s);
+  GM_HIP(hipStreamSynchronize(s));
 }
 
 static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
-  if (plan(g)) return plan(g);
+  const uint32_t wave_max = std::min(g->tune.tc_wave_max, kWaveMax);
+  const uint32_t wave_work = g->tune.tc_wave_work, block_work = g->tune.tc_block_work;
+  if (TcPlan* p = plan(g)) {
+    if (p->wave_max == wave_max && p->wave_work == wave_work && p->block_work == block_work)
+      return p;
+    free_tc_plan(g);
+  }
   const int64_t n = g->n, m = g->m;
   std::vector<uint32_t> in_off(n + 1), out_off(n + 1);
   std::vector<int32_t> out_idx(m);
@@ -358,8 +372,8 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
     const uint32_t p0 = work_off[x], p1 = work_off[x + 1];
     if (p0 == p1) continue;
     const uint32_t d = din(x);
-    const int cls = d <= kWaveMax ? 0 : d <= kBlockMax ? 1 : 2;
-    const uint32_t budget = cls == 0 ? kWaveWork : kBlockWork;
+    const int cls = d <= wave_max ? 0 : d <= kBlockMax ? 1 : 2;
+    const uint32_t budget = cls == 0 ? wave_work : block_work;
     const uint32_t max_partners = cls == 0 ? UINT32_MAX : (uint32_t)kBlockWaves * 64;
     uint32_t table = 0;
     if (cls == 2) {
@@ -392,6 +406,9 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
     });
   TcPlan* p = new TcPlan();
   g->tc_plan = p;
+  p->wave_max = wave_max;
+  p->wave_work = wave_work;
+  p->block_work = block_work;
   try {
     for (int c = 0; c < 3; ++c) {
       p->nitems[c] = (int64_t)items[c].size();

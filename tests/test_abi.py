@@ -108,3 +108,30 @@ def test_python_binding_raises(lib):
     assert ei.value.status == _lib.GM_EINVAL
     with pytest.raises(ValueError):
         gm.Graph.from_coo(4, [0, 1], [1])
+
+
+def test_union_plan_tuning_validation_without_device(lib):
+    bogus = ctypes.c_void_p(0x1234)
+    out = ctypes.c_void_p()
+    parts = (ctypes.c_void_p * 2)(0x1234, 0x5678)
+    assert lib.gm_graph_union(None, 2, None, ctypes.byref(out)) == _lib.GM_EINVAL
+    assert lib.gm_graph_union(parts, 0, None, ctypes.byref(out)) == _lib.GM_EINVAL
+    assert lib.gm_graph_union(parts, 2, None, None) == _lib.GM_EINVAL
+    assert lib.gm_graph_union(parts, 2, None, ctypes.byref(out)) == _lib.GM_ESTATE
+    runs = (_lib.gm_plan_run * 1)()
+    runs[0].g = 0x1234
+    runs[0].prog = _lib.gm_program(_lib.GM_PROG_BFS, _lib.GM_ORDER_OUT, 0.15, 0)
+    runs[0].max_iters = 8
+    assert lib.gm_plan_create(None, 1, None, ctypes.byref(out)) == _lib.GM_EINVAL
+    assert lib.gm_plan_create(runs, 0, None, ctypes.byref(out)) == _lib.GM_EINVAL
+    assert lib.gm_plan_create(runs, 1, None, ctypes.byref(out)) == _lib.GM_ESTATE
+    assert out.value is None
+    res = (_lib.gm_plan_result * 1)()
+    assert lib.gm_plan_launch(bogus, None) == _lib.GM_ESTATE
+    assert lib.gm_plan_results(bogus, res, None) == _lib.GM_ESTATE
+    assert lib.gm_plan_destroy(bogus) == _lib.GM_ESTATE
+    t = _lib.gm_tuning()
+    assert lib.gm_graph_get_tuning(bogus, ctypes.byref(t)) == _lib.GM_ESTATE
+    assert lib.gm_graph_set_tuning(bogus, ctypes.byref(t)) == _lib.GM_ESTATE
+    prog = _lib.gm_program(_lib.GM_PROG_BFS, _lib.GM_ORDER_OUT, 0.15, 0)
+    assert lib.gm_autotune(bogus, ctypes.byref(prog), 0, None, 0, -1, 3, None, None) == _lib.GM_ESTATE
