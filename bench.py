@@ -15,12 +15,24 @@ message (Alg. 1's column walk): BFS and SSSP report it from the library's
 counters, PageRank traverses all m edges per superstep, triangle counting
 sends one message along each of the m_dag DAG edges.
 
+After the timed steps (and outside them) the batched and adjoint forms are
+measured against the plain runs they replace, on the same GPU:
+  RMAT scale 20: 64-source BFS and SSSP, 128-seed personalised PageRank
+  (20 supersteps) against 64 / 128 plain runs; the mixed batch of 32 RMAT
+  graphs of scales 12-18 (BFS from each vertex 0 + 20 PageRank supersteps)
+  as one captured launch against the 32 solo runs;
+  collaborative filtering on 480,189 x 17,770 users x items with 100M
+  ratings, K = 32: loss (forward) against both factor gradients (adjoint);
+  weighted PageRank on RMAT scale 22, T = 20: forward against the
+  edge-weight gradient (adjoint).
+
 Prints one JSON line. Inputs are generated and loaded before the timed region
 (graph loading is excluded, as in the paper's measurements).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -31,6 +43,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GTEPS per generalized-SpMV iteration + % HBM peak; batched/adjoint vs plain"
 HBM_PEAK_GBS = 8000.0
+PR_SOURCE = os.path.join(ROOT, "paper_1503_07241_amd", "csrc", "pagerank.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pr_dense_rmat22_traffic.txt")
 
 
 def log(msg):
@@ -44,6 +58,44 @@ def ensure_built():
         __graft_entry__.build()
 
 
+class Timer:
+    """HIP events on torch's current stream (the stream the library launches on)."""
+
+    def __init__(self):
+        import torch
+        self.a = torch.cuda.Event(enable_timing=True)
+        self.b = torch.cuda.Event(enable_timing=True)
+
+    def ms(self, fn, reps=3):
+        import torch
+        fn()  # warm-up
+        out = []
+        for _ in range(reps):
+            self.a.record()
+            fn()
+            self.b.record()
+            torch.cuda.synchronize()
+            out.append(self.a.elapsed_time(self.b))
+        out.sort()
+        return out[len(out) // 2]
+
+
+def measured_traffic():
+    """HBM bytes per PageRank superstep from the committed counter summary,
+    or None when pagerank.hip changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(PR_SOURCE, "rb").read()).hexdigest()
+    if kv.get("pagerank.hip sha256") != sha or "hbm bytes per superstep" not in kv:
+        return None
+    return int(float(kv["hbm bytes per superstep"]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +103,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched/adjoint comparisons")
+    ap.add_argument("--pr-only", type=int, default=0, metavar="K",
+                    help="only run K PageRank passes (20 supersteps) and a 1 GiB copy, for "
+                         "hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -71,6 +127,9 @@ def main():
     n, s, d = gg.rmat(scale)
     w = gg.weights_u32(s, d)
     log("generated RMAT scale %d in %.1fs" % (scale, time.time() - t0))
+    if args.pr_only:
+        pr_counter_run(gm, torch, n, s, d, args.pr_only)
+        return
     g_sym = gm.Graph.from_coo(n, s, d, prep=gm.GM_PREP_DROP_SELF_LOOPS | gm.GM_PREP_SYMMETRIZE,
                               layouts=gm.GM_LAYOUT_OUT)
     g_dir = gm.Graph.from_coo(n, s, d, w=w, prep=gm.GM_PREP_DROP_SELF_LOOPS,
@@ -140,24 +199,41 @@ def main():
         step(True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    log("timed %d steps in %.2fs" % (args.steps, wall))
     ms_step = 1e3 * wall / args.steps
     edges_step = sum(edges.values())
     gteps = edges_step / (wall / args.steps) / 1e9
-
-    # Dominant kernel: the PageRank pull superstep (one launch per superstep).
-    # Algorithmic bytes per superstep: every in-edge index (4 m), per row with
-    # in-edges its offset, 1/outdeg and new message (12 n_dst), and every
-    # message that is sent read once (4 n_src).
-    pr_ms_launch = acc["pr"] / args.steps / T_PR
-    info = g_dir.info()
-    pr_bytes = 4 * m_dir + 12 * info.n_dst + 4 * info.n_src
-    achieved = pr_bytes / (pr_ms_launch * 1e-3) / 1e9
     programs = {}
     for k in ev:
         ms = acc[k] / args.steps
         programs[k] = {"ms": round(ms, 4), "edges": int(edges[k]),
                        "gteps": round(edges[k] / (ms * 1e-3) / 1e9, 2)}
     log("programs: %s" % json.dumps(programs))
+
+    # Dominant SpMV kernel: the PageRank superstep (pr_dense + the combine of
+    # split rows). Its time per superstep is the difference of a 21- and a
+    # 1-superstep run over 20, which removes the per-run set-up kernels.
+    # Algorithmic bytes per superstep: every in-edge index (4 m), per row with
+    # in-edges its offset, 1/outdeg and new message (12 n_dst), and every
+    # message that is sent read once (4 n_src).
+    tm = Timer()
+
+    def pr_run(T):
+        def f():
+            rank.fill_(1.0)
+            gm.run_vertex_program(g_dir, gm.GM_PROG_PAGERANK, None, T, rank)
+        return f
+
+    t21, t1 = tm.ms(pr_run(21), 5), tm.ms(pr_run(1), 5)
+    pr_ms_launch = (t21 - t1) / 20
+    info = g_dir.info()
+    pr_bytes = 4 * m_dir + 12 * info.n_dst + 4 * info.n_src
+    achieved = pr_bytes / (pr_ms_launch * 1e-3) / 1e9
+    traffic = measured_traffic()
+
+    forms = None
+    if not args.no_forms:
+        forms = measure_forms(gm, gg, torch, np, tm, g_dir, n, m_dir)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -181,22 +257,172 @@ def main():
                    "scale": scale, "n": n, "m_dir": m_dir, "m_sym": m_sym, "m_dag": m_dag,
                    "edges_per_step": int(edges_step)},
         "programs": programs,
-        "roofline": {"kernel": "pr_pull (PageRank superstep)", "bound": "hbm",
+        "roofline": {"kernel": "pr_dense (PageRank superstep)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_launch": int(pr_bytes),
-                     "launch_ms": round(pr_ms_launch, 5)},
+                     "launch_ms": round(pr_ms_launch, 5),
+                     "pr_gteps": round(m_dir / (pr_ms_launch * 1e-3) / 1e9, 2)},
+        "forms": forms,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def measure_forms(gm, gg, torch, np, tm, g22, n22, m22):
+    """Batched and adjoint forms against the plain runs they stand for."""
+    dev = torch.device("cuda:0")
+    res = {}
+    t0 = time.time()
+
+    def ids(a):
+        return torch.tensor(np.asarray(a), dtype=torch.int32, device=dev)
+
+    # ---- batched sources, RMAT scale 20 ----
+    n, s, d = gg.rmat(20)
+    w = gg.weights_u32(s, d)
+    gs = gm.Graph.from_coo(n, s, d, prep=gm.GM_PREP_DROP_SELF_LOOPS | gm.GM_PREP_SYMMETRIZE,
+                           layouts=gm.GM_LAYOUT_OUT)
+    gd = gm.Graph.from_coo(n, s, d, w=w, prep=gm.GM_PREP_DROP_SELF_LOOPS)
+    S = gg.sources(n, s, d, 64, gg.SEED_BATCH_SOURCES)
+    P = gg.sources(n, s, d, 128, gg.SEED_PPR_SEEDS)
+    Sd, Pd = ids(S), ids(P)
+    one = [ids([v]) for v in S]
+    onep = [ids([v]) for v in P]
+    prop = torch.empty(n, dtype=torch.int32, device=dev)
+    prank = torch.empty(n, dtype=torch.float32, device=dev)
+    blk64 = torch.empty((n, 64), dtype=torch.int32, device=dev)
+    blk128 = torch.empty((n, 128), dtype=torch.float32, device=dev)
+    plain_edges = {"bfs": 0, "sssp": 0}
+
+    def plain_min(kind, g, inf):
+        def f():
+            tot = 0
+            for r in one:
+                prop.fill_(inf)
+                prop[r] = 0
+                gm.run_vertex_program(g, kind, r, -1, prop)
+                tot += g.last_run_stats().edges_scanned
+            plain_edges["bfs" if kind == gm.GM_PROG_BFS else "sssp"] = tot
+        return f
+
+    def plain_ppr():
+        for r in onep:
+            prank.zero_()
+            prank[r] = 1.0
+            gm.run_vertex_program(gd, gm.GM_PROG_PPR, r, 20, prank)
+
+    entries = [
+        ("bfs64", lambda: gm.run_batched(gs, gm.GM_PROG_BFS, Sd, -1, blk64),
+         plain_min(gm.GM_PROG_BFS, gs, gm.INF_LEVEL), "bfs"),
+        ("sssp64", lambda: gm.run_batched(gd, gm.GM_PROG_SSSP, Sd, -1, blk64),
+         plain_min(gm.GM_PROG_SSSP, gd, -1), "sssp"),
+        ("ppr128", lambda: gm.run_batched(gd, gm.GM_PROG_PPR, Pd, 20, blk128), plain_ppr, None),
+    ]
+    for name, batched, plain, ek in entries:
+        tb = tm.ms(batched, 3)
+        tp = tm.ms(plain, 1)
+        e = plain_edges[ek] if ek else 20 * len(P) * gd.m
+        res[name] = {"batched_ms": round(tb, 3), "plain_ms": round(tp, 3),
+                     "speedup": round(tp / tb, 2),
+                     "batched_gteps": round(e / (tb * 1e-3) / 1e9, 2),
+                     "plain_gteps": round(e / (tp * 1e-3) / 1e9, 2)}
+    log("batched forms: %s (%.1fs)" % (json.dumps(res), time.time() - t0))
+    del blk64, blk128
+
+    # ---- mixed batch: 32 graphs, one captured launch ----
+    raws = [gg.rmat(sc, seed=seed) for sc, seed in gg.mixed_batch_specs()]
+    msym = [gm.Graph.from_coo(a, b, c, prep=gm.GM_PREP_DROP_SELF_LOOPS | gm.GM_PREP_SYMMETRIZE,
+                              layouts=gm.GM_LAYOUT_OUT) for a, b, c in raws]
+    mdir = [gm.Graph.from_coo(a, b, c) for a, b, c in raws]
+    usym, udir = gm.Graph.union(msym), gm.Graph.union(mdir)
+    base = gm.union_bases(msym)
+    N = int(base[-1])
+    roots = ids(base[:-1])
+    ulv = torch.empty(N, dtype=torch.int32, device=dev)
+    upr = torch.empty(N, dtype=torch.float32, device=dev)
+    plan = gm.Plan([gm.PlanRun(usym, gm.GM_PROG_BFS, ulv, roots, max_iters=32),
+                    gm.PlanRun(udir, gm.GM_PROG_PAGERANK, upr, max_iters=20)])
+    zero = ids([0])
+    solo = [(torch.empty(a, dtype=torch.int32, device=dev),
+             torch.empty(a, dtype=torch.float32, device=dev)) for a, _, _ in raws]
+
+    def solo_runs():
+        for gsy, gdi, (lv, pr) in zip(msym, mdir, solo):
+            lv.fill_(gm.INF_LEVEL)
+            lv[0] = 0
+            gm.run_vertex_program(gsy, gm.GM_PROG_BFS, zero, -1, lv)
+            pr.fill_(1.0)
+            gm.run_vertex_program(gdi, gm.GM_PROG_PAGERANK, None, 20, pr)
+
+    tb = tm.ms(plan.launch, 5)
+    tp = tm.ms(solo_runs, 3)
+    conv = plan.results()[0][1]
+    res["mixed32"] = {"graphs": len(raws), "vertices": N, "one_launch_ms": round(tb, 3),
+                      "solo_runs_ms": round(tp, 3), "speedup": round(tp / tb, 2),
+                      "bfs_converged": bool(conv)}
+    plan.close()
+    log("mixed batch: %s (%.1fs)" % (json.dumps(res["mixed32"]), time.time() - t0))
+
+    # ---- adjoint: collaborative filtering, 100M ratings ----
+    R = gg.cf_ratings()
+    PU, PV = gg.cf_point(R.n_users, R.n_items)
+    rg = gm.RatingGraph.from_coo(R.n_users, R.n_items, R.user, R.item, R.rating)
+    del R
+    pu, pv = torch.tensor(PU, device=dev), torch.tensor(PV, device=dev)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    gu, gv = torch.empty_like(pu), torch.empty_like(pv)
+    tf = tm.ms(lambda: gm.cf_forward(rg, pu, pv, 0.05, loss), 5)
+    tbk = tm.ms(lambda: gm.cf_backward(rg, pu, pv, 0.05, 1.0, gu, gv), 5)
+    tu = tm.ms(lambda: gm.cf_backward(rg, pu, pv, 0.05, 1.0, gu, None), 5)
+    tv = tm.ms(lambda: gm.cf_backward(rg, pu, pv, 0.05, 1.0, None, gv), 5)
+    ratings = 100_000_000
+    res["cf_100M_k32"] = {"forward_ms": round(tf, 3), "backward_ms": round(tbk, 3),
+                          "row_pass_ms": round(tu, 3), "transpose_pass_ms": round(tv, 3),
+                          "backward_over_forward": round(tbk / tf, 2),
+                          "forward_gratings_s": round(ratings / (tf * 1e-3) / 1e9, 2),
+                          "transpose_gratings_s": round(ratings / (tv * 1e-3) / 1e9, 2)}
+    del rg, pu, pv, gu, gv
+    log("cf: %s (%.1fs)" % (json.dumps(res["cf_100M_k32"]), time.time() - t0))
+
+    # ---- adjoint: PageRank edge-weight gradient, RMAT scale 22, T = 20 ----
+    T = 20
+    wt = torch.ones(m22, dtype=torch.float32, device=dev)
+    hist = torch.empty((T + 1, n22), dtype=torch.float32, device=dev)
+    hist[0].fill_(1.0)
+    c = torch.tensor(gg.uniform_f32(n22, gg.SEED_PR_UPSTREAM), device=dev)
+    gw = torch.empty_like(wt)
+    tf = tm.ms(lambda: gm.pagerank_forward_w(g22, wt, 0.15, T, hist), 3)
+    tbk = tm.ms(lambda: gm.pagerank_vjp_w(g22, wt, 0.15, T, hist, c, gw), 3)
+    res["pr_weight_grad_rmat22_T20"] = {
+        "forward_ms": round(tf, 3), "vjp_ms": round(tbk, 3), "vjp_over_forward": round(tbk / tf, 2),
+        "forward_gteps": round(T * m22 / (tf * 1e-3) / 1e9, 2),
+        "vjp_gteps": round(T * m22 / (tbk * 1e-3) / 1e9, 2)}
+    log("pr grad: %s (%.1fs)" % (json.dumps(res["pr_weight_grad_rmat22_T20"]), time.time() - t0))
+    return res
+
+
+def pr_counter_run(gm, torch, n, s, d, K):
+    """K PageRank runs (20 supersteps each) on the scale-22 directed graph and
+    one copy of 1 GiB (256 Mi floats) for calibrating the byte counters."""
+    g = gm.Graph.from_coo(n, s, d)
+    rank = torch.empty(n, dtype=torch.float32, device="cuda")
+    for _ in range(K):
+        rank.fill_(1.0)
+        gm.run_vertex_program(g, gm.GM_PROG_PAGERANK, None, 20, rank)
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    info = g.info()
+    print(json.dumps({"pr_runs": K, "m": info.m, "n_dst": info.n_dst, "n_src": info.n_src,
+                      "copy_bytes": 1 << 30}), flush=True)
 
 
 def cpu_baseline(n, s, d, w):
     """The oracle (single-threaded C) on a bounded sample of the same workload:
     BFS + Dijkstra SSSP + 2 PageRank supersteps on the same scale-22 graph,
     reported as traversed edges per second (GTEPS)."""
-    import numpy as np
-
     import oracle
     t0 = time.time()
     gs = oracle.prepare(n, s, d, mode="symmetric")
