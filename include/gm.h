@@ -398,6 +398,9 @@ typedef struct gm_tuning {
                                (256..2^24; 2^14) */
   uint32_t tc_block_work;   /* TC: partner elements per workgroup work item
                                (256..2^26; 2^18) */
+  uint32_t pr_hot;          /* PageRank/PPR pull: the messages of the pr_hot
+                               highest-in-degree vertices are staged in LDS by
+                               every workgroup (0..32768; 32768) */
 } gm_tuning;
 
 /* Read g's parameters. Errors: GM_ESTATE, GM_EINVAL (out NULL). */
@@ -413,8 +416,8 @@ gm_status gm_graph_set_tuning(gm_graph g, const gm_tuning* t);
  * descent; median of `trials` timed runs per candidate after a warm-up run):
  *   BFS: pull_div, superstep_batch, push_blocks; SSSP: superstep_batch,
  *   push_blocks; batched SSSP: push_blocks; batched PPR: ppr_chunk;
- *   TC: tc_wave_max, tc_wave_work, tc_block_work; PageRank and batched BFS
- *   have no parameters (the current values are returned).
+ *   TC: tc_wave_max, tc_wave_work, tc_block_work; PageRank: pr_hot;
+ *   batched BFS has no parameters (the current values are returned).
  * batched selects gm_run_batched semantics with `count` = k sources; ids are
  * device sources / frontier ids as for the corresponding call (NULL for
  * PageRank and TC); max_iters as for that call (> 0 for PageRank and PPR).

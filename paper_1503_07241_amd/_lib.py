@@ -63,7 +63,7 @@ class gm_plan_result(ctypes.Structure):
 
 
 TUNING_FIELDS = ("pull_div", "superstep_batch", "push_blocks", "ppr_chunk", "tc_wave_max",
-                 "tc_wave_work", "tc_block_work")
+                 "tc_wave_work", "tc_block_work", "pr_hot")
 
 
 class gm_tuning(ctypes.Structure):

@@ -4,9 +4,11 @@
 // Sec. 3). Column s of every result equals the plain run from source s.
 //
 //  - BFS (k <= 64): the frontier of vertex v over all sources is one 64-bit
-//    mask (REDUCE = or). Pull superstep: v ORs the masks of its neighbours
-//    until every source that has not reached v is covered; new bits get
-//    level t + 1.
+//    mask (REDUCE = or); new bits get level t + 1. Each superstep pushes
+//    (small frontier: edges of the active vertices split evenly over
+//    wavefronts) or pulls (large frontier: every vertex ORs its neighbours'
+//    masks until every source that has not reached it is covered), as
+//    decided on the device from the frontier's out-edge count.
 //  - SSSP (k <= 64): distances are an n x k uint32 block. Active vertices
 //    (any source changed) are compacted with a snapshot of their distance
 //    rows (SEND); their out-edges are split evenly over wavefronts, lane s
@@ -42,62 +44,6 @@ __device__ inline unsigned long long full_mask(int k) {
   return k >= 64 ? ~0ull : ((1ull << k) - 1);
 }
 
-// ---------------------------------------------------------------- BFS -----
-__global__ void bbfs_init(int64_t n, int k, const int32_t* __restrict__ src, int32_t* level,
-                          unsigned long long* vis, unsigned long long* fr) {
-  const int64_t total = n * k;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x)
-    level[i] = (int32_t)kInfBfs;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * blockDim.x) {
-    vis[v] = 0;
-    fr[v] = 0;
-  }
-}
-
-__global__ void bbfs_seed(int k, const int32_t* __restrict__ src, int32_t* level,
-                          unsigned long long* vis, unsigned long long* fr) {
-  for (int s = threadIdx.x; s < k; s += blockDim.x) {
-    const int32_t v = src[s];
-    level[(int64_t)v * k + s] = 0;
-    atomicOr(&vis[v], 1ull << s);
-    atomicOr(&fr[v], 1ull << s);
-  }
-}
-
-__global__ __launch_bounds__(kThreads) void bbfs_pull(
-    int64_t n, int k, int32_t t, const uint32_t* __restrict__ off, const int32_t* __restrict__ idx,
-    const unsigned long long* __restrict__ fr, unsigned long long* __restrict__ vis,
-    unsigned long long* __restrict__ fnext, int32_t* __restrict__ level,
-    const unsigned int* __restrict__ prev, unsigned int* __restrict__ changed) {
-  // a recorded superstep after the one that found nothing new does nothing
-  if (prev && !*prev) return;
-  const unsigned long long full = full_mask(k);
-  int any = 0;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * blockDim.x) {
-    const unsigned long long seen = vis[v];
-    unsigned long long acc = 0;
-    if (seen != full) {
-      const uint32_t e1 = off[v + 1];
-      for (uint32_t e = off[v]; e < e1; ++e) {
-        acc |= fr[idx[e]];
-        if ((acc | seen) == full) break;
-      }
-    }
-    const unsigned long long nw = acc & ~seen;
-    fnext[v] = nw;
-    if (nw) {
-      vis[v] = seen | nw;
-      for (unsigned long long b = nw; b; b &= b - 1) level[v * k + (__ffsll((long long)b) - 1)] = t + 1;
-      any = 1;
-    }
-  }
-  // Every writer stores the same value: a plain store is enough.
-  if (__syncthreads_or(any) && threadIdx.x == 0) *changed = 1u;
-}
-
 // ---------------------------------------------------------------- SSSP ----
 struct BCtl {
   unsigned long long packed;  // (active vertices << 32) | their out-edges
@@ -131,6 +77,338 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x, int lane) {
     if (lane >= o) x += t;
   }
   return x;
+}
+
+// ---------------------------------------------------------------- BFS -----
+// Superstep t reads the frontier masks fr (bit s: source s reached the
+// vertex at level t) and writes the next ones. Direction per superstep, chosen
+// on the device from the frontier's size: push (few active vertices: their
+// edges are split evenly over wavefronts and each edge ORs the sender's mask
+// into the receiver's next mask) or pull (every vertex not yet reached by all
+// sources ORs its neighbours' masks, stopping once nothing is left to learn;
+// vertices are taken in decreasing degree order, a power-of-two number of
+// lanes per vertex as in the PageRank pull). Levels are unique, so both
+// directions give the same result.
+
+// Frontier of one superstep (written by the previous one).
+struct BfsCtl {
+  unsigned long long active;  // vertices with a non-empty mask
+  unsigned long long edges;   // their degrees
+  uint32_t push;              // 1: push superstep
+  uint32_t pad;
+};
+
+constexpr int kBfsStatBlocks = 1024;  // grid of the apply and pull kernels
+constexpr int kBfsClasses = 12;
+constexpr uint32_t kBfsClassMax[kBfsClasses] = {0, 1, 2, 4, 8, 16, 32, 64, 128, 256, 512,
+                                                0xFFFFFFFFu};
+constexpr int kBfsClassLanes[kBfsClasses] = {1, 1, 1, 1, 1, 2, 4, 8, 16, 32, 64, 64};
+constexpr int kBfsClassUnroll[kBfsClasses] = {1, 1, 2, 4, 8, 8, 8, 8, 8, 8, 8, 8};
+
+// Vertices in decreasing degree order cut into wavefront units (class c: 64 /
+// kBfsClassLanes[c] vertices per unit), longest class first.
+struct BfsBins {
+  int64_t class_begin[kBfsClasses];  // position in the order
+  int64_t class_rows[kBfsClasses];
+  int64_t class_unit0[kBfsClasses];  // decreases with c; class 0 (degree 0) is never pulled
+  int64_t nunits;
+};
+
+__global__ void bbfs_init(int64_t n, int k, int32_t* level, unsigned long long* vis,
+                          unsigned long long* fr0, unsigned long long* fr1, BfsCtl* ctl0) {
+  const int64_t total = n * k;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x)
+    level[i] = (int32_t)kInfBfs;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    vis[v] = 0;
+    fr0[v] = 0;
+    fr1[v] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl0->active = (unsigned long long)k;  // at most k source vertices
+    ctl0->edges = 0;
+    ctl0->push = 1;
+  }
+}
+
+__global__ void bbfs_seed(int k, const int32_t* __restrict__ src, int32_t* level,
+                          unsigned long long* vis, unsigned long long* fr) {
+  for (int s = threadIdx.x; s < k; s += blockDim.x) {
+    const int32_t v = src[s];
+    level[(int64_t)v * k + s] = 0;
+    atomicOr(&vis[v], 1ull << s);
+    atomicOr(&fr[v], 1ull << s);
+  }
+}
+
+__device__ inline void set_levels(int32_t* level, int64_t v, int k, unsigned long long bits,
+                                  int32_t lev) {
+  for (unsigned long long b = bits; b; b &= b - 1) level[v * k + (__ffsll((long long)b) - 1)] = lev;
+}
+
+// Block-wide sum of (count, edges) into stat[blockIdx.x] (every block writes).
+__device__ inline void block_stat(unsigned long long cnt, unsigned long long edges,
+                                  unsigned long long* stat) {
+  __shared__ unsigned long long sc[kThreads / 64], se[kThreads / 64];
+  for (int o = 32; o > 0; o >>= 1) {
+    cnt += __shfl_xor(cnt, o, 64);
+    edges += __shfl_xor(edges, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sc[threadIdx.x >> 6] = cnt;
+    se[threadIdx.x >> 6] = edges;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long c = 0, e = 0;
+    for (int i = 0; i < kThreads / 64; ++i) {
+      c += sc[i];
+      e += se[i];
+    }
+    stat[2 * blockIdx.x] = c;
+    stat[2 * blockIdx.x + 1] = e;
+  }
+}
+
+// SEND of a push superstep: queue the active vertices with their first edge
+// and the exclusive prefix of their degrees.
+__global__ __launch_bounds__(kThreads) void bbfs_send(
+    const BfsCtl* __restrict__ ctl, int64_t n, const unsigned long long* __restrict__ fr,
+    const uint32_t* __restrict__ off, int32_t* __restrict__ q, uint32_t* __restrict__ qbeg,
+    uint32_t* __restrict__ qest, BCtl* __restrict__ qctl) {
+  if (!ctl->push || ctl->active == 0) return;
+  __shared__ uint32_t sh[2 * kWaves];
+  __shared__ unsigned long long base;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t v0 = (int64_t)blockIdx.x * kThreads; v0 < n; v0 += (int64_t)gridDim.x * kThreads) {
+    const int64_t v = v0 + threadIdx.x;
+    const bool a = v < n && fr[v] != 0;
+    const uint32_t cnt = a ? 1u : 0u;
+    const uint32_t deg = a ? off[v + 1] - off[v] : 0u;
+    const uint32_t ci = wave_incl_scan(cnt, lane), ei = wave_incl_scan(deg, lane);
+    if (lane == 63) {
+      sh[wave] = ci;
+      sh[kWaves + wave] = ei;
+    }
+    __syncthreads();
+    uint32_t cb = 0, eb = 0, ct = 0, et = 0;
+    for (int i = 0; i < kWaves; ++i) {
+      if (i < wave) {
+        cb += sh[i];
+        eb += sh[kWaves + i];
+      }
+      ct += sh[i];
+      et += sh[kWaves + i];
+    }
+    if (threadIdx.x == 0 && ct) base = atomicAdd(&qctl->packed, ((unsigned long long)ct << 32) | et);
+    __syncthreads();
+    if (ct && a) {
+      const unsigned long long bp = base;
+      const uint32_t slot = (uint32_t)(bp >> 32) + cb + ci - cnt;
+      q[slot] = (int32_t)v;
+      qbeg[slot] = off[v];
+      qest[slot] = (uint32_t)bp + eb + ei - deg;
+    }
+    __syncthreads();
+  }
+}
+
+// PROCESS + REDUCE of a push superstep: one edge per lane, the edges of the
+// queued vertices split evenly over the wavefronts.
+__global__ __launch_bounds__(kThreads) void bbfs_push(
+    const BfsCtl* __restrict__ ctl, const BCtl* __restrict__ qctl, const int32_t* __restrict__ q,
+    const uint32_t* __restrict__ qbeg, const uint32_t* __restrict__ qest,
+    const int32_t* __restrict__ idx, const unsigned long long* __restrict__ fr,
+    const unsigned long long* __restrict__ vis, unsigned long long* fnext) {
+  if (!ctl->push || ctl->active == 0) return;
+  const uint32_t count = (uint32_t)(qctl->packed >> 32);
+  const uint64_t E = (uint32_t)qctl->packed;
+  if (count == 0 || E == 0) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t nw = (uint64_t)gridDim.x * kWaves;
+  const uint64_t wid = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const uint32_t e_begin = (uint32_t)(E * wid / nw), e_end = (uint32_t)(E * (wid + 1) / nw);
+  if (e_begin >= e_end) return;
+  uint32_t lo = 0, hi = count;  // last slot whose prefix is <= e_begin, in [lo, hi)
+  while (hi - lo > 64) {
+    const uint32_t span = hi - lo;
+    const uint32_t p = lo + (uint32_t)((uint64_t)span * lane / 64);
+    const int last = 63 - __clzll(__ballot(qest[p] <= e_begin));
+    const uint32_t nlo = lo + (uint32_t)((uint64_t)span * last / 64);
+    hi = last == 63 ? hi : lo + (uint32_t)((uint64_t)span * (last + 1) / 64);
+    lo = nlo;
+  }
+  {
+    const uint32_t p = lo + lane;
+    lo += 63 - __clzll(__ballot(p < hi && qest[p] <= e_begin));
+  }
+  uint32_t e = e_begin;
+  for (uint32_t s0 = lo; e < e_end; s0 += 64) {
+    const uint32_t s = s0 + lane;
+    const bool valid = s < count;
+    const uint32_t est = valid ? qest[s] : (uint32_t)E;
+    const uint32_t beg = valid ? qbeg[s] : 0u;
+    const unsigned long long mk = valid ? fr[q[s]] : 0ull;
+    const uint32_t win_end = s0 + 64 < count ? qest[s0 + 64] : (uint32_t)E;
+    const uint32_t stop = win_end < e_end ? win_end : e_end;
+    for (; e < stop; e += 64) {
+      const uint32_t ee = e + lane;
+      int j = 0;  // owner: the last lane whose prefix is <= ee
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1) {
+        const uint32_t ex = __shfl(est, j + step, 64);
+        if (ex <= ee) j += step;
+      }
+      const uint32_t ej = __shfl(est, j, 64);
+      const uint32_t bj = __shfl(beg, j, 64);
+      const unsigned long long m = __shfl(mk, j, 64);
+      if (ee < stop) {
+        const int32_t v = idx[bj + (ee - ej)];
+        const unsigned long long nw_bits = m & ~vis[v];
+        if (nw_bits)
+          __hip_atomic_fetch_or(&fnext[v], nw_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    e = stop;
+  }
+}
+
+// APPLY of a push superstep: new bits become visited and get level t + 1.
+// Frontier statistics count out-edges (what the next push would walk).
+__global__ __launch_bounds__(kThreads) void bbfs_apply(
+    const BfsCtl* __restrict__ ctl, int64_t n, int k, int32_t t, const uint32_t* __restrict__ off,
+    unsigned long long* vis, unsigned long long* fnext, int32_t* level,
+    unsigned long long* stat) {
+  if (!ctl->push || ctl->active == 0) return;
+  unsigned long long cnt = 0, edges = 0;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long m = fnext[v];
+    if (m) {
+      const unsigned long long seen = vis[v];
+      const unsigned long long nw = m & ~seen;
+      fnext[v] = nw;
+      if (nw) {
+        vis[v] = seen | nw;
+        set_levels(level, v, k, nw, t + 1);
+        ++cnt;
+        edges += off[v + 1] - off[v];
+      }
+    }
+  }
+  block_stat(cnt, edges, stat);
+}
+
+__device__ inline unsigned long long group_or(unsigned long long v, int width) {
+  for (int o = width >> 1; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+
+// OR of the frontier masks of the neighbours [b, e) of one vertex, taken by
+// `lanes` lanes with kU loads in flight each; stops once acc | seen == full
+// (checked by the whole lane group after each pass).
+template <int kU>
+__device__ inline unsigned long long pull_or(const int32_t* __restrict__ idx,
+                                             const unsigned long long* __restrict__ fr,
+                                             uint32_t b, uint32_t e, int sub, int lanes,
+                                             unsigned long long seen, unsigned long long full) {
+  unsigned long long acc = 0;
+  for (uint32_t k0 = b + sub; k0 < e + sub; k0 += kU * lanes) {
+    int32_t u[kU];
+#pragma unroll
+    for (int q = 0; q < kU; ++q) {
+      const uint32_t kk = k0 + q * lanes;
+      u[q] = idx[kk < e ? kk : e - 1];
+    }
+    unsigned long long m[kU];
+#pragma unroll
+    for (int q = 0; q < kU; ++q) m[q] = fr[u[q]];
+#pragma unroll
+    for (int q = 0; q < kU; ++q) acc |= k0 + q * lanes < e ? m[q] : 0ull;
+    if ((group_or(acc, lanes) | seen) == full) break;
+  }
+  return group_or(acc, lanes);
+}
+
+// PROCESS + REDUCE + APPLY of a pull superstep.
+__global__ __launch_bounds__(kThreads) void bbfs_pull(
+    const BfsCtl* __restrict__ ctl, int k, int32_t t, BfsBins bins,
+    const int32_t* __restrict__ order, const uint32_t* __restrict__ off,
+    const int32_t* __restrict__ idx, const uint32_t* __restrict__ out_off,
+    const unsigned long long* __restrict__ fr, unsigned long long* vis,
+    unsigned long long* fnext, int32_t* level, unsigned long long* stat) {
+  if (ctl->push || ctl->active == 0) return;
+  const unsigned long long full = full_mask(k);
+  const int lane = threadIdx.x & 63;
+  unsigned long long cnt = 0, edges = 0;
+  const int64_t stride = (int64_t)gridDim.x * kWaves;
+  for (int64_t u = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); u < bins.nunits;
+       u += stride) {
+    int cls = 1;
+    while (u < bins.class_unit0[cls]) ++cls;
+    const int lanes = kBfsClassLanes[cls];
+    const int64_t local = (u - bins.class_unit0[cls]) * (64 / lanes) + lane / lanes;
+    const bool valid = local < bins.class_rows[cls];
+    const int64_t v = valid ? order[bins.class_begin[cls] + local] : 0;
+    const int sub = lane % lanes;
+    const unsigned long long seen = valid ? vis[v] : full;
+    unsigned long long acc = 0;
+    uint32_t b = 0, e = 0;
+    if (valid) {
+      b = off[v];
+      e = off[v + 1];
+    }
+    if (seen != full) {
+      switch (kBfsClassUnroll[cls]) {
+        case 1: acc = pull_or<1>(idx, fr, b, e, sub, lanes, seen, full); break;
+        case 2: acc = pull_or<2>(idx, fr, b, e, sub, lanes, seen, full); break;
+        case 4: acc = pull_or<4>(idx, fr, b, e, sub, lanes, seen, full); break;
+        default: acc = pull_or<8>(idx, fr, b, e, sub, lanes, seen, full); break;
+      }
+    }
+    const unsigned long long nw = acc & ~seen;
+    if (valid && sub == 0 && nw) {
+      vis[v] = seen | nw;
+      fnext[v] = nw;
+      set_levels(level, v, k, nw, t + 1);
+      ++cnt;
+      edges += out_off[v + 1] - out_off[v];
+    }
+  }
+  block_stat(cnt, edges, stat);
+}
+
+// Frontier of the next superstep and its direction (one workgroup).
+__global__ void bbfs_decide(const BfsCtl* __restrict__ ctl, const unsigned long long* __restrict__ stat,
+                            int nstat, uint64_t m, uint32_t pull_div, BfsCtl* __restrict__ next) {
+  __shared__ unsigned long long sc[kWaves], se[kWaves];
+  unsigned long long c = 0, e = 0;
+  if (ctl->active != 0)
+    for (int i = threadIdx.x; i < nstat; i += blockDim.x) {
+      c += stat[2 * i];
+      e += stat[2 * i + 1];
+    }
+  for (int o = 32; o > 0; o >>= 1) {
+    c += __shfl_xor(c, o, 64);
+    e += __shfl_xor(e, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sc[threadIdx.x >> 6] = c;
+    se[threadIdx.x >> 6] = e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    c = e = 0;
+    for (int i = 0; i < kWaves; ++i) {
+      c += sc[i];
+      e += se[i];
+    }
+    next->active = c;
+    next->edges = e;
+    next->push = e * pull_div <= m ? 1u : 0u;
+  }
 }
 
 // SEND: active masks -> queue (vertex, first edge, edge prefix) plus a
@@ -367,8 +645,15 @@ struct Batch {
   // BFS
   unsigned long long* vis = nullptr;
   unsigned long long* fr[2] = {nullptr, nullptr};
-  unsigned int* flags = nullptr;  // kMaxPlanSteps "changed" words
-  unsigned int* host_flag = nullptr;
+  BfsCtl* bctl = nullptr;  // kMaxPlanSteps + 1 records: the frontier of each superstep
+  BfsCtl* host_bctl = nullptr;
+  unsigned long long* bstat = nullptr;  // 2 * kBfsStatBlocks partial counts
+  int32_t* border = nullptr;            // vertices by decreasing pull degree
+  BfsBins bbins{};
+  int32_t* bq = nullptr;                // push queue
+  uint32_t* bqbeg = nullptr;
+  uint32_t* bqest = nullptr;
+  BCtl* bqctl = nullptr;                // kMaxPlanSteps queue records
   // SSSP
   unsigned long long* act[2] = {nullptr, nullptr};
   int32_t* q = nullptr;
@@ -452,15 +737,68 @@ void ensure_ppr_items(gm_graph g, Batch* b, hipStream_t s) {
   GM_HIP(hipStreamSynchronize(s));
 }
 
-void ensure_bfs_ws(Batch* b, int64_t n) {
+// Pull adjacency of batched BFS: the out-lists of a symmetrised graph, else
+// the in-lists.
+void bfs_adjacency(gm_graph g, const uint32_t** off, const int32_t** idx) {
+  const bool sym = (g->prep & (GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG)) == GM_PREP_SYMMETRIZE;
+  *off = sym ? g->out_off : g->in_off;
+  *idx = sym ? g->out_idx : g->in_idx;
+}
+
+void ensure_bfs_ws(gm_graph g, Batch* b, hipStream_t s) {
   if (b->vis) return;
+  const int64_t n = g->n;
+  const uint32_t* doff;
+  const int32_t* didx;
+  bfs_adjacency(g, &doff, &didx);
+  // vertices by decreasing pull degree (counting sort), cut into classes
+  std::vector<uint32_t> off(n + 1);
+  GM_HIP(hipMemcpyAsync(off.data(), doff, (n + 1) * 4, hipMemcpyDeviceToHost, s));
+  GM_HIP(hipStreamSynchronize(s));
+  uint32_t maxd = 0;
+  for (int64_t v = 0; v < n; ++v) maxd = std::max(maxd, off[v + 1] - off[v]);
+  std::vector<int64_t> cnt((size_t)maxd + 2, 0);
+  for (int64_t v = 0; v < n; ++v) ++cnt[maxd - (off[v + 1] - off[v])];
+  int64_t acc = 0;
+  for (size_t i = 0; i < cnt.size(); ++i) {
+    const int64_t c = cnt[i];
+    cnt[i] = acc;
+    acc += c;
+  }
+  std::vector<int32_t> order(n);
+  for (int64_t v = 0; v < n; ++v) order[cnt[maxd - (off[v + 1] - off[v])]++] = (int32_t)v;
+  BfsBins& bins = b->bbins;
+  int64_t i = 0, unit = 0;
+  for (int c = kBfsClasses - 1; c >= 0; --c) {
+    const int64_t r0 = i;
+    if (c == 0)
+      i = n;
+    else
+      while (i < n && off[order[i] + 1] - off[order[i]] > kBfsClassMax[c - 1]) ++i;
+    bins.class_begin[c] = r0;
+    bins.class_rows[c] = i - r0;
+    bins.class_unit0[c] = unit;
+    if (c > 0) {
+      const int64_t rpu = 64 / kBfsClassLanes[c];
+      unit += (bins.class_rows[c] + rpu - 1) / rpu;
+    }
+  }
+  bins.nunits = unit;
   b->vis = dalloc<unsigned long long>(n);
   b->fr[0] = dalloc<unsigned long long>(n);
   b->fr[1] = dalloc<unsigned long long>(n);
-  b->flags = dalloc<unsigned int>(kMaxPlanSteps);
+  b->bctl = dalloc<BfsCtl>(kMaxPlanSteps + 1);
+  b->bstat = dalloc<unsigned long long>(2 * kBfsStatBlocks);
+  b->border = dalloc<int32_t>(n);
+  b->bq = dalloc<int32_t>(n);
+  b->bqbeg = dalloc<uint32_t>(n);
+  b->bqest = dalloc<uint32_t>(n);
+  b->bqctl = dalloc<BCtl>(kMaxPlanSteps);
   void* h = nullptr;
-  GM_HIP(hipHostMalloc(&h, sizeof(unsigned int), hipHostMallocDefault));
-  b->host_flag = static_cast<unsigned int*>(h);
+  GM_HIP(hipHostMalloc(&h, sizeof(BfsCtl), hipHostMallocDefault));
+  b->host_bctl = static_cast<BfsCtl*>(h);
+  GM_HIP(hipMemcpyAsync(b->border, order.data(), n * 4, hipMemcpyHostToDevice, s));
+  GM_HIP(hipStreamSynchronize(s));
 }
 
 void ensure_sssp_ws(gm_graph g, Batch* b, int k) {
@@ -506,28 +844,37 @@ void ensure_ppr_ws(gm_graph g, Batch* b, int k, hipStream_t s) {
   }
 }
 
-// Pull adjacency of batched BFS: the out-lists of a symmetrised graph, else
-// the in-lists.
-void bfs_adjacency(gm_graph g, const uint32_t** off, const int32_t** idx) {
-  const bool sym = (g->prep & (GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG)) == GM_PREP_SYMMETRIZE;
-  *off = sym ? g->out_off : g->in_off;
-  *idx = sym ? g->out_idx : g->in_idx;
-}
-
 void bfs_init(gm_graph g, Batch* b, const int32_t* sources, int k, int32_t* level, hipStream_t s) {
   const int64_t n = g->n;
-  bbfs_init<<<blocks_for(n * k), kThreads, 0, s>>>(n, k, sources, level, b->vis, b->fr[0]);
+  bbfs_init<<<blocks_for(n * k), kThreads, 0, s>>>(n, k, level, b->vis, b->fr[0], b->fr[1], b->bctl);
   bbfs_seed<<<1, 64, 0, s>>>(k, sources, level, b->vis, b->fr[0]);
   GM_HIP(hipGetLastError());
 }
 
-void bfs_superstep(gm_graph g, Batch* b, int k, int32_t t, int cur, int32_t* level,
-                   const unsigned int* prev, unsigned int* changed, hipStream_t s) {
+// Superstep t (new vertices get level t + 1): frontier fr[cur] described by
+// bctl[rec]; writes fr[cur ^ 1] and bctl[rec + 1]; clears fr[cur]. Does
+// nothing if bctl[rec] is empty.
+void bfs_superstep(gm_graph g, Batch* b, int k, int32_t t, int32_t rec, int cur, int32_t* level,
+                   hipStream_t s) {
+  const int64_t n = g->n;
   const uint32_t* off;
   const int32_t* idx;
   bfs_adjacency(g, &off, &idx);
-  bbfs_pull<<<blocks_for(g->n), kThreads, 0, s>>>(g->n, k, t, off, idx, b->fr[cur], b->vis,
-                                                  b->fr[cur ^ 1], level, prev, changed);
+  const BfsCtl* c = b->bctl + rec;
+  BCtl* qc = b->bqctl + rec;
+  reset_bctl<<<1, 1, 0, s>>>(qc);
+  bbfs_send<<<blocks_for(n, 4096), kThreads, 0, s>>>(c, n, b->fr[cur], g->out_off, b->bq, b->bqbeg,
+                                                     b->bqest, qc);
+  bbfs_push<<<g->tune.push_blocks, kThreads, 0, s>>>(c, qc, b->bq, b->bqbeg, b->bqest, g->out_idx,
+                                                     b->fr[cur], b->vis, b->fr[cur ^ 1]);
+  bbfs_apply<<<kBfsStatBlocks, kThreads, 0, s>>>(c, n, k, t, g->out_off, b->vis, b->fr[cur ^ 1],
+                                                 level, b->bstat);
+  bbfs_pull<<<kBfsStatBlocks, kThreads, 0, s>>>(c, k, t, b->bbins, b->border, off, idx, g->out_off,
+                                                b->fr[cur], b->vis, b->fr[cur ^ 1], level,
+                                                b->bstat);
+  bbfs_decide<<<1, kThreads, 0, s>>>(c, b->bstat, kBfsStatBlocks, (uint64_t)g->m, g->tune.pull_div,
+                                     b->bctl + rec + 1);
+  fill_u32(reinterpret_cast<uint32_t*>(b->fr[cur]), 2 * n, 0u, s);
   GM_HIP(hipGetLastError());
 }
 
@@ -581,19 +928,22 @@ void ppr_supersteps(gm_graph g, Batch* b, const int32_t* seeds, int k, float r, 
 }
 
 // Outcome of recorded batched BFS supersteps: superstep t found nothing new
-// iff changed[t] == 0 (that superstep still counts, as in the plain run).
-__global__ void bbfs_summary(const unsigned int* __restrict__ changed, int32_t steps,
-                             PlanResult* res) {
+// iff the frontier it leaves (bctl[t + 1]) is empty; that superstep still
+// counts, as in the plain run.
+__global__ void bbfs_summary(const BfsCtl* __restrict__ bctl, int32_t steps, PlanResult* res) {
   int32_t it = steps, conv = 0;
-  for (int32_t t = 0; t < steps; ++t)
-    if (!changed[t]) {
+  unsigned long long e = 0;
+  for (int32_t t = 0; t < steps; ++t) {
+    e += bctl[t].edges;
+    if (bctl[t + 1].active == 0) {
       it = t + 1;
       conv = 1;
       break;
     }
+  }
   res->iters = it;
   res->converged = conv;
-  res->edges = 0;
+  res->edges = e;
 }
 
 // Outcome of recorded batched SSSP supersteps: the first superstep with no
@@ -635,8 +985,14 @@ void free_batch(gm_graph g) {
   dfree(b->vis);
   dfree(b->fr[0]);
   dfree(b->fr[1]);
-  dfree(b->flags);
-  if (b->host_flag) (void)hipHostFree(b->host_flag);
+  dfree(b->bctl);
+  if (b->host_bctl) (void)hipHostFree(b->host_bctl);
+  dfree(b->bstat);
+  dfree(b->border);
+  dfree(b->bq);
+  dfree(b->bqbeg);
+  dfree(b->bqest);
+  dfree(b->bqctl);
   dfree(b->act[0]);
   dfree(b->q);
   dfree(b->qbeg);
@@ -657,22 +1013,32 @@ void free_batch(gm_graph g) {
 int32_t run_batched_bfs(gm_graph g, const int32_t* sources, int k, int32_t max_iters,
                         int32_t* level, hipStream_t s) {
   Batch* b = ensure_batch(g);
-  ensure_bfs_ws(b, g->n);
+  ensure_bfs_ws(g, b, s);
   bfs_init(g, b, sources, k, level, s);
   int cur = 0;
   int32_t t = 0;
+  // bctl holds kMaxPlanSteps + 1 records; longer runs restart at record 0
+  // with the last frontier record carried over.
+  int32_t rec = 0;
   for (;; ++t) {
     if (max_iters > 0 && t >= max_iters) break;
-    fill_u32(b->flags, 1, 0u, s);
-    bfs_superstep(g, b, k, t, cur, level, nullptr, b->flags, s);
-    GM_HIP(hipMemcpyAsync(b->host_flag, b->flags, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    if (rec == kMaxPlanSteps) {
+      GM_HIP(hipMemcpyAsync(b->bctl, b->bctl + rec, sizeof(BfsCtl), hipMemcpyDeviceToDevice, s));
+      rec = 0;
+    }
+    bfs_superstep(g, b, k, t, rec, cur, level, s);
+    GM_HIP(hipMemcpyAsync(b->host_bctl, b->bctl + rec + 1, sizeof(BfsCtl), hipMemcpyDeviceToHost,
+                          s));
     GM_HIP(hipStreamSynchronize(s));
     cur ^= 1;
-    if (!*b->host_flag) {
+    ++rec;
+    if (b->host_bctl->active == 0) {
       ++t;  // this superstep scanned the deepest frontier and found nothing new
       break;
     }
   }
+  // leave both frontiers cleared for the next run
+  fill_u32(reinterpret_cast<uint32_t*>(b->fr[cur]), 2 * g->n, 0u, s);
   return t;
 }
 
@@ -707,7 +1073,7 @@ void run_batched_ppr(gm_graph g, const int32_t* seeds, int k, float r, int32_t i
 void prepare_batched(gm_graph g, int kind, int k, hipStream_t s) {
   Batch* b = ensure_batch(g);
   if (kind == GM_PROG_BFS)
-    ensure_bfs_ws(b, g->n);
+    ensure_bfs_ws(g, b, s);
   else if (kind == GM_PROG_SSSP)
     ensure_sssp_ws(g, b, k);
   else
@@ -723,13 +1089,13 @@ void enqueue_batched(gm_graph g, int kind, const int32_t* sources, int k, int32_
     if (!b->vis || steps > kMaxPlanSteps) throw Unsupported{"captured run not prepared"};
     int32_t* level = static_cast<int32_t*>(block);
     bfs_init(g, b, sources, k, level, s);
-    fill_u32(b->flags, steps, 0u, s);
     int cur = 0;
     for (int32_t t = 0; t < steps; ++t) {
-      bfs_superstep(g, b, k, t, cur, level, t > 0 ? b->flags + t - 1 : nullptr, b->flags + t, s);
+      bfs_superstep(g, b, k, t, t, cur, level, s);
       cur ^= 1;
     }
-    bbfs_summary<<<1, 1, 0, s>>>(b->flags, steps, res);
+    bbfs_summary<<<1, 1, 0, s>>>(b->bctl, steps, res);
+    fill_u32(reinterpret_cast<uint32_t*>(b->fr[cur]), 2 * g->n, 0u, s);
   } else if (kind == GM_PROG_SSSP) {
     if (!b->act[0] || b->qrow_k < k || steps > kMaxPlanSteps)
       throw Unsupported{"captured run not prepared"};

@@ -2,7 +2,7 @@
 // generalized SpMV over the in-adjacency, with APPLY and the next SEND fused
 // into the same kernel.
 //
-// One superstep = one launch of pr_dense (+ pr_finish for split rows):
+// One superstep = one launch of pr_pull (+ pr_finish for split rows):
 //   y_v   = sum_{u -> v} x_u (* w_uv)          PROCESS = msg (* w), REDUCE = +
 //   PR_v  = r * tele(v) + (1 - r) * y_v        APPLY, for every vertex
 //   x'_v  = PR_v / outdeg(v)                   SEND for the next superstep
@@ -13,13 +13,16 @@
 // Dense layout (built once per graph, on first use): vertices are relabelled
 // in decreasing in-degree order and the in-adjacency is rebuilt in the new
 // labels. Rows of similar length are then contiguous, so each degree class
-// gets its own number of lanes per row (from 1 up to a whole workgroup, so
-// that every lane gathers at most eight messages, all in flight at once; the
-// longest rows are cut into chunks reduced by separate workgroups), every
-// access to per-row data is a coalesced stream, and the most frequently
-// gathered messages (high-degree vertices) sit together at low labels where
-// they stay cache resident. The caller's rank vector is mapped into the new
-// labels by the first SEND and back after the last APPLY.
+// gets its own number of lanes per row (from 1 up to a wavefront, so that a
+// lane gathers up to eight messages at once; the longest rows are cut into
+// chunks reduced by separate wavefronts), every access to per-row data is a
+// coalesced stream, and the most frequently gathered messages (high-degree
+// vertices, which in RMAT graphs have high in- and out-degree alike) sit
+// together at low labels: the first of them (a tuning parameter, up to
+// kHotMax) are copied to LDS by every workgroup and read from there, the next
+// ones stay cache resident. The
+// caller's rank vector is mapped into the new labels by the first SEND and
+// back after the last APPLY.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -32,19 +35,21 @@ namespace gm {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / 64;
+constexpr int kPullThreads = 1024;  // one workgroup per CU: its LDS holds the hot messages
+constexpr int kPullWaves = kPullThreads / 64;
 constexpr int kUnroll = 8;  // most edges per lane; all of a lane's loads are in flight at once
-constexpr uint32_t kChunk = kThreads * kUnroll;  // edges per chunk of a split row
+constexpr int kHotMax = 32768;  // at most this many hot messages in LDS (128 KB)
+constexpr uint32_t kChunk = 4096;  // rows longer than this are cut into chunks of kChunk edges
 
 // Degree classes c = 0..kClasses-1: in-degree in (kClassMax[c-1],
 // kClassMax[c]] (class 0: in-degree 0), each row taken by kClassLanes[c]
-// lanes with kClassUnroll[c] edges per lane. Degree ranges double from class
-// to class, so at most half of a lane's load slots are padding. The last
-// class is a workgroup per row; rows longer than kChunk are split.
-constexpr int kClasses = 13;
-constexpr uint32_t kClassMax[kClasses] = {0, 1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048};
-constexpr int kClassLanes[kClasses] = {1, 1, 1, 1, 1, 2, 4, 8, 16, 32, 64, 256, 256};
-constexpr int kClassUnroll[kClasses] = {1, 1, 2, 4, 8, 8, 8, 8, 8, 8, 8, 4, 8};
+// lanes with kClassUnroll[c] edges per lane and pass. Degree ranges double
+// from class to class up to 512, so at most half of a lane's load slots are
+// padding; the last class (a wavefront per row, looping) reaches kChunk.
+constexpr int kClasses = 12;
+constexpr uint32_t kClassMax[kClasses] = {0, 1, 2, 4, 8, 16, 32, 64, 128, 256, 512, kChunk};
+constexpr int kClassLanes[kClasses] = {1, 1, 1, 1, 1, 2, 4, 8, 16, 32, 64, 64};
+constexpr int kClassUnroll[kClasses] = {1, 1, 2, 4, 8, 8, 8, 8, 8, 8, 8, 8};
 
 struct SplitChunk {
   uint32_t row;  // new label
@@ -60,13 +65,16 @@ struct SplitRow {
   uint32_t pad;
 };
 
-// Block layout of one pr_dense launch: chunk blocks first, then the classes
-// from the longest rows (c = kClasses - 1) down to in-degree 0 (c = 0).
+// Work units of one superstep, one wavefront each: the chunks of split rows
+// first, then the classes from the longest rows (c = kClasses - 1) down to
+// in-degree 1 (c = 1); a unit of class c is 64 / kClassLanes[c] consecutive
+// rows. Rows with in-degree 0 are written once per run (pr_const_rows).
 struct Bins {
   int64_t nchunks;
   int64_t class_begin[kClasses];  // first row (new label)
   int64_t class_rows[kClasses];
-  int64_t class_block0[kClasses];  // first block; decreases with c
+  int64_t class_unit0[kClasses];  // first unit; decreases with c (class 0: end)
+  int64_t nunits;
 };
 
 struct Dense {
@@ -85,7 +93,7 @@ struct Dense {
   SplitRow* splits = nullptr;
   double* partial = nullptr;
   int64_t nsplit = 0;
-  int64_t nblocks = 0;
+  int cus = 0;                  // compute units of the device
   Bins bins{};
 };
 
@@ -109,11 +117,15 @@ __device__ inline void apply_row(uint32_t v, double y, float r, int32_t seed,
 // `lanes` (this lane starts at b + sub), kU loads in flight per lane.
 // Positions past the end are clamped to the last edge and their values
 // dropped by a select, so every load is unconditional and all of a lane's
-// index loads, then all of its gathers, are issued back to back.
+// index loads, then all of its gathers, are issued back to back. Index and
+// edge-value streams are read once per superstep and loaded non-temporally,
+// which keeps the gathered messages in the caches. A message of a label
+// below hot_n comes from the LDS copy (the lane's global gather then reads
+// x[0], one line shared by all such lanes); the others from x.
 template <int kU, bool kWeighted>
 __device__ inline double row_partial(const int32_t* __restrict__ idx, const float* __restrict__ w,
-                                     const float* __restrict__ x, uint32_t b, uint32_t e,
-                                     int sub, int lanes) {
+                                     const float* __restrict__ x, const float* hot, int hot_n,
+                                     uint32_t b, uint32_t e, int sub, int lanes) {
   double acc = 0.0;
   for (uint32_t k0 = b + sub; k0 < e; k0 += kU * lanes) {
     uint32_t k[kU];
@@ -126,12 +138,17 @@ __device__ inline double row_partial(const int32_t* __restrict__ idx, const floa
     float wv[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      src[u] = idx[k[u]];
-      if constexpr (kWeighted) wv[u] = w[k[u]];
+      src[u] = __builtin_nontemporal_load(idx + k[u]);
+      if constexpr (kWeighted) wv[u] = __builtin_nontemporal_load(w + k[u]);
     }
     float val[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) val[u] = x[src[u]];
+    for (int u = 0; u < kU; ++u) {
+      const bool in_lds = src[u] < hot_n;
+      const float g = x[in_lds ? 0 : src[u]];
+      const float l = hot[in_lds ? src[u] : 0];
+      val[u] = in_lds ? l : g;
+    }
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       if constexpr (kWeighted) val[u] *= wv[u];
@@ -144,68 +161,61 @@ __device__ inline double row_partial(const int32_t* __restrict__ idx, const floa
 template <bool kWeighted>
 __device__ inline double row_partial_u(int unroll, const int32_t* __restrict__ idx,
                                        const float* __restrict__ w, const float* __restrict__ x,
-                                       uint32_t b, uint32_t e, int sub, int lanes) {
+                                       const float* hot, int hot_n, uint32_t b, uint32_t e,
+                                       int sub, int lanes) {
   switch (unroll) {
     case 1:
-      return row_partial<1, kWeighted>(idx, w, x, b, e, sub, lanes);
+      return row_partial<1, kWeighted>(idx, w, x, hot, hot_n, b, e, sub, lanes);
     case 2:
-      return row_partial<2, kWeighted>(idx, w, x, b, e, sub, lanes);
+      return row_partial<2, kWeighted>(idx, w, x, hot, hot_n, b, e, sub, lanes);
     case 4:
-      return row_partial<4, kWeighted>(idx, w, x, b, e, sub, lanes);
+      return row_partial<4, kWeighted>(idx, w, x, hot, hot_n, b, e, sub, lanes);
     default:
-      return row_partial<8, kWeighted>(idx, w, x, b, e, sub, lanes);
+      return row_partial<8, kWeighted>(idx, w, x, hot, hot_n, b, e, sub, lanes);
   }
 }
 
+// One superstep: y = A^T x (pull over in-edges), APPLY, next SEND. Each
+// workgroup first copies the messages of the hottest labels to LDS, then its
+// wavefronts take work units with a stride of all wavefronts of the grid.
 template <bool kWeighted, bool kPersonal>
-__global__ __launch_bounds__(kThreads) void pr_dense(
+__global__ __launch_bounds__(kPullThreads) void pr_pull(
     const uint32_t* __restrict__ off, const int32_t* __restrict__ idx,
     const float* __restrict__ w, const float* __restrict__ x_in,
     const float* __restrict__ inv_outdeg, float r, int32_t seed, float* __restrict__ x_out,
     float* __restrict__ pr_out, const SplitChunk* __restrict__ chunks,
-    double* __restrict__ partial, Bins bins) {
-  __shared__ double wsum[kWaves];
-  const int64_t blk = blockIdx.x;
-  const int tid = threadIdx.x;
-  if (blk < bins.nchunks) {
-    // One chunk of a split row: partial sum, combined by pr_finish.
-    const SplitChunk c = chunks[blk];
-    double acc =
-        row_partial<kUnroll, kWeighted>(idx, w, x_in, c.edge_begin, c.edge_end, tid, kThreads);
-    acc = group_sum(acc, 64);
-    if ((tid & 63) == 0) wsum[tid >> 6] = acc;
-    __syncthreads();
-    if (tid == 0) partial[blk] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
-    return;
+    double* __restrict__ partial, Bins bins, int hot_n) {
+  extern __shared__ float hot[];  // hot_n floats
+  for (int i = threadIdx.x; i < hot_n; i += kPullThreads) hot[i] = x_in[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * kPullWaves;
+  for (int64_t u = (int64_t)blockIdx.x * kPullWaves + (threadIdx.x >> 6); u < bins.nunits;
+       u += stride) {
+    if (u < bins.nchunks) {
+      // One chunk of a split row: partial sum, combined by pr_finish.
+      const SplitChunk c = chunks[u];
+      double acc = row_partial<kUnroll, kWeighted>(idx, w, x_in, hot, hot_n, c.edge_begin,
+                                                   c.edge_end, lane, 64);
+      acc = group_sum(acc, 64);
+      if (lane == 0) partial[u] = acc;
+      continue;
+    }
+    // Class of this unit: the class with the largest first unit <= u.
+    int cls = 1;
+    while (u < bins.class_unit0[cls]) ++cls;
+    const int lanes = kClassLanes[cls];
+    const int64_t local = (u - bins.class_unit0[cls]) * (64 / lanes) + lane / lanes;
+    const bool valid = local < bins.class_rows[cls];
+    const uint32_t row = (uint32_t)(bins.class_begin[cls] + (valid ? local : 0));
+    const int sub = lane % lanes;
+    double y = 0.0;
+    if (valid)
+      y = row_partial_u<kWeighted>(kClassUnroll[cls], idx, w, x_in, hot, hot_n, off[row],
+                                   off[row + 1], sub, lanes);
+    y = group_sum(y, lanes);
+    if (valid && sub == 0) apply_row<kPersonal>(row, y, r, seed, inv_outdeg, x_out, pr_out);
   }
-  // Degree class of this block: the class with the largest first block <= blk.
-  int cls = 0;
-  while (blk < bins.class_block0[cls]) ++cls;
-  const int lanes = kClassLanes[cls];
-  if (lanes == kThreads) {
-    // A whole workgroup per row.
-    const uint32_t row = (uint32_t)(bins.class_begin[cls] + (blk - bins.class_block0[cls]));
-    double acc = row_partial_u<kWeighted>(kClassUnroll[cls], idx, w, x_in, off[row], off[row + 1],
-                                          tid, kThreads);
-    acc = group_sum(acc, 64);
-    if ((tid & 63) == 0) wsum[tid >> 6] = acc;
-    __syncthreads();
-    if (tid == 0)
-      apply_row<kPersonal>(row, (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]), r, seed, inv_outdeg,
-                           x_out, pr_out);
-    return;
-  }
-  const int64_t rows_per_block = kThreads / lanes;
-  const int64_t local = (blk - bins.class_block0[cls]) * rows_per_block + tid / lanes;
-  const bool valid = local < bins.class_rows[cls];
-  const uint32_t row = (uint32_t)(bins.class_begin[cls] + (valid ? local : 0));
-  const int sub = tid % lanes;
-  double y = 0.0;
-  if (valid && cls > 0)
-    y = row_partial_u<kWeighted>(kClassUnroll[cls], idx, w, x_in, off[row], off[row + 1], sub,
-                                 lanes);
-  y = group_sum(y, lanes);
-  if (valid && sub == 0) apply_row<kPersonal>(row, y, r, seed, inv_outdeg, x_out, pr_out);
 }
 
 template <bool kPersonal>
@@ -384,7 +394,7 @@ void ensure_pull_schedule(gm_graph g, hipStream_t st) {
     Bins& bins = d->bins;
     bins.nchunks = (int64_t)chunks.size();
     d->nsplit = (int64_t)splits.size();
-    int64_t block = bins.nchunks;
+    int64_t unit = bins.nchunks;
     for (int c = kClasses - 1; c >= 0; --c) {
       const int64_t r0 = i;
       if (c == 0)
@@ -393,11 +403,16 @@ void ensure_pull_schedule(gm_graph g, hipStream_t st) {
         while (i < n && noff[i + 1] - noff[i] > kClassMax[c - 1]) ++i;
       bins.class_begin[c] = r0;
       bins.class_rows[c] = i - r0;
-      bins.class_block0[c] = block;
-      const int64_t rpb = kThreads / kClassLanes[c];
-      block += (bins.class_rows[c] + rpb - 1) / rpb;
+      bins.class_unit0[c] = unit;
+      if (c > 0) {
+        const int64_t rpu = 64 / kClassLanes[c];
+        unit += (bins.class_rows[c] + rpu - 1) / rpu;
+      }
     }
-    d->nblocks = block;
+    bins.nunits = unit;
+    int dev = 0;
+    GM_HIP(hipGetDevice(&dev));
+    GM_HIP(hipDeviceGetAttribute(&d->cus, hipDeviceAttributeMultiprocessorCount, dev));
     d->new_of = dalloc<int32_t>(n);
     d->old_of = dalloc<int32_t>(n);
     d->off = dalloc<uint32_t>(n + 1);
@@ -451,6 +466,19 @@ void ensure_pull_schedule(gm_graph g, hipStream_t st) {
   }
 }
 
+// Workgroups of one pr_pull launch: as many as fit on the device at once
+// with `lds` bytes of LDS each (the kernel strides over its work units), no
+// more than there are units.
+static unsigned pull_grid(Dense* d, size_t lds, bool weighted, bool personal) {
+  const void* k = weighted ? (personal ? (const void*)pr_pull<true, true> : (const void*)pr_pull<true, false>)
+                           : (personal ? (const void*)pr_pull<false, true> : (const void*)pr_pull<false, false>);
+  int per_cu = 0;
+  GM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kPullThreads, lds));
+  const int64_t fit = (int64_t)std::max(per_cu, 1) * std::max(d->cus, 1);
+  const int64_t want = (d->bins.nunits + kPullWaves - 1) / kPullWaves;
+  return (unsigned)std::max<int64_t>(1, std::min(fit, want));
+}
+
 // Supersteps of (personalised, optionally weighted) PageRank from the rank
 // vector `rank0` (caller labels). w: relabelled edge values or NULL. After
 // the last superstep the ranks go to `rank_out`; with `hist` (T + 1 rows),
@@ -474,27 +502,27 @@ static void pagerank_driver(gm_graph g, Dense* d, float r, int32_t iters, const 
                                                                  d->inv_outdeg, xo, po);
     GM_HIP(hipGetLastError());
   };
-  // The blocks of the in-degree-0 class come last; the per-superstep launch
-  // stops before them.
-  const unsigned grid = (unsigned)d->bins.class_block0[0];
+  const int hot_n = (int)std::min<int64_t>(std::min<int64_t>(g->tune.pr_hot, kHotMax), n);
+  const size_t lds = (size_t)hot_n * sizeof(float);
+  const unsigned grid = pull_grid(d, lds, weighted, personal);
   const_rows(d->x[1], d->pr);
   for (int32_t it = 0; it < iters; ++it) {
     const float* xin = d->x[it & 1];
     float* xout = d->x[(it + 1) & 1];
     float* pout = (hist || it == iters - 1) ? d->pr : nullptr;
     auto launch = [&](auto kern) {
-      if (grid > 0)
-        kern<<<grid, kThreads, 0, st>>>(d->off, d->idx, w, xin, d->inv_outdeg, r, seed_new, xout,
-                                        pout, d->chunks, d->partial, d->bins);
+      if (d->bins.nunits > 0)
+        kern<<<grid, kPullThreads, lds, st>>>(d->off, d->idx, w, xin, d->inv_outdeg, r, seed_new,
+                                              xout, pout, d->chunks, d->partial, d->bins, hot_n);
     };
     if (weighted && personal)
-      launch(pr_dense<true, true>);
+      launch(pr_pull<true, true>);
     else if (weighted)
-      launch(pr_dense<true, false>);
+      launch(pr_pull<true, false>);
     else if (personal)
-      launch(pr_dense<false, true>);
+      launch(pr_pull<false, true>);
     else
-      launch(pr_dense<false, false>);
+      launch(pr_pull<false, false>);
     if (d->nsplit > 0) {
       const unsigned fb = (unsigned)((d->nsplit + kThreads - 1) / kThreads);
       if (personal)

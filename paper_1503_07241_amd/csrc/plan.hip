@@ -184,7 +184,8 @@ gm_status check_tuning(const gm_tuning& t) {
            {"ppr_chunk", t.ppr_chunk, {64, 65536}},
            {"tc_wave_max", t.tc_wave_max, {64, 1024}},
            {"tc_wave_work", t.tc_wave_work, {256, 1u << 24}},
-           {"tc_block_work", t.tc_block_work, {256, 1u << 26}}};
+           {"tc_block_work", t.tc_block_work, {256, 1u << 26}},
+           {"pr_hot", t.pr_hot, {0, 32768}}};
   for (const F& x : f)
     if (x.v < x.r.lo || x.v > x.r.hi)
       return fail(GM_EINVAL, "%s = %u outside [%u, %u]", x.name, x.v, x.r.lo, x.r.hi);
@@ -200,6 +201,7 @@ gm_tuning to_abi(const Tuning& t) {
   o.tc_wave_max = t.tc_wave_max;
   o.tc_wave_work = t.tc_wave_work;
   o.tc_block_work = t.tc_block_work;
+  o.pr_hot = t.pr_hot;
   return o;
 }
 
@@ -211,6 +213,7 @@ void from_abi(const gm_tuning& o, Tuning* t) {
   t->tc_wave_max = o.tc_wave_max;
   t->tc_wave_work = o.tc_wave_work;
   t->tc_block_work = o.tc_block_work;
+  t->pr_hot = o.pr_hot;
 }
 
 struct Events {
@@ -516,6 +519,8 @@ gm_status gm_autotune(gm_graph g, const gm_program* prog, int32_t batched, const
       params.push_back({&Tuning::push_blocks, {512, 1024, 2048, 4096, 8192}});
     } else if (batched && kind == GM_PROG_PPR) {
       params.push_back({&Tuning::ppr_chunk, {128, 256, 512, 1024, 2048, 4096}});
+    } else if (!batched && kind == GM_PROG_PAGERANK) {
+      params.push_back({&Tuning::pr_hot, {0, 4096, 8192, 16384, 32768}});
     } else if (kind == GM_PROG_TC) {
       params.push_back({&Tuning::tc_wave_max, {256, 512, 1024}});
       params.push_back({&Tuning::tc_wave_work, {1u << 12, 1u << 14, 1u << 16}});
