@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--pr-only", type=int, default=0, metavar="K",
                     help="only run K PageRank passes (20 supersteps) and a 1 GiB copy, for "
                          "hardware-counter runs")
+    ap.add_argument("--tc-only", type=int, default=0, metavar="K",
+                    help="only run K triangle counts, for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -129,6 +131,15 @@ def main():
     log("generated RMAT scale %d in %.1fs" % (scale, time.time() - t0))
     if args.pr_only:
         pr_counter_run(gm, torch, n, s, d, args.pr_only)
+        return
+    if args.tc_only:
+        g = gm.Graph.from_coo(n, s, d, prep=gm.GM_PREP_UPPER_DAG)
+        tri = torch.empty(n, dtype=torch.int64, device=dev)
+        for _ in range(args.tc_only):
+            tri.zero_()
+            gm.run_vertex_program(g, gm.GM_PROG_TC, None, 1, tri)
+        torch.cuda.synchronize()
+        print(json.dumps({"tc_runs": args.tc_only, "m_dag": g.m}), flush=True)
         return
     g_sym = gm.Graph.from_coo(n, s, d, prep=gm.GM_PREP_DROP_SELF_LOOPS | gm.GM_PREP_SYMMETRIZE,
                               layouts=gm.GM_LAYOUT_OUT)

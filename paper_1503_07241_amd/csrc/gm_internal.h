@@ -85,6 +85,10 @@ struct PlanResult {
   unsigned long long edges;  // out-edges of the vertices that sent
 };
 
+// Neighbour-index arrays hold this many extra entries after the last edge,
+// so that kernels may read an edge's aligned 16-byte quad whole.
+constexpr int64_t kIdxPad = 4;
+
 // Most supersteps a captured BFS/SSSP run records.
 constexpr int kMaxPlanSteps = 64;
 

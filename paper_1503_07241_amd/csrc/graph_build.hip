@@ -289,7 +289,7 @@ void build_graph(gm_graph g, const int32_t* src, const int32_t* dst, const void*
   // Out-adjacency (always built: it fixes the canonical edge order).
   {
     DevBuf<uint32_t> off(n + 1);
-    DevBuf<int32_t> idx(m);
+    DevBuf<int32_t> idx(m + kIdxPad);
     row_offsets<<<grid_for(n + 1), kThreads, 0, s>>>(ukeys.p, m, b, n, off.p);
     if (m > 0) low_ids<<<grid_for(m), kThreads, 0, s>>>(ukeys.p, m, b, idx.p);
     GM_HIP(hipGetLastError());
@@ -325,7 +325,7 @@ void build_graph(gm_graph g, const int32_t* src, const int32_t* dst, const void*
       eid2.p = eq;
     }
     DevBuf<uint32_t> off(n + 1);
-    DevBuf<int32_t> idx(m);
+    DevBuf<int32_t> idx(m + kIdxPad);
     row_offsets<<<grid_for(n + 1), kThreads, 0, s>>>(tk.p, m, b, n, off.p);
     if (m > 0) low_ids<<<grid_for(m), kThreads, 0, s>>>(tk.p, m, b, idx.p);
     GM_HIP(hipGetLastError());

@@ -15,8 +15,9 @@
 // probe per element. The match count of edge (u -> v) is credited to the
 // receiver v, as APPLY prescribes. Owner/partner lists are built once per
 // graph and cut into work items of bounded size, one wavefront or workgroup
-// each. Partner lists are walked in windows of 64 per wavefront with their
-// elements spread evenly over the lanes (prefix sum + 6-step owner search).
+// each. Each lane walks one partner's in-list (an owner's partners are sorted
+// by list length, so the lanes of a wavefront walk similar lengths), four
+// elements per 16-byte load, one bucket read per element in most cases.
 // All counts are exact integers, independent of scheduling.
 #include <algorithm>
 #include <vector>
@@ -29,14 +30,28 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr uint32_t kWaveMax = 1024;          // owners with |in(x)| <= this: LDS table per wavefront
-constexpr uint32_t kBlockMax = 8192;         // owners up to this: LDS table per workgroup
-constexpr uint32_t kWaveSlots = 2048;
-constexpr uint32_t kBlockSlots = 16384;      // 64 KB
 constexpr uint32_t kCreditPartner = 0x80000000u;  // partner entry flag: credit goes to it
 constexpr int32_t kEmpty = -1;
-constexpr int kRounds = 4;                   // element loads in flight per lane
-constexpr int kBlockThreads = 512;           // workgroup size of the LDS-table class
-constexpr int kBlockWaves = kBlockThreads / 64;
+
+// Table classes by the owner's in-list length d: LDS tables per wavefront,
+// LDS tables per workgroup of growing size (small tables leave room for
+// more resident wavefronts), global tables for the longest lists. A table
+// has at least 2 d slots.
+enum TcKind { kWaveTable, kBlockTable, kGlobalTable };
+struct TcClass {
+  uint32_t max_d;
+  uint32_t slots;  // LDS slots per table
+  int threads;     // workgroup size
+  TcKind kind;
+};
+constexpr int kClassesTc = 7;
+constexpr TcClass kTcClass[kClassesTc] = {{256, 512, 256, kWaveTable},          // 2 KB per wavefront
+                                          {kWaveMax, 2048, 256, kWaveTable},    // 8 KB per wavefront
+                                          {2048, 4096, 512, kBlockTable},       // 16 KB
+                                          {4096, 8192, 512, kBlockTable},       // 32 KB
+                                          {8192, 16384, 512, kBlockTable},      // 64 KB
+                                          {16384, 32768, 1024, kBlockTable},    // 128 KB
+                                          {UINT32_MAX, 0, 512, kGlobalTable}};
 
 // A work item: owner x and a range of its partner list.
 struct Item {
@@ -47,8 +62,8 @@ struct Item {
 };
 
 struct TcPlan {
-  Item* items[3] = {nullptr, nullptr, nullptr};  // wave / block / global-table classes
-  int64_t nitems[3] = {0, 0, 0};
+  Item* items[kClassesTc] = {};  // per table class
+  int64_t nitems[kClassesTc] = {};
   uint32_t* work = nullptr;        // partner id | kCreditPartner, grouped by owner
   int32_t* gtable = nullptr;       // hash tables of the largest owners
   uint64_t* gtable_off = nullptr;  // per table: first slot
@@ -72,28 +87,69 @@ __device__ inline uint32_t hash_id(int32_t id) {
   return x;
 }
 
-__device__ inline void table_insert(int32_t* T, uint32_t mask, int32_t id) {
-  uint32_t s = hash_id(id) & mask;
-  while (atomicCAS(&T[s], kEmpty, id) != kEmpty) s = (s + 1) & mask;
-}
-
-// The table holds at most half as many ids as slots, so a probe ends.
-__device__ inline bool table_has(const int32_t* T, uint32_t mask, int32_t id) {
-  uint32_t s = hash_id(id) & mask;
+// Tables are buckets of 4 slots (one 16-byte LDS or global read); a key
+// lives in its home bucket or, when that is full, in the next buckets
+// (linear probing over buckets). At most half of the slots are used, so most
+// lookups read one bucket.
+__device__ inline void table_insert(int32_t* T, uint32_t bmask, int32_t id) {
+  uint32_t b = hash_id(id) & bmask;
   for (;;) {
-    const int32_t t = T[s];
-    if (t == id) return true;
-    if (t == kEmpty) return false;
-    s = (s + 1) & mask;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (atomicCAS(&T[4 * b + i], kEmpty, id) == kEmpty) return;
+    b = (b + 1) & bmask;
   }
 }
 
-__device__ inline uint32_t wave_incl_scan(uint32_t x, int lane) {
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t t = __shfl_up(x, o, 64);
-    if (lane >= o) x += t;
+// 1 if key is one of the bucket's slots.
+__device__ inline uint32_t in_bucket(int4 q, int32_t key) {
+  const uint32_t a = min((uint32_t)(q.x ^ key), (uint32_t)(q.y ^ key));
+  const uint32_t b = min((uint32_t)(q.z ^ key), (uint32_t)(q.w ^ key));
+  return min(a, b) == 0u ? 1u : 0u;
+}
+
+// True if no slot of the bucket is free (keys are >= 0, kEmpty is all ones).
+__device__ inline bool bucket_full(int4 q) {
+  return max(max((uint32_t)q.x, (uint32_t)q.y), max((uint32_t)q.z, (uint32_t)q.w)) != 0xFFFFFFFFu;
+}
+
+// Matches of the elements of in-list [s, e) in the table (nb = bmask + 1
+// buckets). Elements are read from the 16-byte aligned quads that hold them
+// (the index array is padded so the last quad is readable), two quads per
+// pass with both loads in flight; the eight home buckets are read back to
+// back, the rare continuations after.
+__device__ inline uint32_t count_list(const int4* T4, uint32_t bmask,
+                                      const int32_t* __restrict__ in_idx, uint32_t s,
+                                      uint32_t e) {
+  uint32_t cnt = 0;
+  for (uint32_t a = s & ~3u; a < e; a += 8) {
+    const int4 v0 = *reinterpret_cast<const int4*>(in_idx + a);
+    // the second quad may start at or past e: read the first one again then
+    const uint32_t a1 = a + 4 < e ? a + 4 : a;
+    const int4 v1 = *reinterpret_cast<const int4*>(in_idx + a1);
+    const int32_t key[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+    uint32_t bk[8];
+    int4 q[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      bk[i] = hash_id(key[i]) & bmask;
+      q[i] = T4[bk[i]];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const bool ok = a + i >= s && a + i < e;
+      uint32_t hit = in_bucket(q[i], key[i]);
+      bool more = ok && !hit && bucket_full(q[i]);
+      while (more) {
+        bk[i] = (bk[i] + 1) & bmask;
+        q[i] = T4[bk[i]];
+        hit = in_bucket(q[i], key[i]);
+        more = !hit && bucket_full(q[i]);
+      }
+      cnt += ok ? hit : 0u;
+    }
   }
-  return x;
+  return cnt;
 }
 
 __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
@@ -101,162 +157,113 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
   return v;
 }
 
-__device__ inline unsigned long long lanes_below(int lane) {
-  return lane ? (~0ull >> (64 - lane)) : 0ull;
-}
-
-// Walk partners [p_begin, p_end) with stride j_step (windows of 64 partners,
-// one per lane) through table T. Matches credited to the owner are returned;
-// matches credited to a partner are added to counts[partner]. wcnt is this
-// wavefront's 64-entry LDS scratch.
-__device__ inline unsigned long long walk_partners(const int32_t* T, uint32_t mask,
+// Partners [p_begin, p_end) of one owner, one partner per lane (the first
+// partner of this wavefront is p_begin + lane, then steps of j_step; an
+// owner's partners are sorted by decreasing in-list length, so the lanes of
+// a window walk lists of similar length). Matches credited to the owner are
+// returned; those credited to a partner are added to counts[partner].
+__device__ inline unsigned long long walk_partners(const int4* T4, uint32_t bmask,
                                                    const uint32_t* __restrict__ work,
                                                    uint32_t p_begin, uint32_t p_end,
                                                    uint32_t j_step,
                                                    const uint32_t* __restrict__ in_off,
                                                    const int32_t* __restrict__ in_idx,
-                                                   unsigned long long* counts, uint32_t* wcnt) {
+                                                   unsigned long long* counts) {
   const int lane = threadIdx.x & 63;
-  unsigned long long own_cnt = 0;
-  for (uint32_t j0 = p_begin; j0 < p_end; j0 += j_step) {
-    const uint32_t j = j0 + lane;
-    uint32_t pb = 0, pd = 0, entry = 0;
-    if (j < p_end) {
-      entry = work[j];
-      const int32_t y = (int32_t)(entry & ~kCreditPartner);
-      pb = in_off[y];
-      pd = in_off[y + 1] - pb;
+  unsigned long long own = 0;
+  for (uint32_t j = p_begin + lane; j < p_end; j += j_step) {
+    const uint32_t entry = work[j];
+    const int32_t y = (int32_t)(entry & ~kCreditPartner);
+    const uint32_t cnt = count_list(T4, bmask, in_idx, in_off[y], in_off[y + 1]);
+    if (entry & kCreditPartner) {
+      if (cnt) atomicAdd(&counts[y], (unsigned long long)cnt);
+    } else {
+      own += cnt;
     }
-    wcnt[lane] = 0;
-    const uint32_t incl = wave_incl_scan(pd, lane);
-    const uint32_t excl = incl - pd;
-    const uint32_t tot = __shfl(incl, 63, 64);
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-    for (uint32_t i0 = 0; i0 < tot; i0 += 64 * kRounds) {
-      // kRounds rounds of 64 elements: all element loads first, then probes.
-      int own[kRounds];
-      int32_t elem[kRounds];
-#pragma unroll
-      for (int r = 0; r < kRounds; ++r) {
-        const uint32_t i = i0 + r * 64 + lane;
-        int o = 0;  // partner owning element i: the last lane with excl <= i
-#pragma unroll
-        for (int step = 32; step > 0; step >>= 1) {
-          const uint32_t ex = __shfl(excl, o + step, 64);
-          if (ex <= i) o += step;
-        }
-        const uint32_t oex = __shfl(excl, o, 64);
-        const uint32_t opb = __shfl(pb, o, 64);
-        own[r] = o;
-        elem[r] = in_idx[i < tot ? opb + (i - oex) : 0u];
-      }
-#pragma unroll
-      for (int r = 0; r < kRounds; ++r) {
-        const uint32_t i = i0 + r * 64 + lane;
-        const int o = own[r];
-        const bool hit = i < tot && table_has(T, mask, elem[r]);
-        // Lanes of one partner are contiguous: the first lane of each run
-        // adds the run's hits to the partner's counter (one adder each).
-        const int prev = __shfl_up(o, 1, 64);
-        const bool head = i < tot && (lane == 0 || prev != o);
-        const unsigned long long heads = __ballot(head);
-        const unsigned long long hits = __ballot(hit);
-        const unsigned long long after = heads & ~lanes_below(lane + 1);
-        const int end = after ? __ffsll((long long)after) - 1 : 64;
-        const unsigned long long run = (end == 64 ? ~0ull : lanes_below(end)) & ~lanes_below(lane);
-        if (head) {
-          const uint32_t cnt = (uint32_t)__popcll(hits & run);
-          if (cnt) atomicAdd(&wcnt[o], cnt);
-        }
-      }
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-    const uint32_t mine = wcnt[lane];
-    if (j < p_end && mine) {
-      if (entry & kCreditPartner)
-        atomicAdd(&counts[entry & ~kCreditPartner], (unsigned long long)mine);
-      else
-        own_cnt += mine;
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
   }
-  return own_cnt;
+  return own;
 }
 
-// One wavefront per work item of an owner with |in(x)| <= kWaveMax.
+// Bucket mask of the table of an owner with d in-neighbours: at least twice
+// as many slots as keys, at least 16 buckets.
+__device__ __host__ inline uint32_t table_buckets(uint32_t d) {
+  uint32_t slots = 64;
+  while (slots < 2 * d) slots <<= 1;
+  return slots / 4;
+}
+
+// One wavefront per work item of an owner whose table fits kSlots slots.
+template <uint32_t kSlots>
 __global__ __launch_bounds__(kThreads) void tc_wave(const Item* __restrict__ items, int64_t nitems,
                                                     const uint32_t* __restrict__ in_off,
                                                     const int32_t* __restrict__ in_idx,
                                                     const uint32_t* __restrict__ work,
                                                     unsigned long long* counts) {
-  __shared__ int32_t tables[kWaves][kWaveSlots];
-  __shared__ uint32_t wcnt[kWaves][64];
+  __shared__ int4 tables[kWaves][kSlots / 4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t r = (int64_t)blockIdx.x * kWaves + wave;
   if (r >= nitems) return;  // the whole wavefront leaves together
   const Item it = items[r];
   const int32_t x = it.owner;
   const uint32_t b = in_off[x], d = in_off[x + 1] - b;
-  uint32_t slots = 64;
-  while (slots < 2 * d) slots <<= 1;
-  int32_t* T = tables[wave];
-  for (uint32_t k = lane; k < slots; k += 64) T[k] = kEmpty;
+  const uint32_t nb = table_buckets(d);
+  int4* T4 = tables[wave];
+  for (uint32_t k = lane; k < nb; k += 64) T4[k] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
-  for (uint32_t k = lane; k < d; k += 64) table_insert(T, slots - 1, in_idx[b + k]);
+  int32_t* T = reinterpret_cast<int32_t*>(T4);
+  for (uint32_t k = lane; k < d; k += 64) table_insert(T, nb - 1, in_idx[b + k]);
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
-  const unsigned long long c = wave_sum_u64(
-      walk_partners(T, slots - 1, work, it.p_begin, it.p_end, 64, in_off, in_idx, counts,
-                    wcnt[wave]));
+  const unsigned long long c =
+      wave_sum_u64(walk_partners(T4, nb - 1, work, it.p_begin, it.p_end, 64, in_off, in_idx, counts));
   if (lane == 0 && c) atomicAdd(&counts[x], c);
 }
 
-// One workgroup per work item; the owner's table in LDS (kGlobal = false) or
-// one of the precomputed global tables.
-template <bool kGlobal>
-__global__ __launch_bounds__(kBlockThreads) void tc_block(const Item* __restrict__ items,
-                                                     const uint32_t* __restrict__ in_off,
-                                                     const int32_t* __restrict__ in_idx,
-                                                     const uint32_t* __restrict__ work,
-                                                     const int32_t* __restrict__ gtable,
-                                                     const uint64_t* __restrict__ gtable_off,
-                                                     const uint32_t* __restrict__ gtable_mask,
-                                                     unsigned long long* counts) {
-  __shared__ int32_t ltable[kGlobal ? 1 : kBlockSlots];
-  __shared__ uint32_t wcnt[kBlockWaves][64];
-  __shared__ unsigned long long part[kBlockWaves];
+// One workgroup of kThr threads per work item; the owner's table in LDS
+// (kSlots slots; kSlots = 0: one of the precomputed global tables).
+// Wavefront w takes partners p_begin + 64 w + lane, then steps of one
+// workgroup.
+template <uint32_t kSlots, int kThr>
+__global__ __launch_bounds__(kThr) void tc_block(const Item* __restrict__ items,
+                                                 const uint32_t* __restrict__ in_off,
+                                                 const int32_t* __restrict__ in_idx,
+                                                 const uint32_t* __restrict__ work,
+                                                 const int32_t* __restrict__ gtable,
+                                                 const uint64_t* __restrict__ gtable_off,
+                                                 const uint32_t* __restrict__ gtable_mask,
+                                                 unsigned long long* counts) {
+  constexpr bool kGlobal = kSlots == 0;
+  constexpr int kW = kThr / 64;
+  __shared__ int4 ltable[kGlobal ? 1 : kSlots / 4];
+  __shared__ unsigned long long part[kW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const Item it = items[blockIdx.x];
   const int32_t x = it.owner;
-  const int32_t* T;
-  uint32_t mask;
+  const int4* T4;
+  uint32_t bmask;
   if constexpr (kGlobal) {
-    T = gtable + gtable_off[it.table];
-    mask = gtable_mask[it.table];
+    T4 = reinterpret_cast<const int4*>(gtable + gtable_off[it.table]);
+    bmask = gtable_mask[it.table];
   } else {
     const uint32_t b = in_off[x], d = in_off[x + 1] - b;
-    uint32_t slots = 64;
-    while (slots < 2 * d) slots <<= 1;
-    mask = slots - 1;
-    for (uint32_t k = threadIdx.x; k < slots; k += kBlockThreads) ltable[k] = kEmpty;
+    const uint32_t nb = table_buckets(d);
+    bmask = nb - 1;
+    for (uint32_t k = threadIdx.x; k < nb; k += kThr)
+      ltable[k] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
     __syncthreads();
-    for (uint32_t k = threadIdx.x; k < d; k += kBlockThreads)
-      table_insert(ltable, mask, in_idx[b + k]);
+    int32_t* T = reinterpret_cast<int32_t*>(ltable);
+    for (uint32_t k = threadIdx.x; k < d; k += kThr) table_insert(T, bmask, in_idx[b + k]);
     __syncthreads();
-    T = ltable;
+    T4 = ltable;
   }
-  const unsigned long long c =
-      wave_sum_u64(walk_partners(T, mask, work, it.p_begin + wave * 64, it.p_end,
-                                 kBlockWaves * 64, in_off, in_idx, counts, wcnt[wave]));
+  const unsigned long long c = wave_sum_u64(
+      walk_partners(T4, bmask, work, it.p_begin + wave * 64, it.p_end, kThr, in_off, in_idx, counts));
   if (lane == 0) part[wave] = c;
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long t = 0;
-    for (int i = 0; i < kBlockWaves; ++i) t += part[i];
+    for (int i = 0; i < kW; ++i) t += part[i];
     if (t) atomicAdd(&counts[x], t);
   }
 }
@@ -270,11 +277,11 @@ __global__ __launch_bounds__(kThreads) void build_tables(const int32_t* __restri
                                                          int32_t* __restrict__ gtable) {
   const int32_t x = owner[blockIdx.x];
   int32_t* T = gtable + toff[blockIdx.x];
-  const uint32_t mask = tmask[blockIdx.x];
+  const uint32_t bmask = tmask[blockIdx.x];
   const uint32_t b = in_off[x], d = in_off[x + 1] - b;
-  for (uint32_t k = threadIdx.x; k <= mask; k += kThreads) T[k] = kEmpty;
+  for (uint32_t k = threadIdx.x; k < 4 * (bmask + 1); k += kThreads) T[k] = kEmpty;
   __syncthreads();
-  for (uint32_t k = threadIdx.x; k < d; k += kThreads) table_insert(T, mask, in_idx[b + k]);
+  for (uint32_t k = threadIdx.x; k < d; k += kThreads) table_insert(T, bmask, in_idx[b + k]);
 }
 
 __global__ void sum_u64(const unsigned long long* __restrict__ a, int64_t n,
@@ -305,7 +312,7 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s);
 void free_tc_plan(gm_graph g) {
   TcPlan* p = plan(g);
   if (!p) return;
-  for (int c = 0; c < 3; ++c) dfree(p->items[c]);
+  for (int c = 0; c < kClassesTc; ++c) dfree(p->items[c]);
   dfree(p->work);
   dfree(p->gtable);
   dfree(p->gtable_off);
@@ -359,11 +366,18 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
       else
         work[cur[v]++] = (uint32_t)u;  // owner v scans in(u), credits itself
     }
+  // Each owner's partners by decreasing in-list length (lanes of a window then
+  // walk lists of similar length).
+  for (int64_t x = 0; x < n; ++x)
+    std::stable_sort(work.begin() + work_off[x], work.begin() + work_off[x + 1],
+                     [&](uint32_t a, uint32_t b) {
+                       return din(a & ~kCreditPartner) > din(b & ~kCreditPartner);
+                     });
   // Work items: each owner's partners cut where the scanned elements reach
   // the class's budget (a partner longer than the budget is an item alone);
   // workgroup items also hold at most one 64-partner window per wavefront so
   // that all of their wavefronts have partners to walk.
-  std::vector<Item> items[3];
+  std::vector<Item> items[kClassesTc];
   std::vector<uint64_t> goff;
   std::vector<uint32_t> gmask;
   std::vector<int32_t> gowner;
@@ -372,18 +386,25 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
     const uint32_t p0 = work_off[x], p1 = work_off[x + 1];
     if (p0 == p1) continue;
     const uint32_t d = din(x);
-    const int cls = d <= wave_max ? 0 : d <= kBlockMax ? 1 : 2;
-    const uint32_t budget = cls == 0 ? wave_work : block_work;
-    const uint32_t max_partners = cls == 0 ? UINT32_MAX : (uint32_t)kBlockWaves * 64;
+    int cls = 0;
+    if (d <= wave_max) {
+      cls = d <= kTcClass[0].max_d ? 0 : 1;
+    } else {
+      cls = 2;
+      while (d > kTcClass[cls].max_d) ++cls;
+    }
+    const TcClass& tcl = kTcClass[cls];
+    const uint32_t budget = tcl.kind == kWaveTable ? wave_work : block_work;
+    // a workgroup item holds at most one partner per thread
+    const uint32_t max_partners = tcl.kind == kWaveTable ? UINT32_MAX : (uint32_t)tcl.threads;
     uint32_t table = 0;
-    if (cls == 2) {
-      uint64_t slots = 64;
-      while (slots < 2ull * d) slots <<= 1;
+    if (tcl.kind == kGlobalTable) {
+      const uint32_t nb = table_buckets(d);
       table = (uint32_t)goff.size();
       goff.push_back(gslots);
-      gmask.push_back((uint32_t)(slots - 1));
+      gmask.push_back(nb - 1);
       gowner.push_back((int32_t)x);
-      gslots += slots;
+      gslots += 4ull * nb;
     }
     uint32_t start = p0;
     uint64_t acc = 0;
@@ -400,7 +421,7 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
     items[cls].push_back({(int32_t)x, start, p1, table});
   }
   // Largest items first so the long ones start early.
-  for (int c = 0; c < 3; ++c)
+  for (int c = 0; c < kClassesTc; ++c)
     std::stable_sort(items[c].begin(), items[c].end(), [&](const Item& a, const Item& b) {
       return a.p_end - a.p_begin > b.p_end - b.p_begin;
     });
@@ -410,7 +431,7 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
   p->wave_work = wave_work;
   p->block_work = block_work;
   try {
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < kClassesTc; ++c) {
       p->nitems[c] = (int64_t)items[c].size();
       p->items[c] = dalloc<Item>(items[c].size());
       if (!items[c].empty())
@@ -447,18 +468,32 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
 void run_triangle_count(gm_graph g, unsigned long long* counts, unsigned long long* total_host,
                         hipStream_t s) {
   TcPlan* p = ensure_plan(g, s);
-  if (p->nitems[2] > 0)
-    tc_block<true><<<(unsigned)p->nitems[2], kBlockThreads, 0, s>>>(
-        p->items[2], g->in_off, g->in_idx, p->work, p->gtable, p->gtable_off, p->gtable_mask,
-        counts);
-  if (p->nitems[1] > 0)
-    tc_block<false><<<(unsigned)p->nitems[1], kBlockThreads, 0, s>>>(
-        p->items[1], g->in_off, g->in_idx, p->work, nullptr, nullptr, nullptr, counts);
-  if (p->nitems[0] > 0) {
-    const int64_t blocks = (p->nitems[0] + kWaves - 1) / kWaves;
-    tc_wave<<<(unsigned)blocks, kThreads, 0, s>>>(p->items[0], p->nitems[0], g->in_off, g->in_idx,
-                                                  p->work, counts);
-  }
+  static_assert(kTcClass[0].slots == 512 && kTcClass[1].slots == 2048 &&
+                    kTcClass[2].slots == 4096 && kTcClass[3].slots == 8192 &&
+                    kTcClass[4].slots == 16384 && kTcClass[5].slots == 32768 &&
+                    kTcClass[5].threads == 1024 && kTcClass[6].kind == kGlobalTable,
+                "kernel instances below follow the class table");
+  // longest owners first, so the long items start early
+  const auto block = [&](int c, auto kern) {
+    if (p->nitems[c] > 0)
+      kern<<<(unsigned)p->nitems[c], kTcClass[c].threads, 0, s>>>(
+          p->items[c], g->in_off, g->in_idx, p->work, p->gtable, p->gtable_off, p->gtable_mask,
+          counts);
+  };
+  block(6, tc_block<0, 512>);
+  block(5, tc_block<32768, 1024>);
+  block(4, tc_block<16384, 512>);
+  block(3, tc_block<8192, 512>);
+  block(2, tc_block<4096, 512>);
+  const auto wave = [&](int c, auto kern) {
+    if (p->nitems[c] > 0) {
+      const int64_t blocks = (p->nitems[c] + kWaves - 1) / kWaves;
+      kern<<<(unsigned)blocks, kThreads, 0, s>>>(p->items[c], p->nitems[c], g->in_off, g->in_idx,
+                                                 p->work, counts);
+    }
+  };
+  wave(1, tc_wave<2048>);
+  wave(0, tc_wave<512>);
   GM_HIP(hipGetLastError());
   if (total_host) {
     zero_u64<<<1, 64, 0, s>>>(p->total, 1);

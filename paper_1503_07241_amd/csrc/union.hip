@@ -47,7 +47,7 @@ void build_union(gm_graph u, const gm_graph* parts, int32_t count, hipStream_t s
   const bool weighted = u->wtype != GM_W_NONE;
   const bool in = (u->layouts & GM_LAYOUT_IN) != 0;
   u->out_off = dalloc<uint32_t>(n + 1);
-  u->out_idx = dalloc<int32_t>(m);
+  u->out_idx = dalloc<int32_t>(m + kIdxPad);
   u->inv_outdeg = dalloc<float>(n);
   u->device_bytes = (n + 1) * 4 + m * 4 + n * 4;
   if (weighted) {
@@ -56,7 +56,7 @@ void build_union(gm_graph u, const gm_graph* parts, int32_t count, hipStream_t s
   }
   if (in) {
     u->in_off = dalloc<uint32_t>(n + 1);
-    u->in_idx = dalloc<int32_t>(m);
+    u->in_idx = dalloc<int32_t>(m + kIdxPad);
     u->in_eid = dalloc<uint32_t>(m);
     u->device_bytes += (n + 1) * 4 + 2 * m * 4;
     if (weighted) {
