@@ -9,10 +9,11 @@
 // N_triangles of Eq. (7).
 //
 // Work organisation: the intersection for DAG edge (u -> v) is computed by
-// the endpoint whose in-list is longer (its "owner"; ties go to v). An owner
-// x puts in(x) in a hash table (LDS, or global memory for very long lists)
-// once, then streams the shorter in-list of every partner through it, one
-// probe per element. The match count of edge (u -> v) is credited to the
+// one endpoint (its "owner"): an owner x puts in(x) in a hash table (LDS, or
+// global memory for very long lists) once, then streams the in-list of every
+// partner through it, one probe per element, stopping at the first element
+// >= x (in(x) holds only smaller ids). The endpoint whose partner stream is
+// shorter owns the edge. The match count of edge (u -> v) is credited to the
 // receiver v, as APPLY prescribes. Owner/partner lists are built once per
 // graph and cut into work items of bounded size, one wavefront or workgroup
 // each. Each lane walks one partner's in-list (an owner's partners are sorted
@@ -113,20 +114,28 @@ __device__ inline bool bucket_full(int4 q) {
   return max(max((uint32_t)q.x, (uint32_t)q.y), max((uint32_t)q.z, (uint32_t)q.w)) != 0xFFFFFFFFu;
 }
 
-// Matches of the elements of in-list [s, e) in the table (nb = bmask + 1
-// buckets). Elements are read from the 16-byte aligned quads that hold them
+// Matches of the elements below lim of the sorted in-list [s, e) in the
+// table (nb = bmask + 1 buckets); the walk stops at the first element >= lim. Elements are read from the 16-byte aligned quads that hold them
 // (the index array is padded so the last quad is readable), two quads per
-// pass with both loads in flight; the eight home buckets are read back to
-// back, the rare continuations after.
+// pass; the next pass's quads are loaded before this pass's elements are
+// probed, and the eight home buckets are read back to back, the rare
+// continuations after. Positions past the list are clamped to a quad
+// already read, so every load is unconditional.
 __device__ inline uint32_t count_list(const int4* T4, uint32_t bmask,
                                       const int32_t* __restrict__ in_idx, uint32_t s,
-                                      uint32_t e) {
+                                      uint32_t e, int32_t lim) {
   uint32_t cnt = 0;
-  for (uint32_t a = s & ~3u; a < e; a += 8) {
-    const int4 v0 = *reinterpret_cast<const int4*>(in_idx + a);
-    // the second quad may start at or past e: read the first one again then
-    const uint32_t a1 = a + 4 < e ? a + 4 : a;
-    const int4 v1 = *reinterpret_cast<const int4*>(in_idx + a1);
+  uint32_t a = s & ~3u;
+  if (a >= e) return 0;
+  int4 v0 = *reinterpret_cast<const int4*>(in_idx + a);
+  int4 v1 = *reinterpret_cast<const int4*>(in_idx + (a + 4 < e ? a + 4 : a));
+  for (;;) {
+    const uint32_t an = a + 8;
+    const bool more = an < e;
+    const uint32_t p0 = more ? an : a;
+    const uint32_t p1 = an + 4 < e ? an + 4 : p0;
+    const int4 w0 = *reinterpret_cast<const int4*>(in_idx + p0);
+    const int4 w1 = *reinterpret_cast<const int4*>(in_idx + p1);
     const int32_t key[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
     uint32_t bk[8];
     int4 q[8];
@@ -135,19 +144,26 @@ __device__ inline uint32_t count_list(const int4* T4, uint32_t bmask,
       bk[i] = hash_id(key[i]) & bmask;
       q[i] = T4[bk[i]];
     }
+    bool past = false;  // an element >= lim: the rest of the sorted list is too
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const bool ok = a + i >= s && a + i < e;
+      const bool in_list = a + i >= s && a + i < e;
+      past |= in_list && key[i] >= lim;
+      const bool ok = in_list && key[i] < lim;
       uint32_t hit = in_bucket(q[i], key[i]);
-      bool more = ok && !hit && bucket_full(q[i]);
-      while (more) {
+      bool more_probe = ok && !hit && bucket_full(q[i]);
+      while (more_probe) {
         bk[i] = (bk[i] + 1) & bmask;
         q[i] = T4[bk[i]];
         hit = in_bucket(q[i], key[i]);
-        more = !hit && bucket_full(q[i]);
+        more_probe = !hit && bucket_full(q[i]);
       }
       cnt += ok ? hit : 0u;
     }
+    if (!more || past) break;
+    a = an;
+    v0 = w0;
+    v1 = w1;
   }
   return cnt;
 }
@@ -162,7 +178,7 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
 // owner's partners are sorted by decreasing in-list length, so the lanes of
 // a window walk lists of similar length). Matches credited to the owner are
 // returned; those credited to a partner are added to counts[partner].
-__device__ inline unsigned long long walk_partners(const int4* T4, uint32_t bmask,
+__device__ inline unsigned long long walk_partners(const int4* T4, uint32_t bmask, int32_t owner,
                                                    const uint32_t* __restrict__ work,
                                                    uint32_t p_begin, uint32_t p_end,
                                                    uint32_t j_step,
@@ -174,7 +190,7 @@ __device__ inline unsigned long long walk_partners(const int4* T4, uint32_t bmas
   for (uint32_t j = p_begin + lane; j < p_end; j += j_step) {
     const uint32_t entry = work[j];
     const int32_t y = (int32_t)(entry & ~kCreditPartner);
-    const uint32_t cnt = count_list(T4, bmask, in_idx, in_off[y], in_off[y + 1]);
+    const uint32_t cnt = count_list(T4, bmask, in_idx, in_off[y], in_off[y + 1], owner);
     if (entry & kCreditPartner) {
       if (cnt) atomicAdd(&counts[y], (unsigned long long)cnt);
     } else {
@@ -216,7 +232,7 @@ __global__ __launch_bounds__(kThreads) void tc_wave(const Item* __restrict__ ite
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
   const unsigned long long c =
-      wave_sum_u64(walk_partners(T4, nb - 1, work, it.p_begin, it.p_end, 64, in_off, in_idx, counts));
+      wave_sum_u64(walk_partners(T4, nb - 1, x, work, it.p_begin, it.p_end, 64, in_off, in_idx, counts));
   if (lane == 0 && c) atomicAdd(&counts[x], c);
 }
 
@@ -258,7 +274,7 @@ __global__ __launch_bounds__(kThr) void tc_block(const Item* __restrict__ items,
     T4 = ltable;
   }
   const unsigned long long c = wave_sum_u64(
-      walk_partners(T4, bmask, work, it.p_begin + wave * 64, it.p_end, kThr, in_off, in_idx, counts));
+      walk_partners(T4, bmask, x, work, it.p_begin + wave * 64, it.p_end, kThr, in_off, in_idx, counts));
   if (lane == 0) part[wave] = c;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -339,40 +355,63 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
   }
   const int64_t n = g->n, m = g->m;
   std::vector<uint32_t> in_off(n + 1), out_off(n + 1);
-  std::vector<int32_t> out_idx(m);
+  std::vector<int32_t> out_idx(m), in_idx(m);
   GM_HIP(hipMemcpyAsync(in_off.data(), g->in_off, (n + 1) * 4, hipMemcpyDeviceToHost, s));
   GM_HIP(hipMemcpyAsync(out_off.data(), g->out_off, (n + 1) * 4, hipMemcpyDeviceToHost, s));
-  if (m > 0)
+  if (m > 0) {
     GM_HIP(hipMemcpyAsync(out_idx.data(), g->out_idx, m * 4, hipMemcpyDeviceToHost, s));
+    GM_HIP(hipMemcpyAsync(in_idx.data(), g->in_idx, m * 4, hipMemcpyDeviceToHost, s));
+  }
   GM_HIP(hipStreamSynchronize(s));
   auto din = [&](int64_t v) { return in_off[v + 1] - in_off[v]; };
-  // Owner of DAG edge (u -> v): the endpoint with the longer in-list (ties: v).
-  // Edges with an empty in-list at either end close no triangle and are skipped.
+  // For DAG edge (u -> v), u < v: in(u) ∩ in(v) = in(u) ∩ (in(v) ∩ [0, u)).
+  // Either v owns it (its table holds in(v); lanes stream in(u), |in(u)|
+  // elements, credit to v = the owner) or u owns it (table in(u); lanes stream
+  // the prefix of in(v) below u, credit to the partner v). The cheaper stream
+  // decides; an edge with nothing to stream closes no triangle. Streams stop
+  // at the owner's id in both cases, since in(x) holds only ids below x.
+  std::vector<uint32_t> cost(m, 0);  // streamed elements per DAG edge (0: skipped)
+  std::vector<uint8_t> by_u(m, 0);   // 1: u owns the edge
   std::vector<uint32_t> work_off(n + 1, 0);
   for (int64_t u = 0; u < n; ++u)
     for (uint32_t e = out_off[u]; e < out_off[u + 1]; ++e) {
       const int32_t v = out_idx[e];
-      if (din(u) == 0 || din(v) == 0) continue;
-      ++work_off[(din(u) > din(v) ? u : v) + 1];
+      const uint32_t a = din(u);
+      const int32_t* vb = in_idx.data() + in_off[v];
+      const uint32_t b = (uint32_t)(std::lower_bound(vb, vb + din(v), (int32_t)u) - vb);
+      if (a == 0 || b == 0) continue;
+      by_u[e] = b < a ? 1 : 0;
+      cost[e] = b < a ? b : a;
+      ++work_off[(by_u[e] ? u : v) + 1];
     }
   for (int64_t v = 0; v < n; ++v) work_off[v + 1] += work_off[v];
-  std::vector<uint32_t> work(work_off[n]), cur(work_off.begin(), work_off.end() - 1);
+  std::vector<uint32_t> work(work_off[n]), wcost(work_off[n]);
+  std::vector<uint32_t> cur(work_off.begin(), work_off.end() - 1);
   for (int64_t u = 0; u < n; ++u)
     for (uint32_t e = out_off[u]; e < out_off[u + 1]; ++e) {
+      if (cost[e] == 0) continue;
       const int32_t v = out_idx[e];
-      if (din(u) == 0 || din(v) == 0) continue;
-      if (din(u) > din(v))
-        work[cur[u]++] = (uint32_t)v | kCreditPartner;  // owner u scans in(v), credits v
-      else
-        work[cur[v]++] = (uint32_t)u;  // owner v scans in(u), credits itself
+      const uint32_t j = by_u[e] ? cur[u]++ : cur[v]++;
+      work[j] = by_u[e] ? ((uint32_t)v | kCreditPartner) : (uint32_t)u;
+      wcost[j] = cost[e];
     }
-  // Each owner's partners by decreasing in-list length (lanes of a window then
+  // Each owner's partners by decreasing stream length (lanes of a window then
   // walk lists of similar length).
-  for (int64_t x = 0; x < n; ++x)
-    std::stable_sort(work.begin() + work_off[x], work.begin() + work_off[x + 1],
-                     [&](uint32_t a, uint32_t b) {
-                       return din(a & ~kCreditPartner) > din(b & ~kCreditPartner);
-                     });
+  {
+    std::vector<uint64_t> tmp;
+    for (int64_t x = 0; x < n; ++x) {
+      const uint32_t p0 = work_off[x], p1 = work_off[x + 1];
+      if (p1 - p0 < 2) continue;
+      tmp.resize(p1 - p0);
+      for (uint32_t j = p0; j < p1; ++j)
+        tmp[j - p0] = ((uint64_t)(UINT32_MAX - wcost[j]) << 32) | work[j];
+      std::sort(tmp.begin(), tmp.end());
+      for (uint32_t j = p0; j < p1; ++j) {
+        work[j] = (uint32_t)tmp[j - p0];
+        wcost[j] = UINT32_MAX - (uint32_t)(tmp[j - p0] >> 32);
+      }
+    }
+  }
   // Work items: each owner's partners cut where the scanned elements reach
   // the class's budget (a partner longer than the budget is an item alone);
   // workgroup items also hold at most one 64-partner window per wavefront so
@@ -409,8 +448,7 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
     uint32_t start = p0;
     uint64_t acc = 0;
     for (uint32_t j = p0; j < p1; ++j) {
-      const uint32_t y = work[j] & ~kCreditPartner;
-      const uint64_t len = din(y);
+      const uint64_t len = wcost[j];
       if (acc > 0 && (acc + len > budget || j - start >= max_partners)) {
         items[cls].push_back({(int32_t)x, start, j, table});
         start = j;
