@@ -65,6 +65,8 @@ def _load():
         lib.orc_tc_total.restype = ctypes.c_uint64
         lib.orc_cf.argtypes = [i64, i64, i64, vp, vp, vp, i32, vp, vp, f64, vp, vp, vp]
         lib.orc_cf.restype = ctypes.c_int
+        lib.orc_bfs_certificate.argtypes = [i64, i64, vp, vp, vp, i32, i32]
+        lib.orc_bfs_certificate.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -248,6 +250,38 @@ def pagerank_vjp_w(g: Graph, w: np.ndarray, c: np.ndarray, r: float = 0.15, T: i
                                   _p(grad)):
         raise MemoryError
     return grad
+
+
+def bfs_certificate(n: int, src: np.ndarray, dst: np.ndarray, levels: np.ndarray,
+                    root: int) -> int:
+    """0 iff `levels` are the BFS hop distances from `root` (Sec. 3 II,
+    Eq. (2)) on the undirected graph whose directed entries are (src, dst),
+    both directions listed; else the code of the first failed condition
+    (see oracle.c). Linear in the number of entries, so it checks results at
+    any size."""
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    lv = np.ascontiguousarray(levels, dtype=np.int32)
+    return int(_load().orc_bfs_certificate(n, len(src), _p(src), _p(dst), _p(lv), root, INF_I32))
+
+
+def pagerank_step_rows(prev: np.ndarray, outdeg: np.ndarray, src: np.ndarray, dst: np.ndarray,
+                       rows: np.ndarray, r: float = 0.15, w: np.ndarray | None = None) -> np.ndarray:
+    """One superstep of Eq. (1) (with edge weights w when given) for the
+    listed rows only, in FP64: r + (1 - r) * sum over the edges (u -> v) with
+    v a listed row of w_uv * prev[u] / outdeg(u). (src, dst[, w]) must hold
+    every in-edge of the listed rows (other edges are ignored)."""
+    rows = np.asarray(rows, dtype=np.int64)
+    order = np.argsort(rows, kind="stable")
+    y = np.zeros(len(rows), dtype=np.float64)
+    sel = np.isin(dst, rows)
+    su = src[sel].astype(np.int64)
+    sv = dst[sel].astype(np.int64)
+    val = prev[su].astype(np.float64) / outdeg[su].astype(np.float64)
+    if w is not None:
+        val = val * w[sel].astype(np.float64)
+    np.add.at(y, order[np.searchsorted(rows[order], sv)], val)
+    return r + (1.0 - r) * y
 
 
 def dag_in_lists(dag: Graph) -> Graph:

@@ -377,3 +377,37 @@ int orc_cf(int64_t n_users, int64_t n_items, int64_t m, const int32_t* user, con
   *loss = L;
   return 0;
 }
+
+/*
+ * BFS certificate (Sec. 3 II, Eq. (2)): levels lv of an undirected graph given
+ * as a list of directed entries (both directions of every edge present) are
+ * the hop distances from root iff lv[root] = 0, every entry (u, v) with u
+ * reached has v reached with lv[v] <= lv[u] + 1, an entry never joins a
+ * reached and an unreached vertex, and every reached v != root has an entry
+ * (u, v) with lv[u] = lv[v] - 1. The first two give lv <= distance along
+ * any path; the parent entries give a path of length lv[v]. Returns 0 if
+ * certified, else a code naming the first failed condition (1 root, 2 edge
+ * step, 3 reached/unreached mix, 4 missing parent, 5 negative level).
+ */
+int orc_bfs_certificate(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                        const int32_t* lv, int32_t root, int32_t inf) {
+  if (lv[root] != 0) return 1;
+  uint8_t* parent = (uint8_t*)calloc((size_t)n, 1);
+  if (!parent) return -1;
+  int rc = 0;
+  for (int64_t e = 0; e < m && rc == 0; ++e) {
+    const int32_t a = lv[src[e]], b = lv[dst[e]];
+    if (a == inf || b == inf) {
+      if (a != b) rc = 3;
+      continue;
+    }
+    if (b > a + 1) rc = 2;
+    if (b == a + 1) parent[dst[e]] = 1;
+  }
+  for (int64_t v = 0; v < n && rc == 0; ++v) {
+    if (lv[v] < 0) rc = 5;
+    else if (lv[v] != inf && v != root && !parent[v]) rc = 4;
+  }
+  free(parent);
+  return rc;
+}

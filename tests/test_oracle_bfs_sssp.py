@@ -203,3 +203,36 @@ def test_bsp_resume_equals_uninterrupted():
     assert it1 == 3
     p2, _, it2 = oracle.run_min_program(g, p1, a1, weighted=True)
     assert np.array_equal(p2, full) and it1 + it2 == it_full
+
+
+def test_oracle_bfs_certificate_function():
+    """oracle.bfs_certificate (the linear-time check used at full scale)
+    accepts true levels (oracle BFS and SciPy's unweighted shortest paths) and
+    rejects each kind of planted error."""
+    n, s, d = gg.rmat(11)
+    g = oracle.prepare(n, s, d, mode="symmetric")
+    rows = g.rows().astype(np.int32)
+    level = oracle.bfs(g, 0)
+    assert oracle.bfs_certificate(n, rows, g.idx, level, 0) == 0
+    A = sp.csr_matrix((np.ones(g.m), g.idx, g.off), shape=(n, n))
+    dsp = csgraph.shortest_path(A, unweighted=True, indices=0)
+    sc = np.where(np.isinf(dsp), INF_I, dsp).astype(np.int32)
+    assert oracle.bfs_certificate(n, rows, g.idx, sc, 0) == 0
+    reached = np.flatnonzero((level != INF_I) & (level > 0))
+    unreached = np.flatnonzero(level == INF_I)
+    assert len(unreached) > 0
+    bad = level.copy(); bad[0] = 1
+    assert oracle.bfs_certificate(n, rows, g.idx, bad, 0) == 1
+    bad = level.copy(); bad[reached[7]] += 1            # too far from a neighbour
+    assert oracle.bfs_certificate(n, rows, g.idx, bad, 0) in (2, 4)
+    bad = level.copy(); bad[reached[7]] -= 1            # no parent one level up
+    assert oracle.bfs_certificate(n, rows, g.idx, bad, 0) in (2, 4)
+    bad = level.copy(); bad[reached[3]] = INF_I          # reached vertex dropped
+    assert oracle.bfs_certificate(n, rows, g.idx, bad, 0) == 3
+    iso = np.flatnonzero(g.degree() == 0)
+    bad = level.copy(); bad[iso[0]] = 2                  # isolated vertex "reached"
+    assert oracle.bfs_certificate(n, rows, g.idx, bad, 0) == 4
+    # a planted mistake the numpy certificate above also catches
+    with pytest.raises(AssertionError):
+        b2 = level.copy(); b2[reached[7]] += 1
+        check_bfs_certificate(g, 0, b2)

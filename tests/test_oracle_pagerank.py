@@ -162,3 +162,25 @@ def test_personalized_on_cycle_closed_form():
     ppr = oracle.personalized_pagerank(g, 0, R, 400)
     want = R * (1 - R) ** np.arange(n) / (1 - (1 - R) ** n)
     assert np.allclose(ppr, want, rtol=1e-12)
+
+
+def test_pagerank_step_rows_is_one_superstep():
+    """oracle.pagerank_step_rows (one superstep for sampled rows, used at full
+    scale) reproduces step t -> t + 1 of the FP64 history, unweighted and
+    weighted, including rows with no in-edge (value r)."""
+    n, s, d = gg.rmat(10, seed=7)
+    g = oracle.prepare(n, s, d)
+    src, dst = g.rows(), g.idx.astype(np.int64)
+    outdeg = g.degree()
+    rows = np.array([0, 1, 2, 5, 17, 100, 511, n - 1])
+    hist = oracle.pagerank_history(g, 0.15, 5)
+    for t in range(5):
+        got = oracle.pagerank_step_rows(hist[t], outdeg, src, dst, rows, 0.15)
+        assert np.allclose(got, hist[t + 1][rows], rtol=1e-13, atol=0)
+    w = gg.weights_f32(g.rows().astype(np.int32), g.idx, 3, 0.5, 1.5).astype(np.float64)
+    hw = oracle.pagerank_history(g, 0.15, 3, w=w)
+    got = oracle.pagerank_step_rows(hw[2], outdeg, src, dst, rows, 0.15, w=w)
+    assert np.allclose(got, hw[3][rows], rtol=1e-13, atol=0)
+    indeg = np.bincount(dst, minlength=n)
+    z = np.flatnonzero(indeg == 0)[:3]
+    assert np.allclose(oracle.pagerank_step_rows(hist[2], outdeg, src, dst, z), 0.15)
