@@ -274,7 +274,9 @@ def pagerank_step_rows(prev: np.ndarray, outdeg: np.ndarray, src: np.ndarray, ds
     rows = np.asarray(rows, dtype=np.int64)
     order = np.argsort(rows, kind="stable")
     y = np.zeros(len(rows), dtype=np.float64)
-    sel = np.isin(dst, rows)
+    mark = np.zeros(len(prev), dtype=bool)
+    mark[rows] = True
+    sel = mark[dst]
     su = src[sel].astype(np.int64)
     sv = dst[sel].astype(np.int64)
     val = prev[su].astype(np.float64) / outdeg[su].astype(np.float64)
