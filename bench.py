@@ -24,7 +24,11 @@ measured against the plain runs they replace, on the same GPU:
   collaborative filtering on 480,189 x 17,770 users x items with 100M
   ratings, K = 32: loss (forward) against both factor gradients (adjoint);
   weighted PageRank on RMAT scale 22, T = 20: forward against the
-  edge-weight gradient (adjoint).
+  edge-weight gradient (adjoint);
+  RMAT scale 26 (67,108,864 vertices): PageRank per superstep (GB/s against
+  the HBM peak: its vectors no longer fit the caches), BFS from vertex 0,
+  32-source batched BFS against 32 plain runs, and the weight gradient
+  (T = 20) against its forward pass.
 
 Prints one JSON line. Inputs are generated and loaded before the timed region
 (graph loading is excluded, as in the paper's measurements).
@@ -104,6 +108,7 @@ def main():
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched/adjoint comparisons")
+    ap.add_argument("--no-scale26", action="store_true", help="skip the RMAT scale-26 measurements")
     ap.add_argument("--pr-only", type=int, default=0, metavar="K",
                     help="only run K PageRank passes (20 supersteps) and a 1 GiB copy, for "
                          "hardware-counter runs")
@@ -245,6 +250,12 @@ def main():
     forms = None
     if not args.no_forms:
         forms = measure_forms(gm, gg, torch, np, tm, g_dir, n, m_dir)
+    if not args.no_scale26:
+        for g in (g_sym, g_dir, g_dag):
+            g.close()
+        torch.cuda.empty_cache()
+        forms = forms or {}
+        forms["rmat26"] = measure_scale26(gm, gg, torch, np, tm)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -410,6 +421,86 @@ def measure_forms(gm, gg, torch, np, tm, g22, n22, m22):
         "forward_gteps": round(T * m22 / (tf * 1e-3) / 1e9, 2),
         "vjp_gteps": round(T * m22 / (tbk * 1e-3) / 1e9, 2)}
     log("pr grad: %s (%.1fs)" % (json.dumps(res["pr_weight_grad_rmat22_T20"]), time.time() - t0))
+    return res
+
+
+def measure_scale26(gm, gg, torch, np, tm):
+    """RMAT scale 26: PageRank per superstep, BFS, 32-source batched BFS and
+    the PageRank weight gradient, each after a warm-up run."""
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    n, s, d = gg.rmat(26)
+    res = {"n": n}
+    g = gm.Graph.from_coo(n, s, d)
+    info = g.info()
+    m = info.m
+    res["m_dir"] = m
+    log("scale 26 directed graph: m=%d (%.1fs)" % (m, time.time() - t0))
+    rank = torch.empty(n, dtype=torch.float32, device=dev)
+
+    def pr(T):
+        def f():
+            rank.fill_(1.0)
+            gm.run_vertex_program(g, gm.GM_PROG_PAGERANK, None, T, rank)
+        return f
+
+    per = (tm.ms(pr(21), 3) - tm.ms(pr(1), 3)) / 20
+    alg = 4 * m + 12 * info.n_dst + 4 * info.n_src
+    res["pagerank"] = {"ms_per_superstep": round(per, 4),
+                       "gteps": round(m / (per * 1e-3) / 1e9, 2),
+                       "algorithmic_gbs": round(alg / (per * 1e-3) / 1e9, 1),
+                       "hbm_frac": round(alg / (per * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    T = 20
+    w = torch.ones(m, dtype=torch.float32, device=dev)
+    hist = torch.empty((T + 1, n), dtype=torch.float32, device=dev)
+    hist[0].fill_(1.0)
+    c = torch.tensor(gg.uniform_f32(n, gg.SEED_PR_UPSTREAM), device=dev)
+    gw = torch.empty_like(w)
+    tf = tm.ms(lambda: gm.pagerank_forward_w(g, w, 0.15, T, hist), 1)
+    tb = tm.ms(lambda: gm.pagerank_vjp_w(g, w, 0.15, T, hist, c, gw), 1)
+    res["pr_weight_grad_T20"] = {"forward_ms": round(tf, 2), "vjp_ms": round(tb, 2),
+                                 "vjp_over_forward": round(tb / tf, 2),
+                                 "vjp_gteps": round(T * m / (tb * 1e-3) / 1e9, 2)}
+    del w, hist, gw, rank
+    g.close()
+    torch.cuda.empty_cache()
+    log("scale 26 PageRank: %s (%.1fs)" % (json.dumps(res), time.time() - t0))
+    gs = gm.Graph.from_coo(n, s, d, prep=gm.GM_PREP_DROP_SELF_LOOPS | gm.GM_PREP_SYMMETRIZE,
+                           layouts=gm.GM_LAYOUT_OUT)
+    S = gg.sources(n, s, d, 32, gg.SEED_BATCH_SOURCES)
+    del s, d
+    Sd = torch.tensor(S, dtype=torch.int32, device=dev)
+    one = [torch.tensor([v], dtype=torch.int32, device=dev) for v in S]
+    lv = torch.empty(n, dtype=torch.int32, device=dev)
+    edges = {}
+
+    def bfs(r):
+        def f():
+            lv.fill_(gm.INF_LEVEL)
+            lv[r] = 0
+            gm.run_vertex_program(gs, gm.GM_PROG_BFS, r, -1, lv)
+            edges[int(r[0])] = gs.last_run_stats().edges_scanned
+        return f
+
+    tb0 = tm.ms(bfs(one[0]), 3)
+    res["bfs"] = {"ms": round(tb0, 3), "gteps": round(edges[int(S[0])] / (tb0 * 1e-3) / 1e9, 2)}
+
+    def plain_all():
+        for r in one:
+            bfs(r)()
+
+    tp = tm.ms(plain_all, 1)
+    blk = torch.empty((n, 32), dtype=torch.int32, device=dev)
+    tbb = tm.ms(lambda: gm.run_batched(gs, gm.GM_PROG_BFS, Sd, -1, blk), 2)
+    e_all = sum(edges.values())
+    res["bfs32"] = {"batched_ms": round(tbb, 2), "plain_ms": round(tp, 2),
+                    "speedup": round(tp / tbb, 2),
+                    "batched_gteps": round(e_all / (tbb * 1e-3) / 1e9, 2),
+                    "plain_gteps": round(e_all / (tp * 1e-3) / 1e9, 2)}
+    del blk, lv
+    gs.close()
+    torch.cuda.empty_cache()
+    log("scale 26: %s (%.1fs)" % (json.dumps(res), time.time() - t0))
     return res
 
 
