@@ -48,7 +48,7 @@ sys.path.insert(0, ROOT)
 METRIC = "GTEPS per generalized-SpMV iteration + % HBM peak; batched/adjoint vs plain"
 HBM_PEAK_GBS = 8000.0
 PR_SOURCE = os.path.join(ROOT, "paper_1503_07241_amd", "csrc", "pagerank.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pr_dense_rmat22_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pr_pull_rmat22_traffic.txt")
 
 
 def log(msg):
@@ -226,7 +226,7 @@ def main():
                        "gteps": round(edges[k] / (ms * 1e-3) / 1e9, 2)}
     log("programs: %s" % json.dumps(programs))
 
-    # Dominant SpMV kernel: the PageRank superstep (pr_dense + the combine of
+    # Dominant SpMV kernel: the PageRank superstep (pr_pull + the combine of
     # split rows). Its time per superstep is the difference of a 21- and a
     # 1-superstep run over 20, which removes the per-run set-up kernels.
     # Algorithmic bytes per superstep: every in-edge index (4 m), per row with
@@ -279,7 +279,7 @@ def main():
                    "scale": scale, "n": n, "m_dir": m_dir, "m_sym": m_sym, "m_dag": m_dag,
                    "edges_per_step": int(edges_step)},
         "programs": programs,
-        "roofline": {"kernel": "pr_dense (PageRank superstep)", "bound": "hbm",
+        "roofline": {"kernel": "pr_pull (PageRank superstep)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_launch": int(pr_bytes),
