@@ -11,14 +11,14 @@
 // so that the GD updates of Eqs. (5)-(6) are p <- p - (gamma / 2) dL/dp.
 //
 // Both passes run the same kernel over a compressed layout (rows: CSR by user;
-// columns: CSC by item). A group of L lanes (L = K rounded up to a power of
-// two) owns one work item - a segment (user or item) or a chunk of at most
-// kChunk of its ratings - and keeps the segment's factor in registers, one
-// coordinate per lane; each rating gathers the other side's factor row
-// (coalesced), forms e with a shuffle-reduced dot product and accumulates
-// e * p_other. Chunked segments write partial sums that a second kernel adds
-// in chunk order. All sums are in double; the loss is reduced per workgroup
-// and then in a fixed order, so results are deterministic.
+// columns: CSC by item). A wavefront owns one work item - a segment (user or
+// item) or a chunk of at most kChunk of its ratings - split into groups of G
+// lanes, each lane holding four coordinates of the segment's factor in
+// registers; a group takes one rating at a time, gathers the other side's
+// factor row (coalesced), forms e with a shuffle-reduced FP32 dot product and
+// accumulates e * p_other in double. Chunked segments write partial sums
+// that a second kernel adds in chunk order. The loss is reduced per
+// workgroup and then in a fixed order, so results are deterministic.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -69,58 +69,96 @@ __device__ inline double group_sum(double v, int lanes) {
   return v;
 }
 
-// Work items of one side; lanes-per-group L is a power of two >= K.
+__device__ inline float group_sum_f(float v, int lanes) {
+  for (int o = lanes >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// One wavefront per work item (a segment, or a chunk of a long one). The
+// wavefront is cut into 64 / G groups of G lanes; a group takes one rating
+// at a time, each of its lanes holding four coordinates of the two factor
+// rows (G = K / 4 rounded up to a power of two), so one rating costs four
+// multiply-adds per lane and log2(G) shuffles for the dot product. Groups
+// take the item's ratings in turn, kUnroll at once; their partial gradient
+// sums are combined over the groups at the end of the item.
 template <bool kGrad, bool kLoss>
 __global__ __launch_bounds__(kThreads) void cf_pass(
-    int K, int L, const CfItem* __restrict__ items, int64_t nitems,
-    const uint32_t* __restrict__ off, const int32_t* __restrict__ other_idx,
-    const uint8_t* __restrict__ val, const float* __restrict__ P_own,
-    const float* __restrict__ P_other, float lambda, float scale, float* __restrict__ grad,
-    double* __restrict__ partial, double* __restrict__ loss_part) {
+    int K, int G, const CfItem* __restrict__ items, int64_t nitems,
+    const int32_t* __restrict__ other_idx, const uint8_t* __restrict__ val,
+    const float* __restrict__ P_own, const float* __restrict__ P_other, float lambda,
+    float scale, float* __restrict__ grad, double* __restrict__ partial,
+    double* __restrict__ loss_part) {
   __shared__ double lsum[kThreads / 64];
-  const int tid = threadIdx.x;
-  const int sub = tid % L;
-  const int64_t it = (int64_t)blockIdx.x * (kThreads / L) + tid / L;
-  const bool valid = it < nitems && sub < K;
+  const int lane = threadIdx.x & 63;
+  const int grp = lane / G, sub = lane % G, ngrp = 64 / G;
+  const int k0 = 4 * sub;
+  const int64_t it = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   double loss = 0.0;
-  if (it < nitems) {
+  if (it < nitems) {  // wavefront-uniform
     const CfItem item = items[it];
-    const float own = valid ? P_own[(int64_t)item.seg * K + sub] : 0.0f;
-    double acc = 0.0;
-    for (uint32_t e0 = item.begin; e0 < item.end; e0 += kUnroll) {
+    float own[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      own[c] = k0 + c < K ? P_own[(int64_t)item.seg * K + k0 + c] : 0.0f;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const uint32_t step = (uint32_t)ngrp * kUnroll;
+    for (uint32_t e0 = item.begin + grp; e0 < item.end + grp; e0 += step) {
       int32_t j[kUnroll];
-      float g[kUnroll], o[kUnroll];
+      float g[kUnroll];
+      bool ok[kUnroll];
 #pragma unroll
       for (int q = 0; q < kUnroll; ++q) {
-        const uint32_t e = e0 + q < item.end ? e0 + q : item.end - 1;
-        j[q] = other_idx[e];
-        g[q] = (float)val[e];
+        const uint32_t e = e0 + q * ngrp;
+        ok[q] = e < item.end;
+        const uint32_t ec = ok[q] ? e : item.end - 1;
+        j[q] = other_idx[ec];
+        g[q] = (float)val[ec];
       }
+      float o[kUnroll][4];
 #pragma unroll
-      for (int q = 0; q < kUnroll; ++q) o[q] = valid ? P_other[(int64_t)j[q] * K + sub] : 0.0f;
+      for (int q = 0; q < kUnroll; ++q)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          o[q][c] = k0 + c < K ? P_other[(int64_t)j[q] * K + k0 + c] : 0.0f;
 #pragma unroll
       for (int q = 0; q < kUnroll; ++q) {
-        const double dot = group_sum((double)own * (double)o[q], L);
-        const double err = (double)g[q] - dot;
-        if (e0 + q < item.end) {
-          if (kGrad) acc += err * (double)o[q];
+        float d = own[0] * o[q][0];
+        d = fmaf(own[1], o[q][1], d);
+        d = fmaf(own[2], o[q][2], d);
+        d = fmaf(own[3], o[q][3], d);
+        const double err = (double)g[q] - (double)group_sum_f(d, G);
+        if (ok[q]) {
+          if (kGrad) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] += err * (double)o[q][c];
+          }
           if (kLoss && sub == 0) loss += err * err;
         }
       }
     }
-    if (kGrad && valid) {
-      if (item.partial >= 0)
-        partial[(int64_t)item.partial * K + sub] = acc;
-      else
-        grad[(int64_t)item.seg * K + sub] =
-            (float)((double)scale * (-2.0 * acc + 2.0 * (double)lambda * (double)own));
+    if (kGrad) {
+      // combine the groups: lanes with the same sub hold the same coordinates
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        for (int off = G; off < 64; off <<= 1) acc[c] += __shfl_xor(acc[c], off, 64);
+      if (grp == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (k0 + c >= K) continue;
+          if (item.partial >= 0)
+            partial[(int64_t)item.partial * K + k0 + c] = acc[c];
+          else
+            grad[(int64_t)item.seg * K + k0 + c] = (float)((double)scale *
+                (-2.0 * acc[c] + 2.0 * (double)lambda * (double)own[c]));
+        }
+      }
     }
   }
   if (kLoss) {
     for (int o = 32; o > 0; o >>= 1) loss += __shfl_xor(loss, o, 64);
-    if ((tid & 63) == 0) lsum[tid >> 6] = loss;
+    if ((threadIdx.x & 63) == 0) lsum[threadIdx.x >> 6] = loss;
     __syncthreads();
-    if (tid == 0) loss_part[blockIdx.x] = (lsum[0] + lsum[1]) + (lsum[2] + lsum[3]);
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = (lsum[0] + lsum[1]) + (lsum[2] + lsum[3]);
   }
 }
 
@@ -406,18 +444,19 @@ static CfPlan* ensure_plan(gm_graph g, int K, hipStream_t s) {
   return p;
 }
 
-static int lanes_for(int K) {
-  int L = 1;
-  while (L < K) L <<= 1;
-  return L;
+// Lanes per rating: four coordinates per lane, a power of two.
+static int group_for(int K) {
+  int G = 1;
+  while (4 * G < K) G <<= 1;
+  return G;
 }
 
 void run_cf_forward(gm_graph g, int K, const float* PU, const float* PV, float lambda,
                     double* loss_dev, hipStream_t s) {
   CfPlan* p = ensure_plan(g, K, s);
-  const int L = lanes_for(K);
+  const int G = group_for(K);
   const CfSide& rows = p->side[0];
-  const unsigned blocks = (unsigned)((rows.nitems + kThreads / L - 1) / (kThreads / L));
+  const unsigned blocks = (unsigned)((rows.nitems + kThreads / 64 - 1) / (kThreads / 64));
   const int64_t nu = g->n_rows * K, nv = g->n_cols * K;
   const unsigned bu = blocks_for(nu, 1024), bv = blocks_for(nv, 1024);
   const int64_t need = (int64_t)blocks + bu + bv;
@@ -428,9 +467,9 @@ void run_cf_forward(gm_graph g, int K, const float* PU, const float* PV, float l
     p->nloss = need;
   }
   if (rows.nitems > 0)
-    cf_pass<false, true><<<blocks, kThreads, 0, s>>>(K, L, rows.items, rows.nitems, g->out_off,
-                                                     g->out_idx, g->out_val, PU, PV, lambda, 1.0f,
-                                                     nullptr, nullptr, p->loss_part);
+    cf_pass<false, true><<<blocks, kThreads, 0, s>>>(K, G, rows.items, rows.nitems, g->out_idx,
+                                                     g->out_val, PU, PV, lambda, 1.0f, nullptr,
+                                                     nullptr, p->loss_part);
   sq_norm<<<bu, kThreads, 0, s>>>(PU, nu, p->loss_part + blocks);
   sq_norm<<<bv, kThreads, 0, s>>>(PV, nv, p->loss_part + blocks + bu);
   finish_loss<<<1, kThreads, 0, s>>>(p->loss_part, rows.nitems > 0 ? blocks : 0,
@@ -442,7 +481,7 @@ void run_cf_forward(gm_graph g, int K, const float* PU, const float* PV, float l
 void run_cf_backward(gm_graph g, int K, const float* PU, const float* PV, float lambda, float scale,
                      float* gPU, float* gPV, hipStream_t s) {
   CfPlan* p = ensure_plan(g, K, s);
-  const int L = lanes_for(K);
+  const int G = group_for(K);
   for (int side = 0; side < 2; ++side) {
     float* grad = side == 0 ? gPU : gPV;
     if (!grad) continue;
@@ -450,11 +489,11 @@ void run_cf_backward(gm_graph g, int K, const float* PU, const float* PV, float 
     const float* own = side == 0 ? PU : PV;
     const float* other = side == 0 ? PV : PU;
     if (sd.nitems > 0) {
-      const unsigned blocks = (unsigned)((sd.nitems + kThreads / L - 1) / (kThreads / L));
+      const unsigned blocks = (unsigned)((sd.nitems + kThreads / 64 - 1) / (kThreads / 64));
       cf_pass<true, false><<<blocks, kThreads, 0, s>>>(
-          K, L, sd.items, sd.nitems, side == 0 ? g->out_off : g->in_off,
-          side == 0 ? g->out_idx : g->in_idx, side == 0 ? g->out_val : g->in_val, own, other,
-          lambda, scale, grad, p->partial, nullptr);
+          K, G, sd.items, sd.nitems, side == 0 ? g->out_idx : g->in_idx,
+          side == 0 ? g->out_val : g->in_val, own, other, lambda, scale, grad, p->partial,
+          nullptr);
       GM_HIP(hipGetLastError());
     }
     if (sd.nsplit > 0) {
