@@ -36,9 +36,11 @@ constexpr int32_t kEmpty = -1;
 
 // Table classes by the owner's in-list length d: LDS tables per wavefront,
 // LDS tables per workgroup of growing size (small tables leave room for
-// more resident wavefronts), global tables for the longest lists. A table
-// has at least 2 d slots.
-enum TcKind { kWaveTable, kBlockTable, kGlobalTable };
+// more resident wavefronts); longer in-lists are cut into pieces of the
+// largest table size, each piece an owner of its own whose partners stream
+// only their elements in the piece's id range. A table has at least 2 d
+// slots.
+enum TcKind { kWaveTable, kBlockTable, kSplitTable };
 struct TcClass {
   uint32_t max_d;
   uint32_t slots;  // LDS slots per table
@@ -52,25 +54,38 @@ constexpr TcClass kTcClass[kClassesTc] = {{256, 512, 256, kWaveTable},          
                                           {4096, 8192, 512, kBlockTable},       // 32 KB
                                           {8192, 16384, 512, kBlockTable},      // 64 KB
                                           {16384, 32768, 1024, kBlockTable},    // 128 KB
-                                          {UINT32_MAX, 0, 512, kGlobalTable}};
+                                          {UINT32_MAX, 32768, 1024, kSplitTable}};
+constexpr uint32_t kPieceMax = 16384;  // in-list entries per piece of a split owner
 
 // A work item: owner x and a range of its partner list.
 struct Item {
   int32_t owner;
   uint32_t p_begin;
   uint32_t p_end;
-  uint32_t table;  // global-table index (largest owners), else unused
+  uint32_t pad;
+};
+
+// A work item of one piece of a split owner: the piece is in(x) positions
+// [tb, te) (ids [lo, hi)); partner j starts at element pstart[sbase + j -
+// p_begin] of its in-list and stops at hi.
+struct PieceItem {
+  int32_t owner;
+  uint32_t p_begin;
+  uint32_t p_end;
+  uint32_t tb;
+  uint32_t te;
+  int32_t hi;
+  uint32_t sbase;
+  uint32_t pad;
 };
 
 struct TcPlan {
   Item* items[kClassesTc] = {};  // per table class
   int64_t nitems[kClassesTc] = {};
   uint32_t* work = nullptr;        // partner id | kCreditPartner, grouped by owner
-  int32_t* gtable = nullptr;       // hash tables of the largest owners
-  uint64_t* gtable_off = nullptr;  // per table: first slot
-  uint32_t* gtable_mask = nullptr;
-  int32_t* gtable_owner = nullptr;
-  int64_t ntables = 0;
+  PieceItem* pieces = nullptr;     // work items of split owners
+  int64_t npieces = 0;
+  uint32_t* pstart = nullptr;      // per piece item and partner: first element >= the piece's low id
   unsigned long long* total = nullptr;
   // tuning the plan was built with
   uint32_t wave_max = 0, wave_work = 0, block_work = 0;
@@ -178,19 +193,25 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
 // owner's partners are sorted by decreasing in-list length, so the lanes of
 // a window walk lists of similar length). Matches credited to the owner are
 // returned; those credited to a partner are added to counts[partner].
-__device__ inline unsigned long long walk_partners(const int4* T4, uint32_t bmask, int32_t owner,
+// (Split owners: partner j's walk starts at element pstart[j + pshift] and
+// stops at lim, the piece's upper id; otherwise it starts at the list head and
+// stops at the owner's id.)
+__device__ inline unsigned long long walk_partners(const int4* T4, uint32_t bmask, int32_t lim,
                                                    const uint32_t* __restrict__ work,
                                                    uint32_t p_begin, uint32_t p_end,
                                                    uint32_t j_step,
                                                    const uint32_t* __restrict__ in_off,
                                                    const int32_t* __restrict__ in_idx,
-                                                   unsigned long long* counts) {
+                                                   unsigned long long* counts,
+                                                   const uint32_t* __restrict__ pstart = nullptr,
+                                                   int64_t pshift = 0) {
   const int lane = threadIdx.x & 63;
   unsigned long long own = 0;
   for (uint32_t j = p_begin + lane; j < p_end; j += j_step) {
     const uint32_t entry = work[j];
     const int32_t y = (int32_t)(entry & ~kCreditPartner);
-    const uint32_t cnt = count_list(T4, bmask, in_idx, in_off[y], in_off[y + 1], owner);
+    const uint32_t first = pstart ? pstart[j + pshift] : in_off[y];
+    const uint32_t cnt = count_list(T4, bmask, in_idx, first, in_off[y + 1], lim);
     if (entry & kCreditPartner) {
       if (cnt) atomicAdd(&counts[y], (unsigned long long)cnt);
     } else {
@@ -236,45 +257,32 @@ __global__ __launch_bounds__(kThreads) void tc_wave(const Item* __restrict__ ite
   if (lane == 0 && c) atomicAdd(&counts[x], c);
 }
 
-// One workgroup of kThr threads per work item; the owner's table in LDS
-// (kSlots slots; kSlots = 0: one of the precomputed global tables).
-// Wavefront w takes partners p_begin + 64 w + lane, then steps of one
-// workgroup.
+// One workgroup of kThr threads per work item, the owner's table (kSlots
+// slots) in LDS. Wavefront w takes partners p_begin + 64 w + lane, then
+// steps of one workgroup.
 template <uint32_t kSlots, int kThr>
 __global__ __launch_bounds__(kThr) void tc_block(const Item* __restrict__ items,
                                                  const uint32_t* __restrict__ in_off,
                                                  const int32_t* __restrict__ in_idx,
                                                  const uint32_t* __restrict__ work,
-                                                 const int32_t* __restrict__ gtable,
-                                                 const uint64_t* __restrict__ gtable_off,
-                                                 const uint32_t* __restrict__ gtable_mask,
                                                  unsigned long long* counts) {
-  constexpr bool kGlobal = kSlots == 0;
   constexpr int kW = kThr / 64;
-  __shared__ int4 ltable[kGlobal ? 1 : kSlots / 4];
+  __shared__ int4 ltable[kSlots / 4];
   __shared__ unsigned long long part[kW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const Item it = items[blockIdx.x];
   const int32_t x = it.owner;
-  const int4* T4;
-  uint32_t bmask;
-  if constexpr (kGlobal) {
-    T4 = reinterpret_cast<const int4*>(gtable + gtable_off[it.table]);
-    bmask = gtable_mask[it.table];
-  } else {
-    const uint32_t b = in_off[x], d = in_off[x + 1] - b;
-    const uint32_t nb = table_buckets(d);
-    bmask = nb - 1;
-    for (uint32_t k = threadIdx.x; k < nb; k += kThr)
-      ltable[k] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
-    __syncthreads();
-    int32_t* T = reinterpret_cast<int32_t*>(ltable);
-    for (uint32_t k = threadIdx.x; k < d; k += kThr) table_insert(T, bmask, in_idx[b + k]);
-    __syncthreads();
-    T4 = ltable;
-  }
-  const unsigned long long c = wave_sum_u64(
-      walk_partners(T4, bmask, x, work, it.p_begin + wave * 64, it.p_end, kThr, in_off, in_idx, counts));
+  const uint32_t b = in_off[x], d = in_off[x + 1] - b;
+  const uint32_t nb = table_buckets(d);
+  const uint32_t bmask = nb - 1;
+  for (uint32_t k = threadIdx.x; k < nb; k += kThr)
+    ltable[k] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
+  __syncthreads();
+  int32_t* T = reinterpret_cast<int32_t*>(ltable);
+  for (uint32_t k = threadIdx.x; k < d; k += kThr) table_insert(T, bmask, in_idx[b + k]);
+  __syncthreads();
+  const unsigned long long c = wave_sum_u64(walk_partners(
+      ltable, bmask, x, work, it.p_begin + wave * 64, it.p_end, kThr, in_off, in_idx, counts));
   if (lane == 0) part[wave] = c;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -284,20 +292,38 @@ __global__ __launch_bounds__(kThr) void tc_block(const Item* __restrict__ items,
   }
 }
 
-// Global tables of the largest owners, built once per graph.
-__global__ __launch_bounds__(kThreads) void build_tables(const int32_t* __restrict__ owner,
-                                                         const uint64_t* __restrict__ toff,
-                                                         const uint32_t* __restrict__ tmask,
-                                                         const uint32_t* __restrict__ in_off,
-                                                         const int32_t* __restrict__ in_idx,
-                                                         int32_t* __restrict__ gtable) {
-  const int32_t x = owner[blockIdx.x];
-  int32_t* T = gtable + toff[blockIdx.x];
-  const uint32_t bmask = tmask[blockIdx.x];
-  const uint32_t b = in_off[x], d = in_off[x + 1] - b;
-  for (uint32_t k = threadIdx.x; k < 4 * (bmask + 1); k += kThreads) T[k] = kEmpty;
+// One workgroup per work item of a piece of a split owner.
+template <uint32_t kSlots, int kThr>
+__global__ __launch_bounds__(kThr) void tc_piece(const PieceItem* __restrict__ items,
+                                                 const uint32_t* __restrict__ in_off,
+                                                 const int32_t* __restrict__ in_idx,
+                                                 const uint32_t* __restrict__ work,
+                                                 const uint32_t* __restrict__ pstart,
+                                                 unsigned long long* counts) {
+  constexpr int kW = kThr / 64;
+  __shared__ int4 ltable[kSlots / 4];
+  __shared__ unsigned long long part[kW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const PieceItem it = items[blockIdx.x];
+  const uint32_t d = it.te - it.tb;
+  const uint32_t nb = table_buckets(d);
+  const uint32_t bmask = nb - 1;
+  for (uint32_t k = threadIdx.x; k < nb; k += kThr)
+    ltable[k] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
   __syncthreads();
-  for (uint32_t k = threadIdx.x; k < d; k += kThreads) table_insert(T, bmask, in_idx[b + k]);
+  int32_t* T = reinterpret_cast<int32_t*>(ltable);
+  for (uint32_t k = threadIdx.x; k < d; k += kThr) table_insert(T, bmask, in_idx[it.tb + k]);
+  __syncthreads();
+  const unsigned long long c = wave_sum_u64(
+      walk_partners(ltable, bmask, it.hi, work, it.p_begin + wave * 64, it.p_end, kThr, in_off,
+                    in_idx, counts, pstart, (int64_t)it.sbase - (int64_t)it.p_begin));
+  if (lane == 0) part[wave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int i = 0; i < kW; ++i) t += part[i];
+    if (t) atomicAdd(&counts[it.owner], t);
+  }
 }
 
 __global__ void sum_u64(const unsigned long long* __restrict__ a, int64_t n,
@@ -330,10 +356,8 @@ void free_tc_plan(gm_graph g) {
   if (!p) return;
   for (int c = 0; c < kClassesTc; ++c) dfree(p->items[c]);
   dfree(p->work);
-  dfree(p->gtable);
-  dfree(p->gtable_off);
-  dfree(p->gtable_mask);
-  dfree(p->gtable_owner);
+  dfree(p->pieces);
+  dfree(p->pstart);
   dfree(p->total);
   delete p;
   g->tc_plan = nullptr;
@@ -417,10 +441,8 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
   // workgroup items also hold at most one 64-partner window per wavefront so
   // that all of their wavefronts have partners to walk.
   std::vector<Item> items[kClassesTc];
-  std::vector<uint64_t> goff;
-  std::vector<uint32_t> gmask;
-  std::vector<int32_t> gowner;
-  uint64_t gslots = 0;
+  std::vector<PieceItem> pieces;
+  std::vector<uint32_t> pstart;
   for (int64_t x = 0; x < n; ++x) {
     const uint32_t p0 = work_off[x], p1 = work_off[x + 1];
     if (p0 == p1) continue;
@@ -436,27 +458,55 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
     const uint32_t budget = tcl.kind == kWaveTable ? wave_work : block_work;
     // a workgroup item holds at most one partner per thread
     const uint32_t max_partners = tcl.kind == kWaveTable ? UINT32_MAX : (uint32_t)tcl.threads;
-    uint32_t table = 0;
-    if (tcl.kind == kGlobalTable) {
-      const uint32_t nb = table_buckets(d);
-      table = (uint32_t)goff.size();
-      goff.push_back(gslots);
-      gmask.push_back(nb - 1);
-      gowner.push_back((int32_t)x);
-      gslots += 4ull * nb;
+    if (tcl.kind == kSplitTable) {
+      // pieces of kPieceMax in-list entries; a partner streams the part of its
+      // list in the piece's id range [lo, hi)
+      const uint32_t xb = in_off[x];
+      for (uint32_t tb = 0; tb < d; tb += kPieceMax) {
+        const uint32_t te = std::min(d, tb + kPieceMax);
+        const int32_t lo = in_idx[xb + tb];
+        const int32_t hi = te < d ? in_idx[xb + te] : (int32_t)x;
+        uint32_t start = p0;
+        uint64_t acc = 0;
+        std::vector<uint32_t> first(p1 - p0);
+        std::vector<uint32_t> len(p1 - p0);
+        for (uint32_t j = p0; j < p1; ++j) {
+          const uint32_t y = work[j] & ~kCreditPartner;
+          const int32_t* yb = in_idx.data() + in_off[y];
+          const int32_t* ye = yb + din(y);
+          const int32_t* f = std::lower_bound(yb, ye, lo);
+          first[j - p0] = (uint32_t)(f - in_idx.data());
+          len[j - p0] = (uint32_t)(std::lower_bound(f, ye, hi) - f);
+        }
+        auto flush = [&](uint32_t a, uint32_t b) {
+          PieceItem pi{(int32_t)x, a, b, xb + tb, xb + te, hi, (uint32_t)pstart.size(), 0};
+          for (uint32_t j = a; j < b; ++j) pstart.push_back(first[j - p0]);
+          pieces.push_back(pi);
+        };
+        for (uint32_t j = p0; j < p1; ++j) {
+          if (acc > 0 && (acc + len[j - p0] > budget || j - start >= max_partners)) {
+            flush(start, j);
+            start = j;
+            acc = 0;
+          }
+          acc += len[j - p0];
+        }
+        flush(start, p1);
+      }
+      continue;
     }
     uint32_t start = p0;
     uint64_t acc = 0;
     for (uint32_t j = p0; j < p1; ++j) {
       const uint64_t len = wcost[j];
       if (acc > 0 && (acc + len > budget || j - start >= max_partners)) {
-        items[cls].push_back({(int32_t)x, start, j, table});
+        items[cls].push_back({(int32_t)x, start, j, 0});
         start = j;
         acc = 0;
       }
       acc += len;
     }
-    items[cls].push_back({(int32_t)x, start, p1, table});
+    items[cls].push_back({(int32_t)x, start, p1, 0});
   }
   // Largest items first so the long ones start early.
   for (int c = 0; c < kClassesTc; ++c)
@@ -479,20 +529,16 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
     p->work = dalloc<uint32_t>(work.size());
     if (!work.empty())
       GM_HIP(hipMemcpyAsync(p->work, work.data(), work.size() * 4, hipMemcpyHostToDevice, s));
-    p->ntables = (int64_t)goff.size();
-    p->gtable = dalloc<int32_t>(gslots);
-    p->gtable_off = dalloc<uint64_t>(goff.size());
-    p->gtable_mask = dalloc<uint32_t>(gmask.size());
-    p->gtable_owner = dalloc<int32_t>(gowner.size());
-    if (p->ntables > 0) {
-      GM_HIP(hipMemcpyAsync(p->gtable_off, goff.data(), goff.size() * 8, hipMemcpyHostToDevice, s));
-      GM_HIP(hipMemcpyAsync(p->gtable_mask, gmask.data(), gmask.size() * 4, hipMemcpyHostToDevice,
-                            s));
-      GM_HIP(hipMemcpyAsync(p->gtable_owner, gowner.data(), gowner.size() * 4,
+    std::stable_sort(pieces.begin(), pieces.end(), [&](const PieceItem& a, const PieceItem& b) {
+      return a.p_end - a.p_begin > b.p_end - b.p_begin;
+    });
+    p->npieces = (int64_t)pieces.size();
+    p->pieces = dalloc<PieceItem>(pieces.size());
+    p->pstart = dalloc<uint32_t>(pstart.size());
+    if (!pieces.empty()) {
+      GM_HIP(hipMemcpyAsync(p->pieces, pieces.data(), pieces.size() * sizeof(PieceItem),
                             hipMemcpyHostToDevice, s));
-      build_tables<<<(unsigned)p->ntables, kThreads, 0, s>>>(
-          p->gtable_owner, p->gtable_off, p->gtable_mask, g->in_off, g->in_idx, p->gtable);
-      GM_HIP(hipGetLastError());
+      GM_HIP(hipMemcpyAsync(p->pstart, pstart.data(), pstart.size() * 4, hipMemcpyHostToDevice, s));
     }
     p->total = dalloc<unsigned long long>(1);
     GM_HIP(hipStreamSynchronize(s));
@@ -509,16 +555,19 @@ void run_triangle_count(gm_graph g, unsigned long long* counts, unsigned long lo
   static_assert(kTcClass[0].slots == 512 && kTcClass[1].slots == 2048 &&
                     kTcClass[2].slots == 4096 && kTcClass[3].slots == 8192 &&
                     kTcClass[4].slots == 16384 && kTcClass[5].slots == 32768 &&
-                    kTcClass[5].threads == 1024 && kTcClass[6].kind == kGlobalTable,
+                    kTcClass[5].threads == 1024 && kTcClass[6].kind == kSplitTable &&
+                    kTcClass[6].slots == 32768 && kTcClass[6].threads == 1024 &&
+                    2 * kPieceMax <= kTcClass[6].slots,
                 "kernel instances below follow the class table");
   // longest owners first, so the long items start early
+  if (p->npieces > 0)
+    tc_piece<32768, 1024><<<(unsigned)p->npieces, 1024, 0, s>>>(p->pieces, g->in_off, g->in_idx,
+                                                                 p->work, p->pstart, counts);
   const auto block = [&](int c, auto kern) {
     if (p->nitems[c] > 0)
-      kern<<<(unsigned)p->nitems[c], kTcClass[c].threads, 0, s>>>(
-          p->items[c], g->in_off, g->in_idx, p->work, p->gtable, p->gtable_off, p->gtable_mask,
-          counts);
+      kern<<<(unsigned)p->nitems[c], kTcClass[c].threads, 0, s>>>(p->items[c], g->in_off,
+                                                                   g->in_idx, p->work, counts);
   };
-  block(6, tc_block<0, 512>);
   block(5, tc_block<32768, 1024>);
   block(4, tc_block<16384, 512>);
   block(3, tc_block<8192, 512>);
