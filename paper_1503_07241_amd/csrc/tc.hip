@@ -83,9 +83,11 @@ struct TcPlan {
   Item* items[kClassesTc] = {};  // per table class
   int64_t nitems[kClassesTc] = {};
   uint32_t* work = nullptr;        // partner id | kCreditPartner, grouped by owner
+  uint32_t* wlen = nullptr;        // per partner entry: elements streamed
   PieceItem* pieces = nullptr;     // work items of split owners
   int64_t npieces = 0;
   uint32_t* pstart = nullptr;      // per piece item and partner: first element >= the piece's low id
+  uint32_t* plen = nullptr;        // ... and the number of its elements in the piece's range
   unsigned long long* total = nullptr;
   // tuning the plan was built with
   uint32_t wave_max = 0, wave_work = 0, block_work = 0;
@@ -129,94 +131,131 @@ __device__ inline bool bucket_full(int4 q) {
   return max(max((uint32_t)q.x, (uint32_t)q.y), max((uint32_t)q.z, (uint32_t)q.w)) != 0xFFFFFFFFu;
 }
 
-// Matches of the elements below lim of the sorted in-list [s, e) in the
-// table (nb = bmask + 1 buckets); the walk stops at the first element >= lim. Elements are read from the 16-byte aligned quads that hold them
-// (the index array is padded so the last quad is readable), two quads per
-// pass; the next pass's quads are loaded before this pass's elements are
-// probed, and the eight home buckets are read back to back, the rare
-// continuations after. Positions past the list are clamped to a quad
-// already read, so every load is unconditional.
-__device__ inline uint32_t count_list(const int4* T4, uint32_t bmask,
-                                      const int32_t* __restrict__ in_idx, uint32_t s,
-                                      uint32_t e, int32_t lim) {
-  uint32_t cnt = 0;
-  uint32_t a = s & ~3u;
-  if (a >= e) return 0;
-  int4 v0 = *reinterpret_cast<const int4*>(in_idx + a);
-  int4 v1 = *reinterpret_cast<const int4*>(in_idx + (a + 4 < e ? a + 4 : a));
-  for (;;) {
-    const uint32_t an = a + 8;
-    const bool more = an < e;
-    const uint32_t p0 = more ? an : a;
-    const uint32_t p1 = an + 4 < e ? an + 4 : p0;
-    const int4 w0 = *reinterpret_cast<const int4*>(in_idx + p0);
-    const int4 w1 = *reinterpret_cast<const int4*>(in_idx + p1);
-    const int32_t key[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-    uint32_t bk[8];
-    int4 q[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      bk[i] = hash_id(key[i]) & bmask;
-      q[i] = T4[bk[i]];
-    }
-    bool past = false;  // an element >= lim: the rest of the sorted list is too
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const bool in_list = a + i >= s && a + i < e;
-      past |= in_list && key[i] >= lim;
-      const bool ok = in_list && key[i] < lim;
-      uint32_t hit = in_bucket(q[i], key[i]);
-      bool more_probe = ok && !hit && bucket_full(q[i]);
-      while (more_probe) {
-        bk[i] = (bk[i] + 1) & bmask;
-        q[i] = T4[bk[i]];
-        hit = in_bucket(q[i], key[i]);
-        more_probe = !hit && bucket_full(q[i]);
-      }
-      cnt += ok ? hit : 0u;
-    }
-    if (!more || past) break;
-    a = an;
-    v0 = w0;
-    v1 = w1;
-  }
-  return cnt;
-}
-
 __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-// Partners [p_begin, p_end) of one owner, one partner per lane (the first
-// partner of this wavefront is p_begin + lane, then steps of j_step; an
-// owner's partners are sorted by decreasing in-list length, so the lanes of
-// a window walk lists of similar length). Matches credited to the owner are
-// returned; those credited to a partner are added to counts[partner].
-// (Split owners: partner j's walk starts at element pstart[j + pshift] and
-// stops at lim, the piece's upper id; otherwise it starts at the list head and
-// stops at the owner's id.)
-__device__ inline unsigned long long walk_partners(const int4* T4, uint32_t bmask, int32_t lim,
+__device__ inline uint32_t wave_incl_scan(uint32_t x, int lane) {
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(x, o, 64);
+    if (lane >= o) x += t;
+  }
+  return x;
+}
+
+// Matches of one aligned quad of in_idx (elements 4q .. 4q + 3, those in
+// [s, e) counted) in the table.
+__device__ inline uint32_t probe_quad(const int4* T4, uint32_t bmask, int4 v, uint32_t q,
+                                      uint32_t s, uint32_t e) {
+  const int32_t key[4] = {v.x, v.y, v.z, v.w};
+  uint32_t bk[4];
+  int4 b[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    bk[i] = hash_id(key[i]) & bmask;
+    b[i] = T4[bk[i]];
+  }
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t pos = 4 * q + i;
+    const bool ok = pos >= s && pos < e;
+    uint32_t hit = in_bucket(b[i], key[i]);
+    bool more = ok && !hit && bucket_full(b[i]);
+    while (more) {  // rare: the key's home bucket is full
+      bk[i] = (bk[i] + 1) & bmask;
+      b[i] = T4[bk[i]];
+      hit = in_bucket(b[i], key[i]);
+      more = !hit && bucket_full(b[i]);
+    }
+    cnt += ok ? hit : 0u;
+  }
+  return cnt;
+}
+
+// Partners [p_begin, p_end) of one owner in windows of 64 (lane l of a
+// window holds partner j0 + l; windows step by j_step). A partner streams
+// the elements [s, s + len) of the index array: s = in_off[y] and len =
+// lens[j], or, for the pieces of a split owner, s = pstart[j + shift] and
+// len = lens[j + shift]. The window's streams are cut into aligned quads of
+// four elements, spread evenly over the lanes (a lane finds a quad's partner
+// by a 6-step search over the window's quad prefix sums), two quads per lane
+// in flight. Matches credited to the owner are returned; those credited to
+// a partner are added to counts[partner]. wcnt: the wavefront's 64 LDS
+// counters.
+__device__ inline unsigned long long walk_partners(const int4* T4, uint32_t bmask,
                                                    const uint32_t* __restrict__ work,
                                                    uint32_t p_begin, uint32_t p_end,
                                                    uint32_t j_step,
                                                    const uint32_t* __restrict__ in_off,
                                                    const int32_t* __restrict__ in_idx,
-                                                   unsigned long long* counts,
+                                                   unsigned long long* counts, uint32_t* wcnt,
+                                                   const uint32_t* __restrict__ lens,
                                                    const uint32_t* __restrict__ pstart = nullptr,
-                                                   int64_t pshift = 0) {
+                                                   int64_t shift = 0) {
   const int lane = threadIdx.x & 63;
   unsigned long long own = 0;
-  for (uint32_t j = p_begin + lane; j < p_end; j += j_step) {
-    const uint32_t entry = work[j];
-    const int32_t y = (int32_t)(entry & ~kCreditPartner);
-    const uint32_t first = pstart ? pstart[j + pshift] : in_off[y];
-    const uint32_t cnt = count_list(T4, bmask, in_idx, first, in_off[y + 1], lim);
-    if (entry & kCreditPartner) {
-      if (cnt) atomicAdd(&counts[y], (unsigned long long)cnt);
-    } else {
-      own += cnt;
+  for (uint32_t j0 = p_begin; j0 < p_end; j0 += j_step) {
+    const uint32_t j = j0 + lane;
+    uint32_t entry = 0, s = 0, e = 0;
+    if (j < p_end) {
+      entry = work[j];
+      const uint32_t y = entry & ~kCreditPartner;
+      s = pstart ? pstart[j + shift] : in_off[y];
+      e = s + lens[j + shift];
     }
+    const uint32_t qa = s >> 2;
+    const uint32_t nq = e > s ? ((e + 3) >> 2) - qa : 0u;
+    const uint32_t incl = wave_incl_scan(nq, lane);
+    const uint32_t excl = incl - nq;
+    const uint32_t total = __shfl(incl, 63, 64);
+    wcnt[lane] = 0;
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t i0 = 0; i0 < total; i0 += 128) {
+      int o[2];
+      uint32_t q[2], so[2], eo[2];
+      int4 v[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const uint32_t i = i0 + u * 64 + lane;
+        int w = 0;  // the partner of quad i: the last lane whose prefix is <= i
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+          const uint32_t ex = __shfl(excl, w + step, 64);
+          if (ex <= i) w += step;
+        }
+        // every lane takes part in every shuffle (a lane outside the shuffle
+        // would hand out no data), then the quads past the end are masked
+        const uint32_t qw = __shfl(qa, w, 64);
+        const uint32_t xw = __shfl(excl, w, 64);
+        const uint32_t sw = __shfl(s, w, 64);
+        const uint32_t ew = __shfl(e, w, 64);
+        const bool live = i < total;
+        o[u] = w;
+        q[u] = live ? qw + (i - xw) : 0u;
+        so[u] = sw;
+        eo[u] = live ? ew : 0u;  // a quad past the end counts nothing
+        v[u] = *reinterpret_cast<const int4*>(in_idx + 4 * (size_t)q[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const uint32_t c = probe_quad(T4, bmask, v[u], q[u], so[u], eo[u]);
+        if (c) atomicAdd(&wcnt[o[u]], c);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t mine = wcnt[lane];
+    if (j < p_end && mine) {
+      if (entry & kCreditPartner)
+        atomicAdd(&counts[entry & ~kCreditPartner], (unsigned long long)mine);
+      else
+        own += mine;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
   }
   return own;
 }
@@ -235,8 +274,10 @@ __global__ __launch_bounds__(kThreads) void tc_wave(const Item* __restrict__ ite
                                                     const uint32_t* __restrict__ in_off,
                                                     const int32_t* __restrict__ in_idx,
                                                     const uint32_t* __restrict__ work,
+                                                    const uint32_t* __restrict__ wlen,
                                                     unsigned long long* counts) {
   __shared__ int4 tables[kWaves][kSlots / 4];
+  __shared__ uint32_t wcnt[kWaves][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t r = (int64_t)blockIdx.x * kWaves + wave;
   if (r >= nitems) return;  // the whole wavefront leaves together
@@ -252,8 +293,8 @@ __global__ __launch_bounds__(kThreads) void tc_wave(const Item* __restrict__ ite
   for (uint32_t k = lane; k < d; k += 64) table_insert(T, nb - 1, in_idx[b + k]);
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
-  const unsigned long long c =
-      wave_sum_u64(walk_partners(T4, nb - 1, x, work, it.p_begin, it.p_end, 64, in_off, in_idx, counts));
+  const unsigned long long c = wave_sum_u64(walk_partners(
+      T4, nb - 1, work, it.p_begin, it.p_end, 64, in_off, in_idx, counts, wcnt[wave], wlen));
   if (lane == 0 && c) atomicAdd(&counts[x], c);
 }
 
@@ -265,9 +306,11 @@ __global__ __launch_bounds__(kThr) void tc_block(const Item* __restrict__ items,
                                                  const uint32_t* __restrict__ in_off,
                                                  const int32_t* __restrict__ in_idx,
                                                  const uint32_t* __restrict__ work,
+                                                 const uint32_t* __restrict__ wlen,
                                                  unsigned long long* counts) {
   constexpr int kW = kThr / 64;
   __shared__ int4 ltable[kSlots / 4];
+  __shared__ uint32_t wcnt[kW][64];
   __shared__ unsigned long long part[kW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const Item it = items[blockIdx.x];
@@ -282,7 +325,8 @@ __global__ __launch_bounds__(kThr) void tc_block(const Item* __restrict__ items,
   for (uint32_t k = threadIdx.x; k < d; k += kThr) table_insert(T, bmask, in_idx[b + k]);
   __syncthreads();
   const unsigned long long c = wave_sum_u64(walk_partners(
-      ltable, bmask, x, work, it.p_begin + wave * 64, it.p_end, kThr, in_off, in_idx, counts));
+      ltable, bmask, work, it.p_begin + wave * 64, it.p_end, kThr, in_off, in_idx, counts,
+      wcnt[wave], wlen));
   if (lane == 0) part[wave] = c;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -299,9 +343,11 @@ __global__ __launch_bounds__(kThr) void tc_piece(const PieceItem* __restrict__ i
                                                  const int32_t* __restrict__ in_idx,
                                                  const uint32_t* __restrict__ work,
                                                  const uint32_t* __restrict__ pstart,
+                                                 const uint32_t* __restrict__ plen,
                                                  unsigned long long* counts) {
   constexpr int kW = kThr / 64;
   __shared__ int4 ltable[kSlots / 4];
+  __shared__ uint32_t wcnt[kW][64];
   __shared__ unsigned long long part[kW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const PieceItem it = items[blockIdx.x];
@@ -314,9 +360,9 @@ __global__ __launch_bounds__(kThr) void tc_piece(const PieceItem* __restrict__ i
   int32_t* T = reinterpret_cast<int32_t*>(ltable);
   for (uint32_t k = threadIdx.x; k < d; k += kThr) table_insert(T, bmask, in_idx[it.tb + k]);
   __syncthreads();
-  const unsigned long long c = wave_sum_u64(
-      walk_partners(ltable, bmask, it.hi, work, it.p_begin + wave * 64, it.p_end, kThr, in_off,
-                    in_idx, counts, pstart, (int64_t)it.sbase - (int64_t)it.p_begin));
+  const unsigned long long c = wave_sum_u64(walk_partners(
+      ltable, bmask, work, it.p_begin + wave * 64, it.p_end, kThr, in_off, in_idx, counts,
+      wcnt[wave], plen, pstart, (int64_t)it.sbase - (int64_t)it.p_begin));
   if (lane == 0) part[wave] = c;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -358,6 +404,8 @@ void free_tc_plan(gm_graph g) {
   dfree(p->work);
   dfree(p->pieces);
   dfree(p->pstart);
+  dfree(p->plen);
+  dfree(p->wlen);
   dfree(p->total);
   delete p;
   g->tc_plan = nullptr;
@@ -442,7 +490,7 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
   // that all of their wavefronts have partners to walk.
   std::vector<Item> items[kClassesTc];
   std::vector<PieceItem> pieces;
-  std::vector<uint32_t> pstart;
+  std::vector<uint32_t> pstart, plen;
   for (int64_t x = 0; x < n; ++x) {
     const uint32_t p0 = work_off[x], p1 = work_off[x + 1];
     if (p0 == p1) continue;
@@ -480,7 +528,10 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
         }
         auto flush = [&](uint32_t a, uint32_t b) {
           PieceItem pi{(int32_t)x, a, b, xb + tb, xb + te, hi, (uint32_t)pstart.size(), 0};
-          for (uint32_t j = a; j < b; ++j) pstart.push_back(first[j - p0]);
+          for (uint32_t j = a; j < b; ++j) {
+            pstart.push_back(first[j - p0]);
+            plen.push_back(len[j - p0]);
+          }
           pieces.push_back(pi);
         };
         for (uint32_t j = p0; j < p1; ++j) {
@@ -535,11 +586,16 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
     p->npieces = (int64_t)pieces.size();
     p->pieces = dalloc<PieceItem>(pieces.size());
     p->pstart = dalloc<uint32_t>(pstart.size());
+    p->plen = dalloc<uint32_t>(plen.size());
     if (!pieces.empty()) {
       GM_HIP(hipMemcpyAsync(p->pieces, pieces.data(), pieces.size() * sizeof(PieceItem),
                             hipMemcpyHostToDevice, s));
       GM_HIP(hipMemcpyAsync(p->pstart, pstart.data(), pstart.size() * 4, hipMemcpyHostToDevice, s));
+      GM_HIP(hipMemcpyAsync(p->plen, plen.data(), plen.size() * 4, hipMemcpyHostToDevice, s));
     }
+    p->wlen = dalloc<uint32_t>(wcost.size());
+    if (!wcost.empty())
+      GM_HIP(hipMemcpyAsync(p->wlen, wcost.data(), wcost.size() * 4, hipMemcpyHostToDevice, s));
     p->total = dalloc<unsigned long long>(1);
     GM_HIP(hipStreamSynchronize(s));
   } catch (...) {
@@ -561,12 +617,12 @@ void run_triangle_count(gm_graph g, unsigned long long* counts, unsigned long lo
                 "kernel instances below follow the class table");
   // longest owners first, so the long items start early
   if (p->npieces > 0)
-    tc_piece<32768, 1024><<<(unsigned)p->npieces, 1024, 0, s>>>(p->pieces, g->in_off, g->in_idx,
-                                                                 p->work, p->pstart, counts);
+    tc_piece<32768, 1024><<<(unsigned)p->npieces, 1024, 0, s>>>(
+        p->pieces, g->in_off, g->in_idx, p->work, p->pstart, p->plen, counts);
   const auto block = [&](int c, auto kern) {
     if (p->nitems[c] > 0)
-      kern<<<(unsigned)p->nitems[c], kTcClass[c].threads, 0, s>>>(p->items[c], g->in_off,
-                                                                   g->in_idx, p->work, counts);
+      kern<<<(unsigned)p->nitems[c], kTcClass[c].threads, 0, s>>>(
+          p->items[c], g->in_off, g->in_idx, p->work, p->wlen, counts);
   };
   block(5, tc_block<32768, 1024>);
   block(4, tc_block<16384, 512>);
@@ -576,7 +632,7 @@ void run_triangle_count(gm_graph g, unsigned long long* counts, unsigned long lo
     if (p->nitems[c] > 0) {
       const int64_t blocks = (p->nitems[c] + kWaves - 1) / kWaves;
       kern<<<(unsigned)blocks, kThreads, 0, s>>>(p->items[c], p->nitems[c], g->in_off, g->in_idx,
-                                                 p->work, counts);
+                                                 p->work, p->wlen, counts);
     }
   };
   wave(1, tc_wave<2048>);
