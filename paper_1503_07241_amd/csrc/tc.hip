@@ -174,23 +174,33 @@ __device__ inline uint32_t probe_quad(const int4* T4, uint32_t bmask, int4 v, ui
   return cnt;
 }
 
+// Per-wavefront LDS scratch of a partner window.
+struct Window {
+  uint32_t excl[65];  // first quad of each lane's partner in the window's quad sequence; [64] = total
+  uint32_t qa[64];    // the partner's first aligned quad in the index array
+  uint32_t s[64];     // its stream [s, e)
+  uint32_t e[64];
+  uint32_t cnt[64];   // its matches
+};
+
 // Partners [p_begin, p_end) of one owner in windows of 64 (lane l of a
 // window holds partner j0 + l; windows step by j_step). A partner streams
 // the elements [s, s + len) of the index array: s = in_off[y] and len =
 // lens[j], or, for the pieces of a split owner, s = pstart[j + shift] and
 // len = lens[j + shift]. The window's streams are cut into aligned quads of
-// four elements, spread evenly over the lanes (a lane finds a quad's partner
-// by a 6-step search over the window's quad prefix sums), two quads per lane
-// in flight. Matches credited to the owner are returned; those credited to
-// a partner are added to counts[partner]. wcnt: the wavefront's 64 LDS
-// counters.
+// four elements and the quad sequence into 64 equal contiguous ranges, one
+// per lane: a lane finds the partner of its first quad by binary search over
+// the window's prefix sums (in LDS), then walks its range, moving to the next
+// partner at each boundary, the next quad's load issued before the current
+// quad is probed. Matches credited to the owner are returned; those credited
+// to a partner are added to counts[partner].
 __device__ inline unsigned long long walk_partners(const int4* T4, uint32_t bmask,
                                                    const uint32_t* __restrict__ work,
                                                    uint32_t p_begin, uint32_t p_end,
                                                    uint32_t j_step,
                                                    const uint32_t* __restrict__ in_off,
                                                    const int32_t* __restrict__ in_idx,
-                                                   unsigned long long* counts, uint32_t* wcnt,
+                                                   unsigned long long* counts, Window* W,
                                                    const uint32_t* __restrict__ lens,
                                                    const uint32_t* __restrict__ pstart = nullptr,
                                                    int64_t shift = 0) {
@@ -208,46 +218,51 @@ __device__ inline unsigned long long walk_partners(const int4* T4, uint32_t bmas
     const uint32_t qa = s >> 2;
     const uint32_t nq = e > s ? ((e + 3) >> 2) - qa : 0u;
     const uint32_t incl = wave_incl_scan(nq, lane);
-    const uint32_t excl = incl - nq;
     const uint32_t total = __shfl(incl, 63, 64);
-    wcnt[lane] = 0;
+    W->excl[lane] = incl - nq;
+    if (lane == 63) W->excl[64] = total;
+    W->qa[lane] = qa;
+    W->s[lane] = s;
+    W->e[lane] = e;
+    W->cnt[lane] = 0;
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
-    for (uint32_t i0 = 0; i0 < total; i0 += 128) {
-      int o[2];
-      uint32_t q[2], so[2], eo[2];
-      int4 v[2];
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const uint32_t i = i0 + u * 64 + lane;
-        int w = 0;  // the partner of quad i: the last lane whose prefix is <= i
-#pragma unroll
-        for (int step = 32; step > 0; step >>= 1) {
-          const uint32_t ex = __shfl(excl, w + step, 64);
-          if (ex <= i) w += step;
+    const uint32_t per = (total + 63) / 64;
+    uint32_t idx = min(total, per * lane);
+    const uint32_t iend = min(total, idx + per);
+    if (idx < iend) {
+      int o = 0;  // the last lane whose first quad is <= idx
+      for (int step = 32; step > 0; step >>= 1)
+        if (W->excl[o + step] <= idx) o += step;
+      uint32_t bound = W->excl[o + 1];
+      uint32_t q = W->qa[o] + (idx - W->excl[o]);
+      uint32_t so = W->s[o], eo = W->e[o];
+      int4 v = *reinterpret_cast<const int4*>(in_idx + 4 * (size_t)q);
+      while (idx < iend) {
+        const int4 cv = v;
+        const uint32_t cq = q, cs = so, ce = eo;
+        const int co = o;
+        ++idx;
+        ++q;
+        if (idx < iend) {
+          if (idx == bound) {  // next partner with quads
+            do {
+              ++o;
+              bound = W->excl[o + 1];
+            } while (bound <= idx);
+            q = W->qa[o];
+            so = W->s[o];
+            eo = W->e[o];
+          }
+          v = *reinterpret_cast<const int4*>(in_idx + 4 * (size_t)q);
         }
-        // every lane takes part in every shuffle (a lane outside the shuffle
-        // would hand out no data), then the quads past the end are masked
-        const uint32_t qw = __shfl(qa, w, 64);
-        const uint32_t xw = __shfl(excl, w, 64);
-        const uint32_t sw = __shfl(s, w, 64);
-        const uint32_t ew = __shfl(e, w, 64);
-        const bool live = i < total;
-        o[u] = w;
-        q[u] = live ? qw + (i - xw) : 0u;
-        so[u] = sw;
-        eo[u] = live ? ew : 0u;  // a quad past the end counts nothing
-        v[u] = *reinterpret_cast<const int4*>(in_idx + 4 * (size_t)q[u]);
-      }
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const uint32_t c = probe_quad(T4, bmask, v[u], q[u], so[u], eo[u]);
-        if (c) atomicAdd(&wcnt[o[u]], c);
+        const uint32_t c = probe_quad(T4, bmask, cv, cq, cs, ce);
+        if (c) atomicAdd(&W->cnt[co], c);
       }
     }
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
-    const uint32_t mine = wcnt[lane];
+    const uint32_t mine = W->cnt[lane];
     if (j < p_end && mine) {
       if (entry & kCreditPartner)
         atomicAdd(&counts[entry & ~kCreditPartner], (unsigned long long)mine);
@@ -277,7 +292,7 @@ __global__ __launch_bounds__(kThreads) void tc_wave(const Item* __restrict__ ite
                                                     const uint32_t* __restrict__ wlen,
                                                     unsigned long long* counts) {
   __shared__ int4 tables[kWaves][kSlots / 4];
-  __shared__ uint32_t wcnt[kWaves][64];
+  __shared__ Window wins[kWaves];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t r = (int64_t)blockIdx.x * kWaves + wave;
   if (r >= nitems) return;  // the whole wavefront leaves together
@@ -294,7 +309,7 @@ __global__ __launch_bounds__(kThreads) void tc_wave(const Item* __restrict__ ite
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
   const unsigned long long c = wave_sum_u64(walk_partners(
-      T4, nb - 1, work, it.p_begin, it.p_end, 64, in_off, in_idx, counts, wcnt[wave], wlen));
+      T4, nb - 1, work, it.p_begin, it.p_end, 64, in_off, in_idx, counts, &wins[wave], wlen));
   if (lane == 0 && c) atomicAdd(&counts[x], c);
 }
 
@@ -310,7 +325,7 @@ __global__ __launch_bounds__(kThr) void tc_block(const Item* __restrict__ items,
                                                  unsigned long long* counts) {
   constexpr int kW = kThr / 64;
   __shared__ int4 ltable[kSlots / 4];
-  __shared__ uint32_t wcnt[kW][64];
+  __shared__ Window wins[kW];
   __shared__ unsigned long long part[kW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const Item it = items[blockIdx.x];
@@ -326,7 +341,7 @@ __global__ __launch_bounds__(kThr) void tc_block(const Item* __restrict__ items,
   __syncthreads();
   const unsigned long long c = wave_sum_u64(walk_partners(
       ltable, bmask, work, it.p_begin + wave * 64, it.p_end, kThr, in_off, in_idx, counts,
-      wcnt[wave], wlen));
+      &wins[wave], wlen));
   if (lane == 0) part[wave] = c;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -347,7 +362,7 @@ __global__ __launch_bounds__(kThr) void tc_piece(const PieceItem* __restrict__ i
                                                  unsigned long long* counts) {
   constexpr int kW = kThr / 64;
   __shared__ int4 ltable[kSlots / 4];
-  __shared__ uint32_t wcnt[kW][64];
+  __shared__ Window wins[kW];
   __shared__ unsigned long long part[kW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const PieceItem it = items[blockIdx.x];
@@ -362,7 +377,7 @@ __global__ __launch_bounds__(kThr) void tc_piece(const PieceItem* __restrict__ i
   __syncthreads();
   const unsigned long long c = wave_sum_u64(walk_partners(
       ltable, bmask, work, it.p_begin + wave * 64, it.p_end, kThr, in_off, in_idx, counts,
-      wcnt[wave], plen, pstart, (int64_t)it.sbase - (int64_t)it.p_begin));
+      &wins[wave], plen, pstart, (int64_t)it.sbase - (int64_t)it.p_begin));
   if (lane == 0) part[wave] = c;
   __syncthreads();
   if (threadIdx.x == 0) {
