@@ -91,6 +91,12 @@ struct TcPlan {
   unsigned long long* total = nullptr;
   // tuning the plan was built with
   uint32_t wave_max = 0, wave_work = 0, block_work = 0;
+  // one stream per table-class launch (forked from and joined to the
+  // caller's stream), so that the launches overlap instead of each ending in
+  // a tail of idle compute units
+  hipStream_t lanes[kClassesTc] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t done[kClassesTc] = {};
 };
 
 // 32-bit integer mixer (xor-shift-multiply rounds); every output bit depends
@@ -421,6 +427,11 @@ void free_tc_plan(gm_graph g) {
   dfree(p->pstart);
   dfree(p->plen);
   dfree(p->wlen);
+  for (int c = 0; c < kClassesTc; ++c) {
+    if (p->lanes[c]) (void)hipStreamDestroy(p->lanes[c]);
+    if (p->done[c]) (void)hipEventDestroy(p->done[c]);
+  }
+  if (p->fork) (void)hipEventDestroy(p->fork);
   dfree(p->total);
   delete p;
   g->tc_plan = nullptr;
@@ -612,6 +623,11 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
     if (!wcost.empty())
       GM_HIP(hipMemcpyAsync(p->wlen, wcost.data(), wcost.size() * 4, hipMemcpyHostToDevice, s));
     p->total = dalloc<unsigned long long>(1);
+    GM_HIP(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming));
+    for (int c = 0; c < kClassesTc; ++c) {
+      GM_HIP(hipStreamCreateWithFlags(&p->lanes[c], hipStreamNonBlocking));
+      GM_HIP(hipEventCreateWithFlags(&p->done[c], hipEventDisableTiming));
+    }
     GM_HIP(hipStreamSynchronize(s));
   } catch (...) {
     free_tc_plan(g);
@@ -630,14 +646,29 @@ void run_triangle_count(gm_graph g, unsigned long long* counts, unsigned long lo
                     kTcClass[6].slots == 32768 && kTcClass[6].threads == 1024 &&
                     2 * kPieceMax <= kTcClass[6].slots,
                 "kernel instances below follow the class table");
-  // longest owners first, so the long items start early
-  if (p->npieces > 0)
-    tc_piece<32768, 1024><<<(unsigned)p->npieces, 1024, 0, s>>>(
+  // Each class on its own stream, forked from s and joined back: the
+  // launches run side by side (counts are only added to, atomically).
+  GM_HIP(hipEventRecord(p->fork, s));
+  const auto on = [&](int c) {
+    GM_HIP(hipStreamWaitEvent(p->lanes[c], p->fork, 0));
+    return p->lanes[c];
+  };
+  const auto join = [&](int c) {
+    GM_HIP(hipGetLastError());
+    GM_HIP(hipEventRecord(p->done[c], p->lanes[c]));
+    GM_HIP(hipStreamWaitEvent(s, p->done[c], 0));
+  };
+  if (p->npieces > 0) {
+    tc_piece<32768, 1024><<<(unsigned)p->npieces, 1024, 0, on(6)>>>(
         p->pieces, g->in_off, g->in_idx, p->work, p->pstart, p->plen, counts);
+    join(6);
+  }
   const auto block = [&](int c, auto kern) {
-    if (p->nitems[c] > 0)
-      kern<<<(unsigned)p->nitems[c], kTcClass[c].threads, 0, s>>>(
+    if (p->nitems[c] > 0) {
+      kern<<<(unsigned)p->nitems[c], kTcClass[c].threads, 0, on(c)>>>(
           p->items[c], g->in_off, g->in_idx, p->work, p->wlen, counts);
+      join(c);
+    }
   };
   block(5, tc_block<32768, 1024>);
   block(4, tc_block<16384, 512>);
@@ -646,13 +677,13 @@ void run_triangle_count(gm_graph g, unsigned long long* counts, unsigned long lo
   const auto wave = [&](int c, auto kern) {
     if (p->nitems[c] > 0) {
       const int64_t blocks = (p->nitems[c] + kWaves - 1) / kWaves;
-      kern<<<(unsigned)blocks, kThreads, 0, s>>>(p->items[c], p->nitems[c], g->in_off, g->in_idx,
-                                                 p->work, p->wlen, counts);
+      kern<<<(unsigned)blocks, kThreads, 0, on(c)>>>(p->items[c], p->nitems[c], g->in_off,
+                                                     g->in_idx, p->work, p->wlen, counts);
+      join(c);
     }
   };
   wave(1, tc_wave<2048>);
   wave(0, tc_wave<512>);
-  GM_HIP(hipGetLastError());
   if (total_host) {
     zero_u64<<<1, 64, 0, s>>>(p->total, 1);
     int64_t blocks = (g->n + kThreads - 1) / kThreads;
