@@ -400,7 +400,8 @@ typedef struct gm_tuning {
                                (256..2^26; 2^18) */
   uint32_t pr_hot;          /* PageRank/PPR pull: the messages of the pr_hot
                                highest-in-degree vertices are staged in LDS by
-                               every workgroup (0..32768; 32768) */
+                               every workgroup (0..40960; 40960, capped by the
+                               device's LDS per workgroup) */
 } gm_tuning;
 
 /* Read g's parameters. Errors: GM_ESTATE, GM_EINVAL (out NULL). */

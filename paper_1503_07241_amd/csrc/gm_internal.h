@@ -75,7 +75,7 @@ struct Tuning {
   uint32_t tc_wave_work = 1u << 14;
   uint32_t tc_block_work = 1u << 18;
   // PageRank / PPR pull: messages of the first pr_hot labels read from LDS
-  uint32_t pr_hot = 32768;
+  uint32_t pr_hot = 40960;
 };
 
 // Per-run outcome recorded on the device by a captured plan.

@@ -2,7 +2,8 @@
 // generalized SpMV over the in-adjacency, with APPLY and the next SEND fused
 // into the same kernel.
 //
-// One superstep = one launch of pr_pull (+ pr_finish for split rows):
+// One superstep = one launch of pr_pull (+ pr_cross for rows that span
+// tiles):
 //   y_v   = sum_{u -> v} x_u (* w_uv)          PROCESS = msg (* w), REDUCE = +
 //   PR_v  = r * tele(v) + (1 - r) * y_v        APPLY, for every vertex
 //   x'_v  = PR_v / outdeg(v)                   SEND for the next superstep
@@ -12,17 +13,16 @@
 //
 // Dense layout (built once per graph, on first use): vertices are relabelled
 // in decreasing in-degree order and the in-adjacency is rebuilt in the new
-// labels. Rows of similar length are then contiguous, so each degree class
-// gets its own number of lanes per row (from 1 up to a wavefront, so that a
-// lane gathers up to eight messages at once; the longest rows are cut into
-// chunks reduced by separate wavefronts), every access to per-row data is a
-// coalesced stream, and the most frequently gathered messages (high-degree
-// vertices, which in RMAT graphs have high in- and out-degree alike) sit
-// together at low labels: the first of them (a tuning parameter, up to
-// kHotMax) are copied to LDS by every workgroup and read from there, the next
-// ones stay cache resident. The
-// caller's rank vector is mapped into the new labels by the first SEND and
-// back after the last APPLY.
+// labels. Rows with in-edges are then [0, rows) and the rest are written once
+// per run; the edge stream is cut into equal tiles regardless of row lengths
+// (a bitmap marks the first edge of each row), so every wavefront streams the
+// same number of edges with fully coalesced loads; and the most frequently
+// gathered messages (high-degree vertices, which in RMAT graphs have high in-
+// and out-degree alike) sit together at low labels: the first of them (a
+// tuning parameter, up to kHotMax) are copied to LDS by every workgroup and
+// read from there, the next ones stay cache resident. The caller's rank
+// vector is mapped into the new labels by the first SEND and back after the
+// last APPLY.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -37,199 +37,290 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kPullThreads = 1024;  // one workgroup per CU: its LDS holds the hot messages
 constexpr int kPullWaves = kPullThreads / 64;
-constexpr int kUnroll = 8;  // most edges per lane; all of a lane's loads are in flight at once
-constexpr int kHotMax = 32768;  // at most this many hot messages in LDS (128 KB)
-constexpr uint32_t kChunk = 4096;  // rows longer than this are cut into chunks of kChunk edges
+constexpr int kRounds = 4;                  // rounds of 256 edges per tile
+constexpr int64_t kTile = kRounds * 256;    // edges per tile: 4 consecutive per lane and round
+constexpr int kHotMax = 40960;  // at most this many hot messages in LDS (160 KB)
+constexpr int kCrossLanes = 16;  // lanes per row that spans tiles
 
-// Degree classes c = 0..kClasses-1: in-degree in (kClassMax[c-1],
-// kClassMax[c]] (class 0: in-degree 0), each row taken by kClassLanes[c]
-// lanes with kClassUnroll[c] edges per lane and pass. Degree ranges double
-// from class to class up to 512, so at most half of a lane's load slots are
-// padding; the last class (a wavefront per row, looping) reaches kChunk.
-constexpr int kClasses = 12;
-constexpr uint32_t kClassMax[kClasses] = {0, 1, 2, 4, 8, 16, 32, 64, 128, 256, 512, kChunk};
-constexpr int kClassLanes[kClasses] = {1, 1, 1, 1, 1, 2, 4, 8, 16, 32, 64, 64};
-constexpr int kClassUnroll[kClasses] = {1, 1, 2, 4, 8, 8, 8, 8, 8, 8, 8, 8};
-
-struct SplitChunk {
-  uint32_t row;  // new label
-  uint32_t edge_begin;
-  uint32_t edge_end;
-  uint32_t pad;
-};
-
-struct SplitRow {
+// A row of the relabelled in-adjacency whose edges lie in more than one
+// tile: tiles ta (where it starts) to tb (where it ends).
+struct Cross {
   uint32_t row;
-  uint32_t first_chunk;
-  uint32_t nchunks;
+  uint32_t ta;
+  uint32_t tb;
   uint32_t pad;
-};
-
-// Work units of one superstep, one wavefront each: the chunks of split rows
-// first, then the classes from the longest rows (c = kClasses - 1) down to
-// in-degree 1 (c = 1); a unit of class c is 64 / kClassLanes[c] consecutive
-// rows. Rows with in-degree 0 are written once per run (pr_const_rows).
-struct Bins {
-  int64_t nchunks;
-  int64_t class_begin[kClasses];  // first row (new label)
-  int64_t class_rows[kClasses];
-  int64_t class_unit0[kClasses];  // first unit; decreases with c (class 0: end)
-  int64_t nunits;
 };
 
 struct Dense {
   int64_t n = 0, m = 0;
   int32_t* new_of = nullptr;    // old label -> new label
   int32_t* old_of = nullptr;    // new label -> old label
-  uint32_t* off = nullptr;      // relabelled in-adjacency
-  int32_t* idx = nullptr;
-  float* w = nullptr;           // edge values in the relabelled order (weighted graphs)
+  int32_t* idx = nullptr;       // relabelled in-adjacency, padded to whole tiles with 0
+  float* w = nullptr;           // edge values in the relabelled order (weighted graphs), padded
   uint32_t* ceid = nullptr;     // canonical (CSR) edge id of each relabelled in-edge
-  float* wdyn = nullptr;        // caller-supplied edge values, relabelled per call
+  float* wdyn = nullptr;        // caller-supplied edge values, relabelled per call, padded
   float* inv_outdeg = nullptr;  // new labels
   float* x[2] = {nullptr, nullptr};
   float* pr = nullptr;          // PR in new labels (last superstep)
-  SplitChunk* chunks = nullptr;
-  SplitRow* splits = nullptr;
-  double* partial = nullptr;
-  int64_t nsplit = 0;
+  uint32_t* starts = nullptr;   // bit e set: edge e is the first of its row (and bit m)
+  uint32_t* tile_row = nullptr; // row holding the first edge of each tile
+  double* head = nullptr;       // per tile: sum of the part of a row begun before the tile
+  double* tail = nullptr;       // per tile: sum of the part of a row that goes on after it
+  Cross* cross = nullptr;
+  int64_t ntiles = 0, ncross = 0;
+  int64_t rows = 0;             // rows with in-edges: new labels [0, rows)
   int cus = 0;                  // compute units of the device
-  Bins bins{};
+  int lds_max = 0;              // bytes of LDS a workgroup may use
 };
 
-__device__ inline double group_sum(double v, int width) {
-  for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// APPLY: PR_v from the sum y of its in-messages.
+template <bool kPersonal>
+__device__ inline float pr_value(uint32_t v, double y, float r, int32_t seed) {
+  double tele = 1.0;
+  if constexpr (kPersonal) tele = (int32_t)v == seed ? 1.0 : 0.0;
+  return (float)((double)r * tele + (1.0 - (double)r) * y);
 }
 
+// APPLY and the next SEND of row v.
 template <bool kPersonal>
 __device__ inline void apply_row(uint32_t v, double y, float r, int32_t seed,
                                  const float* __restrict__ inv_outdeg, float* __restrict__ x_out,
                                  float* __restrict__ pr_out) {
-  double tele = 1.0;
-  if constexpr (kPersonal) tele = (int32_t)v == seed ? 1.0 : 0.0;
-  const float pr = (float)((double)r * tele + (1.0 - (double)r) * y);
+  const float pr = pr_value<kPersonal>(v, y, r, seed);
   x_out[v] = pr * inv_outdeg[v];
   if (pr_out) pr_out[v] = pr;
 }
 
-// Sum of the messages of in-edges [b, e) taken by `lanes` lanes with stride
-// `lanes` (this lane starts at b + sub), kU loads in flight per lane.
-// Positions past the end are clamped to the last edge and their values
-// dropped by a select, so every load is unconditional and all of a lane's
-// index loads, then all of its gathers, are issued back to back. Index and
-// edge-value streams are read once per superstep and loaded non-temporally,
-// which keeps the gathered messages in the caches. A message of a label
-// below hot_n comes from the LDS copy (the lane's global gather then reads
-// x[0], one line shared by all such lanes); the others from x.
-template <int kU, bool kWeighted>
-__device__ inline double row_partial(const int32_t* __restrict__ idx, const float* __restrict__ w,
-                                     const float* __restrict__ x, const float* hot, int hot_n,
-                                     uint32_t b, uint32_t e, int sub, int lanes) {
-  double acc = 0.0;
-  for (uint32_t k0 = b + sub; k0 < e; k0 += kU * lanes) {
-    uint32_t k[kU];
+// Copy of the first hot_n messages to LDS: all of a thread's 16-byte loads
+// are issued before the first store.
+__device__ inline void load_hot(const float* __restrict__ x_in, float* hot, int hot_n) {
+  constexpr int kPer = kHotMax / 4 / kPullThreads;
+  const int n4 = hot_n >> 2;
+  v4f tmp[kPer];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const uint32_t kk = k0 + u * lanes;
-      k[u] = kk < e ? kk : e - 1;
-    }
-    int32_t src[kU];
-    float wv[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      src[u] = __builtin_nontemporal_load(idx + k[u]);
-      if constexpr (kWeighted) wv[u] = __builtin_nontemporal_load(w + k[u]);
-    }
-    float val[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const bool in_lds = src[u] < hot_n;
-      const float g = x[in_lds ? 0 : src[u]];
-      const float l = hot[in_lds ? src[u] : 0];
-      val[u] = in_lds ? l : g;
-    }
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      if constexpr (kWeighted) val[u] *= wv[u];
-      acc += k0 + u * lanes < e ? (double)val[u] : 0.0;
-    }
+  for (int k = 0; k < kPer; ++k) {
+    const int i = threadIdx.x + k * kPullThreads;
+    if (i < n4) tmp[k] = reinterpret_cast<const v4f*>(x_in)[i];
   }
-  return acc;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = threadIdx.x + k * kPullThreads;
+    if (i < n4) reinterpret_cast<v4f*>(hot)[i] = tmp[k];
+  }
+  for (int i = 4 * n4 + threadIdx.x; i < hot_n; i += kPullThreads) hot[i] = x_in[i];
+  __syncthreads();
 }
+
+// Segmented-sum state of a run of edges: c = number of row starts in it, s =
+// sum of the messages after the last of them (of all, if c = 0). Combining
+// an earlier run a with a later run b is associative, which makes the
+// segmented sum a scan.
+struct Seg {
+  int c;
+  double s;
+};
+
+__device__ inline Seg seg_join(Seg a, Seg b) { return {a.c + b.c, b.c > 0 ? b.s : a.s + b.s}; }
+
+// Data-parallel move of a Seg between lanes (DPP control kCtrl); a lane
+// whose source is outside its row of 16 lanes keeps `old`.
+template <int kCtrl>
+__device__ inline Seg seg_dpp(Seg old, Seg v) {
+  const unsigned long long ob = (unsigned long long)__double_as_longlong(old.s);
+  const unsigned long long vb = (unsigned long long)__double_as_longlong(v.s);
+  const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)ob, (int)(uint32_t)vb, kCtrl, 0xF, 0xF,
+                                             false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(ob >> 32), (int)(uint32_t)(vb >> 32),
+                                             kCtrl, 0xF, 0xF, false);
+  const int c = __builtin_amdgcn_update_dpp(old.c, v.c, kCtrl, 0xF, 0xF, false);
+  return {c, __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) |
+                                              (uint32_t)lo))};
+}
+
+__device__ inline Seg seg_lane(Seg v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v.s);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return {__builtin_amdgcn_readlane(v.c, lane),
+          __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo))};
+}
+
+// Wavefront scan of one round: from each lane's own run `own` and the run
+// `carry` of everything before the round, the lane's exclusive prefix (all
+// earlier lanes, carry included); `carry` moves on to the end of the round.
+__device__ inline Seg seg_scan(Seg own, Seg& carry, int lane) {
+  constexpr Seg id{0, 0.0};
+  Seg x = own;  // inclusive scan within each row of 16 lanes (row_shr 1, 2, 4, 8)
+  x = seg_join(seg_dpp<0x111>(id, x), x);
+  x = seg_join(seg_dpp<0x112>(id, x), x);
+  x = seg_join(seg_dpp<0x114>(id, x), x);
+  x = seg_join(seg_dpp<0x118>(id, x), x);
+  const Seg p1 = seg_join(carry, seg_lane(x, 15));
+  const Seg p2 = seg_join(p1, seg_lane(x, 31));
+  const Seg p3 = seg_join(p2, seg_lane(x, 47));
+  const int row = lane >> 4;
+  const Seg before = row == 0 ? carry : row == 1 ? p1 : row == 2 ? p2 : p3;
+  const Seg incl = seg_join(before, x);
+  carry = seg_lane(incl, 63);
+  return seg_dpp<0x111>(before, incl);  // the row's first lane takes `before`
+}
+
+// One superstep: y = A^T x (pull over in-edges), APPLY, next SEND.
+//
+// The relabelled in-edges are cut into tiles of kTile consecutive edges,
+// whatever the rows; a wavefront takes a tile in kRounds rounds of 256
+// edges, 4 consecutive ones per lane, so every index load is one coalesced
+// 16-byte load per lane, and all of a tile's gathers are in flight at once
+// (they, not the index stream, bound the kernel: most go to a different
+// cache line each). Row sums are a segmented scan over the tile (in double,
+// in a fixed order): the lane holding the last edge of a row that begins in
+// the tile applies it; a row begun in an earlier tile leaves its part in
+// head[t], one that goes on past the tile's end its part in tail[t], and
+// pr_cross finishes those rows. Each workgroup first copies the messages of
+// the hottest labels to LDS (hot_n of them; a label below hot_n is read from
+// there, its global gather then reads x[0], one line shared by all such
+// lanes). Gathers use 32-bit byte offsets, hence n < 2^30.
+template <bool kWeighted>
+struct TileLoad {
+  v4i src[kRounds];
+  v4f w[kRounds];
+  uint32_t fa[kRounds], fb[kRounds];  // word of `starts` with the lane's bits, and the next
+};
 
 template <bool kWeighted>
-__device__ inline double row_partial_u(int unroll, const int32_t* __restrict__ idx,
-                                       const float* __restrict__ w, const float* __restrict__ x,
-                                       const float* hot, int hot_n, uint32_t b, uint32_t e,
-                                       int sub, int lanes) {
-  switch (unroll) {
-    case 1:
-      return row_partial<1, kWeighted>(idx, w, x, hot, hot_n, b, e, sub, lanes);
-    case 2:
-      return row_partial<2, kWeighted>(idx, w, x, hot, hot_n, b, e, sub, lanes);
-    case 4:
-      return row_partial<4, kWeighted>(idx, w, x, hot, hot_n, b, e, sub, lanes);
-    default:
-      return row_partial<8, kWeighted>(idx, w, x, hot, hot_n, b, e, sub, lanes);
+__device__ inline void load_tile(TileLoad<kWeighted>& L, const int32_t* __restrict__ idx,
+                                 const float* __restrict__ w, const uint32_t* __restrict__ starts,
+                                 int64_t e) {
+#pragma unroll
+  for (int v = 0; v < kRounds; ++v) {
+    const int64_t ev = e + v * 256;
+    L.src[v] = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(idx + ev));
+    if constexpr (kWeighted) L.w[v] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(w + ev));
+    L.fa[v] = starts[ev >> 5];
+    L.fb[v] = starts[(ev >> 5) + 1];
   }
 }
 
-// One superstep: y = A^T x (pull over in-edges), APPLY, next SEND. Each
-// workgroup first copies the messages of the hottest labels to LDS, then its
-// wavefronts take work units with a stride of all wavefronts of the grid.
 template <bool kWeighted, bool kPersonal>
 __global__ __launch_bounds__(kPullThreads) void pr_pull(
-    const uint32_t* __restrict__ off, const int32_t* __restrict__ idx,
-    const float* __restrict__ w, const float* __restrict__ x_in,
-    const float* __restrict__ inv_outdeg, float r, int32_t seed, float* __restrict__ x_out,
-    float* __restrict__ pr_out, const SplitChunk* __restrict__ chunks,
-    double* __restrict__ partial, Bins bins, int hot_n) {
+    const int32_t* __restrict__ idx, const float* __restrict__ w,
+    const uint32_t* __restrict__ starts, const uint32_t* __restrict__ tile_row, int64_t ntiles,
+    const float* __restrict__ x_in, const float* __restrict__ inv_outdeg, float r, int32_t seed,
+    float* __restrict__ x_out, float* __restrict__ pr_out, double* __restrict__ head,
+    double* __restrict__ tail, int hot_n) {
   extern __shared__ float hot[];  // hot_n floats
-  for (int i = threadIdx.x; i < hot_n; i += kPullThreads) hot[i] = x_in[i];
-  __syncthreads();
+  load_hot(x_in, hot, hot_n);
   const int lane = threadIdx.x & 63;
   const int64_t stride = (int64_t)gridDim.x * kPullWaves;
-  for (int64_t u = (int64_t)blockIdx.x * kPullWaves + (threadIdx.x >> 6); u < bins.nunits;
-       u += stride) {
-    if (u < bins.nchunks) {
-      // One chunk of a split row: partial sum, combined by pr_finish.
-      const SplitChunk c = chunks[u];
-      double acc = row_partial<kUnroll, kWeighted>(idx, w, x_in, hot, hot_n, c.edge_begin,
-                                                   c.edge_end, lane, 64);
-      acc = group_sum(acc, 64);
-      if (lane == 0) partial[u] = acc;
-      continue;
+  const int sh = (lane & 7) * 4;  // this lane's 4 bits in its word of `starts`
+  const char* xb = reinterpret_cast<const char*>(x_in);
+  int64_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * kPullWaves + (threadIdx.x >> 6));
+  if (t >= ntiles) return;
+  TileLoad<kWeighted> cur;
+  for (; t < ntiles; t += stride) {
+    load_tile(cur, idx, w, starts, t * kTile + lane * 4);
+    float val[kRounds][4];
+#pragma unroll
+    for (int v = 0; v < kRounds; ++v)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t s = (uint32_t)cur.src[v][q];
+        const bool in_lds = s < (uint32_t)hot_n;
+        const float g = *reinterpret_cast<const float*>(xb + (in_lds ? 0u : s << 2));
+        const float l = hot[in_lds ? s : 0u];
+        val[v][q] = in_lds ? l : g;
+        if constexpr (kWeighted) val[v][q] *= cur.w[v][q];
+      }
+    uint32_t nib[kRounds], next[kRounds];
+#pragma unroll
+    for (int v = 0; v < kRounds; ++v) {
+      nib[v] = (cur.fa[v] >> sh) & 0xFu;  // bit q: edge q of the lane starts a row
+      next[v] = sh == 28 ? (cur.fb[v] & 1u) : (cur.fa[v] >> (sh + 4)) & 1u;
     }
-    // Class of this unit: the class with the largest first unit <= u.
-    int cls = 1;
-    while (u < bins.class_unit0[cls]) ++cls;
-    const int lanes = kClassLanes[cls];
-    const int64_t local = (u - bins.class_unit0[cls]) * (64 / lanes) + lane / lanes;
-    const bool valid = local < bins.class_rows[cls];
-    const uint32_t row = (uint32_t)(bins.class_begin[cls] + (valid ? local : 0));
-    const int sub = lane % lanes;
-    double y = 0.0;
-    if (valid)
-      y = row_partial_u<kWeighted>(kClassUnroll[cls], idx, w, x_in, hot, hot_n, off[row],
-                                   off[row + 1], sub, lanes);
-    y = group_sum(y, lanes);
-    if (valid && sub == 0) apply_row<kPersonal>(row, y, r, seed, inv_outdeg, x_out, pr_out);
+    __builtin_amdgcn_sched_barrier(0);
+    const uint32_t row0 = tile_row[t];
+    // A start at the tile's first edge opens row0 itself, not the next row.
+    const int f0 = __builtin_amdgcn_readfirstlane((int)(nib[0] & 1u));
+    Seg carry{0, 0.0};
+    float prv[kRounds][4];
+    uint32_t rowv[kRounds][4];
+    uint32_t done = 0;  // bit 4v+q: edge (v, q) ends a row begun in the tile
+#pragma unroll
+    for (int v = 0; v < kRounds; ++v) {
+      double s[4];
+      s[0] = (double)val[v][0];
+#pragma unroll
+      for (int q = 1; q < 4; ++q)
+        s[q] = ((nib[v] >> q) & 1u ? 0.0 : s[q - 1]) + (double)val[v][q];
+      const Seg ex = seg_scan(Seg{(int)__popc(nib[v]), s[3]}, carry, lane);
+      const uint32_t ends = (nib[v] >> 1) | (next[v] << 3);  // bit q: edge q ends its row
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        rowv[v][q] = row0;
+        prv[v][q] = 0.0f;
+        if ((ends >> q) & 1u) {
+          const int lc = (int)__popc(nib[v] & ((2u << q) - 1u));  // starts at or before edge q
+          const int c = ex.c + lc;                                 // ... since the tile's first
+          const double y = lc > 0 ? s[q] : ex.s + s[q];
+          if (c > 0) {
+            rowv[v][q] = row0 + (uint32_t)(c - f0);
+            prv[v][q] = pr_value<kPersonal>(rowv[v][q], y, r, seed);
+            done |= 1u << (4 * v + q);
+          } else {
+            head[t] = y;
+          }
+        }
+      }
+      if (v == kRounds - 1 && lane == 63 && !(ends >> 3)) {
+        const int c = ex.c + (int)__popc(nib[v]);
+        const double y = nib[v] ? s[3] : ex.s + s[3];
+        if (c > 0)
+          tail[t] = y;
+        else
+          head[t] = y;
+      }
+    }
+    float inv[kRounds][4];
+#pragma unroll
+    for (int v = 0; v < kRounds; ++v)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        inv[v][q] = 0.0f;
+        if ((done >> (4 * v + q)) & 1u) inv[v][q] = inv_outdeg[rowv[v][q]];
+      }
+#pragma unroll
+    for (int v = 0; v < kRounds; ++v)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if ((done >> (4 * v + q)) & 1u) {
+          x_out[rowv[v][q]] = prv[v][q] * inv[v][q];
+          if (pr_out) pr_out[rowv[v][q]] = prv[v][q];
+        }
   }
 }
 
+// Rows spanning tiles ta..tb: tail[ta] + head[ta + 1] + ... + head[tb],
+// summed by kCrossLanes lanes in a fixed order, then APPLY and SEND.
 template <bool kPersonal>
-__global__ void pr_finish(const SplitRow* __restrict__ splits, int64_t nsplit,
-                          const double* __restrict__ partial, const float* __restrict__ inv_outdeg,
-                          float r, int32_t seed, float* __restrict__ x_out,
-                          float* __restrict__ pr_out) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nsplit;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const SplitRow sr = splits[i];
-    double y = 0.0;
-    for (uint32_t c = 0; c < sr.nchunks; ++c) y += partial[sr.first_chunk + c];
-    apply_row<kPersonal>(sr.row, y, r, seed, inv_outdeg, x_out, pr_out);
+__global__ void pr_cross(const Cross* __restrict__ cross, int64_t ncross,
+                         const double* __restrict__ head, const double* __restrict__ tail,
+                         const float* __restrict__ inv_outdeg, float r, int32_t seed,
+                         float* __restrict__ x_out, float* __restrict__ pr_out) {
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = gid / kCrossLanes;
+  const int j = (int)(gid % kCrossLanes);
+  double acc = 0.0;
+  Cross c{0, 0, 0, 0};
+  if (i < ncross) {
+    c = cross[i];
+    if (j == 0) acc = tail[c.ta];
+    for (uint32_t t = c.ta + 1 + j; t <= c.tb; t += kCrossLanes) acc += head[t];
   }
+  for (int o = kCrossLanes >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (i < ncross && j == 0) apply_row<kPersonal>(c.row, acc, r, seed, inv_outdeg, x_out, pr_out);
 }
 
 // Rows without in-edges: PR = r * tele(v) in every superstep after the first,
@@ -326,7 +417,6 @@ void free_pull_schedule(gm_graph g) {
   if (!d) return;
   dfree(d->new_of);
   dfree(d->old_of);
-  dfree(d->off);
   dfree(d->idx);
   dfree(d->w);
   dfree(d->ceid);
@@ -335,9 +425,11 @@ void free_pull_schedule(gm_graph g) {
   dfree(d->x[0]);
   dfree(d->x[1]);
   dfree(d->pr);
-  dfree(d->chunks);
-  dfree(d->splits);
-  dfree(d->partial);
+  dfree(d->starts);
+  dfree(d->tile_row);
+  dfree(d->head);
+  dfree(d->tail);
+  dfree(d->cross);
   delete d;
   g->pr_sched = nullptr;
   ++g->ws_gen;
@@ -346,6 +438,7 @@ void free_pull_schedule(gm_graph g) {
 void ensure_pull_schedule(gm_graph g, hipStream_t st) {
   if (dense(g)) return;
   const int64_t n = g->n, m = g->m;
+  if (n >= (int64_t)1 << 30) throw Unsupported{"PageRank pull takes fewer than 2^30 vertices"};
   // Counting sort of the vertices by decreasing in-degree (ties by label).
   std::vector<uint32_t> off(n + 1);
   GM_HIP(hipMemcpyAsync(off.data(), g->in_off, (n + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost,
@@ -377,62 +470,55 @@ void ensure_pull_schedule(gm_graph g, hipStream_t st) {
   try {
     d->n = n;
     d->m = m;
-    // Split rows first, then the degree classes from long to empty rows.
-    std::vector<SplitChunk> chunks;
-    std::vector<SplitRow> splits;
-    int64_t i = 0;
-    while (i < n && noff[i + 1] - noff[i] > kChunk) {
-      const uint32_t deg = noff[i + 1] - noff[i];
-      const uint32_t nch = (deg + kChunk - 1) / kChunk;
-      splits.push_back({(uint32_t)i, (uint32_t)chunks.size(), nch, 0});
-      for (uint32_t c = 0; c < nch; ++c) {
-        const uint32_t eb = noff[i] + c * kChunk;
-        chunks.push_back({(uint32_t)i, eb, std::min(eb + kChunk, noff[i + 1]), 0});
-      }
-      ++i;
+    // Rows with in-edges come first (decreasing in-degree).
+    int64_t rows = 0;
+    while (rows < n && noff[rows + 1] > noff[rows]) ++rows;
+    d->rows = rows;
+    // Tiles of kTile edges; the index stream is padded to whole tiles.
+    const int64_t ntiles = (m + kTile - 1) / kTile;
+    const int64_t mpad = ntiles * kTile;
+    d->ntiles = ntiles;
+    std::vector<uint32_t> starts((size_t)(mpad / 32 + 1), 0u);
+    for (int64_t v = 0; v < rows; ++v) starts[noff[v] >> 5] |= 1u << (noff[v] & 31);
+    starts[(size_t)(m >> 5)] |= 1u << (m & 31);
+    std::vector<uint32_t> tile_row((size_t)ntiles);
+    std::vector<Cross> cross;
+    int64_t v = 0;
+    for (int64_t t = 0; t < ntiles; ++t) {
+      while (noff[v + 1] <= (uint64_t)(t * kTile)) ++v;
+      tile_row[(size_t)t] = (uint32_t)v;
     }
-    Bins& bins = d->bins;
-    bins.nchunks = (int64_t)chunks.size();
-    d->nsplit = (int64_t)splits.size();
-    int64_t unit = bins.nchunks;
-    for (int c = kClasses - 1; c >= 0; --c) {
-      const int64_t r0 = i;
-      if (c == 0)
-        i = n;  // the rest has in-degree 0
-      else
-        while (i < n && noff[i + 1] - noff[i] > kClassMax[c - 1]) ++i;
-      bins.class_begin[c] = r0;
-      bins.class_rows[c] = i - r0;
-      bins.class_unit0[c] = unit;
-      if (c > 0) {
-        const int64_t rpu = 64 / kClassLanes[c];
-        unit += (bins.class_rows[c] + rpu - 1) / rpu;
-      }
+    for (int64_t u = 0; u < rows; ++u) {
+      const uint32_t ta = (uint32_t)(noff[u] / kTile), tb = (uint32_t)((noff[u + 1] - 1) / kTile);
+      if (ta != tb) cross.push_back({(uint32_t)u, ta, tb, 0});
     }
-    bins.nunits = unit;
+    d->ncross = (int64_t)cross.size();
     int dev = 0;
     GM_HIP(hipGetDevice(&dev));
     GM_HIP(hipDeviceGetAttribute(&d->cus, hipDeviceAttributeMultiprocessorCount, dev));
+    GM_HIP(hipDeviceGetAttribute(&d->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     d->new_of = dalloc<int32_t>(n);
     d->old_of = dalloc<int32_t>(n);
-    d->off = dalloc<uint32_t>(n + 1);
-    d->idx = dalloc<int32_t>(m);
+    d->idx = dalloc<int32_t>(mpad);
     d->inv_outdeg = dalloc<float>(n);
     d->x[0] = dalloc<float>(n);
     d->x[1] = dalloc<float>(n);
     d->pr = dalloc<float>(n);
-    d->chunks = dalloc<SplitChunk>(chunks.size());
-    d->splits = dalloc<SplitRow>(splits.size());
-    d->partial = dalloc<double>(chunks.size());
+    d->starts = dalloc<uint32_t>(starts.size());
+    d->tile_row = dalloc<uint32_t>(tile_row.size());
+    d->head = dalloc<double>(ntiles);
+    d->tail = dalloc<double>(ntiles);
+    d->cross = dalloc<Cross>(cross.size());
     GM_HIP(hipMemcpyAsync(d->new_of, new_of.data(), n * 4, hipMemcpyHostToDevice, st));
     GM_HIP(hipMemcpyAsync(d->old_of, old_of.data(), n * 4, hipMemcpyHostToDevice, st));
-    GM_HIP(hipMemcpyAsync(d->off, noff.data(), (n + 1) * 4, hipMemcpyHostToDevice, st));
-    if (!chunks.empty())
-      GM_HIP(hipMemcpyAsync(d->chunks, chunks.data(), chunks.size() * sizeof(SplitChunk),
+    GM_HIP(hipMemcpyAsync(d->starts, starts.data(), starts.size() * 4, hipMemcpyHostToDevice, st));
+    if (ntiles > 0)
+      GM_HIP(hipMemcpyAsync(d->tile_row, tile_row.data(), tile_row.size() * 4,
                             hipMemcpyHostToDevice, st));
-    if (!splits.empty())
-      GM_HIP(hipMemcpyAsync(d->splits, splits.data(), splits.size() * sizeof(SplitRow),
+    if (!cross.empty())
+      GM_HIP(hipMemcpyAsync(d->cross, cross.data(), cross.size() * sizeof(Cross),
                             hipMemcpyHostToDevice, st));
+    if (mpad > m) GM_HIP(hipMemsetAsync(d->idx + m, 0, (mpad - m) * 4, st));
     gather_f32<<<blocks_for(n), kThreads, 0, st>>>(g->inv_outdeg, d->old_of, n, d->inv_outdeg);
     GM_HIP(hipGetLastError());
     if (m > 0) {
@@ -452,7 +538,10 @@ void ensure_pull_schedule(gm_graph g, hipStream_t st) {
       if (err == hipSuccess) (void)hipStreamSynchronize(st);
       dfree(tmp);
       GM_HIP(err);
-      if (g->wtype == GM_W_F32) d->w = dalloc<float>(m);
+      if (g->wtype == GM_W_F32) {
+        d->w = dalloc<float>(mpad);
+        if (mpad > m) GM_HIP(hipMemsetAsync(d->w + m, 0, (mpad - m) * 4, st));
+      }
       d->ceid = dalloc<uint32_t>(m);
       relabel_finish<<<blocks_for(m), kThreads, 0, st>>>(kb.current(), vb.current(), m, b,
                                                          static_cast<const float*>(g->in_w),
@@ -467,15 +556,15 @@ void ensure_pull_schedule(gm_graph g, hipStream_t st) {
 }
 
 // Workgroups of one pr_pull launch: as many as fit on the device at once
-// with `lds` bytes of LDS each (the kernel strides over its work units), no
-// more than there are units.
+// with `lds` bytes of LDS each (the kernel strides over the tiles), no more
+// than there are tiles.
 static unsigned pull_grid(Dense* d, size_t lds, bool weighted, bool personal) {
   const void* k = weighted ? (personal ? (const void*)pr_pull<true, true> : (const void*)pr_pull<true, false>)
                            : (personal ? (const void*)pr_pull<false, true> : (const void*)pr_pull<false, false>);
   int per_cu = 0;
   GM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kPullThreads, lds));
   const int64_t fit = (int64_t)std::max(per_cu, 1) * std::max(d->cus, 1);
-  const int64_t want = (d->bins.nunits + kPullWaves - 1) / kPullWaves;
+  const int64_t want = (d->ntiles + kPullWaves - 1) / kPullWaves;
   return (unsigned)std::max<int64_t>(1, std::min(fit, want));
 }
 
@@ -491,7 +580,7 @@ static void pagerank_driver(gm_graph g, Dense* d, float r, int32_t iters, const 
   const bool personal = seed_new >= 0;
   pr_send0<<<blocks_for(n), kThreads, 0, st>>>(rank0, d->old_of, d->inv_outdeg, n, d->x[0]);
   GM_HIP(hipGetLastError());
-  const int64_t c0 = d->bins.class_begin[0], n0 = d->bins.class_rows[0];
+  const int64_t c0 = d->rows, n0 = n - d->rows;
   auto const_rows = [&](float* xo, float* po) {
     if (n0 == 0) return;
     if (personal)
@@ -502,7 +591,8 @@ static void pagerank_driver(gm_graph g, Dense* d, float r, int32_t iters, const 
                                                                  d->inv_outdeg, xo, po);
     GM_HIP(hipGetLastError());
   };
-  const int hot_n = (int)std::min<int64_t>(std::min<int64_t>(g->tune.pr_hot, kHotMax), n);
+  const int64_t hot_cap = std::min<int64_t>(kHotMax, d->lds_max / (int64_t)sizeof(float));
+  const int hot_n = (int)std::min<int64_t>(std::min<int64_t>(g->tune.pr_hot, hot_cap), n);
   const size_t lds = (size_t)hot_n * sizeof(float);
   const unsigned grid = pull_grid(d, lds, weighted, personal);
   const_rows(d->x[1], d->pr);
@@ -511,9 +601,10 @@ static void pagerank_driver(gm_graph g, Dense* d, float r, int32_t iters, const 
     float* xout = d->x[(it + 1) & 1];
     float* pout = (hist || it == iters - 1) ? d->pr : nullptr;
     auto launch = [&](auto kern) {
-      if (d->bins.nunits > 0)
-        kern<<<grid, kPullThreads, lds, st>>>(d->off, d->idx, w, xin, d->inv_outdeg, r, seed_new,
-                                              xout, pout, d->chunks, d->partial, d->bins, hot_n);
+      if (d->ntiles > 0)
+        kern<<<grid, kPullThreads, lds, st>>>(d->idx, w, d->starts, d->tile_row, d->ntiles, xin,
+                                              d->inv_outdeg, r, seed_new, xout, pout, d->head,
+                                              d->tail, hot_n);
     };
     if (weighted && personal)
       launch(pr_pull<true, true>);
@@ -523,14 +614,14 @@ static void pagerank_driver(gm_graph g, Dense* d, float r, int32_t iters, const 
       launch(pr_pull<false, true>);
     else
       launch(pr_pull<false, false>);
-    if (d->nsplit > 0) {
-      const unsigned fb = (unsigned)((d->nsplit + kThreads - 1) / kThreads);
+    if (d->ncross > 0) {
+      const unsigned fb = (unsigned)((d->ncross * kCrossLanes + kThreads - 1) / kThreads);
       if (personal)
-        pr_finish<true><<<fb, kThreads, 0, st>>>(d->splits, d->nsplit, d->partial, d->inv_outdeg,
-                                                  r, seed_new, xout, pout);
+        pr_cross<true><<<fb, kThreads, 0, st>>>(d->cross, d->ncross, d->head, d->tail,
+                                                 d->inv_outdeg, r, seed_new, xout, pout);
       else
-        pr_finish<false><<<fb, kThreads, 0, st>>>(d->splits, d->nsplit, d->partial, d->inv_outdeg,
-                                                   r, seed_new, xout, pout);
+        pr_cross<false><<<fb, kThreads, 0, st>>>(d->cross, d->ncross, d->head, d->tail,
+                                                  d->inv_outdeg, r, seed_new, xout, pout);
     }
     GM_HIP(hipGetLastError());
     if (it == 0) const_rows(d->x[0], nullptr);  // x[0] held PR^0 messages until now
@@ -571,7 +662,11 @@ void run_pagerank_history(gm_graph g, const float* w, float r, int32_t T, float*
                           hipStream_t st) {
   ensure_pull_schedule(g, st);
   Dense* d = dense(g);
-  if (!d->wdyn) d->wdyn = dalloc<float>(g->m);
+  if (!d->wdyn) {
+    const int64_t mpad = d->ntiles * kTile;
+    d->wdyn = dalloc<float>(mpad);
+    if (mpad > g->m) GM_HIP(hipMemsetAsync(d->wdyn + g->m, 0, (mpad - g->m) * 4, st));
+  }
   if (g->m > 0) {
     gather_w<<<blocks_for(g->m), kThreads, 0, st>>>(w, d->ceid, g->m, d->wdyn);
     GM_HIP(hipGetLastError());

@@ -185,7 +185,7 @@ gm_status check_tuning(const gm_tuning& t) {
            {"tc_wave_max", t.tc_wave_max, {64, 1024}},
            {"tc_wave_work", t.tc_wave_work, {256, 1u << 24}},
            {"tc_block_work", t.tc_block_work, {256, 1u << 26}},
-           {"pr_hot", t.pr_hot, {0, 32768}}};
+           {"pr_hot", t.pr_hot, {0, 40960}}};
   for (const F& x : f)
     if (x.v < x.r.lo || x.v > x.r.hi)
       return fail(GM_EINVAL, "%s = %u outside [%u, %u]", x.name, x.v, x.r.lo, x.r.hi);
@@ -520,7 +520,7 @@ gm_status gm_autotune(gm_graph g, const gm_program* prog, int32_t batched, const
     } else if (batched && kind == GM_PROG_PPR) {
       params.push_back({&Tuning::ppr_chunk, {128, 256, 512, 1024, 2048, 4096}});
     } else if (!batched && kind == GM_PROG_PAGERANK) {
-      params.push_back({&Tuning::pr_hot, {0, 4096, 8192, 16384, 32768}});
+      params.push_back({&Tuning::pr_hot, {0, 8192, 16384, 32768, 40960}});
     } else if (kind == GM_PROG_TC) {
       params.push_back({&Tuning::tc_wave_max, {256, 512, 1024}});
       params.push_back({&Tuning::tc_wave_work, {1u << 12, 1u << 14, 1u << 16}});
