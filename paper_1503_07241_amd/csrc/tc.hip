@@ -99,24 +99,22 @@ struct TcPlan {
   hipEvent_t done[kClassesTc] = {};
 };
 
-// 32-bit integer mixer (xor-shift-multiply rounds); every output bit depends
-// on every input bit, which matters because RMAT ids have very skewed bits.
-__device__ inline uint32_t hash_id(int32_t id) {
-  uint32_t x = (uint32_t)id;
-  x ^= x >> 16;
-  x *= 0x7feb352du;
-  x ^= x >> 15;
-  x *= 0x846ca68bu;
-  x ^= x >> 16;
-  return x;
+// Home bucket of a key in a table of 2^(32 - shift) buckets: the top bits
+// of the key times an odd constant (multiplicative hashing), which spreads
+// the skewed low bits of RMAT ids over the whole table.
+__device__ inline uint32_t home_bucket(int32_t id, uint32_t shift) {
+  return ((uint32_t)id * 0x9E3779B1u) >> shift;
 }
+
+// Shift for a table with bmask + 1 buckets (a power of two, at least 16).
+__device__ inline uint32_t bucket_shift(uint32_t bmask) { return 32u - (uint32_t)__popc(bmask); }
 
 // Tables are buckets of 4 slots (one 16-byte LDS or global read); a key
 // lives in its home bucket or, when that is full, in the next buckets
 // (linear probing over buckets). At most half of the slots are used, so most
 // lookups read one bucket.
 __device__ inline void table_insert(int32_t* T, uint32_t bmask, int32_t id) {
-  uint32_t b = hash_id(id) & bmask;
+  uint32_t b = home_bucket(id, bucket_shift(bmask));
   for (;;) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -132,10 +130,9 @@ __device__ inline uint32_t in_bucket(int4 q, int32_t key) {
   return min(a, b) == 0u ? 1u : 0u;
 }
 
-// True if no slot of the bucket is free (keys are >= 0, kEmpty is all ones).
-__device__ inline bool bucket_full(int4 q) {
-  return max(max((uint32_t)q.x, (uint32_t)q.y), max((uint32_t)q.z, (uint32_t)q.w)) != 0xFFFFFFFFu;
-}
+// True if no slot of the bucket is free: inserts fill slots in order, so
+// the last one is taken only in a full bucket.
+__device__ inline bool bucket_full(int4 q) { return q.w != kEmpty; }
 
 __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -152,30 +149,33 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x, int lane) {
 
 // Matches of one aligned quad of in_idx (elements 4q .. 4q + 3, those in
 // [s, e) counted) in the table.
-__device__ inline uint32_t probe_quad(const int4* T4, uint32_t bmask, int4 v, uint32_t q,
-                                      uint32_t s, uint32_t e) {
+__device__ inline uint32_t probe_quad(const int4* T4, uint32_t bmask, uint32_t shift, int4 v,
+                                      uint32_t q, uint32_t s, uint32_t e) {
   const int32_t key[4] = {v.x, v.y, v.z, v.w};
   uint32_t bk[4];
   int4 b[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    bk[i] = hash_id(key[i]) & bmask;
+    bk[i] = home_bucket(key[i], shift);
     b[i] = T4[bk[i]];
   }
+  // Elements of the quad inside [s, e): bits lo .. hi - 1.
+  const int32_t base = (int32_t)(4 * q);
+  const int32_t lo = (int32_t)s - base, hi = (int32_t)e - base;
+  const uint32_t ok = (hi >= 4 ? 0xFu : (1u << hi) - 1u) & (lo <= 0 ? 0xFu : ~((1u << lo) - 1u));
   uint32_t cnt = 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const uint32_t pos = 4 * q + i;
-    const bool ok = pos >= s && pos < e;
+    const bool in = (ok >> i) & 1u;
     uint32_t hit = in_bucket(b[i], key[i]);
-    bool more = ok && !hit && bucket_full(b[i]);
+    bool more = in && !hit && bucket_full(b[i]);
     while (more) {  // rare: the key's home bucket is full
       bk[i] = (bk[i] + 1) & bmask;
       b[i] = T4[bk[i]];
       hit = in_bucket(b[i], key[i]);
       more = !hit && bucket_full(b[i]);
     }
-    cnt += ok ? hit : 0u;
+    cnt += in ? hit : 0u;
   }
   return cnt;
 }
@@ -211,6 +211,7 @@ __device__ inline unsigned long long walk_partners(const int4* T4, uint32_t bmas
                                                    const uint32_t* __restrict__ pstart = nullptr,
                                                    int64_t shift = 0) {
   const int lane = threadIdx.x & 63;
+  const uint32_t hshift = bucket_shift(bmask);
   unsigned long long own = 0;
   for (uint32_t j0 = p_begin; j0 < p_end; j0 += j_step) {
     const uint32_t j = j0 + lane;
@@ -262,7 +263,7 @@ __device__ inline unsigned long long walk_partners(const int4* T4, uint32_t bmas
           }
           v = *reinterpret_cast<const int4*>(in_idx + 4 * (size_t)q);
         }
-        const uint32_t c = probe_quad(T4, bmask, cv, cq, cs, ce);
+        const uint32_t c = probe_quad(T4, bmask, hshift, cv, cq, cs, ce);
         if (c) atomicAdd(&W->cnt[co], c);
       }
     }
