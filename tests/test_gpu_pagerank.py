@@ -56,6 +56,54 @@ def test_pagerank_long_rows_split():
         assert W.max_rel_err(run_pr(g, n), ref) <= TOL
 
 
+def _rows_graph(degrees, extra_sources, seed):
+    """Row v (v < len(degrees)) gets degrees[v] in-edges from distinct random
+    sources among all n vertices (no self loops)."""
+    rng = np.random.default_rng(seed)
+    nrows = len(degrees)
+    n = nrows + extra_sources
+    src, dst = [], []
+    for v, k in enumerate(degrees):
+        cand = rng.choice(n - 1, size=k, replace=False)
+        cand = np.where(cand >= v, cand + 1, cand)
+        src.append(cand)
+        dst.append(np.full(k, v))
+    return n, np.concatenate(src).astype(np.int32), np.concatenate(dst).astype(np.int32)
+
+
+# In-degree multisets whose running sums, in decreasing order (the kernel's
+# row order), put row ends exactly on, just before and just after multiples
+# of the 1024-edge tile, rows spanning several tiles, and runs of in-degree-1
+# rows; totals that fill the last tile exactly and that leave it ragged.
+TILE_CASES = [
+    [3072, 1024, 1000, 24] + [1] * 1024,
+    [3072, 1024, 1000, 24] + [1] * 1023,
+    [2049, 1023, 1, 1],
+    [1025] + [2] * 600 + [1] * 5,
+    [1024],
+    [5] * 3 + [1] * 7,
+    [700, 324] + [3] * 341 + [1],
+]
+
+
+@pytest.mark.parametrize("case", range(len(TILE_CASES)))
+def test_pagerank_tile_boundaries(case):
+    degrees = TILE_CASES[case]
+    n, s, d = _rows_graph(degrees, 4000, seed=100 + case)
+    g = gm.Graph.from_coo(n, s, d)
+    og = oracle.prepare(n, s, d)
+    assert W.max_rel_err(run_pr(g, n), oracle.pagerank(og, 0.15, 20)) <= TOL
+    wf = gg.weights_f32(s, d, 12 + case, 0.5, 1.5)
+    gw = gm.Graph.from_coo(n, s, d, w=wf)
+    ogw = oracle.prepare(n, s, d, w=wf)
+    ref = oracle.pagerank(ogw, 0.15, 20, w=ogw.w.astype(np.float64))
+    assert W.max_rel_err(run_pr(gw, n), ref) <= TOL
+    for seed in (0, 1):
+        got = run_pr(g, n, kind=gm.GM_PROG_PPR, seed=seed)
+        ref = oracle.personalized_pagerank(og, seed, 0.15, 20)
+        assert np.abs(got - ref).sum() / np.abs(ref).sum() <= TOL
+
+
 def test_pagerank_closed_forms():
     n = 1000
     cyc = gm.Graph.from_coo(n, np.arange(n), (np.arange(n) + 1) % n)
