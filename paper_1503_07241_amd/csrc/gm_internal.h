@@ -86,8 +86,9 @@ struct PlanResult {
 };
 
 // Neighbour-index arrays hold this many extra entries after the last edge,
-// so that kernels may read an edge's aligned 16-byte quad whole.
-constexpr int64_t kIdxPad = 4;
+// so that kernels may read the aligned 64-byte line holding an edge whole
+// (triangle counting reads aligned 32-byte units).
+constexpr int64_t kIdxPad = 16;
 
 // Most supersteps a captured BFS/SSSP run records.
 constexpr int kMaxPlanSteps = 64;

@@ -9,16 +9,16 @@
 // N_triangles of Eq. (7).
 //
 // Work organisation: the intersection for DAG edge (u -> v) is computed by
-// one endpoint (its "owner"): an owner x puts in(x) in a hash table (LDS, or
-// global memory for very long lists) once, then streams the in-list of every
+// one endpoint (its "owner"): an owner x puts in(x) in a hash table in LDS
+// (very long lists in LDS-sized pieces) once, then streams the in-list of every
 // partner through it, one probe per element, stopping at the first element
 // >= x (in(x) holds only smaller ids). The endpoint whose partner stream is
 // shorter owns the edge. The match count of edge (u -> v) is credited to the
 // receiver v, as APPLY prescribes. Owner/partner lists are built once per
 // graph and cut into work items of bounded size, one wavefront or workgroup
-// each. Each lane walks one partner's in-list (an owner's partners are sorted
-// by list length, so the lanes of a wavefront walk similar lengths), four
-// elements per 16-byte load, one bucket read per element in most cases.
+// each. The lanes of a wavefront split a window of 64 partners' streams
+// into equal runs of 32-byte units, one bucket read per element in most
+// cases.
 // All counts are exact integers, independent of scheduling.
 #include <algorithm>
 #include <vector>
@@ -147,10 +147,9 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x, int lane) {
   return x;
 }
 
-// Matches of one aligned quad of in_idx (elements 4q .. 4q + 3, those in
-// [s, e) counted) in the table.
-__device__ inline uint32_t probe_quad(const int4* T4, uint32_t bmask, uint32_t shift, int4 v,
-                                      uint32_t q, uint32_t s, uint32_t e) {
+// Matches in the table of the elements of quad v whose bits are set in ok.
+__device__ __forceinline__ uint32_t probe_quad(const int4* T4, uint32_t bmask, uint32_t shift, int4 v,
+                                      uint32_t ok) {
   const int32_t key[4] = {v.x, v.y, v.z, v.w};
   uint32_t bk[4];
   int4 b[4];
@@ -159,10 +158,6 @@ __device__ inline uint32_t probe_quad(const int4* T4, uint32_t bmask, uint32_t s
     bk[i] = home_bucket(key[i], shift);
     b[i] = T4[bk[i]];
   }
-  // Elements of the quad inside [s, e): bits lo .. hi - 1.
-  const int32_t base = (int32_t)(4 * q);
-  const int32_t lo = (int32_t)s - base, hi = (int32_t)e - base;
-  const uint32_t ok = (hi >= 4 ? 0xFu : (1u << hi) - 1u) & (lo <= 0 ? 0xFu : ~((1u << lo) - 1u));
   uint32_t cnt = 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -180,10 +175,48 @@ __device__ inline uint32_t probe_quad(const int4* T4, uint32_t bmask, uint32_t s
   return cnt;
 }
 
+// Elements per unit of a partner stream: an aligned 32-byte half line of
+// in_idx, loaded whole, so that a line is requested from L2 about twice (a
+// lane that took a line a quad at a time would mostly find it evicted from
+// L1 before its next quad; whole 64-byte lines cost more registers than the
+// saved requests are worth).
+constexpr uint32_t kLine = 8;
+
+struct Line {
+  int4 q[kLine / 4];
+};
+
+__device__ __forceinline__ Line load_line(const int32_t* __restrict__ in_idx, uint32_t l) {
+  const int4* p = reinterpret_cast<const int4*>(in_idx + (size_t)kLine * l);
+  Line L;
+#pragma unroll
+  for (int k = 0; k < (int)kLine / 4; ++k) L.q[k] = p[k];
+  return L;
+}
+
+// Matches of unit l of in_idx (elements kLine l .. kLine l + kLine - 1,
+// those in [s, e) counted) in the table.
+__device__ __forceinline__ uint32_t probe_line(const int4* T4, uint32_t bmask, uint32_t shift,
+                                      const Line& L, uint32_t l, uint32_t s, uint32_t e) {
+  const int32_t base = (int32_t)(kLine * l);
+  const int32_t lo = (int32_t)s - base, hi = (int32_t)e - base;
+  constexpr uint32_t kAll = (1u << kLine) - 1u;
+  const uint32_t ok =
+      (hi >= (int32_t)kLine ? kAll : (1u << hi) - 1u) & (lo <= 0 ? kAll : ~((1u << lo) - 1u));
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int k = 0; k < (int)kLine / 4; ++k) {
+    cnt += probe_quad(T4, bmask, shift, L.q[k], (ok >> (4 * k)) & 0xFu);
+    // one quad's buckets in registers at a time
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  return cnt;
+}
+
 // Per-wavefront LDS scratch of a partner window.
 struct Window {
-  uint32_t excl[65];  // first quad of each lane's partner in the window's quad sequence; [64] = total
-  uint32_t qa[64];    // the partner's first aligned quad in the index array
+  uint32_t excl[65];  // first unit of each lane's partner in the window's unit sequence; [64] = total
+  uint32_t la[64];    // the partner's first aligned unit in the index array
   uint32_t s[64];     // its stream [s, e)
   uint32_t e[64];
   uint32_t cnt[64];   // its matches
@@ -193,14 +226,14 @@ struct Window {
 // window holds partner j0 + l; windows step by j_step). A partner streams
 // the elements [s, s + len) of the index array: s = in_off[y] and len =
 // lens[j], or, for the pieces of a split owner, s = pstart[j + shift] and
-// len = lens[j + shift]. The window's streams are cut into aligned quads of
-// four elements and the quad sequence into 64 equal contiguous ranges, one
-// per lane: a lane finds the partner of its first quad by binary search over
+// len = lens[j + shift]. The window's streams are cut into aligned units of
+// kLine elements and the unit sequence into 64 equal contiguous ranges, one
+// per lane: a lane finds the partner of its first unit by binary search over
 // the window's prefix sums (in LDS), then walks its range, moving to the next
-// partner at each boundary, the next quad's load issued before the current
-// quad is probed. Matches credited to the owner are returned; those credited
+// partner at each boundary, the next unit's loads issued before the current
+// unit is probed. Matches credited to the owner are returned; those credited
 // to a partner are added to counts[partner].
-__device__ inline unsigned long long walk_partners(const int4* T4, uint32_t bmask,
+__device__ __forceinline__ unsigned long long walk_partners(const int4* T4, uint32_t bmask,
                                                    const uint32_t* __restrict__ work,
                                                    uint32_t p_begin, uint32_t p_end,
                                                    uint32_t j_step,
@@ -222,13 +255,13 @@ __device__ inline unsigned long long walk_partners(const int4* T4, uint32_t bmas
       s = pstart ? pstart[j + shift] : in_off[y];
       e = s + lens[j + shift];
     }
-    const uint32_t qa = s >> 2;
-    const uint32_t nq = e > s ? ((e + 3) >> 2) - qa : 0u;
-    const uint32_t incl = wave_incl_scan(nq, lane);
+    const uint32_t la = s / kLine;
+    const uint32_t nl = e > s ? (e + kLine - 1) / kLine - la : 0u;
+    const uint32_t incl = wave_incl_scan(nl, lane);
     const uint32_t total = __shfl(incl, 63, 64);
-    W->excl[lane] = incl - nq;
+    W->excl[lane] = incl - nl;
     if (lane == 63) W->excl[64] = total;
-    W->qa[lane] = qa;
+    W->la[lane] = la;
     W->s[lane] = s;
     W->e[lane] = e;
     W->cnt[lane] = 0;
@@ -238,32 +271,32 @@ __device__ inline unsigned long long walk_partners(const int4* T4, uint32_t bmas
     uint32_t idx = min(total, per * lane);
     const uint32_t iend = min(total, idx + per);
     if (idx < iend) {
-      int o = 0;  // the last lane whose first quad is <= idx
+      int o = 0;  // the last lane whose first unit is <= idx
       for (int step = 32; step > 0; step >>= 1)
         if (W->excl[o + step] <= idx) o += step;
       uint32_t bound = W->excl[o + 1];
-      uint32_t q = W->qa[o] + (idx - W->excl[o]);
+      uint32_t l = W->la[o] + (idx - W->excl[o]);
       uint32_t so = W->s[o], eo = W->e[o];
-      int4 v = *reinterpret_cast<const int4*>(in_idx + 4 * (size_t)q);
+      Line v = load_line(in_idx, l);
       while (idx < iend) {
-        const int4 cv = v;
-        const uint32_t cq = q, cs = so, ce = eo;
+        const Line cv = v;
+        const uint32_t cl = l, cs = so, ce = eo;
         const int co = o;
         ++idx;
-        ++q;
+        ++l;
         if (idx < iend) {
-          if (idx == bound) {  // next partner with quads
+          if (idx == bound) {  // next partner with units
             do {
               ++o;
               bound = W->excl[o + 1];
             } while (bound <= idx);
-            q = W->qa[o];
+            l = W->la[o];
             so = W->s[o];
             eo = W->e[o];
           }
-          v = *reinterpret_cast<const int4*>(in_idx + 4 * (size_t)q);
+          v = load_line(in_idx, l);
         }
-        const uint32_t c = probe_quad(T4, bmask, hshift, cv, cq, cs, ce);
+        const uint32_t c = probe_line(T4, bmask, hshift, cv, cl, cs, ce);
         if (c) atomicAdd(&W->cnt[co], c);
       }
     }
