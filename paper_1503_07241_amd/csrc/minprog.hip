@@ -162,15 +162,17 @@ __global__ __launch_bounds__(kThreads) void send_kernel(
   }
 }
 
-// PROCESS + REDUCE(min) + APPLY(min) of one edge; non-returning atomics only.
-// The value of v drops this superstep iff cand < (any value of v read during
-// the superstep), so marking v after such a read is exactly "v changed".
+// PROCESS + REDUCE(min) + APPLY(min) of one edge. A cached read of v's value
+// (the value at kernel start or a later, lower one: values only drop) filters
+// out most edges; the others do an atomic min, and v is marked changed
+// exactly when the value the atomic replaced was larger than cand.
 __device__ inline void relax(uint32_t cand, int32_t v, uint32_t* prop, uint32_t* next) {
-  if (cand < __hip_atomic_load(&prop[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-    __hip_atomic_fetch_min(&prop[v], cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t bit = 1u << (v & 31);
-    if (!(__hip_atomic_load(&next[v >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit))
-      __hip_atomic_fetch_or(&next[v >> 5], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (cand < __hip_atomic_load(&prop[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT)) {
+    const uint32_t old =
+        __hip_atomic_fetch_min(&prop[v], cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cand < old)
+      __hip_atomic_fetch_or(&next[v >> 5], 1u << (v & 31), __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
