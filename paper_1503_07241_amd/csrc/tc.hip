@@ -100,10 +100,11 @@ struct TcPlan {
 };
 
 // Home bucket of a key in a table of 2^(32 - shift) buckets: the top bits
-// of the key times an odd constant (multiplicative hashing), which spreads
-// the skewed low bits of RMAT ids over the whole table.
+// of the key's low 24 bits times an odd constant (multiplicative hashing,
+// with the full-rate 24-bit multiply), which spreads the skewed low bits of
+// RMAT ids over the whole table; the key's top byte is xored in.
 __device__ inline uint32_t home_bucket(int32_t id, uint32_t shift) {
-  return ((uint32_t)id * 0x9E3779B1u) >> shift;
+  return (__umul24((uint32_t)id, 0x9E3779u) ^ ((uint32_t)id & 0xFF000000u)) >> shift;
 }
 
 // Shift for a table with bmask + 1 buckets (a power of two, at least 16).
@@ -147,34 +148,6 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x, int lane) {
   return x;
 }
 
-// Matches in the table of the elements of quad v whose bits are set in ok.
-__device__ __forceinline__ uint32_t probe_quad(const int4* T4, uint32_t bmask, uint32_t shift, int4 v,
-                                      uint32_t ok) {
-  const int32_t key[4] = {v.x, v.y, v.z, v.w};
-  uint32_t bk[4];
-  int4 b[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    bk[i] = home_bucket(key[i], shift);
-    b[i] = T4[bk[i]];
-  }
-  uint32_t cnt = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const bool in = (ok >> i) & 1u;
-    uint32_t hit = in_bucket(b[i], key[i]);
-    bool more = in && !hit && bucket_full(b[i]);
-    while (more) {  // rare: the key's home bucket is full
-      bk[i] = (bk[i] + 1) & bmask;
-      b[i] = T4[bk[i]];
-      hit = in_bucket(b[i], key[i]);
-      more = !hit && bucket_full(b[i]);
-    }
-    cnt += in ? hit : 0u;
-  }
-  return cnt;
-}
-
 // Elements per unit of a partner stream: an aligned 32-byte half line of
 // in_idx, loaded whole, so that a line is requested from L2 about twice (a
 // lane that took a line a quad at a time would mostly find it evicted from
@@ -195,22 +168,50 @@ __device__ __forceinline__ Line load_line(const int32_t* __restrict__ in_idx, ui
 }
 
 // Matches of unit l of in_idx (elements kLine l .. kLine l + kLine - 1,
-// those in [s, e) counted) in the table.
+// those in [s, e) counted) in the table. Every element reads its home
+// bucket; the few whose home bucket is full without holding them go on to
+// the next buckets in a separate pass.
 __device__ __forceinline__ uint32_t probe_line(const int4* T4, uint32_t bmask, uint32_t shift,
-                                      const Line& L, uint32_t l, uint32_t s, uint32_t e) {
+                                               const Line& L, uint32_t l, uint32_t s, uint32_t e) {
   const int32_t base = (int32_t)(kLine * l);
   const int32_t lo = (int32_t)s - base, hi = (int32_t)e - base;
   constexpr uint32_t kAll = (1u << kLine) - 1u;
   const uint32_t ok =
       (hi >= (int32_t)kLine ? kAll : (1u << hi) - 1u) & (lo <= 0 ? kAll : ~((1u << lo) - 1u));
-  uint32_t cnt = 0;
+  int32_t key[kLine];
 #pragma unroll
   for (int k = 0; k < (int)kLine / 4; ++k) {
-    cnt += probe_quad(T4, bmask, shift, L.q[k], (ok >> (4 * k)) & 0xFu);
-    // one quad's buckets in registers at a time
-    __builtin_amdgcn_sched_barrier(0);
+    key[4 * k] = L.q[k].x;
+    key[4 * k + 1] = L.q[k].y;
+    key[4 * k + 2] = L.q[k].z;
+    key[4 * k + 3] = L.q[k].w;
   }
-  return cnt;
+  uint32_t hits = 0, more = 0;  // bit i: element i found / home bucket full without it
+#pragma unroll
+  for (int i = 0; i < (int)kLine; ++i) {
+    const int4 b = T4[home_bucket(key[i], shift)];
+    const uint32_t h = in_bucket(b, key[i]);
+    hits |= h << i;
+    more |= (h == 0u && bucket_full(b)) ? 1u << i : 0u;
+  }
+  more &= ok;
+  if (more) {  // rare: linear probing past a full home bucket
+#pragma unroll
+    for (int i = 0; i < (int)kLine; ++i) {
+      if (!((more >> i) & 1u)) continue;
+      uint32_t bk = home_bucket(key[i], shift);
+      for (;;) {
+        bk = (bk + 1) & bmask;
+        const int4 b = T4[bk];
+        if (in_bucket(b, key[i])) {
+          hits |= 1u << i;
+          break;
+        }
+        if (!bucket_full(b)) break;
+      }
+    }
+  }
+  return (uint32_t)__popc(hits & ok);
 }
 
 // Per-wavefront LDS scratch of a partner window.
