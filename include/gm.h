@@ -397,7 +397,7 @@ typedef struct gm_tuning {
   uint32_t tc_wave_work;    /* TC: partner elements per wavefront work item
                                (256..2^24; 2^14) */
   uint32_t tc_block_work;   /* TC: partner elements per workgroup work item
-                               (256..2^26; 2^20) */
+                               (256..2^26; 2^23) */
   uint32_t pr_hot;          /* PageRank/PPR pull: the messages of the pr_hot
                                highest-in-degree vertices are staged in LDS by
                                every workgroup (0..40960; 40960, capped by the

@@ -73,7 +73,7 @@ struct Tuning {
   uint32_t tc_wave_max = 1024;
   // TC: partner-list elements per wavefront / workgroup work item
   uint32_t tc_wave_work = 1u << 14;
-  uint32_t tc_block_work = 1u << 20;
+  uint32_t tc_block_work = 1u << 23;
   // PageRank / PPR pull: messages of the first pr_hot labels read from LDS
   uint32_t pr_hot = 40960;
 };

@@ -524,7 +524,7 @@ gm_status gm_autotune(gm_graph g, const gm_program* prog, int32_t batched, const
     } else if (kind == GM_PROG_TC) {
       params.push_back({&Tuning::tc_wave_max, {256, 512, 1024}});
       params.push_back({&Tuning::tc_wave_work, {1u << 12, 1u << 14, 1u << 16}});
-      params.push_back({&Tuning::tc_block_work, {1u << 18, 1u << 20, 1u << 22}});
+      params.push_back({&Tuning::tc_block_work, {1u << 21, 1u << 23, 1u << 25}});
     }
     const Tuning before = g->tune;
     for (const Param& prm : params) {

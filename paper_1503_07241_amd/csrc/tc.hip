@@ -546,9 +546,10 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
     }
   }
   // Work items: each owner's partners cut where the scanned elements reach
-  // the class's budget (a partner longer than the budget is an item alone);
-  // workgroup items also hold at most one 64-partner window per wavefront so
-  // that all of their wavefronts have partners to walk.
+  // the class's budget (a partner longer than the budget is an item alone).
+  // The wavefronts of a workgroup item take its 64-partner windows in turn,
+  // however many there are, so that the owner's table is built once per
+  // budget's worth of elements.
   std::vector<Item> items[kClassesTc];
   std::vector<PieceItem> pieces;
   std::vector<uint32_t> pstart, plen;
@@ -565,8 +566,6 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
     }
     const TcClass& tcl = kTcClass[cls];
     const uint32_t budget = tcl.kind == kWaveTable ? wave_work : block_work;
-    // a workgroup item holds at most one partner per thread
-    const uint32_t max_partners = tcl.kind == kWaveTable ? UINT32_MAX : (uint32_t)tcl.threads;
     if (tcl.kind == kSplitTable) {
       // pieces of kPieceMax in-list entries; a partner streams the part of its
       // list in the piece's id range [lo, hi)
@@ -596,7 +595,7 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
           pieces.push_back(pi);
         };
         for (uint32_t j = p0; j < p1; ++j) {
-          if (acc > 0 && (acc + len[j - p0] > budget || j - start >= max_partners)) {
+          if (acc > 0 && acc + len[j - p0] > budget) {
             flush(start, j);
             start = j;
             acc = 0;
@@ -611,7 +610,7 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
     uint64_t acc = 0;
     for (uint32_t j = p0; j < p1; ++j) {
       const uint64_t len = wcost[j];
-      if (acc > 0 && (acc + len > budget || j - start >= max_partners)) {
+      if (acc > 0 && acc + len > budget) {
         items[cls].push_back({(int32_t)x, start, j, 0});
         start = j;
         acc = 0;
