@@ -109,10 +109,14 @@ __global__ __launch_bounds__(kThreads) void seed_bits(const int32_t* __restrict_
 }
 
 // SEND: frontier bitvector -> queue (vertex, message, first edge, edge prefix).
+// A thread takes one 32-bit word; for a nonzero word it reads the 33
+// offsets around its 32 vertices at once (independent loads, unrolled), so
+// that a dense word costs one memory round trip, not one per set bit.
 __global__ __launch_bounds__(kThreads) void send_kernel(
-    const uint32_t* __restrict__ bits, int64_t words, const uint32_t* __restrict__ prop,
-    const uint32_t* __restrict__ off, int32_t* __restrict__ q, uint32_t* __restrict__ qmsg,
-    uint32_t* __restrict__ qbeg, uint32_t* __restrict__ qest, Ctl* __restrict__ ctl) {
+    const uint32_t* __restrict__ bits, int64_t words, int64_t n,
+    const uint32_t* __restrict__ prop, const uint32_t* __restrict__ off, int32_t* __restrict__ q,
+    uint32_t* __restrict__ qmsg, uint32_t* __restrict__ qbeg, uint32_t* __restrict__ qest,
+    Ctl* __restrict__ ctl) {
   __shared__ uint32_t sh[2 * kWaves];
   __shared__ unsigned long long base_packed;
   uint32_t mn = 0xFFFFFFFFu, mx = 0;
@@ -121,10 +125,14 @@ __global__ __launch_bounds__(kThreads) void send_kernel(
     const int64_t wi = w0 + threadIdx.x;
     const uint32_t word = wi < words ? bits[wi] : 0u;
     const uint32_t cnt = __popc(word);
+    const int64_t v0 = wi * 32;
+    uint32_t o[33];
     uint32_t edges = 0;
-    for (uint32_t b = word; b; b &= b - 1) {
-      const uint32_t v = (uint32_t)(wi * 32) + (__ffs(b) - 1);
-      edges += off[v + 1] - off[v];
+    if (word) {
+#pragma unroll
+      for (int k = 0; k <= 32; ++k) o[k] = off[v0 + k < n ? v0 + k : n];
+#pragma unroll
+      for (int k = 0; k < 32; ++k) edges += (word >> k) & 1u ? o[k + 1] - o[k] : 0u;
     }
     uint32_t ctot, etot;
     const uint32_t cex = block_excl_scan(cnt, sh, &ctot);
@@ -135,20 +143,25 @@ __global__ __launch_bounds__(kThreads) void send_kernel(
     __syncthreads();
     const unsigned long long bp = base_packed;
     __syncthreads();
-    uint32_t slot = (uint32_t)(bp >> 32) + cex;
-    uint32_t est = (uint32_t)bp + eex;
-    for (uint32_t b = word; b; b &= b - 1) {
-      const uint32_t v = (uint32_t)(wi * 32) + (__ffs(b) - 1);
-      const uint32_t msg = prop[v];
-      const uint32_t ob = off[v];
-      q[slot] = (int32_t)v;
-      qmsg[slot] = msg;
-      qbeg[slot] = ob;
-      qest[slot] = est;
-      est += off[v + 1] - ob;
-      ++slot;
-      mn = msg < mn ? msg : mn;
-      mx = msg > mx ? msg : mx;
+    if (word) {
+      uint32_t slot = (uint32_t)(bp >> 32) + cex;
+      uint32_t est = (uint32_t)bp + eex;
+      uint32_t msg[32];
+#pragma unroll
+      for (int k = 0; k < 32; ++k) msg[k] = (word >> k) & 1u ? prop[v0 + k] : 0u;
+#pragma unroll
+      for (int k = 0; k < 32; ++k) {
+        if ((word >> k) & 1u) {
+          q[slot] = (int32_t)(v0 + k);
+          qmsg[slot] = msg[k];
+          qbeg[slot] = o[k];
+          qest[slot] = est;
+          est += o[k + 1] - o[k];
+          ++slot;
+          mn = msg[k] < mn ? msg[k] : mn;
+          mx = msg[k] > mx ? msg[k] : mx;
+        }
+      }
     }
   }
   for (int o = 32; o > 0; o >>= 1) {
@@ -412,7 +425,8 @@ void enqueue_superstep(gm_graph g, Workspace* ws, int kind, Ctl* c, int cur, uin
   const uint32_t pull_div = g->tune.pull_div;
   const unsigned push_blocks = g->tune.push_blocks;
   reset_ctl<<<1, 1, 0, s>>>(c);
-  send_kernel<<<blocks_for(words, 4096), kThreads, 0, s>>>(ws->bits[cur], words, prop, g->out_off,
+  send_kernel<<<blocks_for(words, 4096), kThreads, 0, s>>>(ws->bits[cur], words, g->n, prop,
+                                                           g->out_off,
                                                            ws->q, ws->qmsg, ws->qbeg, ws->qest, c);
   if (kind == GM_PROG_SSSP)
     push_kernel<GM_PROG_SSSP><<<push_blocks, kThreads, 0, s>>>(
