@@ -82,6 +82,7 @@ struct PieceItem {
 struct TcPlan {
   Item* items[kClassesTc] = {};  // per table class
   int64_t nitems[kClassesTc] = {};
+  int32_t* keys = nullptr;         // key of every in-list entry (in_idx order), padded
   uint32_t* work = nullptr;        // partner id | kCreditPartner, grouped by owner
   uint32_t* wlen = nullptr;        // per partner entry: elements streamed
   PieceItem* pieces = nullptr;     // work items of split owners
@@ -99,12 +100,20 @@ struct TcPlan {
   hipEvent_t done[kClassesTc] = {};
 };
 
-// Home bucket of a key in a table of 2^(32 - shift) buckets: the top bits
-// of the key's low 24 bits times an odd constant (multiplicative hashing,
-// with the full-rate 24-bit multiply), which spreads the skewed low bits of
-// RMAT ids over the whole table; the key's top byte is xored in.
-__device__ inline uint32_t home_bucket(int32_t id, uint32_t shift) {
-  return (__umul24((uint32_t)id, 0x9E3779u) ^ ((uint32_t)id & 0xFF000000u)) >> shift;
+// Tables and partner streams hold keys, not ids: key = id times an odd
+// constant mod 2^32 (a bijection, so equal keys mean equal ids), computed
+// once per graph. A key's home bucket in a table of 2^(32 - shift) buckets
+// is its top bits (multiplicative hashing, which spreads the skewed low bits
+// of RMAT ids over the whole table). No id below 2^31 has the key -1, the
+// empty-slot mark.
+constexpr uint32_t kKeyMul = 0x9E3779B1u;
+
+__device__ inline uint32_t home_bucket(int32_t key, uint32_t shift) { return (uint32_t)key >> shift; }
+
+__global__ void make_keys(const int32_t* __restrict__ idx, int64_t m, int32_t* __restrict__ keys) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x)
+    keys[i] = (int32_t)((uint32_t)idx[i] * kKeyMul);
 }
 
 // Shift for a table with bmask + 1 buckets (a power of two, at least 16).
@@ -114,12 +123,12 @@ __device__ inline uint32_t bucket_shift(uint32_t bmask) { return 32u - (uint32_t
 // lives in its home bucket or, when that is full, in the next buckets
 // (linear probing over buckets). At most half of the slots are used, so most
 // lookups read one bucket.
-__device__ inline void table_insert(int32_t* T, uint32_t bmask, int32_t id) {
-  uint32_t b = home_bucket(id, bucket_shift(bmask));
+__device__ inline void table_insert(int32_t* T, uint32_t bmask, int32_t key) {
+  uint32_t b = home_bucket(key, bucket_shift(bmask));
   for (;;) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      if (atomicCAS(&T[4 * b + i], kEmpty, id) == kEmpty) return;
+      if (atomicCAS(&T[4 * b + i], kEmpty, key) == kEmpty) return;
     b = (b + 1) & bmask;
   }
 }
@@ -149,25 +158,25 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x, int lane) {
 }
 
 // Elements per unit of a partner stream: an aligned 32-byte half line of
-// in_idx, loaded whole, so that a line is requested from L2 about twice (a
-// lane that took a line a quad at a time would mostly find it evicted from
-// L1 before its next quad; whole 64-byte lines cost more registers than the
-// saved requests are worth).
+// the key array, loaded whole, so that a line is requested from L2 about
+// twice (a lane that took a line a quad at a time would mostly find it
+// evicted from L1 before its next quad; whole 64-byte lines cost more
+// registers than the saved requests are worth).
 constexpr uint32_t kLine = 8;
 
 struct Line {
   int4 q[kLine / 4];
 };
 
-__device__ __forceinline__ Line load_line(const int32_t* __restrict__ in_idx, uint32_t l) {
-  const int4* p = reinterpret_cast<const int4*>(in_idx + (size_t)kLine * l);
+__device__ __forceinline__ Line load_line(const int32_t* __restrict__ keys, uint32_t l) {
+  const int4* p = reinterpret_cast<const int4*>(keys + (size_t)kLine * l);
   Line L;
 #pragma unroll
   for (int k = 0; k < (int)kLine / 4; ++k) L.q[k] = p[k];
   return L;
 }
 
-// Matches of unit l of in_idx (elements kLine l .. kLine l + kLine - 1,
+// Matches of unit l of the key array (elements kLine l .. kLine l + kLine - 1,
 // those in [s, e) counted) in the table. Every element reads its home
 // bucket; the few whose home bucket is full without holding them go on to
 // the next buckets in a separate pass.
@@ -239,7 +248,7 @@ __device__ __forceinline__ unsigned long long walk_partners(const int4* T4, uint
                                                    uint32_t p_begin, uint32_t p_end,
                                                    uint32_t j_step,
                                                    const uint32_t* __restrict__ in_off,
-                                                   const int32_t* __restrict__ in_idx,
+                                                   const int32_t* __restrict__ keys,
                                                    unsigned long long* counts, Window* W,
                                                    const uint32_t* __restrict__ lens,
                                                    const uint32_t* __restrict__ pstart = nullptr,
@@ -278,7 +287,7 @@ __device__ __forceinline__ unsigned long long walk_partners(const int4* T4, uint
       uint32_t bound = W->excl[o + 1];
       uint32_t l = W->la[o] + (idx - W->excl[o]);
       uint32_t so = W->s[o], eo = W->e[o];
-      Line v = load_line(in_idx, l);
+      Line v = load_line(keys, l);
       while (idx < iend) {
         const Line cv = v;
         const uint32_t cl = l, cs = so, ce = eo;
@@ -295,7 +304,7 @@ __device__ __forceinline__ unsigned long long walk_partners(const int4* T4, uint
             so = W->s[o];
             eo = W->e[o];
           }
-          v = load_line(in_idx, l);
+          v = load_line(keys, l);
         }
         const uint32_t c = probe_line(T4, bmask, hshift, cv, cl, cs, ce);
         if (c) atomicAdd(&W->cnt[co], c);
@@ -328,7 +337,7 @@ __device__ __host__ inline uint32_t table_buckets(uint32_t d) {
 template <uint32_t kSlots>
 __global__ __launch_bounds__(kThreads) void tc_wave(const Item* __restrict__ items, int64_t nitems,
                                                     const uint32_t* __restrict__ in_off,
-                                                    const int32_t* __restrict__ in_idx,
+                                                    const int32_t* __restrict__ keys,
                                                     const uint32_t* __restrict__ work,
                                                     const uint32_t* __restrict__ wlen,
                                                     unsigned long long* counts) {
@@ -346,11 +355,11 @@ __global__ __launch_bounds__(kThreads) void tc_wave(const Item* __restrict__ ite
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
   int32_t* T = reinterpret_cast<int32_t*>(T4);
-  for (uint32_t k = lane; k < d; k += 64) table_insert(T, nb - 1, in_idx[b + k]);
+  for (uint32_t k = lane; k < d; k += 64) table_insert(T, nb - 1, keys[b + k]);
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
   const unsigned long long c = wave_sum_u64(walk_partners(
-      T4, nb - 1, work, it.p_begin, it.p_end, 64, in_off, in_idx, counts, &wins[wave], wlen));
+      T4, nb - 1, work, it.p_begin, it.p_end, 64, in_off, keys, counts, &wins[wave], wlen));
   if (lane == 0 && c) atomicAdd(&counts[x], c);
 }
 
@@ -360,7 +369,7 @@ __global__ __launch_bounds__(kThreads) void tc_wave(const Item* __restrict__ ite
 template <uint32_t kSlots, int kThr>
 __global__ __launch_bounds__(kThr) void tc_block(const Item* __restrict__ items,
                                                  const uint32_t* __restrict__ in_off,
-                                                 const int32_t* __restrict__ in_idx,
+                                                 const int32_t* __restrict__ keys,
                                                  const uint32_t* __restrict__ work,
                                                  const uint32_t* __restrict__ wlen,
                                                  unsigned long long* counts) {
@@ -378,10 +387,10 @@ __global__ __launch_bounds__(kThr) void tc_block(const Item* __restrict__ items,
     ltable[k] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
   __syncthreads();
   int32_t* T = reinterpret_cast<int32_t*>(ltable);
-  for (uint32_t k = threadIdx.x; k < d; k += kThr) table_insert(T, bmask, in_idx[b + k]);
+  for (uint32_t k = threadIdx.x; k < d; k += kThr) table_insert(T, bmask, keys[b + k]);
   __syncthreads();
   const unsigned long long c = wave_sum_u64(walk_partners(
-      ltable, bmask, work, it.p_begin + wave * 64, it.p_end, kThr, in_off, in_idx, counts,
+      ltable, bmask, work, it.p_begin + wave * 64, it.p_end, kThr, in_off, keys, counts,
       &wins[wave], wlen));
   if (lane == 0) part[wave] = c;
   __syncthreads();
@@ -396,7 +405,7 @@ __global__ __launch_bounds__(kThr) void tc_block(const Item* __restrict__ items,
 template <uint32_t kSlots, int kThr>
 __global__ __launch_bounds__(kThr) void tc_piece(const PieceItem* __restrict__ items,
                                                  const uint32_t* __restrict__ in_off,
-                                                 const int32_t* __restrict__ in_idx,
+                                                 const int32_t* __restrict__ keys,
                                                  const uint32_t* __restrict__ work,
                                                  const uint32_t* __restrict__ pstart,
                                                  const uint32_t* __restrict__ plen,
@@ -414,10 +423,10 @@ __global__ __launch_bounds__(kThr) void tc_piece(const PieceItem* __restrict__ i
     ltable[k] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
   __syncthreads();
   int32_t* T = reinterpret_cast<int32_t*>(ltable);
-  for (uint32_t k = threadIdx.x; k < d; k += kThr) table_insert(T, bmask, in_idx[it.tb + k]);
+  for (uint32_t k = threadIdx.x; k < d; k += kThr) table_insert(T, bmask, keys[it.tb + k]);
   __syncthreads();
   const unsigned long long c = wave_sum_u64(walk_partners(
-      ltable, bmask, work, it.p_begin + wave * 64, it.p_end, kThr, in_off, in_idx, counts,
+      ltable, bmask, work, it.p_begin + wave * 64, it.p_end, kThr, in_off, keys, counts,
       &wins[wave], plen, pstart, (int64_t)it.sbase - (int64_t)it.p_begin));
   if (lane == 0) part[wave] = c;
   __syncthreads();
@@ -457,6 +466,7 @@ void free_tc_plan(gm_graph g) {
   TcPlan* p = plan(g);
   if (!p) return;
   for (int c = 0; c < kClassesTc; ++c) dfree(p->items[c]);
+  dfree(p->keys);
   dfree(p->work);
   dfree(p->pieces);
   dfree(p->pstart);
@@ -637,6 +647,13 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
         GM_HIP(hipMemcpyAsync(p->items[c], items[c].data(), items[c].size() * sizeof(Item),
                               hipMemcpyHostToDevice, s));
     }
+    p->keys = dalloc<int32_t>(m + kIdxPad);
+    if (m > 0) {
+      int64_t kb = (m + kThreads - 1) / kThreads;
+      if (kb > 65536) kb = 65536;
+      make_keys<<<(unsigned)kb, kThreads, 0, s>>>(g->in_idx, m, p->keys);
+      GM_HIP(hipGetLastError());
+    }
     p->work = dalloc<uint32_t>(work.size());
     if (!work.empty())
       GM_HIP(hipMemcpyAsync(p->work, work.data(), work.size() * 4, hipMemcpyHostToDevice, s));
@@ -694,13 +711,13 @@ void run_triangle_count(gm_graph g, unsigned long long* counts, unsigned long lo
   };
   if (p->npieces > 0) {
     tc_piece<32768, 1024><<<(unsigned)p->npieces, 1024, 0, on(6)>>>(
-        p->pieces, g->in_off, g->in_idx, p->work, p->pstart, p->plen, counts);
+        p->pieces, g->in_off, p->keys, p->work, p->pstart, p->plen, counts);
     join(6);
   }
   const auto block = [&](int c, auto kern) {
     if (p->nitems[c] > 0) {
       kern<<<(unsigned)p->nitems[c], kTcClass[c].threads, 0, on(c)>>>(
-          p->items[c], g->in_off, g->in_idx, p->work, p->wlen, counts);
+          p->items[c], g->in_off, p->keys, p->work, p->wlen, counts);
       join(c);
     }
   };
@@ -712,7 +729,7 @@ void run_triangle_count(gm_graph g, unsigned long long* counts, unsigned long lo
     if (p->nitems[c] > 0) {
       const int64_t blocks = (p->nitems[c] + kWaves - 1) / kWaves;
       kern<<<(unsigned)blocks, kThreads, 0, on(c)>>>(p->items[c], p->nitems[c], g->in_off,
-                                                     g->in_idx, p->work, p->wlen, counts);
+                                                     p->keys, p->work, p->wlen, counts);
       join(c);
     }
   };
