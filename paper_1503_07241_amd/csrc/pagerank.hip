@@ -30,26 +30,17 @@
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "gm_internal.h"
+#include "tiles.h"
 
 namespace gm {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kPullThreads = 1024;  // one workgroup per CU: its LDS holds the hot messages
-constexpr int kPullWaves = kPullThreads / 64;
-constexpr int kRounds = 4;                  // rounds of 256 edges per tile
-constexpr int64_t kTile = kRounds * 256;    // edges per tile: 4 consecutive per lane and round
-constexpr int kHotMax = 40960;  // at most this many hot messages in LDS (160 KB)
-constexpr int kCrossLanes = 16;  // lanes per row that spans tiles
+using namespace tiles;
 
-// A row of the relabelled in-adjacency whose edges lie in more than one
-// tile: tiles ta (where it starts) to tb (where it ends).
-struct Cross {
-  uint32_t row;
-  uint32_t ta;
-  uint32_t tb;
-  uint32_t pad;
-};
+constexpr int kThreads = 256;
+constexpr int kPullThreads = kTileThreads;
+constexpr int kPullWaves = kTileWaves;
+constexpr int kHotMax = kTileHotMax;  // at most this many hot messages in LDS (160 KB)
 
 struct Dense {
   int64_t n = 0, m = 0;
@@ -73,9 +64,6 @@ struct Dense {
   int lds_max = 0;              // bytes of LDS a workgroup may use
 };
 
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-
 // APPLY: PR_v from the sum y of its in-messages.
 template <bool kPersonal>
 __device__ inline float pr_value(uint32_t v, double y, float r, int32_t seed) {
@@ -92,80 +80,6 @@ __device__ inline void apply_row(uint32_t v, double y, float r, int32_t seed,
   const float pr = pr_value<kPersonal>(v, y, r, seed);
   x_out[v] = pr * inv_outdeg[v];
   if (pr_out) pr_out[v] = pr;
-}
-
-// Copy of the first hot_n messages to LDS: all of a thread's 16-byte loads
-// are issued before the first store.
-__device__ inline void load_hot(const float* __restrict__ x_in, float* hot, int hot_n) {
-  constexpr int kPer = kHotMax / 4 / kPullThreads;
-  const int n4 = hot_n >> 2;
-  v4f tmp[kPer];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int i = threadIdx.x + k * kPullThreads;
-    if (i < n4) tmp[k] = reinterpret_cast<const v4f*>(x_in)[i];
-  }
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int i = threadIdx.x + k * kPullThreads;
-    if (i < n4) reinterpret_cast<v4f*>(hot)[i] = tmp[k];
-  }
-  for (int i = 4 * n4 + threadIdx.x; i < hot_n; i += kPullThreads) hot[i] = x_in[i];
-  __syncthreads();
-}
-
-// Segmented-sum state of a run of edges: c = number of row starts in it, s =
-// sum of the messages after the last of them (of all, if c = 0). Combining
-// an earlier run a with a later run b is associative, which makes the
-// segmented sum a scan.
-struct Seg {
-  int c;
-  double s;
-};
-
-__device__ inline Seg seg_join(Seg a, Seg b) { return {a.c + b.c, b.c > 0 ? b.s : a.s + b.s}; }
-
-// Data-parallel move of a Seg between lanes (DPP control kCtrl); a lane
-// whose source is outside its row of 16 lanes keeps `old`.
-template <int kCtrl>
-__device__ inline Seg seg_dpp(Seg old, Seg v) {
-  const unsigned long long ob = (unsigned long long)__double_as_longlong(old.s);
-  const unsigned long long vb = (unsigned long long)__double_as_longlong(v.s);
-  const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)ob, (int)(uint32_t)vb, kCtrl, 0xF, 0xF,
-                                             false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(ob >> 32), (int)(uint32_t)(vb >> 32),
-                                             kCtrl, 0xF, 0xF, false);
-  const int c = __builtin_amdgcn_update_dpp(old.c, v.c, kCtrl, 0xF, 0xF, false);
-  return {c, __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) |
-                                              (uint32_t)lo))};
-}
-
-__device__ inline Seg seg_lane(Seg v, int lane) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v.s);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
-  return {__builtin_amdgcn_readlane(v.c, lane),
-          __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo))};
-}
-
-// Wavefront scan of one round: from each lane's own run `own` and the run
-// `carry` of everything before the round, the lane's exclusive prefix (all
-// earlier lanes, carry included); `carry` moves on to the end of the round.
-__device__ inline Seg seg_scan(Seg own, Seg& carry, int lane) {
-  constexpr Seg id{0, 0.0};
-  Seg x = own;  // inclusive scan within each row of 16 lanes (row_shr 1, 2, 4, 8)
-  x = seg_join(seg_dpp<0x111>(id, x), x);
-  x = seg_join(seg_dpp<0x112>(id, x), x);
-  x = seg_join(seg_dpp<0x114>(id, x), x);
-  x = seg_join(seg_dpp<0x118>(id, x), x);
-  const Seg p1 = seg_join(carry, seg_lane(x, 15));
-  const Seg p2 = seg_join(p1, seg_lane(x, 31));
-  const Seg p3 = seg_join(p2, seg_lane(x, 47));
-  const int row = lane >> 4;
-  const Seg before = row == 0 ? carry : row == 1 ? p1 : row == 2 ? p2 : p3;
-  const Seg incl = seg_join(before, x);
-  carry = seg_lane(incl, 63);
-  return seg_dpp<0x111>(before, incl);  // the row's first lane takes `before`
 }
 
 // One superstep: y = A^T x (pull over in-edges), APPLY, next SEND.
@@ -470,29 +384,16 @@ void ensure_pull_schedule(gm_graph g, hipStream_t st) {
   try {
     d->n = n;
     d->m = m;
-    // Rows with in-edges come first (decreasing in-degree).
-    int64_t rows = 0;
-    while (rows < n && noff[rows + 1] > noff[rows]) ++rows;
-    d->rows = rows;
-    // Tiles of kTile edges; the index stream is padded to whole tiles.
-    const int64_t ntiles = (m + kTile - 1) / kTile;
-    const int64_t mpad = ntiles * kTile;
-    d->ntiles = ntiles;
-    std::vector<uint32_t> starts((size_t)(mpad / 32 + 1), 0u);
-    for (int64_t v = 0; v < rows; ++v) starts[noff[v] >> 5] |= 1u << (noff[v] & 31);
-    starts[(size_t)(m >> 5)] |= 1u << (m & 31);
-    std::vector<uint32_t> tile_row((size_t)ntiles);
-    std::vector<Cross> cross;
-    int64_t v = 0;
-    for (int64_t t = 0; t < ntiles; ++t) {
-      while (noff[v + 1] <= (uint64_t)(t * kTile)) ++v;
-      tile_row[(size_t)t] = (uint32_t)v;
-    }
-    for (int64_t u = 0; u < rows; ++u) {
-      const uint32_t ta = (uint32_t)(noff[u] / kTile), tb = (uint32_t)((noff[u + 1] - 1) / kTile);
-      if (ta != tb) cross.push_back({(uint32_t)u, ta, tb, 0});
-    }
-    d->ncross = (int64_t)cross.size();
+    // Rows with in-edges come first (decreasing in-degree); tiles of kTile
+    // edges, the index stream padded to whole tiles.
+    const TileLayout L = tile_layout(noff, n, m);
+    d->rows = L.rows;
+    d->ntiles = L.ntiles;
+    d->ncross = (int64_t)L.cross.size();
+    const int64_t ntiles = L.ntiles, mpad = L.mpad;
+    const std::vector<uint32_t>& starts = L.starts;
+    const std::vector<uint32_t>& tile_row = L.tile_row;
+    const std::vector<Cross>& cross = L.cross;
     int dev = 0;
     GM_HIP(hipGetDevice(&dev));
     GM_HIP(hipDeviceGetAttribute(&d->cus, hipDeviceAttributeMultiprocessorCount, dev));

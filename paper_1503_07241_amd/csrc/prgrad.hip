@@ -8,188 +8,234 @@
 //   abar^t(u) = (1 - r) / deg(u) * sum_{v: u -> v} w_uv abar^{t+1}(v)
 // The second line is a pull over out-edges (rows of the CSR = columns of
 // G^T), i.e. the product with the transposed matrix. Both lines are one
-// kernel per step, one pass over the CSR in canonical edge order, so the
-// gradient lands in the caller's edge order with one read-modify-write per
-// edge and step.
+// kernel per step, one pass over the out-edges.
 //
-// Rows are scheduled like the forward pull: sorted by out-degree into
-// classes with a power-of-two number of lanes per row (at most eight edges
-// per lane, loads unconditional), rows longer than kChunk split into chunks
-// whose partial sums a second kernel adds in chunk order. Sums in double.
+// Layout (built once per graph): vertices relabelled by decreasing
+// out-degree (rows with out-edges are then [0, rows); RMAT's high
+// out-degree vertices are also the most gathered destinations), the
+// out-adjacency rebuilt in the new labels with each edge's caller (CSR) id,
+// cut into equal edge tiles reduced by a segmented scan like PageRank's pull
+// superstep. Per call the edge values are gathered into the relabelled
+// order once, the gradient is accumulated there (a coalesced read-modify-
+// write per edge and step) and scattered back to the caller's order at the
+// end. Sums in double, in a fixed order.
 #include <algorithm>
 #include <vector>
 
 #include "gm_internal.h"
+#include "tiles.h"
 
 namespace gm {
 namespace {
 
+using namespace tiles;
+
 constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / 64;
-constexpr int kUnroll = 8;
-constexpr uint32_t kChunk = kThreads * kUnroll;
-constexpr int kClasses = 13;
-constexpr uint32_t kClassMax[kClasses] = {0, 1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048};
-constexpr int kClassLanes[kClasses] = {1, 1, 1, 1, 1, 2, 4, 8, 16, 32, 64, 256, 256};
-constexpr int kClassUnroll[kClasses] = {1, 1, 2, 4, 8, 8, 8, 8, 8, 8, 8, 4, 8};
-
-struct Chunk {
-  uint32_t row;
-  uint32_t edge_begin;
-  uint32_t edge_end;
-  uint32_t pad;
-};
-
-struct Split {
-  uint32_t row;
-  uint32_t first;
-  uint32_t count;
-  uint32_t pad;
-};
-
-struct Bins {
-  int64_t nchunks;
-  int64_t class_begin[kClasses];   // first position in the sorted row list
-  int64_t class_rows[kClasses];
-  int64_t class_block0[kClasses];  // decreases with c
-};
 
 struct VjpPlan {
-  int32_t* rows = nullptr;  // rows by decreasing out-degree
-  Chunk* chunks = nullptr;
-  Split* splits = nullptr;
-  int64_t nsplit = 0;
-  double* partial = nullptr;
+  int64_t n = 0, m = 0, rows = 0, ntiles = 0, ncross = 0, mpad = 0;
+  int32_t* old_of = nullptr;    // new label -> caller's label
+  int32_t* idx = nullptr;       // relabelled out-adjacency (new labels), padded with 0
+  uint32_t* ceid = nullptr;     // caller's (CSR) id of each relabelled edge
+  float* inv_outdeg = nullptr;  // new labels
+  uint32_t* starts = nullptr;   // row-start bitmap of the relabelled edges
+  uint32_t* tile_row = nullptr;
+  Cross* cross = nullptr;
+  double* head = nullptr;
+  double* tail = nullptr;
+  float* wv = nullptr;          // edge values in the relabelled order, padded with 0
+  float* gv = nullptr;          // gradient in the relabelled order, padded
+  float* cu = nullptr;          // per row: (1 - r) PR^t(u) / deg(u); n + 1 entries, 0 past rows
   float* abar[2] = {nullptr, nullptr};
-  int64_t nblocks = 0;
-  Bins bins{};
+  int cus = 0, lds_max = 0;
 };
 
-__device__ inline double group_sum(double v, int width) {
-  for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Edges [b, e) of row u with `lanes` lanes (this lane starts at b + sub):
-// gradient update and the sum of w * abar_next. Loads unconditional.
-template <int kU>
-__device__ inline double row_step(const int32_t* __restrict__ idx, const float* __restrict__ w,
-                                  const float* __restrict__ abar_next, float cu,
-                                  float* __restrict__ grad_w, uint32_t b, uint32_t e, int sub,
-                                  int lanes) {
-  double acc = 0.0;
-  for (uint32_t k0 = b + sub; k0 < e; k0 += kU * lanes) {
-    uint32_t k[kU];
+// One reverse step over the tiles: gradient of every edge and the row sums
+// sum_v w_uv abar_next(v), APPLY abar_cur(u) = (1 - r) / deg(u) * sum. The
+// row of every edge comes from a count scan of the row-start bitmap before
+// the gathers, so that each edge's cu(row) is loaded with its message.
+__global__ __launch_bounds__(kTileThreads) void vjp_tile(
+    const int32_t* __restrict__ idx, const float* __restrict__ wv,
+    const uint32_t* __restrict__ starts, const uint32_t* __restrict__ tile_row, int64_t ntiles,
+    const float* __restrict__ abar_next, const float* __restrict__ cu,
+    const float* __restrict__ inv_outdeg, float one_r, float* __restrict__ abar_cur,
+    float* __restrict__ gv, double* __restrict__ head, double* __restrict__ tail, int hot_n) {
+  extern __shared__ float hot[];  // hot_n floats
+  load_hot(abar_next, hot, hot_n);
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * kTileWaves;
+  const int sh = (lane & 7) * 4;  // this lane's 4 bits in its word of `starts`
+  const char* ab = reinterpret_cast<const char*>(abar_next);
+  const char* cb = reinterpret_cast<const char*>(cu);
+  int64_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * kTileWaves + (threadIdx.x >> 6));
+  for (; t < ntiles; t += stride) {
+    const int64_t e0 = t * kTile + lane * 4;
+    v4i src[kRounds];
+    v4f w[kRounds];
+    uint32_t nib[kRounds], next[kRounds];
 #pragma unroll
-    for (int q = 0; q < kU; ++q) {
-      const uint32_t kk = k0 + q * lanes;
-      k[q] = kk < e ? kk : e - 1;
+    for (int v = 0; v < kRounds; ++v) {
+      const int64_t ev = e0 + v * 256;
+      src[v] = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(idx + ev));
+      w[v] = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(wv + ev));
+      const uint32_t fa = starts[ev >> 5], fb = starts[(ev >> 5) + 1];
+      nib[v] = (fa >> sh) & 0xFu;  // bit q: edge q of the lane starts a row
+      next[v] = sh == 28 ? (fb & 1u) : (fa >> (sh + 4)) & 1u;
     }
-    int32_t v[kU];
-    float wv[kU], g[kU];
+    const uint32_t row0 = tile_row[t];
+    // A start at the tile's first edge opens row0 itself, not the next row.
+    const int f0 = __builtin_amdgcn_readfirstlane((int)(nib[0] & 1u));
+    // Row of edge (v, q): row0 + starts before it in the tile (exc[v] from
+    // the lanes before, then the lane's own) - f0.
+    uint32_t exc[kRounds];
+    int ccarry = 0;
 #pragma unroll
-    for (int q = 0; q < kU; ++q) {
-      v[q] = idx[k[q]];
-      wv[q] = w[k[q]];
-      g[q] = grad_w[k[q]];
+    for (int v = 0; v < kRounds; ++v)
+      exc[v] = row0 + (uint32_t)(count_scan((int)__popc(nib[v]), ccarry, lane) - f0);
+    const auto row_of = [&](int v, int q) {
+      return exc[v] + (uint32_t)__popc(nib[v] & ((2u << q) - 1u));
+    };
+    float a[kRounds][4], cv[kRounds][4];
+    v4f g[kRounds];
+#pragma unroll
+    for (int v = 0; v < kRounds; ++v) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t s = (uint32_t)src[v][q];
+        const bool in_lds = s < (uint32_t)hot_n;
+        const float gl = *reinterpret_cast<const float*>(ab + (in_lds ? 0u : s << 2));
+        const float l = hot[in_lds ? s : 0u];
+        a[v][q] = in_lds ? l : gl;
+        cv[v][q] = *reinterpret_cast<const float*>(cb + (row_of(v, q) << 2));
+      }
+      g[v] = *reinterpret_cast<const v4f*>(gv + e0 + v * 256);
     }
-    float a[kU];
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int q = 0; q < kU; ++q) a[q] = abar_next[v[q]];
+    for (int v = 0; v < kRounds; ++v) {
 #pragma unroll
-    for (int q = 0; q < kU; ++q) {
-      if (k0 + q * lanes < e) {
-        acc += (double)wv[q] * (double)a[q];
-        grad_w[k[q]] = g[q] + cu * a[q];
+      for (int q = 0; q < 4; ++q) g[v][q] = g[v][q] + cv[v][q] * a[v][q];
+      *reinterpret_cast<v4f*>(gv + e0 + v * 256) = g[v];
+    }
+    Seg carry{0, 0.0};
+    float yv[kRounds][4];  // row sums ending here (rounded once more when applied)
+    uint32_t done = 0;  // bit 4v+q: edge (v, q) ends a row begun in the tile
+#pragma unroll
+    for (int v = 0; v < kRounds; ++v) {
+      double s[4];
+      s[0] = (double)w[v][0] * (double)a[v][0];
+#pragma unroll
+      for (int q = 1; q < 4; ++q)
+        s[q] = ((nib[v] >> q) & 1u ? 0.0 : s[q - 1]) + (double)w[v][q] * (double)a[v][q];
+      const Seg ex = seg_scan(Seg{(int)__popc(nib[v]), s[3]}, carry, lane);
+      const uint32_t ends = (nib[v] >> 1) | (next[v] << 3);  // bit q: edge q ends its row
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        yv[v][q] = 0.0f;
+        if ((ends >> q) & 1u) {
+          const int lc = (int)__popc(nib[v] & ((2u << q) - 1u));  // starts at or before edge q
+          const double y = lc > 0 ? s[q] : ex.s + s[q];
+          if (ex.c + lc > 0) {
+            yv[v][q] = (float)y;
+            done |= 1u << (4 * v + q);
+          } else {
+            head[t] = y;
+          }
+        }
+      }
+      if (v == kRounds - 1 && lane == 63 && !(ends >> 3)) {
+        const double y = nib[v] ? s[3] : ex.s + s[3];
+        if (ex.c + (int)__popc(nib[v]) > 0)
+          tail[t] = y;
+        else
+          head[t] = y;
       }
     }
-  }
-  return acc;
-}
-
-template <int kU>
-__device__ inline double row_step_u(int unroll, const int32_t* idx, const float* w,
-                                    const float* abar_next, float cu, float* grad_w, uint32_t b,
-                                    uint32_t e, int sub, int lanes) {
-  switch (unroll) {
-    case 1:
-      return row_step<1>(idx, w, abar_next, cu, grad_w, b, e, sub, lanes);
-    case 2:
-      return row_step<2>(idx, w, abar_next, cu, grad_w, b, e, sub, lanes);
-    case 4:
-      return row_step<4>(idx, w, abar_next, cu, grad_w, b, e, sub, lanes);
-    default:
-      return row_step<8>(idx, w, abar_next, cu, grad_w, b, e, sub, lanes);
+    float inv[kRounds][4];
+#pragma unroll
+    for (int v = 0; v < kRounds; ++v)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        inv[v][q] = 0.0f;
+        if ((done >> (4 * v + q)) & 1u) inv[v][q] = inv_outdeg[row_of(v, q)];
+      }
+#pragma unroll
+    for (int v = 0; v < kRounds; ++v)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if ((done >> (4 * v + q)) & 1u)
+          abar_cur[row_of(v, q)] = (float)((double)one_r * (double)inv[v][q] * yv[v][q]);
   }
 }
 
-__global__ __launch_bounds__(kThreads) void vjp_step(
-    const int32_t* __restrict__ rows, const uint32_t* __restrict__ off,
-    const int32_t* __restrict__ idx, const float* __restrict__ w, const float* __restrict__ pr_t,
-    const float* __restrict__ inv_outdeg, float r, const float* __restrict__ abar_next,
-    float* __restrict__ abar_cur, float* __restrict__ grad_w, const Chunk* __restrict__ chunks,
-    double* __restrict__ partial, Bins bins) {
-  __shared__ double wsum[kWaves];
-  const int64_t blk = blockIdx.x;
-  const int tid = threadIdx.x;
-  const float one_r = 1.0f - r;
-  if (blk < bins.nchunks) {
-    const Chunk c = chunks[blk];
-    const float cu = one_r * pr_t[c.row] * inv_outdeg[c.row];
-    double acc = row_step<kUnroll>(idx, w, abar_next, cu, grad_w, c.edge_begin, c.edge_end, tid,
-                                   kThreads);
-    acc = group_sum(acc, 64);
-    if ((tid & 63) == 0) wsum[tid >> 6] = acc;
-    __syncthreads();
-    if (tid == 0) partial[blk] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
-    return;
-  }
-  int cls = 0;
-  while (blk < bins.class_block0[cls]) ++cls;
-  const int lanes = kClassLanes[cls];
-  if (lanes == kThreads) {
-    const uint32_t u = (uint32_t)rows[bins.class_begin[cls] + (blk - bins.class_block0[cls])];
-    const float cu = one_r * pr_t[u] * inv_outdeg[u];
-    double acc = row_step_u<kUnroll>(kClassUnroll[cls], idx, w, abar_next, cu, grad_w, off[u],
-                                     off[u + 1], tid, kThreads);
-    acc = group_sum(acc, 64);
-    if ((tid & 63) == 0) wsum[tid >> 6] = acc;
-    __syncthreads();
-    if (tid == 0)
-      abar_cur[u] = (float)((double)one_r * (double)inv_outdeg[u] *
-                            ((wsum[0] + wsum[1]) + (wsum[2] + wsum[3])));
-    return;
-  }
-  const int64_t local = (blk - bins.class_block0[cls]) * (kThreads / lanes) + tid / lanes;
-  const bool valid = local < bins.class_rows[cls];
-  const uint32_t u = valid ? (uint32_t)rows[bins.class_begin[cls] + local] : 0u;
-  const int sub = tid % lanes;
+// Rows spanning tiles ta..tb: tail[ta] + head[ta + 1] + ... + head[tb],
+// summed by kCrossLanes lanes in a fixed order, then APPLY.
+__global__ void vjp_cross(const Cross* __restrict__ cross, int64_t ncross,
+                          const double* __restrict__ head, const double* __restrict__ tail,
+                          const float* __restrict__ inv_outdeg, float one_r,
+                          float* __restrict__ abar_cur) {
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = gid / kCrossLanes;
+  const int j = (int)(gid % kCrossLanes);
   double acc = 0.0;
-  if (valid && cls > 0) {
-    const float cu = one_r * pr_t[u] * inv_outdeg[u];
-    acc = row_step_u<kUnroll>(kClassUnroll[cls], idx, w, abar_next, cu, grad_w, off[u], off[u + 1],
-                              sub, lanes);
+  Cross c{0, 0, 0, 0};
+  if (i < ncross) {
+    c = cross[i];
+    if (j == 0) acc = tail[c.ta];
+    for (uint32_t t = c.ta + 1 + j; t <= c.tb; t += kCrossLanes) acc += head[t];
   }
-  acc = group_sum(acc, lanes);
-  if (valid && sub == 0) abar_cur[u] = (float)((double)one_r * (double)inv_outdeg[u] * acc);
+  for (int o = kCrossLanes >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (i < ncross && j == 0)
+    abar_cur[c.row] = (float)((double)one_r * (double)inv_outdeg[c.row] * acc);
 }
 
-__global__ void vjp_finish(const Split* __restrict__ splits, int64_t nsplit,
-                           const double* __restrict__ partial, const float* __restrict__ inv_outdeg,
-                           float r, float* __restrict__ abar_cur) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nsplit;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const Split sp = splits[i];
-    double acc = 0.0;
-    for (uint32_t c = 0; c < sp.count; ++c) acc += partial[sp.first + c];
-    abar_cur[sp.row] = (float)((1.0 - (double)r) * (double)inv_outdeg[sp.row] * acc);
-  }
-}
-
-__global__ void copy_f32(const float* __restrict__ a, int64_t n, float* __restrict__ b) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+// cu(u) = (1 - r) PR^t(u) / deg(u) for the rows with out-edges.
+__global__ void vjp_cu(const float* __restrict__ pr_t, const int32_t* __restrict__ old_of,
+                       const float* __restrict__ inv_outdeg, int64_t rows, float one_r,
+                       float* __restrict__ cu) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
        i += (int64_t)gridDim.x * blockDim.x)
-    b[i] = a[i];
+    cu[i] = one_r * pr_t[old_of[i]] * inv_outdeg[i];
+}
+
+// out[i] = in[index[i]] (into the relabelled order).
+__global__ void gather_f32(const float* __restrict__ in, const int32_t* __restrict__ index,
+                           int64_t count, float* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = in[index[i]];
+}
+
+// out[index[i]] = in[i] (back to the caller's edge order).
+__global__ void scatter_f32(const float* __restrict__ in, const uint32_t* __restrict__ index,
+                            int64_t count, float* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[index[i]] = in[i];
+}
+
+__global__ void gather_w(const float* __restrict__ w, const uint32_t* __restrict__ ceid,
+                         int64_t m, float* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = w[ceid[i]];
+}
+
+// Relabelled out-edges of new row i (caller's row old_of[i]): destinations
+// in new labels, caller's edge ids.
+__global__ void build_edges(const uint32_t* __restrict__ off, const int32_t* __restrict__ out_idx,
+                            const int32_t* __restrict__ old_of, const int32_t* __restrict__ new_of,
+                            const uint32_t* __restrict__ noff, int64_t rows,
+                            int32_t* __restrict__ idx, uint32_t* __restrict__ ceid) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t b = off[old_of[i]];
+    const uint32_t k0 = noff[i], d = noff[i + 1] - k0;
+    for (uint32_t j = 0; j < d; ++j) {
+      idx[k0 + j] = new_of[out_idx[b + j]];
+      ceid[k0 + j] = b + j;
+    }
+  }
 }
 
 inline unsigned blocks_for(int64_t n) {
@@ -199,14 +245,23 @@ inline unsigned blocks_for(int64_t n) {
   return (unsigned)b;
 }
 
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  explicit DevBuf(size_t n) : p(dalloc<T>(n)) {}
+  ~DevBuf() { dfree(p); }
+};
+
 VjpPlan* plan(gm_graph g) { return static_cast<VjpPlan*>(g->vjp_plan); }
 
 VjpPlan* ensure_plan(gm_graph g, hipStream_t st) {
   if (plan(g)) return plan(g);
-  const int64_t n = g->n;
+  const int64_t n = g->n, m = g->m;
+  if (n >= (int64_t)1 << 30) throw Unsupported{"PageRank reverse pass takes fewer than 2^30 vertices"};
   std::vector<uint32_t> off(n + 1);
   GM_HIP(hipMemcpyAsync(off.data(), g->out_off, (n + 1) * 4, hipMemcpyDeviceToHost, st));
   GM_HIP(hipStreamSynchronize(st));
+  // Counting sort of the vertices by decreasing out-degree (ties by label).
   const uint32_t maxd = (uint32_t)g->max_out;
   std::vector<int64_t> cnt((size_t)maxd + 2, 0);
   for (int64_t v = 0; v < n; ++v) ++cnt[maxd - (off[v + 1] - off[v])];
@@ -216,54 +271,67 @@ VjpPlan* ensure_plan(gm_graph g, hipStream_t st) {
     c = acc;
     acc += t;
   }
-  std::vector<int32_t> rows(n);
-  for (int64_t v = 0; v < n; ++v) rows[cnt[maxd - (off[v + 1] - off[v])]++] = (int32_t)v;
-  auto deg = [&](int64_t i) { return off[rows[i] + 1] - off[rows[i]]; };
+  std::vector<int32_t> old_of(n), new_of(n);
+  for (int64_t v = 0; v < n; ++v) {
+    const int64_t pos = cnt[maxd - (off[v + 1] - off[v])]++;
+    old_of[pos] = (int32_t)v;
+    new_of[v] = (int32_t)pos;
+  }
+  std::vector<uint32_t> noff(n + 1);
+  noff[0] = 0;
+  for (int64_t i = 0; i < n; ++i) noff[i + 1] = noff[i] + (off[old_of[i] + 1] - off[old_of[i]]);
+  const TileLayout L = tile_layout(noff, n, m);
   VjpPlan* p = new VjpPlan();
   g->vjp_plan = p;
   try {
-    std::vector<Chunk> chunks;
-    std::vector<Split> splits;
-    int64_t i = 0;
-    while (i < n && deg(i) > kChunk) {
-      const uint32_t u = (uint32_t)rows[i];
-      const uint32_t nch = (deg(i) + kChunk - 1) / kChunk;
-      splits.push_back({u, (uint32_t)chunks.size(), nch, 0});
-      for (uint32_t c = 0; c < nch; ++c) {
-        const uint32_t eb = off[u] + c * kChunk;
-        chunks.push_back({u, eb, std::min(eb + kChunk, off[u + 1]), 0});
-      }
-      ++i;
-    }
-    p->bins.nchunks = (int64_t)chunks.size();
-    p->nsplit = (int64_t)splits.size();
-    int64_t block = p->bins.nchunks;
-    for (int c = kClasses - 1; c >= 0; --c) {
-      const int64_t r0 = i;
-      if (c == 0)
-        i = n;
-      else
-        while (i < n && deg(i) > kClassMax[c - 1]) ++i;
-      p->bins.class_begin[c] = r0;
-      p->bins.class_rows[c] = i - r0;
-      p->bins.class_block0[c] = block;
-      const int64_t rpb = kThreads / kClassLanes[c];
-      block += (p->bins.class_rows[c] + rpb - 1) / rpb;
-    }
-    p->nblocks = block;
-    p->rows = dalloc<int32_t>(n);
-    p->chunks = dalloc<Chunk>(chunks.size());
-    p->splits = dalloc<Split>(splits.size());
-    p->partial = dalloc<double>(chunks.size());
+    p->n = n;
+    p->m = m;
+    p->rows = L.rows;
+    p->ntiles = L.ntiles;
+    p->ncross = (int64_t)L.cross.size();
+    p->mpad = L.mpad;
+    int dev = 0;
+    GM_HIP(hipGetDevice(&dev));
+    GM_HIP(hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, dev));
+    GM_HIP(hipDeviceGetAttribute(&p->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    p->old_of = dalloc<int32_t>(n);
+    p->idx = dalloc<int32_t>(L.mpad);
+    p->ceid = dalloc<uint32_t>(m);
+    p->inv_outdeg = dalloc<float>(n);
+    p->starts = dalloc<uint32_t>(L.starts.size());
+    p->tile_row = dalloc<uint32_t>(L.tile_row.size());
+    p->cross = dalloc<Cross>(L.cross.size());
+    p->head = dalloc<double>(L.ntiles);
+    p->tail = dalloc<double>(L.ntiles);
+    p->wv = dalloc<float>(L.mpad);
+    p->gv = dalloc<float>(L.mpad);
+    p->cu = dalloc<float>(n + 1);
     p->abar[0] = dalloc<float>(n);
     p->abar[1] = dalloc<float>(n);
-    GM_HIP(hipMemcpyAsync(p->rows, rows.data(), n * 4, hipMemcpyHostToDevice, st));
-    if (!chunks.empty())
-      GM_HIP(hipMemcpyAsync(p->chunks, chunks.data(), chunks.size() * sizeof(Chunk),
+    DevBuf<int32_t> dnew(n);
+    DevBuf<uint32_t> dnoff(n + 1);
+    GM_HIP(hipMemcpyAsync(p->old_of, old_of.data(), n * 4, hipMemcpyHostToDevice, st));
+    GM_HIP(hipMemcpyAsync(dnew.p, new_of.data(), n * 4, hipMemcpyHostToDevice, st));
+    GM_HIP(hipMemcpyAsync(dnoff.p, noff.data(), (n + 1) * 4, hipMemcpyHostToDevice, st));
+    GM_HIP(hipMemcpyAsync(p->starts, L.starts.data(), L.starts.size() * 4, hipMemcpyHostToDevice,
+                          st));
+    if (L.ntiles > 0)
+      GM_HIP(hipMemcpyAsync(p->tile_row, L.tile_row.data(), L.tile_row.size() * 4,
                             hipMemcpyHostToDevice, st));
-    if (!splits.empty())
-      GM_HIP(hipMemcpyAsync(p->splits, splits.data(), splits.size() * sizeof(Split),
+    if (!L.cross.empty())
+      GM_HIP(hipMemcpyAsync(p->cross, L.cross.data(), L.cross.size() * sizeof(Cross),
                             hipMemcpyHostToDevice, st));
+    if (L.mpad > m) {
+      GM_HIP(hipMemsetAsync(p->idx + m, 0, (L.mpad - m) * 4, st));
+      GM_HIP(hipMemsetAsync(p->wv + m, 0, (L.mpad - m) * 4, st));
+    }
+    GM_HIP(hipMemsetAsync(p->cu, 0, (n + 1) * 4, st));
+    gather_f32<<<blocks_for(n), kThreads, 0, st>>>(g->inv_outdeg, p->old_of, n, p->inv_outdeg);
+    if (L.rows > 0)
+      build_edges<<<blocks_for(L.rows), kThreads, 0, st>>>(g->out_off, g->out_idx, p->old_of,
+                                                           dnew.p, dnoff.p, L.rows, p->idx,
+                                                           p->ceid);
+    GM_HIP(hipGetLastError());
     GM_HIP(hipStreamSynchronize(st));
   } catch (...) {
     free_vjp_plan(g);
@@ -272,15 +340,34 @@ VjpPlan* ensure_plan(gm_graph g, hipStream_t st) {
   return p;
 }
 
+// Workgroups of one vjp_tile launch: as many as fit on the device at once
+// with `lds` bytes of LDS each, no more than there are tiles.
+unsigned tile_grid(VjpPlan* p, size_t lds) {
+  int per_cu = 0;
+  GM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)vjp_tile,
+                                                       kTileThreads, lds));
+  const int64_t fit = (int64_t)std::max(per_cu, 1) * std::max(p->cus, 1);
+  const int64_t want = (p->ntiles + kTileWaves - 1) / kTileWaves;
+  return (unsigned)std::max<int64_t>(1, std::min(fit, want));
+}
+
 }  // namespace
 
 void free_vjp_plan(gm_graph g) {
   VjpPlan* p = plan(g);
   if (!p) return;
-  dfree(p->rows);
-  dfree(p->chunks);
-  dfree(p->splits);
-  dfree(p->partial);
+  dfree(p->old_of);
+  dfree(p->idx);
+  dfree(p->ceid);
+  dfree(p->inv_outdeg);
+  dfree(p->starts);
+  dfree(p->tile_row);
+  dfree(p->cross);
+  dfree(p->head);
+  dfree(p->tail);
+  dfree(p->wv);
+  dfree(p->gv);
+  dfree(p->cu);
   dfree(p->abar[0]);
   dfree(p->abar[1]);
   delete p;
@@ -292,24 +379,39 @@ void run_pagerank_vjp(gm_graph g, const float* w, float r, int32_t T, const floa
                       const float* grad_out, float* grad_w, hipStream_t st) {
   VjpPlan* p = ensure_plan(g, st);
   const int64_t n = g->n, m = g->m;
-  fill_u32(reinterpret_cast<uint32_t*>(grad_w), m, 0u, st);
-  copy_f32<<<blocks_for(n), kThreads, 0, st>>>(grad_out, n, p->abar[0]);  // abar^T = c
+  const float one_r = 1.0f - r;
+  const int64_t hot_cap = std::min<int64_t>(kTileHotMax, p->lds_max / (int64_t)sizeof(float));
+  const int hot_n = (int)std::min<int64_t>(std::min<int64_t>(g->tune.pr_hot, hot_cap), n);
+  const size_t lds = (size_t)hot_n * sizeof(float);
+  const unsigned grid = tile_grid(p, lds);
+  fill_u32(reinterpret_cast<uint32_t*>(p->gv), p->mpad, 0u, st);
+  if (m > 0) gather_w<<<blocks_for(m), kThreads, 0, st>>>(w, p->ceid, m, p->wv);
+  gather_f32<<<blocks_for(n), kThreads, 0, st>>>(grad_out, p->old_of, n, p->abar[0]);  // abar^T = c
+  // Rows without out-edges have abar = 0 from the first reverse step on.
+  if (n > p->rows)
+    fill_u32(reinterpret_cast<uint32_t*>(p->abar[1] + p->rows), n - p->rows, 0u, st);
   GM_HIP(hipGetLastError());
   int cur = 0;
   for (int32_t t = T - 1; t >= 0; --t) {
     const float* an = p->abar[cur];
     float* ac = p->abar[cur ^ 1];
-    if (p->nblocks > 0)
-      vjp_step<<<(unsigned)p->nblocks, kThreads, 0, st>>>(p->rows, g->out_off, g->out_idx, w,
-                                                          hist + (int64_t)t * n, g->inv_outdeg, r,
-                                                          an, ac, grad_w, p->chunks, p->partial,
-                                                          p->bins);
-    if (p->nsplit > 0)
-      vjp_finish<<<(unsigned)((p->nsplit + kThreads - 1) / kThreads), kThreads, 0, st>>>(
-          p->splits, p->nsplit, p->partial, g->inv_outdeg, r, ac);
+    if (p->rows > 0)
+      vjp_cu<<<blocks_for(p->rows), kThreads, 0, st>>>(hist + (int64_t)t * n, p->old_of,
+                                                        p->inv_outdeg, p->rows, one_r, p->cu);
+    if (p->ntiles > 0)
+      vjp_tile<<<grid, kTileThreads, lds, st>>>(p->idx, p->wv, p->starts, p->tile_row, p->ntiles,
+                                                an, p->cu, p->inv_outdeg, one_r, ac, p->gv,
+                                                p->head, p->tail, hot_n);
+    if (p->ncross > 0)
+      vjp_cross<<<(unsigned)((p->ncross * kCrossLanes + kThreads - 1) / kThreads), kThreads, 0,
+                  st>>>(p->cross, p->ncross, p->head, p->tail, p->inv_outdeg, one_r, ac);
     GM_HIP(hipGetLastError());
+    if (t == T - 1 && n > p->rows)  // abar^T (= c) is consumed: its rows without out-edges go to 0
+      fill_u32(reinterpret_cast<uint32_t*>(p->abar[cur] + p->rows), n - p->rows, 0u, st);
     cur ^= 1;
   }
+  if (m > 0) scatter_f32<<<blocks_for(m), kThreads, 0, st>>>(p->gv, p->ceid, m, grad_w);
+  GM_HIP(hipGetLastError());
 }
 
 }  // namespace gm
