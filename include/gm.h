@@ -398,8 +398,9 @@ typedef struct gm_tuning {
                                (256..2^24; 2^14) */
   uint32_t tc_block_work;   /* TC: partner elements per workgroup work item
                                (256..2^26; 2^23) */
-  uint32_t pr_hot;          /* PageRank/PPR pull: the messages of the pr_hot
-                               highest-in-degree vertices are staged in LDS by
+  uint32_t pr_hot;          /* PageRank/PPR pull and the PageRank reverse
+                               pass: the vector entries of the pr_hot
+                               highest-degree vertices are staged in LDS by
                                every workgroup (0..40960; 40960, capped by the
                                device's LDS per workgroup) */
 } gm_tuning;
