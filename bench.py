@@ -47,7 +47,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GTEPS per generalized-SpMV iteration + % HBM peak; batched/adjoint vs plain"
 HBM_PEAK_GBS = 8000.0
-PR_SOURCE = os.path.join(ROOT, "paper_1503_07241_amd", "csrc", "pagerank.hip")
+PR_SOURCES = [os.path.join(ROOT, "paper_1503_07241_amd", "csrc", f)
+              for f in ("pagerank.hip", "tiles.h")]
+
+
+def pr_source_sha():
+    """SHA-256 of the PageRank superstep kernel's sources, in order."""
+    h = hashlib.sha256()
+    for f in PR_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pr_pull_rmat22_traffic.txt")
 
 
@@ -94,8 +103,7 @@ def measured_traffic():
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(PR_SOURCE, "rb").read()).hexdigest()
-    if kv.get("pagerank.hip sha256") != sha or "hbm bytes per superstep" not in kv:
+    if kv.get("source sha256") != pr_source_sha() or "hbm bytes per superstep" not in kv:
         return None
     return int(float(kv["hbm bytes per superstep"]))
 
