@@ -64,11 +64,6 @@ struct CfPlan {
   int64_t nloss = 0;
 };
 
-__device__ inline double group_sum(double v, int lanes) {
-  for (int o = lanes >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 __device__ inline float group_sum_f(float v, int lanes) {
   for (int o = lanes >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
