@@ -173,6 +173,37 @@ def test_pagerank_weight_gradient_long_rows():
     assert rel(gw, oracle.pagerank_vjp_w(og, w, c, 0.15, 20, hist=ref_hist)) <= 1e-5
 
 
+# Out-degree multisets for the reverse pass's edge tiles (its rows are the
+# sources, relabelled by decreasing out-degree): row ends on, just before and
+# just after 1024-edge tile boundaries, rows spanning several tiles, a last
+# tile filled exactly and one left ragged.
+OUT_TILE_CASES = [
+    [3072, 1024, 1000, 24] + [1] * 1024,
+    [2049, 1023, 1, 1],
+    [1025] + [2] * 600 + [1] * 5,
+    [700, 324] + [3] * 341 + [1],
+]
+
+
+@pytest.mark.parametrize("case", range(len(OUT_TILE_CASES)))
+def test_pagerank_weight_gradient_tile_boundaries(case):
+    rng = np.random.default_rng(200 + case)
+    degrees = OUT_TILE_CASES[case]
+    n = len(degrees) + 3000
+    src, dst = [], []
+    for u, k in enumerate(degrees):
+        cand = rng.choice(n - 1, size=k, replace=False)
+        dst.append(np.where(cand >= u, cand + 1, cand))
+        src.append(np.full(k, u))
+    s = np.concatenate(src).astype(np.int32)
+    d = np.concatenate(dst).astype(np.int32)
+    og, w, c, g = pr_setup(n, s, d)
+    for T in (1, 20):
+        hist, gw = gpu_pr_grad(g, n, w, c, T)
+        ref_hist = oracle.pagerank_history(og, 0.15, T, w=w.astype(np.float64))
+        assert rel(gw, oracle.pagerank_vjp_w(og, w, c, 0.15, T, hist=ref_hist)) <= 1e-5
+
+
 def test_pagerank_weight_gradient_autograd_fd():
     n, s, d = W.raw(10)
     og, w, c, g = pr_setup(n, s, d)
