@@ -178,8 +178,10 @@ __device__ __forceinline__ Line load_line(const int32_t* __restrict__ keys, uint
 
 // Matches of unit l of the key array (elements kLine l .. kLine l + kLine - 1,
 // those in [s, e) counted) in the table. Every element reads its home
-// bucket; the few whose home bucket is full without holding them go on to
-// the next buckets in a separate pass.
+// bucket; those whose home bucket is full without holding them go on to the
+// next buckets in one loop that follows a single key per lane at a time (an
+// unrolled pass per element would run for every element position whenever
+// any lane of the wavefront needed it).
 __device__ __forceinline__ uint32_t probe_line(const int4* T4, uint32_t bmask, uint32_t shift,
                                                const Line& L, uint32_t l, uint32_t s, uint32_t e) {
   const int32_t base = (int32_t)(kLine * l);
@@ -204,20 +206,28 @@ __device__ __forceinline__ uint32_t probe_line(const int4* T4, uint32_t bmask, u
     more |= (h == 0u && bucket_full(b)) ? 1u << i : 0u;
   }
   more &= ok;
-  if (more) {  // rare: linear probing past a full home bucket
+  // Keys whose home bucket is full without them go on to the next buckets,
+  // one bucket read per pass for one pending key of each lane (the passes
+  // of a wavefront are the most any of its lanes needs).
+  uint32_t cur = 0, bk = 0;  // bit of the key being followed (0: none), its bucket
+  int32_t ck = 0;
+  while (more | cur) {
+    if (!cur) {
+      const int i = __builtin_ctz(more);
+      cur = 1u << i;
+      more &= more - 1u;
+      ck = key[0];
 #pragma unroll
-    for (int i = 0; i < (int)kLine; ++i) {
-      if (!((more >> i) & 1u)) continue;
-      uint32_t bk = home_bucket(key[i], shift);
-      for (;;) {
-        bk = (bk + 1) & bmask;
-        const int4 b = T4[bk];
-        if (in_bucket(b, key[i])) {
-          hits |= 1u << i;
-          break;
-        }
-        if (!bucket_full(b)) break;
-      }
+      for (int k = 1; k < (int)kLine; ++k) ck = i == k ? key[k] : ck;
+      bk = home_bucket(ck, shift);
+    }
+    bk = (bk + 1) & bmask;
+    const int4 b = T4[bk];
+    if (in_bucket(b, ck)) {
+      hits |= cur;
+      cur = 0;
+    } else if (!bucket_full(b)) {
+      cur = 0;
     }
   }
   return (uint32_t)__popc(hits & ok);
