@@ -124,6 +124,7 @@ __global__ __launch_bounds__(kThreads) void send_kernel(
        w0 += (int64_t)gridDim.x * kThreads) {
     const int64_t wi = w0 + threadIdx.x;
     const uint32_t word = wi < words ? bits[wi] : 0u;
+    if (!__syncthreads_or(word != 0u)) continue;  // no active vertex in the block's words
     const uint32_t cnt = __popc(word);
     const int64_t v0 = wi * 32;
     uint32_t o[33];
@@ -137,7 +138,6 @@ __global__ __launch_bounds__(kThreads) void send_kernel(
     uint32_t ctot, etot;
     const uint32_t cex = block_excl_scan(cnt, sh, &ctot);
     const uint32_t eex = block_excl_scan(edges, sh + kWaves, &etot);
-    if (ctot == 0) continue;  // block-uniform
     if (threadIdx.x == 0)
       base_packed = atomicAdd(&ctl->packed, ((unsigned long long)ctot << 32) | etot);
     __syncthreads();
