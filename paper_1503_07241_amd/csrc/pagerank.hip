@@ -265,17 +265,30 @@ __global__ void pr_unpermute(const float* __restrict__ pr, const int32_t* __rest
     rank[v] = pr[new_of[v]];
 }
 
-// Relabelled in-adjacency keys: (new row << b | new source), value = in-edge id.
+// Row of edge e in a CSR with offsets off (n + 1 entries): the last v with
+// off[v] <= e.
+__device__ inline int64_t row_of_edge(const uint32_t* __restrict__ off, int64_t n, uint32_t e) {
+  int64_t lo = 0, hi = n;  // off[lo] <= e < off[hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= e)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Relabelled in-adjacency keys: (new row << b | new source), value = in-edge
+// id; one thread per edge (a thread per row would serialise the hubs).
 __global__ void relabel_keys(const uint32_t* __restrict__ in_off, const int32_t* __restrict__ in_idx,
-                             const int32_t* __restrict__ new_of, int64_t n, int b,
+                             const int32_t* __restrict__ new_of, int64_t n, int64_t m, int b,
                              unsigned long long* __restrict__ keys, uint32_t* __restrict__ eid) {
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * blockDim.x) {
-    const unsigned long long row = (unsigned long long)(uint32_t)new_of[v] << b;
-    for (uint32_t e = in_off[v]; e < in_off[v + 1]; ++e) {
-      keys[e] = row | (uint32_t)new_of[in_idx[e]];
-      eid[e] = e;
-    }
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = row_of_edge(in_off, n, (uint32_t)e);
+    keys[e] = ((unsigned long long)(uint32_t)new_of[v] << b) | (uint32_t)new_of[in_idx[e]];
+    eid[e] = (uint32_t)e;
   }
 }
 
@@ -427,8 +440,8 @@ void ensure_pull_schedule(gm_graph g, hipStream_t st) {
       while ((1ll << b) < n) ++b;
       DevBuf<unsigned long long> k1(m), k2(m);
       DevBuf<uint32_t> e1(m), e2(m);
-      relabel_keys<<<blocks_for(n), kThreads, 0, st>>>(g->in_off, g->in_idx, d->new_of, n, b, k1.p,
-                                                       e1.p);
+      relabel_keys<<<blocks_for(m), kThreads, 0, st>>>(g->in_off, g->in_idx, d->new_of, n, m, b,
+                                                       k1.p, e1.p);
       GM_HIP(hipGetLastError());
       rocprim::double_buffer<unsigned long long> kb(k1.p, k2.p);
       rocprim::double_buffer<uint32_t> vb(e1.p, e2.p);

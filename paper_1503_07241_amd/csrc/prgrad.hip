@@ -221,20 +221,26 @@ __global__ void gather_w(const float* __restrict__ w, const uint32_t* __restrict
     out[i] = w[ceid[i]];
 }
 
-// Relabelled out-edges of new row i (caller's row old_of[i]): destinations
-// in new labels, caller's edge ids.
+// Relabelled out-edge k (new row i, the last with noff[i] <= k; caller's row
+// old_of[i]): destination in new labels, caller's edge id. One thread per
+// edge (a thread per row would serialise the hubs).
 __global__ void build_edges(const uint32_t* __restrict__ off, const int32_t* __restrict__ out_idx,
                             const int32_t* __restrict__ old_of, const int32_t* __restrict__ new_of,
-                            const uint32_t* __restrict__ noff, int64_t rows,
+                            const uint32_t* __restrict__ noff, int64_t rows, int64_t m,
                             int32_t* __restrict__ idx, uint32_t* __restrict__ ceid) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t b = off[old_of[i]];
-    const uint32_t k0 = noff[i], d = noff[i + 1] - k0;
-    for (uint32_t j = 0; j < d; ++j) {
-      idx[k0 + j] = new_of[out_idx[b + j]];
-      ceid[k0 + j] = b + j;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = rows;  // noff[lo] <= k < noff[hi]
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (noff[mid] <= (uint64_t)k)
+        lo = mid;
+      else
+        hi = mid;
     }
+    const uint32_t e = off[old_of[lo]] + (uint32_t)(k - noff[lo]);
+    idx[k] = new_of[out_idx[e]];
+    ceid[k] = e;
   }
 }
 
@@ -328,9 +334,8 @@ VjpPlan* ensure_plan(gm_graph g, hipStream_t st) {
     GM_HIP(hipMemsetAsync(p->cu, 0, (n + 1) * 4, st));
     gather_f32<<<blocks_for(n), kThreads, 0, st>>>(g->inv_outdeg, p->old_of, n, p->inv_outdeg);
     if (L.rows > 0)
-      build_edges<<<blocks_for(L.rows), kThreads, 0, st>>>(g->out_off, g->out_idx, p->old_of,
-                                                           dnew.p, dnoff.p, L.rows, p->idx,
-                                                           p->ceid);
+      build_edges<<<blocks_for(m), kThreads, 0, st>>>(g->out_off, g->out_idx, p->old_of, dnew.p,
+                                                       dnoff.p, L.rows, m, p->idx, p->ceid);
     GM_HIP(hipGetLastError());
     GM_HIP(hipStreamSynchronize(st));
   } catch (...) {
