@@ -10,10 +10,11 @@
 //
 // Work organisation: the intersection for DAG edge (u -> v) is computed by
 // one endpoint (its "owner"): an owner x puts in(x) in a hash table in LDS
-// (very long lists in LDS-sized pieces) once, then streams the in-list of every
-// partner through it, one probe per element, stopping at the first element
-// >= x (in(x) holds only smaller ids). The endpoint whose partner stream is
-// shorter owns the edge. The match count of edge (u -> v) is credited to the
+// (very long lists in LDS-sized pieces) once, then streams the in-list of
+// every partner through it, one probe per element, up to the last element
+// below x (in(x) holds only smaller ids; the stream lengths are computed
+// with the plan). The endpoint whose partner stream is shorter owns the
+// edge. The match count of edge (u -> v) is credited to the
 // receiver v, as APPLY prescribes. Owner/partner lists are built once per
 // graph and cut into work items of bounded size, one wavefront or workgroup
 // each. The lanes of a wavefront split a window of 64 partners' streams
@@ -119,10 +120,10 @@ __global__ void make_keys(const int32_t* __restrict__ idx, int64_t m, int32_t* _
 // Shift for a table with bmask + 1 buckets (a power of two, at least 16).
 __device__ inline uint32_t bucket_shift(uint32_t bmask) { return 32u - (uint32_t)__popc(bmask); }
 
-// Tables are buckets of 4 slots (one 16-byte LDS or global read); a key
-// lives in its home bucket or, when that is full, in the next buckets
-// (linear probing over buckets). At most half of the slots are used, so most
-// lookups read one bucket.
+// Tables are buckets of 4 slots (one 16-byte LDS read); a key lives in its
+// home bucket or, when that is full, in the next buckets (linear probing
+// over buckets). At most half of the slots are used, so most lookups read
+// one bucket.
 __device__ inline void table_insert(int32_t* T, uint32_t bmask, int32_t key) {
   uint32_t b = home_bucket(key, bucket_shift(bmask));
   for (;;) {
