@@ -386,7 +386,7 @@ gm_status gm_plan_destroy(gm_plan p);
 /* Per-graph schedule parameters. None changes any result, only time. */
 typedef struct gm_tuning {
   uint32_t pull_div;        /* BFS: pull superstep when more than n / pull_div
-                               vertices are active (1..65536; 20) */
+                               vertices are active (1..65536; 128) */
   uint32_t superstep_batch; /* BFS/SSSP: supersteps enqueued between two host
                                checks of the frontier (1..64; 4) */
   uint32_t push_blocks;     /* workgroups of the push kernels, plain and batched

@@ -62,7 +62,7 @@ struct RunStats {
 
 struct Tuning {
   // BFS: pull superstep when the frontier holds more than n / pull_div vertices
-  uint32_t pull_div = 20;
+  uint32_t pull_div = 128;
   // supersteps launched between two host checks of the frontier size
   uint32_t superstep_batch = 4;
   // workgroups of the push kernels (plain and batched SSSP)

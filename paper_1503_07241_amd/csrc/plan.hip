@@ -509,7 +509,7 @@ gm_status gm_autotune(gm_graph g, const gm_program* prog, int32_t batched, const
     };
     std::vector<Param> params;
     if (!batched && kind == GM_PROG_BFS) {
-      params.push_back({&Tuning::pull_div, {4, 8, 16, 32, 64, 128}});
+      params.push_back({&Tuning::pull_div, {16, 32, 64, 128, 256, 512}});
       params.push_back({&Tuning::push_blocks, {512, 1024, 2048, 4096, 8192}});
       params.push_back({&Tuning::superstep_batch, {1, 2, 4, 8, 16}});
     } else if (!batched && kind == GM_PROG_SSSP) {

@@ -275,7 +275,7 @@ def test_autotune_keeps_results_and_sets_values():
     gsym = gm.Graph.from_coo(n, s, d, prep=P_SYM)
     t = gm.autotune(gsym, gm.GM_PROG_BFS, dev([0]), trials=2)
     assert t == gsym.tuning()
-    assert t["pull_div"] in (4, 8, 16, 20, 32, 64, 128)
+    assert t["pull_div"] in (16, 32, 64, 128, 256, 512)
     lv = torch.full((n,), gm.INF_LEVEL, dtype=torch.int32, device=DEV)
     lv[0] = 0
     gm.run_vertex_program(gsym, gm.GM_PROG_BFS, dev([0]), -1, lv)
