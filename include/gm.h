@@ -391,7 +391,7 @@ typedef struct gm_tuning {
                                checks of the frontier (1..64; 4) */
   uint32_t push_blocks;     /* workgroups of the push kernels, plain and batched
                                SSSP (64..65536; 2048) */
-  uint32_t ppr_chunk;       /* batched PPR: in-edges per work item (64..65536; 512) */
+  uint32_t ppr_chunk;       /* batched PPR: in-edges per work item (64..65536; 128) */
   uint32_t tc_wave_max;     /* TC: owners with at most this many in-neighbours
                                use a per-wavefront table (64..1024; 1024) */
   uint32_t tc_wave_work;    /* TC: partner elements per wavefront work item

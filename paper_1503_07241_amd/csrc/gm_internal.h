@@ -68,7 +68,7 @@ struct Tuning {
   // workgroups of the push kernels (plain and batched SSSP)
   uint32_t push_blocks = 2048;
   // batched PPR: in-edges per work item
-  uint32_t ppr_chunk = 512;
+  uint32_t ppr_chunk = 128;
   // TC: owners whose in-list is at most this long use a per-wavefront table
   uint32_t tc_wave_max = 1024;
   // TC: partner-list elements per wavefront / workgroup work item
