@@ -117,8 +117,9 @@ gm_status gm_graph_get_info(gm_graph g, gm_graph_info* info);
 /*
  * Copy the canonical edge list to host arrays of length m: src, dst
  * (either may be NULL) and values w (NULL, or uint32/float per wtype).
- * Errors: GM_ESTATE, GM_EINVAL (w non-NULL on an unweighted graph),
- * GM_EHIP. Synchronous.
+ * For a rating graph (gm_bipartite_from_coo) src is the row and dst the
+ * column of each rating, by row, and w must be NULL. Errors: GM_ESTATE,
+ * GM_EINVAL (w non-NULL on an unweighted graph), GM_EHIP. Synchronous.
  */
 gm_status gm_graph_edges(gm_graph g, int32_t* src, int32_t* dst, void* w);
 

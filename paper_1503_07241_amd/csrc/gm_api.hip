@@ -76,6 +76,14 @@ void graph_unregister(gm_graph g) {
   if (g_reg) g_reg->erase(g);
 }
 
+gm_status check_device(gm_graph g) {
+  int dev = 0;
+  GM_HIP(hipGetDevice(&dev));
+  if (dev != g->device)
+    return fail(GM_EINVAL, "graph lives on device %d, current is %d", g->device, dev);
+  return GM_OK;
+}
+
 }  // namespace gm
 
 using namespace gm;
@@ -158,7 +166,8 @@ gm_status gm_graph_edges(gm_graph g, int32_t* src, int32_t* dst, void* w) {
   if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
   if (w && g->wtype == GM_W_NONE) return fail(GM_EINVAL, "graph has no edge values");
   return guarded([&]() -> gm_status {
-    const int64_t n = g->n, m = g->m;
+    // a rating graph's out-adjacency has one row per user, ids are columns
+    const int64_t n = g->bipartite ? g->n_rows : g->n, m = g->m;
     if (dst && m > 0) GM_HIP(hipMemcpy(dst, g->out_idx, m * sizeof(int32_t), hipMemcpyDeviceToHost));
     if (w && m > 0) GM_HIP(hipMemcpy(w, g->out_w, m * sizeof(uint32_t), hipMemcpyDeviceToHost));
     if (src && m > 0) {
@@ -210,6 +219,7 @@ gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_fro
     if (!(g->prep & GM_PREP_UPPER_DAG) || !(g->layouts & GM_LAYOUT_IN))
       return fail(GM_EUNSUPPORTED, "triangle counting needs GM_PREP_UPPER_DAG and GM_LAYOUT_IN");
     return guarded([&]() -> gm_status {
+      if (const gm_status st = check_device(g)) return st;
       run_triangle_count(g, static_cast<unsigned long long*>(vprop), nullptr,
                          static_cast<hipStream_t>(stream));
       if (active_out) fill_u32(reinterpret_cast<uint32_t*>(active_out), g->n, 0u,
@@ -239,9 +249,7 @@ gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_fro
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() -> gm_status {
-    int dev = 0;
-    GM_HIP(hipGetDevice(&dev));
-    if (dev != g->device) return fail(GM_EINVAL, "graph lives on device %d, current is %d", g->device, dev);
+    if (const gm_status st = check_device(g)) return st;
     if (frontier && frontier->count > 0 && !ids_in_range(frontier->ids, frontier->count, g->n, s))
       return fail(GM_EINVAL, "frontier id outside [0, n)");
     int32_t it = 0;
@@ -277,6 +285,7 @@ gm_status gm_triangle_count(gm_graph g, uint64_t* counts, uint64_t* total, void*
     return fail(GM_EUNSUPPORTED, "triangle counting needs GM_PREP_UPPER_DAG and GM_LAYOUT_IN");
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() -> gm_status {
+    if (const gm_status st = check_device(g)) return st;
     unsigned long long* c = reinterpret_cast<unsigned long long*>(counts);
     unsigned long long* own = nullptr;
     if (!c) own = c = dalloc<unsigned long long>(g->n);
@@ -323,6 +332,7 @@ gm_status gm_run_batched(gm_graph g, const gm_program* prog, const int32_t* sour
     return fail(GM_EUNSUPPORTED, "batched BFS on a directed graph needs GM_LAYOUT_IN");
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() -> gm_status {
+    if (const gm_status st = check_device(g)) return st;
     if (!ids_in_range(sources, k, g->n, s)) return fail(GM_EINVAL, "source id outside [0, n)");
     int32_t it = 0;
     if (kind == GM_PROG_BFS)
@@ -390,6 +400,7 @@ gm_status gm_cf_forward(gm_graph g, int32_t K, const float* PU, const float* PV,
   if (st != GM_OK) return st;
   if (!loss) return fail(GM_EINVAL, "loss is NULL");
   return guarded([&]() -> gm_status {
+    if (const gm_status st = check_device(g)) return st;
     run_cf_forward(g, K, PU, PV, lambda, loss, static_cast<hipStream_t>(stream));
     return ok();
   });
@@ -402,6 +413,7 @@ gm_status gm_cf_backward(gm_graph g, int32_t K, const float* PU, const float* PV
   if (!gPU && !gPV) return fail(GM_EINVAL, "gPU and gPV are both NULL");
   if (!std::isfinite(scale)) return fail(GM_EINVAL, "scale is not finite");
   return guarded([&]() -> gm_status {
+    if (const gm_status st = check_device(g)) return st;
     run_cf_backward(g, K, PU, PV, lambda, scale, gPU, gPV, static_cast<hipStream_t>(stream));
     return ok();
   });
@@ -423,6 +435,7 @@ gm_status gm_pagerank_forward_w(gm_graph g, const float* w, float r, int32_t T, 
   if (st != GM_OK) return st;
   if (!hist) return fail(GM_EINVAL, "hist is NULL");
   return guarded([&]() -> gm_status {
+    if (const gm_status st = check_device(g)) return st;
     run_pagerank_history(g, w, r, T, hist, static_cast<hipStream_t>(stream));
     return ok();
   });
@@ -434,6 +447,7 @@ gm_status gm_pagerank_vjp_w(gm_graph g, const float* w, float r, int32_t T, cons
   if (st != GM_OK) return st;
   if (!hist || !grad_out || !grad_w) return fail(GM_EINVAL, "hist/grad_out/grad_w is NULL");
   return guarded([&]() -> gm_status {
+    if (const gm_status st = check_device(g)) return st;
     run_pagerank_vjp(g, w, r, T, hist, grad_out, grad_w, static_cast<hipStream_t>(stream));
     return ok();
   });

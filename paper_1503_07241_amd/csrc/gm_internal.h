@@ -162,6 +162,9 @@ gm_status guarded(F&& f) {
 // Handle registry (graph handles are validated on every call).
 bool graph_live(gm_graph g);
 void graph_register(gm_graph g);
+// GM_OK when the calling thread's current device holds g, else GM_EINVAL
+// with its message; HIP failures throw HipError (call inside guarded()).
+gm_status check_device(gm_graph g);
 void graph_unregister(gm_graph g);
 
 // Device-side graph construction (graph_build.hip).

@@ -493,6 +493,7 @@ gm_status gm_autotune(gm_graph g, const gm_program* prog, int32_t batched, const
   if (st != GM_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() -> gm_status {
+    if (const gm_status dev_st = check_device(g)) return dev_st;
     if (ids && count > 0 && !ids_in_range(ids, count, g->n, s))
       return fail(GM_EINVAL, "id outside [0, n)");
     const int64_t k = batched ? count : 1;

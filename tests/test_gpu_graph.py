@@ -88,3 +88,16 @@ def test_destroy_then_estate():
     g.close()
     st = gm._lib.load().gm_graph_destroy(h)
     assert st == gm._lib.GM_ESTATE
+
+
+def test_rating_graph_edges():
+    # more columns than rows: the edge list is expanded over the rows only
+    row = np.array([3, 0, 1, 3, 0, 2], np.int32)
+    col = np.array([9, 4, 0, 2, 11, 7], np.int32)
+    val = np.array([5, 1, 2, 3, 4, 5], np.uint8)
+    g = gm.RatingGraph.from_coo(4, 12, row, col, val)
+    s, d = g.edges()
+    order = np.lexsort((col, row))
+    assert np.array_equal(s, row[order]) and np.array_equal(d, col[order])
+    with pytest.raises(gm.GmError):
+        g.edges(with_weights=True)
