@@ -43,6 +43,35 @@ def _ptr(t) -> int | None:
     return int(t.data_ptr())
 
 
+def _dtypes(*names):
+    import torch
+    return tuple(getattr(torch, n) for n in names if hasattr(torch, n))
+
+
+# Element types the library reads through each kind of device pointer
+# (unsigned values may sit in signed tensors of the same width).
+_I32 = ("int32", "uint32")
+_U64 = ("int64", "uint64")
+_F32 = ("float32",)
+_F64 = ("float64",)
+
+
+def _dev(t, name: str, numel: int, kinds) -> int | None:
+    """Device pointer of tensor t after checking what the kernels will assume
+    of it: on the GPU, of one of the element types `kinds`, contiguous, and
+    at least `numel` elements long (the library sees only the address)."""
+    if t is None:
+        return None
+    if t.device.type != "cuda":
+        raise ValueError("%s must be a device tensor (got %s)" % (name, t.device))
+    allowed = _dtypes(*kinds)
+    if t.dtype not in allowed:
+        raise ValueError("%s has dtype %s; expected one of %s" % (name, t.dtype, list(kinds)))
+    if t.numel() < numel:
+        raise ValueError("%s holds %d elements; the call needs %d" % (name, t.numel(), numel))
+    return _ptr(t)
+
+
 def _host(a, dtype):
     a = np.ascontiguousarray(a, dtype=dtype)
     return a, a.ctypes.data
@@ -57,6 +86,7 @@ class Graph:
 
     def __init__(self, handle: int):
         self._h = ctypes.c_void_p(handle)
+        self._dims = None
 
     @property
     def handle(self) -> ctypes.c_void_p:
@@ -97,13 +127,19 @@ class Graph:
                    "gm_graph_get_info")
         return info
 
+    def _nm(self):
+        if self._dims is None:  # a graph's sizes never change
+            info = self.info()
+            self._dims = (info.n, info.m)
+        return self._dims
+
     @property
     def n(self) -> int:
-        return self.info().n
+        return self._nm()[0]
 
     @property
     def m(self) -> int:
-        return self.info().m
+        return self._nm()[1]
 
     def edges(self, with_weights: bool = False):
         """Canonical (src, dst[, w]) host arrays, sorted by (src, dst)."""
@@ -171,11 +207,14 @@ def run_vertex_program(g: Graph, kind: int, frontier, max_iters: int, vprop, act
     prog = _lib.gm_program(kind, GM_ORDER_OUT, r, 0)
     fr = None
     if frontier is not None:
-        fr = _lib.gm_frontier(_ptr(frontier), frontier.numel())
+        fr = _lib.gm_frontier(_dev(frontier, "frontier", 0, _I32), frontier.numel())
+    n = g.n
+    pv = _dev(vprop, "vprop", n, _U64 if kind == GM_PROG_TC else
+              _F32 if kind in (GM_PROG_PAGERANK, GM_PROG_PPR) else _I32)
     it = ctypes.c_int32(0)
     _lib.check(_lib.load().gm_run_vertex_program(
         g.handle, ctypes.byref(prog), None if fr is None else ctypes.byref(fr), max_iters,
-        _ptr(vprop), _ptr(active_out), ctypes.byref(it), _stream(stream)),
+        pv, _dev(active_out, "active_out", n, _I32), ctypes.byref(it), _stream(stream)),
         "gm_run_vertex_program")
     return it.value
 
@@ -184,7 +223,8 @@ def triangle_count(g: Graph, counts=None, stream=None) -> int:
     """gm_triangle_count: exact triangle total; per-vertex counts (device
     uint64 stored in an int64 tensor) are written to `counts` when given."""
     total = ctypes.c_uint64(0)
-    _lib.check(_lib.load().gm_triangle_count(g.handle, _ptr(counts), ctypes.byref(total),
+    _lib.check(_lib.load().gm_triangle_count(g.handle, _dev(counts, "counts", g.n, _U64),
+                                             ctypes.byref(total),
                                              _stream(stream)), "gm_triangle_count")
     return int(total.value)
 
@@ -196,8 +236,11 @@ def run_batched(g: Graph, kind: int, sources, max_iters: int, vprop_block, r: fl
     ranks) that the call initialises. Returns supersteps run."""
     prog = _lib.gm_program(kind, GM_ORDER_OUT, r, 0)
     it = ctypes.c_int32(0)
-    _lib.check(_lib.load().gm_run_batched(g.handle, ctypes.byref(prog), _ptr(sources),
-                                          sources.numel(), max_iters, _ptr(vprop_block),
+    k = sources.numel()
+    pb = _dev(vprop_block, "vprop_block", g.n * k, _F32 if kind == GM_PROG_PPR else _I32)
+    _lib.check(_lib.load().gm_run_batched(g.handle, ctypes.byref(prog),
+                                          _dev(sources, "sources", k, _I32),
+                                          k, max_iters, pb,
                                           ctypes.byref(it), _stream(stream)), "gm_run_batched")
     return it.value
 
@@ -215,7 +258,7 @@ def autotune(g: Graph, kind: int, ids=None, batched: bool = False, max_iters: in
     t = _lib.gm_tuning()
     count = 0 if ids is None else ids.numel()
     _lib.check(_lib.load().gm_autotune(g.handle, ctypes.byref(prog), 1 if batched else 0,
-                                       _ptr(ids), count, max_iters, trials, ctypes.byref(t),
+                                       _dev(ids, "ids", count, _I32), count, max_iters, trials, ctypes.byref(t),
                                        _stream(stream)), "gm_autotune")
     return {f: int(getattr(t, f)) for f in _lib.TUNING_FIELDS}
 
@@ -242,9 +285,13 @@ class Plan:
             arr[i].prog = _lib.gm_program(r.kind, GM_ORDER_OUT, r.r, 0)
             arr[i].batched = 1 if r.batched else 0
             arr[i].max_iters = r.max_iters
-            arr[i].ids = _ptr(r.ids)
-            arr[i].count = 0 if r.ids is None else r.ids.numel()
-            arr[i].vprop = _ptr(r.vprop)
+            count = 0 if r.ids is None else r.ids.numel()
+            arr[i].ids = _dev(r.ids, "ids of run %d" % i, count, _I32)
+            arr[i].count = count
+            kinds = (_U64 if r.kind == GM_PROG_TC else
+                     _F32 if r.kind in (GM_PROG_PAGERANK, GM_PROG_PPR) else _I32)
+            arr[i].vprop = _dev(r.vprop, "vprop of run %d" % i,
+                                r.g.n * (count if r.batched else 1), kinds)
         out = ctypes.c_void_p()
         _lib.check(_lib.load().gm_plan_create(arr, len(runs), _stream(stream), ctypes.byref(out)),
                    "gm_plan_create")
@@ -288,33 +335,57 @@ class RatingGraph(Graph):
         _lib.check(_lib.load().gm_bipartite_from_coo(n_rows, n_cols, len(r), rp, cp, vpp,
                                                      _stream(stream), ctypes.byref(out)),
                    "gm_bipartite_from_coo")
-        return cls(out.value)
+        g = cls(out.value)
+        g.n_rows, g.n_cols = int(n_rows), int(n_cols)
+        return g
+
+
+def _factors(g: RatingGraph, PU, PV) -> int:
+    """K of the factor matrices P_U (n_rows x K) and P_V (n_cols x K)."""
+    if PU.dim() != 2 or PV.dim() != 2 or PU.shape[1] != PV.shape[1]:
+        raise ValueError("PU and PV must be 2-D with the same number of columns")
+    rows, cols = getattr(g, "n_rows", None), getattr(g, "n_cols", None)
+    if rows is not None and (PU.shape[0] != rows or PV.shape[0] != cols):
+        raise ValueError("PU must have %d rows and PV %d" % (rows, cols))
+    return PU.shape[1]  # a graph that is no rating graph is refused by the library
 
 
 def cf_forward(g: RatingGraph, PU, PV, lam: float, loss_out, stream=None) -> None:
     """gm_cf_forward: writes the Eq. (3) loss into loss_out (device float64[1])."""
-    _lib.check(_lib.load().gm_cf_forward(g.handle, PU.shape[1], _ptr(PU), _ptr(PV), lam,
-                                         _ptr(loss_out), _stream(stream)), "gm_cf_forward")
+    K = _factors(g, PU, PV)
+    _lib.check(_lib.load().gm_cf_forward(g.handle, K, _dev(PU, "PU", PU.numel(), _F32),
+                                         _dev(PV, "PV", PV.numel(), _F32), lam,
+                                         _dev(loss_out, "loss_out", 1, _F64), _stream(stream)),
+               "gm_cf_forward")
 
 
 def cf_backward(g: RatingGraph, PU, PV, lam: float, scale: float, gPU=None, gPV=None,
                 stream=None) -> None:
     """gm_cf_backward: scale * dL/dP_U into gPU, scale * dL/dP_V into gPV."""
-    _lib.check(_lib.load().gm_cf_backward(g.handle, PU.shape[1], _ptr(PU), _ptr(PV), lam, scale,
-                                          _ptr(gPU), _ptr(gPV), _stream(stream)),
+    K = _factors(g, PU, PV)
+    _lib.check(_lib.load().gm_cf_backward(g.handle, K, _dev(PU, "PU", PU.numel(), _F32),
+                                          _dev(PV, "PV", PV.numel(), _F32), lam, scale,
+                                          _dev(gPU, "gPU", PU.numel(), _F32),
+                                          _dev(gPV, "gPV", PV.numel(), _F32), _stream(stream)),
                "gm_cf_backward")
 
 
 def pagerank_forward_w(g: Graph, w, r: float, T: int, hist, stream=None) -> None:
     """gm_pagerank_forward_w: hist[0] holds PR^0; rows 1..T are written."""
-    _lib.check(_lib.load().gm_pagerank_forward_w(g.handle, _ptr(w), r, T, _ptr(hist),
+    n, m = g.n, g.m
+    _lib.check(_lib.load().gm_pagerank_forward_w(g.handle, _dev(w, "w", m, _F32), r, T,
+                                                 _dev(hist, "hist", (max(T, 0) + 1) * n, _F32),
                                                  _stream(stream)), "gm_pagerank_forward_w")
 
 
 def pagerank_vjp_w(g: Graph, w, r: float, T: int, hist, grad_out, grad_w, stream=None) -> None:
     """gm_pagerank_vjp_w: grad_w = dL/dw given grad_out = dL/dPR^T."""
-    _lib.check(_lib.load().gm_pagerank_vjp_w(g.handle, _ptr(w), r, T, _ptr(hist), _ptr(grad_out),
-                                             _ptr(grad_w), _stream(stream)), "gm_pagerank_vjp_w")
+    n, m = g.n, g.m
+    _lib.check(_lib.load().gm_pagerank_vjp_w(g.handle, _dev(w, "w", m, _F32), r, T,
+                                             _dev(hist, "hist", (max(T, 0) + 1) * n, _F32),
+                                             _dev(grad_out, "grad_out", n, _F32),
+                                             _dev(grad_w, "grad_w", m, _F32), _stream(stream)),
+               "gm_pagerank_vjp_w")
 
 
 def _autograd():

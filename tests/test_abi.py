@@ -135,3 +135,11 @@ def test_union_plan_tuning_validation_without_device(lib):
     assert lib.gm_graph_set_tuning(bogus, ctypes.byref(t)) == _lib.GM_ESTATE
     prog = _lib.gm_program(_lib.GM_PROG_BFS, _lib.GM_ORDER_OUT, 0.15, 0)
     assert lib.gm_autotune(bogus, ctypes.byref(prog), 0, None, 0, -1, 3, None, None) == _lib.GM_ESTATE
+
+
+def test_binding_refuses_host_tensors():
+    import torch
+    # the library sees only an address: a host buffer must not reach it
+    with pytest.raises(ValueError, match="device tensor"):
+        gm._dev(torch.zeros(4, dtype=torch.float32), "vprop", 4, gm._F32)
+    assert gm._dev(None, "active_out", 4, gm._I32) is None

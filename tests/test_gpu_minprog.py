@@ -150,3 +150,32 @@ def test_argument_errors_on_device():
     with pytest.raises(gm.GmError) as e:  # PageRank needs max_iters > 0
         gm.run_vertex_program(g, gm.GM_PROG_PAGERANK, None, 0, lv.float())
     assert e.value.status == gm._lib.GM_EINVAL
+
+
+def test_binding_checks_device_buffers():
+    n, s, d = W.raw(8)
+    g = gm.Graph.from_coo(n, s, d, prep=P_DIR)
+    lv = torch.zeros(n, dtype=torch.int32, device=DEV)
+    with pytest.raises(ValueError, match="elements"):  # shorter than n
+        gm.run_vertex_program(g, gm.GM_PROG_BFS, ids(0), -1, lv[: n - 1])
+    with pytest.raises(ValueError, match="dtype"):  # ranks are float32
+        gm.run_vertex_program(g, gm.GM_PROG_PAGERANK, None, 2, lv)
+    with pytest.raises(ValueError, match="device tensor"):
+        gm.run_vertex_program(g, gm.GM_PROG_BFS, ids(0), -1, lv.cpu())
+    with pytest.raises(ValueError, match="dtype"):  # frontier ids are int32
+        gm.run_vertex_program(g, gm.GM_PROG_BFS, ids(0).long(), -1, lv)
+    with pytest.raises(ValueError, match="elements"):  # n x k block for k = 2
+        gm.run_batched(g, gm.GM_PROG_BFS, ids(0, 1), -1, lv)
+    with pytest.raises(ValueError, match="elements"):
+        gm.pagerank_forward_w(g, torch.ones(g.m, device=DEV), 0.15, 3,
+                              torch.empty((3, n), dtype=torch.float32, device=DEV))
+    R = gg.cf_ratings(n_users=50, n_items=20, total=400, dmin=2)
+    rg = gm.RatingGraph.from_coo(R.n_users, R.n_items, R.user, R.item, R.rating)
+    loss = torch.empty(1, dtype=torch.float64, device=DEV)
+    with pytest.raises(ValueError, match="rows"):  # P_V must have one row per item
+        gm.cf_forward(rg, torch.zeros((50, 4), device=DEV), torch.zeros((19, 4), device=DEV),
+                      0.05, loss)
+    # nothing above reached a kernel: the same buffers still work
+    lv[0] = 0
+    lv[1:] = gm.INF_LEVEL
+    assert gm.run_vertex_program(g, gm.GM_PROG_BFS, ids(0), -1, lv) >= 1
