@@ -337,6 +337,7 @@ CfSide make_side(const std::vector<uint32_t>& off, int64_t nseg, hipStream_t s) 
   if (!splits.empty())
     GM_HIP(hipMemcpyAsync(side.splits, splits.data(), splits.size() * sizeof(CfSplit),
                           hipMemcpyHostToDevice, s));
+  GM_HIP(hipStreamSynchronize(s));  // the copies read items and splits, which end here
   return side;
 }
 

@@ -220,3 +220,23 @@ def test_pagerank_weight_gradient_autograd_fd():
     Lm = c @ oracle.pagerank(og, 0.15, 20, w=w - h * dirv)
     fd = (Lp - Lm) / (2 * h)
     assert abs(wt.grad.cpu().numpy().astype(np.float64) @ dirv - fd) <= 1e-5 * abs(fd)
+
+
+def test_cf_unrated_rows_columns_and_no_ratings():
+    """Users 1 and 3 and item 2 have no rating: their gradient rows are the
+    L2 term of Eq. (3) alone; a rating graph without ratings leaves only it."""
+    user = np.array([0, 0, 2, 4], np.int32)
+    item = np.array([0, 1, 3, 1], np.int32)
+    rating = np.array([5, 3, 1, 4], np.uint8)
+    rng = np.random.default_rng(11)
+    PU = (0.3 * rng.normal(size=(5, 8))).astype(np.float32)
+    PV = (0.3 * rng.normal(size=(4, 8))).astype(np.float32)
+    for nu, ni, u, i, v in ((5, 4, user, item, rating),
+                            (5, 4, user[:0], item[:0], rating[:0])):
+        g = gm.RatingGraph.from_coo(nu, ni, u, i, v)
+        L, gu, gv = gpu_cf(g, PU, PV)
+        Lr, gur, gvr = oracle.cf_loss_grad(nu, ni, u, i, v, PU, PV, LAM)
+        assert abs(L - Lr) <= 1e-5 * abs(Lr)
+        assert rel(gu, gur) <= 1e-5 and rel(gv, gvr) <= 1e-5
+        assert np.allclose(gu[[1, 3]], 2 * LAM * PU[[1, 3]], rtol=1e-6, atol=0)
+        assert np.allclose(gv[2], 2 * LAM * PV[2], rtol=1e-6, atol=0)

@@ -169,3 +169,23 @@ def test_batched_argument_errors():
     with pytest.raises(gm.GmError) as e:  # no weights
         gm.run_batched(g, gm.GM_PROG_SSSP, dev([0]), -1, blk)
     assert e.value.status == gm._lib.GM_EUNSUPPORTED
+
+
+def test_batched_on_edgeless_graph():
+    n = 300
+    none = np.zeros(0, np.int32)
+    S = [3, 299, 0, 3]
+    g = gm.Graph.from_coo(n, none, none, prep=P_SYM)
+    lv, _ = batched(g, gm.GM_PROG_BFS, S, n, torch.int32)
+    gw = gm.Graph.from_coo(n, none, none, w=np.zeros(0, np.uint32), prep=P_DIR)
+    dist, _ = batched(gw, gm.GM_PROG_SSSP, S, n, torch.int32)
+    og = oracle.prepare(n, none, none, w=np.zeros(0, np.uint32), mode="directed")
+    for j, r in enumerate(S):
+        assert np.array_equal(lv[:, j], oracle.bfs(og, r))
+        assert np.array_equal(dist[:, j].view(np.uint32), oracle.sssp(og, r))
+    pr = torch.empty((n, len(S)), dtype=torch.float32, device=DEV)
+    gm.run_batched(gw, gm.GM_PROG_PPR, dev(S), 20, pr)
+    pr = pr.cpu().numpy()
+    for j, r in enumerate(S):
+        ref = oracle.personalized_pagerank(og, r, 0.15, 20)
+        assert np.allclose(pr[:, j], ref, rtol=1e-6, atol=0)

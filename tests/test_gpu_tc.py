@@ -105,3 +105,11 @@ def test_tc_needs_dag():
     with pytest.raises(gm.GmError) as e:
         gm.triangle_count(g)
     assert e.value.status == gm._lib.GM_EUNSUPPORTED
+
+
+def test_edgeless_dag():
+    g, total, counts = gpu_tc(9, [], [])
+    assert total == 0 and not counts.any()
+    tri = torch.full((9,), 3, dtype=torch.int64, device=DEV)  # APPLY adds nothing
+    assert gm.run_vertex_program(g, gm.GM_PROG_TC, None, 1, tri) == 1
+    assert np.array_equal(tri.cpu().numpy(), np.full(9, 3))
