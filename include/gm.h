@@ -283,7 +283,8 @@ gm_status gm_cf_backward(gm_graph g, int32_t K, const float* PU, const float* PV
  * sum_{u -> v} w_uv PR^t(u) / outdeg(u) (Eq. (1) with edge weights w in
  * canonical edge order, device float[m]; outdeg is the unweighted count).
  * hist is a device float (T + 1) x n array whose row 0 the caller fills
- * with PR^0; the call writes rows 1..T. Needs GM_LAYOUT_IN.
+ * with PR^0; the call writes rows 1..T. Needs GM_LAYOUT_IN. w may be NULL
+ * only when the graph has no edges (an empty tensor's address).
  * Errors: GM_ESTATE; GM_EINVAL (NULL pointers, T < 1, r outside [0, 1]);
  * GM_EUNSUPPORTED (no in-layout, rating graph); GM_ENOMEM; GM_EHIP.
  * Asynchronous.
@@ -296,7 +297,8 @@ gm_status gm_pagerank_forward_w(gm_graph g, const float* w, float r, int32_t T, 
  * grad_out = dL/dPR^T (device float[n]) and the history from
  * gm_pagerank_forward_w, writes grad_w = dL/dw (device float[m], canonical
  * edge order) by T reverse steps, each one pass over the out-edges (the
- * product with the transposed matrix). Errors as gm_pagerank_forward_w.
+ * product with the transposed matrix); grad_w, like w, may be NULL only
+ * when the graph has no edges. Errors as gm_pagerank_forward_w.
  * Asynchronous.
  */
 gm_status gm_pagerank_vjp_w(gm_graph g, const float* w, float r, int32_t T, const float* hist,

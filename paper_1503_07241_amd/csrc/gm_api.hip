@@ -423,7 +423,7 @@ static gm_status check_prw(gm_graph g, const float* w, float r, int32_t T) {
   if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
   if (g->bipartite) return fail(GM_EUNSUPPORTED, "rating graphs take the CF calls only");
   if (!(g->layouts & GM_LAYOUT_IN)) return fail(GM_EUNSUPPORTED, "needs GM_LAYOUT_IN");
-  if (!w) return fail(GM_EINVAL, "w is NULL");
+  if (!w && g->m > 0) return fail(GM_EINVAL, "w is NULL");  // unread without edges
   if (!(r >= 0.0f && r <= 1.0f)) return fail(GM_EINVAL, "r outside [0, 1]");
   if (T < 1) return fail(GM_EINVAL, "T must be >= 1");
   return GM_OK;
@@ -445,7 +445,8 @@ gm_status gm_pagerank_vjp_w(gm_graph g, const float* w, float r, int32_t T, cons
                             const float* grad_out, float* grad_w, void* stream) {
   const gm_status st = check_prw(g, w, r, T);
   if (st != GM_OK) return st;
-  if (!hist || !grad_out || !grad_w) return fail(GM_EINVAL, "hist/grad_out/grad_w is NULL");
+  if (!hist || !grad_out || (!grad_w && g->m > 0))
+    return fail(GM_EINVAL, "hist/grad_out/grad_w is NULL");
   return guarded([&]() -> gm_status {
     if (const gm_status st = check_device(g)) return st;
     run_pagerank_vjp(g, w, r, T, hist, grad_out, grad_w, static_cast<hipStream_t>(stream));

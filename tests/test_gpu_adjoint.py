@@ -240,3 +240,15 @@ def test_cf_unrated_rows_columns_and_no_ratings():
         assert rel(gu, gur) <= 1e-5 and rel(gv, gvr) <= 1e-5
         assert np.allclose(gu[[1, 3]], 2 * LAM * PU[[1, 3]], rtol=1e-6, atol=0)
         assert np.allclose(gv[2], 2 * LAM * PV[2], rtol=1e-6, atol=0)
+
+
+def test_pagerank_weight_gradient_edgeless_graph():
+    n = 40
+    none = np.zeros(0, np.int32)
+    g = gm.Graph.from_coo(n, none, none)
+    wt = torch.zeros(0, device=DEV, requires_grad=True)  # its address is NULL
+    out = gm.PageRankW.apply(wt, g, 0.15, 3)
+    ref = oracle.pagerank(oracle.prepare(n, none, none), 0.15, 3, w=np.zeros(0))
+    assert np.allclose(out.detach().cpu().numpy(), ref, rtol=1e-6, atol=0)
+    out.sum().backward()
+    assert wt.grad.shape == (0,)

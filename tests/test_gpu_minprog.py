@@ -179,3 +179,19 @@ def test_binding_checks_device_buffers():
     lv[0] = 0
     lv[1:] = gm.INF_LEVEL
     assert gm.run_vertex_program(g, gm.GM_PROG_BFS, ids(0), -1, lv) >= 1
+
+
+def test_sssp_saturating_weights():
+    # path sums beyond 2^32 - 1 clamp to UINT32_MAX, as in the oracle
+    from tests.test_oracle_bfs_sssp import SAT_DIST, SAT_PAIRS, SAT_W
+    s = np.array([p[0] for p in SAT_PAIRS], np.int32)
+    d = np.array([p[1] for p in SAT_PAIRS], np.int32)
+    g = gm.Graph.from_coo(6, s, d, w=SAT_W, prep=P_DIR)
+    dist, _, _ = run_sssp(g, 6, 0)
+    assert dist.tolist() == SAT_DIST
+    block = torch.empty((6, 2), dtype=torch.int32, device=DEV)
+    gm.run_batched(g, gm.GM_PROG_SSSP, ids(0, 5), -1, block)
+    out = block.cpu().numpy().view(np.uint32)
+    og = oracle.prepare(6, s, d, w=SAT_W)
+    assert out[:, 0].tolist() == SAT_DIST
+    assert np.array_equal(out[:, 1], oracle.sssp(og, 5))

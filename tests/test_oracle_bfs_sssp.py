@@ -236,3 +236,15 @@ def test_oracle_bfs_certificate_function():
     with pytest.raises(AssertionError):
         b2 = level.copy(); b2[reached[7]] += 1
         check_bfs_certificate(g, 0, b2)
+
+
+# Path sums that reach 2^32 - 1: the distance is the sum clamped at
+# UINT32_MAX (the saturating PROCESS of SSSP), worked out by hand.
+SAT_PAIRS = [(0, 1), (1, 2), (0, 3), (3, 4), (0, 5), (5, 4)]
+SAT_W = np.array([4_000_000_000, 4_000_000_000, INF_U - 1, 1, 2**31, 2**31 - 2], np.uint32)
+SAT_DIST = [0, 4_000_000_000, INF_U, INF_U - 1, INF_U - 1, 2**31]
+
+
+def test_sssp_saturates_at_uint32_max():
+    g = graph_from_pairs(6, SAT_PAIRS, w=SAT_W)
+    assert oracle.sssp(g, 0).tolist() == SAT_DIST
