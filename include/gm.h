@@ -22,7 +22,9 @@
  *    or written before the call returns.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Work is enqueued on it; calls documented as synchronising wait for it.
- *  - A gm_graph is used by one stream at a time (its workspace is shared).
+ *  - A gm_graph is used by one stream and one host thread at a time (its
+ *    workspace and cached schedules are shared); distinct graphs are
+ *    independent and may be used from different threads.
  *  - Vertex ids are int32 in [0, n). Edge counts are limited to 2^32 - 1
  *    stored edges per graph (32-bit offsets); larger graphs give
  *    GM_EUNSUPPORTED.
