@@ -154,6 +154,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"tc_runs": args.tc_only, "m_dag": g.m}), flush=True)
         return
+    t0 = time.time()  # graph loads: host edge lists in, device layouts out
     g_sym = gm.Graph.from_coo(n, s, d, prep=gm.GM_PREP_DROP_SELF_LOOPS | gm.GM_PREP_SYMMETRIZE,
                               layouts=gm.GM_LAYOUT_OUT)
     g_dir = gm.Graph.from_coo(n, s, d, w=w, prep=gm.GM_PREP_DROP_SELF_LOOPS,
