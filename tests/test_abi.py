@@ -143,3 +143,37 @@ def test_binding_refuses_host_tensors():
     with pytest.raises(ValueError, match="device tensor"):
         gm._dev(torch.zeros(4, dtype=torch.float32), "vprop", 4, gm._F32)
     assert gm._dev(None, "active_out", 4, gm._I32) is None
+
+
+class _DeviceStandIn:
+    """Reports a device tensor's attributes without a GPU (the binding's
+    checks read only these)."""
+
+    def __init__(self, dtype, numel, contiguous=True):
+        import types
+        self.device = types.SimpleNamespace(type="cuda")
+        self.dtype, self._n, self._c = dtype, numel, contiguous
+
+    def numel(self):
+        return self._n
+
+    def is_contiguous(self):
+        return self._c
+
+    def data_ptr(self):
+        return 0x1000
+
+
+def test_binding_checks_dtype_length_and_layout():
+    import torch
+    ok = _DeviceStandIn(torch.int32, 10)
+    assert gm._dev(ok, "vprop", 10, gm._I32) == 0x1000
+    assert gm._dev(_DeviceStandIn(torch.uint32, 10), "vprop", 10, gm._I32) == 0x1000
+    with pytest.raises(ValueError, match="elements"):
+        gm._dev(ok, "vprop", 11, gm._I32)
+    with pytest.raises(ValueError, match="dtype"):
+        gm._dev(_DeviceStandIn(torch.float32, 10), "vprop", 10, gm._I32)
+    with pytest.raises(ValueError, match="dtype"):
+        gm._dev(_DeviceStandIn(torch.int32, 10), "counts", 10, gm._U64)
+    with pytest.raises(ValueError, match="contiguous"):
+        gm._dev(_DeviceStandIn(torch.float32, 10, contiguous=False), "hist", 10, gm._F32)
