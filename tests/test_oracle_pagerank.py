@@ -184,3 +184,14 @@ def test_pagerank_step_rows_is_one_superstep():
     indeg = np.bincount(dst, minlength=n)
     z = np.flatnonzero(indeg == 0)[:3]
     assert np.allclose(oracle.pagerank_step_rows(hist[2], outdeg, src, dst, z), 0.15)
+
+
+def test_edgeless_graph_closed_forms():
+    # no in-edges anywhere: Eq. (1) gives r at every vertex from the first
+    # superstep on; personalised, r at the seed and 0 elsewhere
+    none = np.zeros(0, np.int32)
+    g = oracle.prepare(7, none, none)
+    for T in (1, 5):
+        assert np.array_equal(oracle.pagerank(g, 0.15, T), np.full(7, 0.15))
+        ppr = oracle.personalized_pagerank(g, 4, 0.15, T)
+        assert np.array_equal(ppr, np.where(np.arange(7) == 4, 0.15, 0.0))

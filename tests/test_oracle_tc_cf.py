@@ -173,3 +173,16 @@ def test_cf_gradient_matches_gd_update():
     np.add.at(sv, R.item, e[:, None] * PU64[R.user])
     assert np.allclose(PU64 + gamma * (su - lam * PU64), PU64 - gamma / 2 * gU, rtol=1e-12)
     assert np.allclose(PV64 + gamma * (sv - lam * PV64), PV64 - gamma / 2 * gV, rtol=1e-12)
+
+
+def test_cf_without_ratings_is_the_l2_term():
+    # Eq. (3) with no rating: loss = lambda (|P_U|^2 + |P_V|^2), gradients 2 lambda P
+    rng = np.random.default_rng(4)
+    PU = rng.normal(size=(3, 5)).astype(np.float32)
+    PV = rng.normal(size=(2, 5)).astype(np.float32)
+    none = np.zeros(0, np.int32)
+    L, gU, gV = oracle.cf_loss_grad(3, 2, none, none, np.zeros(0, np.uint8), PU, PV, 0.05)
+    l2 = float((PU.astype(np.float64) ** 2).sum() + (PV.astype(np.float64) ** 2).sum())
+    assert L == pytest.approx(0.05 * l2, rel=1e-12)
+    assert np.allclose(gU, 0.1 * PU.astype(np.float64), rtol=1e-12, atol=0)
+    assert np.allclose(gV, 0.1 * PV.astype(np.float64), rtol=1e-12, atol=0)
