@@ -61,7 +61,10 @@ def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
-            build()
+            # built only by __graft_entry__.build() (or build() called
+            # directly): a process that already uses the GPU never starts a
+            # compiler
+            raise RuntimeError("%s is not built: run __graft_entry__.build()" % _LIB)
         lib = ctypes.CDLL(_LIB)
         i32, i64, u64, f64, vp = (
             ctypes.c_int32,

@@ -46,7 +46,10 @@ def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
-            build()
+            # built only by __graft_entry__.build() (or build() called
+            # directly): a process that already uses the GPU never starts a
+            # compiler
+            raise RuntimeError("%s is not built: run __graft_entry__.build()" % _LIB)
         lib = ctypes.CDLL(_LIB)
         i32, i64, f64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
         lib.orc_bfs.argtypes = [i64, vp, vp, i64, vp, vp]
@@ -205,7 +208,9 @@ def pagerank_history(g: Graph, r: float = 0.15, T: int = 20, w: np.ndarray | Non
 
     PR^{t+1}(v) = r*tele(v) + (1-r) * sum_{u->v} w_uv PR^t(u)/outdeg(u), with
     tele = 1 and w = 1 by default (exactly Eq. (1)); PR^0 = 1 (Sec. 3 I).
-    w is given in the out-adjacency (CSR) edge order of g.
+    w is given in the out-adjacency (CSR) edge order of g; alternatively a
+    prebuilt in-adjacency g_in may carry the edge values in its own order (g
+    then serves only for the out-degrees).
     """
     n = g.n
     if w is not None:
@@ -214,7 +219,8 @@ def pagerank_history(g: Graph, r: float = 0.15, T: int = 20, w: np.ndarray | Non
     else:
         if g_in is None:
             g_in = g.transpose()
-        in_w = None
+        # edge values may come with a prebuilt in-adjacency (in its own order)
+        in_w = None if g_in.w is None else np.ascontiguousarray(g_in.w, dtype=np.float64)
     outdeg = np.ascontiguousarray(np.diff(g.off).astype(np.int64))
     tele = np.ones(n) if tele is None else np.asarray(tele, dtype=np.float64)
     hist = np.empty((T + 1, n), dtype=np.float64)

@@ -187,7 +187,7 @@ def test_sssp_rmat14_certificate_and_bsp():
     act[0] = True
     out, act_out, iters = oracle.run_min_program(g, prop, act, weighted=True)
     assert np.array_equal(out, dist) and not act_out.any()
-    assert 5 <= iters <= 40
+    assert 5 <= iters <= 40  # exact counts are pinned on the hand-worked trace below
 
 
 def test_bsp_resume_equals_uninterrupted():
@@ -248,3 +248,23 @@ SAT_DIST = [0, 4_000_000_000, INF_U, INF_U - 1, INF_U - 1, 2**31]
 def test_sssp_saturates_at_uint32_max():
     g = graph_from_pairs(6, SAT_PAIRS, w=SAT_W)
     assert oracle.sssp(g, 0).tolist() == SAT_DIST
+
+
+def test_sssp_superstep_trace_hand_worked():
+    """Alg. 2 supersteps of SSSP on the hand-worked graph of
+    golden/sssp_supersteps_hand.txt: distances and active set after every
+    superstep, and the exact superstep count (5), which the GPU tests then
+    require of the GPU run."""
+    from tests import workloads as W
+    n, s, d, w, src, trace, steps = W.sssp_hand_trace()
+    g = oracle.prepare(n, s, d, w=w)
+    prop = np.full(n, INF_U, dtype=np.uint32)
+    prop[src] = 0
+    act = np.zeros(n, dtype=bool)
+    act[src] = True
+    for k, (dist_k, act_k) in enumerate(trace, start=1):
+        p, a, it = oracle.run_min_program(g, prop, act, weighted=True, max_iters=k)
+        assert it == k and np.array_equal(p, dist_k) and np.array_equal(a, act_k), k
+    p, a, it = oracle.run_min_program(g, prop, act, weighted=True)
+    assert it == steps == 5 and not a.any()
+    assert np.array_equal(p, oracle.sssp(g, src)) and np.array_equal(p, trace[-1][0])

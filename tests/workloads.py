@@ -6,6 +6,7 @@ only from the oracle.
 from __future__ import annotations
 
 import functools
+import os
 
 import numpy as np
 
@@ -70,3 +71,32 @@ def max_rel_err(got, ref) -> float:
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     return float(np.max(np.abs(got - ref) / np.abs(ref))) if len(ref) else 0.0
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def sssp_hand_trace():
+    """The hand-worked SSSP superstep trace of golden/sssp_supersteps_hand.txt:
+    (n, src, dst, w, source, [(dist after k, active set after k), ...], supersteps)."""
+    trace, n, src, dst, w, source, steps = [], 0, [], [], [], 0, 0
+    for line in open(os.path.join(GOLDEN, "sssp_supersteps_hand.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if f[0] == "edges":
+            e = np.array(f[1:], dtype=np.int64).reshape(-1, 3)
+            src, dst, w = e[:, 0].astype(np.int32), e[:, 1].astype(np.int32), e[:, 2].astype(np.uint32)
+        elif f[0] == "n":
+            n = int(f[1])
+        elif f[0] == "source":
+            source = int(f[1])
+        elif f[0] == "after":
+            a = f.index("active")
+            dist = np.array([oracle.INF_U32 if x == "-" else int(x) for x in f[3:a]], np.uint32)
+            act = np.zeros(n, dtype=bool)
+            act[[int(x) for x in f[a + 1:]]] = True
+            trace.append((dist, act))
+        elif f[0] == "supersteps":
+            steps = int(f[1])
+    return n, src, dst, w, source, trace, steps
