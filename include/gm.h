@@ -171,11 +171,38 @@ typedef struct gm_program {
   uint32_t flags; /* reserved, must be 0 */
 } gm_program;
 
-/* Initially active vertices: `count` distinct ids in device memory. */
+/* Initially active vertices: the sparse input vector x of Alg. 1. Either
+ * `count` distinct ids (device int32, `ids`), or the bitvector form of
+ * Sec. 4.4.2 (`bitmap`: device uint32 words, ceil(n / 32) of them, bit
+ * v % 32 of word v / 32 set for an active v; bits at or past n are
+ * ignored). Exactly one of the two forms names the vertices: a non-NULL
+ * bitmap needs ids == NULL and count == 0. */
 typedef struct gm_frontier {
   const int32_t* ids;
   int64_t count;
+  const uint32_t* bitmap;
 } gm_frontier;
+
+/*
+ * Build, now, the per-graph schedules a program run needs, which a first
+ * run would otherwise build: the frontier workspace of BFS and SSSP, the
+ * relabelled pull layout of PageRank and PPR (Sec. 4.4.1 stores the matrix
+ * once in the layout its SpMV reads; this is that step), the owner/partner
+ * work plan of triangle counting (Sec. 4.2, program 2). Lets a caller time
+ * preprocessing and runs apart. prog->kind selects the program; the other
+ * fields are ignored. Errors: GM_ESTATE; GM_EINVAL (prog NULL, unknown
+ * kind); GM_EUNSUPPORTED (as the run would report); GM_ENOMEM; GM_EHIP.
+ * Synchronises `stream`.
+ */
+gm_status gm_graph_prepare(gm_graph g, const gm_program* prog, void* stream);
+
+/*
+ * Free every per-graph schedule and workspace built by runs or
+ * gm_graph_prepare (the graph's own adjacency layouts stay); later runs
+ * build them again. Captured plans that use g become stale. Errors:
+ * GM_ESTATE. Waits for the device.
+ */
+gm_status gm_graph_release(gm_graph g);
 
 /*
  * Run a vertex program (Alg. 2) on graph g. The caller initialises the
@@ -191,11 +218,14 @@ typedef struct gm_frontier {
  * active_out (device int32 of n entries, may be NULL) marks, with 1, the
  * vertices still active afterwards, so a later call can resume from
  * (vprop, active) exactly.
+ * BFS and SSSP accept either frontier form (ids or bitmap); PPR takes its
+ * seed from ids only.
  * Errors: GM_ESTATE; GM_EINVAL (prog/vprop NULL, unknown kind, order not
  * OUT, flags != 0, frontier missing or count < 0 or ids NULL with
- * count > 0, an id out of range, PageRank with max_iters <= 0, r outside
- * [0, 1]); GM_EUNSUPPORTED (program needs a layout or weight type the
- * graph lacks); GM_ENOMEM; GM_EHIP.
+ * count > 0, both ids and bitmap given, a bitmap for PPR, an id out of
+ * range, PageRank with max_iters <= 0, r outside [0, 1]); GM_EUNSUPPORTED
+ * (program needs a layout or weight type the graph lacks); GM_ENOMEM;
+ * GM_EHIP.
  * BFS and SSSP synchronise `stream` once per superstep; PageRank is
  * asynchronous.
  */
@@ -327,6 +357,32 @@ gm_status gm_pagerank_vjp_w(gm_graph g, const float* w, float r, int32_t T, cons
  */
 gm_status gm_graph_union(const gm_graph* parts, int32_t count, void* stream, gm_graph* out);
 
+/*
+ * One program run over several graphs at once (the mixed batch): the graphs
+ * (host array of `count` live handles with equal prep, wtype and layouts)
+ * are joined into their block-diagonal union (as gm_graph_union), the
+ * program runs once on the union - every generalized SpMV of Alg. 1 serves
+ * all graphs - and each graph's part of the result is written to its own
+ * property array. Graph i's result equals gm_run_vertex_program on graph i
+ * alone. vprops: host array of `count` device pointers, vprops[i] holding
+ * n_i entries of the program's type, initialised by the caller as for
+ * gm_run_vertex_program (BFS, SSSP, PageRank, TC; PPR is not supported).
+ * sources: host array of `count` ids, sources[i] in [0, n_i) the initially
+ * active vertex of graph i or -1 for none (BFS, SSSP); NULL for PageRank and
+ * TC. max_iters as for gm_run_vertex_program. *iters_done (host, may be
+ * NULL): supersteps run, the largest count of any graph. The union and a
+ * property array for it are built by the call (device allocations and
+ * copies proportional to the graphs' sizes); callers that repeat the same
+ * batch keep a union (gm_graph_union) and record its runs in a plan.
+ * Errors: GM_EINVAL (NULL arrays, count < 1, differing prep/wtype/layouts, a
+ * source out of range, the run's own argument errors); GM_ESTATE (a handle
+ * not live); GM_EUNSUPPORTED (rating graphs, PPR, a layout or weight type
+ * missing, union too large); GM_ENOMEM; GM_EHIP. Synchronises `stream`.
+ */
+gm_status gm_run_multi_graph(const gm_graph* graphs, int32_t count, const gm_program* prog,
+                             const int32_t* sources, void* const* vprops, int32_t max_iters,
+                             int32_t* iters_done, void* stream);
+
 /* One run recorded in a plan. */
 typedef struct gm_plan_run {
   gm_graph g;
@@ -428,14 +484,24 @@ gm_status gm_graph_set_tuning(gm_graph g, const gm_tuning* t);
  * batched selects gm_run_batched semantics with `count` = k sources; ids are
  * device sources / frontier ids as for the corresponding call (NULL for
  * PageRank and TC); max_iters as for that call (> 0 for PageRank and PPR).
+ * The paper's only tunables are its thread and partition counts (Sec. 5.1,
+ * 8x threads partitions); these are the GPU equivalents.
  * The library allocates the outputs of the trial runs. chosen (host, may be
  * NULL) receives the parameters kept, which stay set on g.
- * Errors: as the corresponding call; GM_EINVAL (trials outside [1, 100]);
+ * cache_path (host string, may be NULL): a JSON file of earlier choices,
+ * keyed by the device architecture, the program (kind, batched, k) and the
+ * graph's shape (log2 of n, log2 of the average degree, rounded). If it
+ * holds the key, those values are set without timing anything; otherwise
+ * the tuner runs and the file is rewritten with the new entry added (a
+ * missing file is created). The file is an object of entries
+ * "key": {"field": value, ...}, one per line.
+ * Errors: as the corresponding call; GM_EINVAL (trials outside [1, 100], a
+ * cache file that cannot be parsed or written, stored values out of range);
  * GM_ENOMEM; GM_EHIP. Synchronises `stream`.
  */
 gm_status gm_autotune(gm_graph g, const gm_program* prog, int32_t batched, const int32_t* ids,
-                      int64_t count, int32_t max_iters, int32_t trials, gm_tuning* chosen,
-                      void* stream);
+                      int64_t count, int32_t max_iters, int32_t trials, const char* cache_path,
+                      gm_tuning* chosen, void* stream);
 
 /* Counters of the last gm_run_vertex_program call on a graph. */
 typedef struct gm_run_stats {

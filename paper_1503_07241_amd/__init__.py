@@ -181,6 +181,16 @@ class Graph:
         _lib.check(_lib.load().gm_graph_set_tuning(self.handle, ctypes.byref(t)),
                    "gm_graph_set_tuning")
 
+    def prepare(self, kind: int, stream=None) -> None:
+        """gm_graph_prepare: build now the schedules a run of `kind` needs."""
+        prog = _lib.gm_program(kind, GM_ORDER_OUT, 0.15, 0)
+        _lib.check(_lib.load().gm_graph_prepare(self.handle, ctypes.byref(prog), _stream(stream)),
+                   "gm_graph_prepare")
+
+    def release(self) -> None:
+        """gm_graph_release: free the per-graph schedules and workspaces."""
+        _lib.check(_lib.load().gm_graph_release(self.handle), "gm_graph_release")
+
     def last_run_stats(self) -> _lib.gm_run_stats:
         st = _lib.gm_run_stats()
         _lib.check(_lib.load().gm_last_run_stats(self.handle, ctypes.byref(st)),
@@ -200,15 +210,21 @@ class Graph:
 
 
 def run_vertex_program(g: Graph, kind: int, frontier, max_iters: int, vprop, active_out=None,
-                       r: float = 0.15, stream=None) -> int:
+                       r: float = 0.15, stream=None, bitmap=None) -> int:
     """gm_run_vertex_program. frontier: device int32 tensor of active ids (or
-    None for PageRank); vprop: device property tensor (int32 levels, uint32
-    distances as int32 storage, float32 ranks). Returns supersteps done."""
+    None for PageRank); bitmap: instead of ids, a device int32/uint32 tensor
+    of ceil(n / 32) words with bit v set for an active v; vprop: device
+    property tensor (int32 levels, uint32 distances as int32 storage, float32
+    ranks). Returns supersteps done."""
     prog = _lib.gm_program(kind, GM_ORDER_OUT, r, 0)
-    fr = None
-    if frontier is not None:
-        fr = _lib.gm_frontier(_dev(frontier, "frontier", 0, _I32), frontier.numel())
     n = g.n
+    fr = None
+    if bitmap is not None:
+        if frontier is not None:
+            raise ValueError("give frontier ids or a bitmap, not both")
+        fr = _lib.gm_frontier(None, 0, _dev(bitmap, "bitmap", (n + 31) // 32, _I32))
+    elif frontier is not None:
+        fr = _lib.gm_frontier(_dev(frontier, "frontier", 0, _I32), frontier.numel(), None)
     pv = _dev(vprop, "vprop", n, _U64 if kind == GM_PROG_TC else
               _F32 if kind in (GM_PROG_PAGERANK, GM_PROG_PPR) else _I32)
     it = ctypes.c_int32(0)
@@ -245,21 +261,48 @@ def run_batched(g: Graph, kind: int, sources, max_iters: int, vprop_block, r: fl
     return it.value
 
 
+def run_multi_graph(graphs, kind: int, sources, vprops, max_iters: int, r: float = 0.15,
+                    stream=None) -> int:
+    """gm_run_multi_graph: one run of `kind` over all graphs (their
+    block-diagonal union); vprops[i] is graph i's device property tensor,
+    initialised by the caller; sources: one id per graph (-1: none) for BFS
+    and SSSP, None for PageRank and TC. Returns supersteps run."""
+    k = len(graphs)
+    if len(vprops) != k or (sources is not None and len(sources) != k):
+        raise ValueError("one property tensor (and source) per graph")
+    kinds = (_U64 if kind == GM_PROG_TC else
+             _F32 if kind in (GM_PROG_PAGERANK, GM_PROG_PPR) else _I32)
+    hs = (ctypes.c_void_p * k)(*[g.handle.value for g in graphs])
+    vp = (ctypes.c_void_p * k)(*[_dev(v, "vprops[%d]" % i, graphs[i].n, kinds)
+                                 for i, v in enumerate(vprops)])
+    src = None
+    if sources is not None:
+        src = (ctypes.c_int32 * k)(*[int(x) for x in sources])
+    prog = _lib.gm_program(kind, GM_ORDER_OUT, r, 0)
+    it = ctypes.c_int32(0)
+    _lib.check(_lib.load().gm_run_multi_graph(hs, k, ctypes.byref(prog), src, vp, max_iters,
+                                              ctypes.byref(it), _stream(stream)),
+               "gm_run_multi_graph")
+    return it.value
+
+
 def union_bases(parts) -> np.ndarray:
     """First vertex of each part in their union (plus the total at the end)."""
     return np.concatenate([[0], np.cumsum([p.n for p in parts])]).astype(np.int64)
 
 
 def autotune(g: Graph, kind: int, ids=None, batched: bool = False, max_iters: int = -1,
-             trials: int = 3, r: float = 0.15, stream=None) -> dict:
+             trials: int = 3, r: float = 0.15, stream=None, cache: str | None = None) -> dict:
     """gm_autotune: times the program for candidate schedule parameters and
-    keeps the fastest on g; returns the parameters kept."""
+    keeps the fastest on g; returns the parameters kept. cache: path of a
+    JSON file of earlier choices (read first, extended after tuning)."""
     prog = _lib.gm_program(kind, GM_ORDER_OUT, r, 0)
     t = _lib.gm_tuning()
     count = 0 if ids is None else ids.numel()
+    path = None if cache is None else str(cache).encode()
     _lib.check(_lib.load().gm_autotune(g.handle, ctypes.byref(prog), 1 if batched else 0,
-                                       _dev(ids, "ids", count, _I32), count, max_iters, trials, ctypes.byref(t),
-                                       _stream(stream)), "gm_autotune")
+                                       _dev(ids, "ids", count, _I32), count, max_iters, trials,
+                                       path, ctypes.byref(t), _stream(stream)), "gm_autotune")
     return {f: int(getattr(t, f)) for f in _lib.TUNING_FIELDS}
 
 

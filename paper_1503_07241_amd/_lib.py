@@ -43,7 +43,7 @@ class gm_program(ctypes.Structure):
 
 
 class gm_frontier(ctypes.Structure):
-    _fields_ = [("ids", ctypes.c_void_p), ("count", ctypes.c_int64)]
+    _fields_ = [("ids", ctypes.c_void_p), ("count", ctypes.c_int64), ("bitmap", ctypes.c_void_p)]
 
 
 class gm_run_stats(ctypes.Structure):
@@ -108,7 +108,12 @@ def load():
         "gm_graph_get_tuning": ([vp, ctypes.POINTER(gm_tuning)], i32),
         "gm_graph_set_tuning": ([vp, ctypes.POINTER(gm_tuning)], i32),
         "gm_autotune": ([vp, ctypes.POINTER(gm_program), i32, vp, i64, i32, i32,
-                         ctypes.POINTER(gm_tuning), vp], i32),
+                         ctypes.c_char_p, ctypes.POINTER(gm_tuning), vp], i32),
+        "gm_graph_prepare": ([vp, ctypes.POINTER(gm_program), vp], i32),
+        "gm_graph_release": ([vp], i32),
+        "gm_run_multi_graph": ([ctypes.POINTER(vp), i32, ctypes.POINTER(gm_program),
+                                ctypes.POINTER(i32), ctypes.POINTER(vp), i32,
+                                ctypes.POINTER(i32), vp], i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)

@@ -7,6 +7,7 @@
 #include <mutex>
 #include <new>
 #include <unordered_set>
+#include <vector>
 
 #include "gm_internal.h"
 
@@ -200,6 +201,58 @@ gm_status gm_graph_destroy(gm_graph g) {
   return ok();
 }
 
+gm_status gm_graph_prepare(gm_graph g, const gm_program* prog, void* stream) {
+  if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
+  if (!prog) return fail(GM_EINVAL, "prog is NULL");
+  if (g->bipartite) return fail(GM_EUNSUPPORTED, "rating graphs take the CF calls only");
+  const int kind = prog->kind;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  switch (kind) {
+    case GM_PROG_BFS:
+      break;
+    case GM_PROG_SSSP:
+      if (g->wtype != GM_W_U32) return fail(GM_EUNSUPPORTED, "SSSP needs uint32 edge weights");
+      break;
+    case GM_PROG_PAGERANK:
+    case GM_PROG_PPR:
+      if (!(g->layouts & GM_LAYOUT_IN)) return fail(GM_EUNSUPPORTED, "PageRank needs GM_LAYOUT_IN");
+      break;
+    case GM_PROG_TC:
+      if (!(g->prep & GM_PREP_UPPER_DAG) || !(g->layouts & GM_LAYOUT_IN))
+        return fail(GM_EUNSUPPORTED, "triangle counting needs GM_PREP_UPPER_DAG and GM_LAYOUT_IN");
+      break;
+    default:
+      return fail(GM_EINVAL, "unknown program kind %d", kind);
+  }
+  return guarded([&]() -> gm_status {
+    if (const gm_status st = check_device(g)) return st;
+    if (kind == GM_PROG_BFS || kind == GM_PROG_SSSP) {
+      prepare_min_program(g, s);
+    } else if (kind == GM_PROG_TC) {
+      prepare_triangle_count(g, s);
+    } else {
+      ensure_pull_schedule(g, s);
+      GM_HIP(hipStreamSynchronize(s));
+    }
+    return ok();
+  });
+}
+
+gm_status gm_graph_release(gm_graph g) {
+  if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
+  return guarded([&]() -> gm_status {
+    if (const gm_status st = check_device(g)) return st;
+    GM_HIP(hipDeviceSynchronize());  // nothing enqueued may still use the buffers
+    free_min_workspace(g);
+    free_pull_schedule(g);
+    free_tc_plan(g);
+    free_batch(g);
+    free_cf_plan(g);
+    free_vjp_plan(g);
+    return ok();
+  });
+}
+
 gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_frontier* frontier,
                                 int32_t max_iters, void* vprop, int32_t* active_out,
                                 int32_t* iters_done, void* stream) {
@@ -240,17 +293,26 @@ gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_fro
   }
   if (kind == GM_PROG_SSSP && g->wtype != GM_W_U32)
     return fail(GM_EUNSUPPORTED, "SSSP needs uint32 edge weights");
+  const uint32_t* bitmap = nullptr;
   if (!dense || kind == GM_PROG_PPR) {
     if (!frontier) return fail(GM_EINVAL, "frontier is NULL");
-    if (frontier->count < 0 || frontier->count > g->n)
-      return fail(GM_EINVAL, "frontier count %lld outside [0, n]", (long long)frontier->count);
-    if (frontier->count > 0 && !frontier->ids) return fail(GM_EINVAL, "frontier ids NULL");
-    if (kind == GM_PROG_PPR && frontier->count < 1) return fail(GM_EINVAL, "PPR needs a seed");
+    if (frontier->bitmap) {
+      if (frontier->ids || frontier->count != 0)
+        return fail(GM_EINVAL, "frontier: give ids or a bitmap, not both");
+      if (kind == GM_PROG_PPR) return fail(GM_EINVAL, "PPR takes its seed from frontier ids");
+      bitmap = frontier->bitmap;
+    } else {
+      if (frontier->count < 0 || frontier->count > g->n)
+        return fail(GM_EINVAL, "frontier count %lld outside [0, n]", (long long)frontier->count);
+      if (frontier->count > 0 && !frontier->ids) return fail(GM_EINVAL, "frontier ids NULL");
+      if (kind == GM_PROG_PPR && frontier->count < 1) return fail(GM_EINVAL, "PPR needs a seed");
+    }
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   return guarded([&]() -> gm_status {
     if (const gm_status st = check_device(g)) return st;
-    if (frontier && frontier->count > 0 && !ids_in_range(frontier->ids, frontier->count, g->n, s))
+    if (frontier && !bitmap && frontier->count > 0 &&
+        !ids_in_range(frontier->ids, frontier->count, g->n, s))
       return fail(GM_EINVAL, "frontier id outside [0, n)");
     int32_t it = 0;
     if (dense) {
@@ -270,7 +332,8 @@ gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_fro
       g->last_stats.pull_supersteps = it;
       g->last_stats.edges_scanned = (unsigned long long)g->m * it;
     } else {
-      it = run_min_program(g, kind, frontier->ids, frontier->count, max_iters,
+      it = run_min_program(g, kind, bitmap ? nullptr : frontier->ids,
+                           bitmap ? 0 : frontier->count, bitmap, max_iters,
                            static_cast<uint32_t*>(vprop), active_out, s, &g->last_stats);
     }
     if (iters_done) *iters_done = it;
@@ -452,6 +515,71 @@ gm_status gm_pagerank_vjp_w(gm_graph g, const float* w, float r, int32_t T, cons
     run_pagerank_vjp(g, w, r, T, hist, grad_out, grad_w, static_cast<hipStream_t>(stream));
     return ok();
   });
+}
+
+gm_status gm_run_multi_graph(const gm_graph* graphs, int32_t count, const gm_program* prog,
+                             const int32_t* sources, void* const* vprops, int32_t max_iters,
+                             int32_t* iters_done, void* stream) {
+  if (!graphs || !vprops || !prog) return fail(GM_EINVAL, "graphs/vprops/prog is NULL");
+  if (count < 1) return fail(GM_EINVAL, "count = %d < 1", count);
+  const int kind = prog->kind;
+  if (kind == GM_PROG_PPR) return fail(GM_EUNSUPPORTED, "PPR is not run over several graphs");
+  if (kind != GM_PROG_BFS && kind != GM_PROG_SSSP && kind != GM_PROG_PAGERANK &&
+      kind != GM_PROG_TC)
+    return fail(GM_EINVAL, "unknown program kind %d", kind);
+  const bool frontier_prog = kind == GM_PROG_BFS || kind == GM_PROG_SSSP;
+  if (frontier_prog && !sources) return fail(GM_EINVAL, "sources is NULL");
+  if (!frontier_prog && sources) return fail(GM_EINVAL, "PageRank and TC take no sources");
+  std::vector<int64_t> base(count + 1, 0);
+  std::vector<int32_t> ids;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!graph_live(graphs[i])) return fail(GM_ESTATE, "graph %d is not live", i);
+    if (!vprops[i]) return fail(GM_EINVAL, "vprops[%d] is NULL", i);
+    base[i + 1] = base[i] + graphs[i]->n;
+    if (frontier_prog) {
+      if (sources[i] < -1 || sources[i] >= graphs[i]->n)
+        return fail(GM_EINVAL, "sources[%d] = %d outside [-1, n_%d)", i, sources[i], i);
+      if (sources[i] >= 0) ids.push_back((int32_t)(base[i] + sources[i]));
+    }
+  }
+  gm_graph u = nullptr;
+  if (const gm_status st = gm_graph_union(graphs, count, stream, &u)) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t elem = kind == GM_PROG_TC ? 8 : 4;
+  void* prop = nullptr;
+  int32_t* dids = nullptr;
+  gm_status st = guarded([&]() -> gm_status {
+    prop = dmalloc((size_t)base[count] * elem);
+    dids = dalloc<int32_t>(ids.size());
+    if (!ids.empty())
+      GM_HIP(hipMemcpyAsync(dids, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, s));
+    for (int32_t i = 0; i < count; ++i)
+      GM_HIP(hipMemcpyAsync(static_cast<char*>(prop) + base[i] * elem, vprops[i],
+                            (size_t)graphs[i]->n * elem, hipMemcpyDeviceToDevice, s));
+    return GM_OK;
+  });
+  if (st == GM_OK) {
+    const gm_frontier fr{dids, (int64_t)ids.size(), nullptr};
+    st = gm_run_vertex_program(u, prog, frontier_prog ? &fr : nullptr, max_iters, prop, nullptr,
+                               iters_done, stream);
+  }
+  if (st == GM_OK) {
+    st = guarded([&]() -> gm_status {
+      for (int32_t i = 0; i < count; ++i)
+        GM_HIP(hipMemcpyAsync(vprops[i], static_cast<char*>(prop) + base[i] * elem,
+                              (size_t)graphs[i]->n * elem, hipMemcpyDeviceToDevice, s));
+      GM_HIP(hipStreamSynchronize(s));
+      return ok();
+    });
+  } else {
+    (void)hipStreamSynchronize(s);
+  }
+  dfree(prop);
+  dfree(dids);
+  char msg[sizeof(g_msg)];
+  std::snprintf(msg, sizeof(msg), "%s", g_msg);  // destroying the union clears it
+  gm_graph_destroy(u);
+  return st == GM_OK ? ok() : fail(st, "%s", msg);
 }
 
 gm_status gm_last_run_stats(gm_graph g, gm_run_stats* out) {

@@ -177,9 +177,10 @@ void ensure_pull_schedule(gm_graph g, hipStream_t s);
 void run_pagerank(gm_graph g, float r, int32_t iters, float* rank, int32_t seed, hipStream_t s);
 
 // Min programs (minprog.hip). Returns supersteps done.
+// The first frontier is `bitmap` (n bits) when non-NULL, else the ids.
 int32_t run_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count,
-                        int32_t max_iters, uint32_t* prop, int32_t* active_out, hipStream_t s,
-                        RunStats* stats);
+                        const uint32_t* bitmap, int32_t max_iters, uint32_t* prop,
+                        int32_t* active_out, hipStream_t s, RunStats* stats);
 void free_min_workspace(gm_graph g);
 void free_pull_schedule(gm_graph g);
 

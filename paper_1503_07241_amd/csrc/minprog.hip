@@ -108,6 +108,17 @@ __global__ __launch_bounds__(kThreads) void seed_bits(const int32_t* __restrict_
   }
 }
 
+// The caller's frontier bitvector (Sec. 4.4.2) as the first frontier; bits
+// at or past n are dropped.
+__global__ __launch_bounds__(kThreads) void seed_bitmap(const uint32_t* __restrict__ in,
+                                                        int64_t words, int64_t n, uint32_t* bits) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t left = n - 32 * i;  // vertices in this word, >= 1
+    bits[i] = in[i] & (left >= 32 ? 0xFFFFFFFFu : (1u << left) - 1u);
+  }
+}
+
 // SEND: frontier bitvector -> queue (vertex, message, first edge, edge prefix).
 // A thread takes one 32-bit word; for a nonzero word it reads the 33
 // offsets around its 32 vertices at once (independent loads, unrolled), so
@@ -526,8 +537,8 @@ void init_min_prop(gm_graph g, int kind, const int32_t* ids, int64_t count, uint
 }
 
 int32_t run_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count,
-                        int32_t max_iters, uint32_t* prop, int32_t* active_out, hipStream_t s,
-                        RunStats* stats) {
+                        const uint32_t* bitmap, int32_t max_iters, uint32_t* prop,
+                        int32_t* active_out, hipStream_t s, RunStats* stats) {
   Workspace* ws = ensure_ws(g, s);
   const int64_t n = g->n;
   const int64_t words = (n + 31) / 32;
@@ -537,13 +548,16 @@ int32_t run_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count,
   int32_t batch = (int32_t)g->tune.superstep_batch;
   if (batch < 1) batch = 1;
   int cur = 0;
-  if (count > 0) {
+  if (bitmap) {
+    seed_bitmap<<<blocks_for(words), kThreads, 0, s>>>(bitmap, words, n, ws->bits[0]);
+    GM_HIP(hipGetLastError());
+  } else if (count > 0) {
     seed_bits<<<blocks_for(count), kThreads, 0, s>>>(ids, count, ws->bits[0]);
     GM_HIP(hipGetLastError());
   }
   int32_t iters = 0;
   RunStats st{};
-  bool done = count == 0;
+  bool done = count == 0 && !bitmap;  // an empty bitmap ends after one SEND
   while (!done) {
     int32_t nb = batch;
     if (max_iters > 0 && max_iters - iters < nb) nb = max_iters - iters;

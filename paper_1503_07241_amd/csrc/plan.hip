@@ -10,9 +10,15 @@
 //  - gm_autotune: coordinate descent over the schedule parameters of a
 //    program, timed with HIP events on the caller's stream.
 #include <algorithm>
+#include <cctype>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <mutex>
+#include <sstream>
+#include <string>
 #include <unordered_set>
 #include <vector>
 
@@ -216,6 +222,135 @@ void from_abi(const gm_tuning& o, Tuning* t) {
   t->pr_hot = o.pr_hot;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner cache: a JSON object of entries "key": {"field": value, ...},
+// one entry per line, fields as in gm_tuning. Only that shape is read.
+// ---------------------------------------------------------------------------
+using TuneCache = std::map<std::string, gm_tuning>;
+
+struct CacheParser {
+  const std::string& t;
+  size_t i = 0;
+  bool ok = true;
+
+  void ws() {
+    while (i < t.size() && std::isspace((unsigned char)t[i])) ++i;
+  }
+  bool eat(char c) {
+    ws();
+    if (i < t.size() && t[i] == c) {
+      ++i;
+      return true;
+    }
+    return false;
+  }
+  void need(char c) {
+    if (!eat(c)) ok = false;
+  }
+  std::string str() {
+    ws();
+    std::string out;
+    if (i >= t.size() || t[i] != '"') {
+      ok = false;
+      return out;
+    }
+    for (++i; i < t.size() && t[i] != '"'; ++i) out += t[i];
+    if (i >= t.size()) ok = false;
+    ++i;
+    return out;
+  }
+  uint64_t num() {
+    ws();
+    uint64_t v = 0;
+    const size_t b = i;
+    while (i < t.size() && std::isdigit((unsigned char)t[i]) && v <= UINT32_MAX)
+      v = v * 10 + (uint64_t)(t[i++] - '0');
+    if (i == b || v > UINT32_MAX) ok = false;
+    return v;
+  }
+};
+
+// Entries of the file at path (an absent file is an empty cache); false if
+// the text is not of the expected shape or a value is out of range.
+bool read_cache(const char* path, TuneCache* out) {
+  std::ifstream f(path);
+  if (!f) return true;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string text = ss.str();
+  CacheParser p{text};
+  p.need('{');
+  if (!p.ok) return false;
+  if (p.eat('}')) return true;
+  do {
+    const std::string key = p.str();
+    p.need(':');
+    p.need('{');
+    gm_tuning t = to_abi(Tuning{});
+    if (!p.eat('}')) {
+      do {
+        const std::string field = p.str();
+        p.need(':');
+        const uint32_t v = (uint32_t)p.num();
+        if (field == "pull_div") t.pull_div = v;
+        else if (field == "superstep_batch") t.superstep_batch = v;
+        else if (field == "push_blocks") t.push_blocks = v;
+        else if (field == "ppr_chunk") t.ppr_chunk = v;
+        else if (field == "tc_wave_max") t.tc_wave_max = v;
+        else if (field == "tc_wave_work") t.tc_wave_work = v;
+        else if (field == "tc_block_work") t.tc_block_work = v;
+        else if (field == "pr_hot") t.pr_hot = v;
+        else p.ok = false;
+      } while (p.ok && p.eat(','));
+      p.need('}');
+    }
+    if (!p.ok || check_tuning(t) != GM_OK) return false;
+    (*out)[key] = t;
+  } while (p.eat(','));
+  p.need('}');
+  return p.ok;
+}
+
+bool write_cache(const char* path, const TuneCache& c) {
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream f(tmp, std::ios::trunc);
+    if (!f) return false;
+    f << "{\n";
+    size_t k = 0;
+    for (const auto& e : c) {
+      const gm_tuning& t = e.second;
+      f << "  \"" << e.first << "\": {\"pull_div\": " << t.pull_div
+        << ", \"superstep_batch\": " << t.superstep_batch << ", \"push_blocks\": " << t.push_blocks
+        << ", \"ppr_chunk\": " << t.ppr_chunk << ", \"tc_wave_max\": " << t.tc_wave_max
+        << ", \"tc_wave_work\": " << t.tc_wave_work << ", \"tc_block_work\": " << t.tc_block_work
+        << ", \"pr_hot\": " << t.pr_hot << "}" << (++k < c.size() ? "," : "") << "\n";
+    }
+    f << "}\n";
+    if (!f) return false;
+  }
+  return std::rename(tmp.c_str(), path) == 0;
+}
+
+// Cache key: device architecture, program, and the graph's shape (log2 n,
+// log2 of the average degree, rounded).
+std::string cache_key(gm_graph g, int kind, bool batched, int64_t k) {
+  hipDeviceProp_t prop;
+  GM_HIP(hipGetDeviceProperties(&prop, g->device));
+  std::string arch = prop.gcnArchName;
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch.resize(colon);
+  static const char* const names[] = {"?", "bfs", "sssp", "pagerank", "ppr", "tc"};
+  const char* name = kind >= 1 && kind <= 5 ? names[kind] : names[0];
+  const int ln = (int)std::lround(std::log2((double)std::max<int64_t>(g->n, 1)));
+  const double avg = (double)std::max<int64_t>(g->m, 1) / (double)std::max<int64_t>(g->n, 1);
+  const int ld = (int)std::lround(std::log2(avg));
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "%s|%s|batched=%d|k=%lld|log2n=%d|log2deg=%d", arch.c_str(), name,
+                batched ? 1 : 0, (long long)k, ln, ld);
+  return buf;
+}
+
 struct Events {
   hipEvent_t a = nullptr, b = nullptr;
   Events() {
@@ -259,7 +394,7 @@ struct Trial {
       uint32_t* prop = static_cast<uint32_t*>(out);
       init_min_prop(g, kind, ids, count, prop, s);
       RunStats st{};
-      run_min_program(g, kind, ids, count, max_iters, prop, nullptr, s, &st);
+      run_min_program(g, kind, ids, count, nullptr, max_iters, prop, nullptr, s, &st);
     } else if (kind == GM_PROG_PAGERANK) {
       fill_f32(static_cast<float*>(out), g->n, 1.0f, s);
       run_pagerank(g, r, max_iters, static_cast<float*>(out), -1, s);
@@ -471,8 +606,8 @@ gm_status gm_graph_set_tuning(gm_graph g, const gm_tuning* t) {
 }
 
 gm_status gm_autotune(gm_graph g, const gm_program* prog, int32_t batched, const int32_t* ids,
-                      int64_t count, int32_t max_iters, int32_t trials, gm_tuning* chosen,
-                      void* stream) {
+                      int64_t count, int32_t max_iters, int32_t trials, const char* cache_path,
+                      gm_tuning* chosen, void* stream) {
   if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
   if (!prog) return fail(GM_EINVAL, "prog is NULL");
   if (trials < 1 || trials > 100) return fail(GM_EINVAL, "trials = %d outside [1, 100]", trials);
@@ -497,6 +632,21 @@ gm_status gm_autotune(gm_graph g, const gm_program* prog, int32_t batched, const
     if (ids && count > 0 && !ids_in_range(ids, count, g->n, s))
       return fail(GM_EINVAL, "id outside [0, n)");
     const int64_t k = batched ? count : 1;
+    TuneCache cache;
+    std::string key;
+    if (cache_path) {
+      if (!read_cache(cache_path, &cache))
+        return fail(GM_EINVAL, "tuning cache %s: not an object of tuning entries", cache_path);
+      key = cache_key(g, kind, batched != 0, k);
+      const auto hit = cache.find(key);
+      if (hit != cache.end()) {
+        const Tuning before = g->tune;
+        from_abi(hit->second, &g->tune);
+        if (std::memcmp(&before, &g->tune, sizeof(Tuning)) != 0) ++g->ws_gen;
+        if (chosen) *chosen = to_abi(g->tune);
+        return ok();
+      }
+    }
     const size_t elem = kind == GM_PROG_TC ? 8 : 4;
     Scratch out;
     out.p = dmalloc((size_t)g->n * k * elem);
@@ -549,6 +699,11 @@ gm_status gm_autotune(gm_graph g, const gm_program* prog, int32_t batched, const
     GM_HIP(hipStreamSynchronize(s));
     if (std::memcmp(&before, &g->tune, sizeof(Tuning)) != 0) ++g->ws_gen;
     if (chosen) *chosen = to_abi(g->tune);
+    if (cache_path) {
+      cache[key] = to_abi(g->tune);
+      if (!write_cache(cache_path, cache))
+        return fail(GM_EINVAL, "tuning cache %s: cannot be written", cache_path);
+    }
     return ok();
   });
 }

@@ -24,6 +24,11 @@
 #include <algorithm>
 #include <vector>
 
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+#include <rocprim/device/device_select.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
+
 #include "gm_internal.h"
 
 namespace gm {
@@ -467,7 +472,340 @@ __global__ void zero_u64(unsigned long long* __restrict__ a, int64_t n) {
     a[i] = 0;
 }
 
+// ---------------------------------------------------------------------------
+// Work plan, built on the device from the DAG's in-adjacency (rocPRIM's
+// radix sort, scan and select as library primitives; every step of the plan
+// is one of the kernels below).
+//
+// For DAG edge (u -> v), u < v: in(u) ∩ in(v) = in(u) ∩ (in(v) ∩ [0, u)).
+// Either v owns it (its table holds in(v); lanes stream in(u), |in(u)|
+// elements, credit to v = the owner) or u owns it (table in(u); lanes stream
+// the prefix of in(v) below u, credit to the partner v). The cheaper stream
+// decides; an edge with nothing to stream closes no triangle. Streams stop
+// at the owner's id in both cases, since in(x) holds only ids below x.
+// Each owner's partners are ordered by decreasing stream length (ties in
+// in-edge order), so that the lanes of a window walk lists of similar length.
+// ---------------------------------------------------------------------------
+constexpr int kPlanThreads = 256;
+
+inline unsigned plan_grid(int64_t n) {
+  int64_t b = (n + kPlanThreads - 1) / kPlanThreads;
+  if (b < 1) b = 1;
+  if (b > 65536) b = 65536;
+  return (unsigned)b;
+}
+
+inline int bits_for(uint64_t x) {  // smallest b with 2^b >= x
+  int b = 0;
+  while (b < 63 && (1ull << b) < x) ++b;
+  return b;
+}
+
+// Table class of an owner with d in-neighbours (wave_max: the longest in-list
+// that gets a per-wavefront table).
+__device__ __host__ inline int tc_class(uint32_t d, uint32_t wave_max) {
+  if (d <= wave_max) return d <= kTcClass[0].max_d ? 0 : 1;
+  int c = 2;
+  while (d > kTcClass[c].max_d) ++c;
+  return c;
+}
+
+// Row of in-edge j: the last v with off[v] <= j.
+__device__ inline uint32_t row_of(const uint32_t* __restrict__ off, int64_t n, uint32_t j) {
+  int64_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= j)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return (uint32_t)lo;
+}
+
+// First position in [b, e) of a sorted id array holding a value >= x.
+__device__ inline uint32_t lower_pos(const int32_t* __restrict__ a, uint32_t b, uint32_t e,
+                                     int32_t x) {
+  while (b < e) {
+    const uint32_t mid = b + ((e - b) >> 1);
+    if (a[mid] < x)
+      b = mid + 1;
+    else
+      e = mid;
+  }
+  return b;
+}
+
+// One thread per in-edge j (u = in_idx[j] -> v = row of j): the sort key
+// (owner, decreasing stream length) and the work entry (partner, with the
+// credit flag when the partner receives the count). Edges with nothing to
+// stream get a key past every owner.
+__global__ void plan_edges(const uint32_t* __restrict__ in_off, const int32_t* __restrict__ in_idx,
+                           int64_t n, int64_t m, int cb, unsigned long long* __restrict__ key,
+                           uint32_t* __restrict__ val) {
+  const unsigned long long cmask = (1ull << cb) - 1;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < m;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t v = row_of(in_off, n, (uint32_t)j);
+    const int32_t u = in_idx[j];
+    const uint32_t a = in_off[u + 1] - in_off[u];  // |in(u)|
+    const uint32_t b = (uint32_t)j - in_off[v];    // |in(v) ∩ [0, u)|
+    if (a == 0 || b == 0) {
+      key[j] = ((unsigned long long)n << cb) | cmask;
+      val[j] = 0;
+      continue;
+    }
+    const bool by_u = b < a;
+    const uint32_t owner = by_u ? (uint32_t)u : v;
+    const uint32_t cost = by_u ? b : a;
+    key[j] = ((unsigned long long)owner << cb) | (cmask - cost);
+    val[j] = by_u ? (v | kCreditPartner) : (uint32_t)u;
+  }
+}
+
+// work_off[x] = first sorted entry of owner x (x = n: the number of entries).
+__global__ void plan_owner_offsets(const unsigned long long* __restrict__ key, int64_t m, int cb,
+                                   int64_t n, uint32_t* __restrict__ work_off) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x <= n;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long t = (unsigned long long)x << cb;
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (key[mid] < t)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    work_off[x] = (uint32_t)lo;
+  }
+}
+
+// Sorted entries -> work entries and stream lengths.
+__global__ void plan_work(const unsigned long long* __restrict__ key,
+                          const uint32_t* __restrict__ val, int64_t w, int cb,
+                          uint32_t* __restrict__ work, uint32_t* __restrict__ wlen) {
+  const unsigned long long cmask = (1ull << cb) - 1;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < w;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    work[j] = val[j];
+    wlen[j] = (uint32_t)(cmask - (key[j] & cmask));
+  }
+}
+
+// Owner of every work entry (binary search over the offsets).
+__device__ inline uint32_t owner_of(const uint32_t* __restrict__ work_off, int64_t n, uint32_t j) {
+  return row_of(work_off, n, j);
+}
+
+// Work items of the owners with a table in LDS: an owner's partners are cut
+// where the streamed elements before a partner cross a multiple of the
+// class's budget (so an item streams at most budget + its last partner's
+// length). flag[j] = 1 where an item starts.
+__global__ void plan_item_flags(const uint32_t* __restrict__ work_off, int64_t n, int64_t w,
+                                const uint32_t* __restrict__ in_off,
+                                const unsigned long long* __restrict__ pre, uint32_t wave_max,
+                                uint32_t wave_work, uint32_t block_work,
+                                uint8_t* __restrict__ flag) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < w;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t x = owner_of(work_off, n, (uint32_t)j);
+    const int c = tc_class(in_off[x + 1] - in_off[x], wave_max);
+    uint8_t f = 0;
+    if (kTcClass[c].kind != kSplitTable) {
+      const unsigned long long budget = kTcClass[c].kind == kWaveTable ? wave_work : block_work;
+      const uint32_t p0 = work_off[x];
+      f = (uint32_t)j == p0 ||
+          (pre[j] - pre[p0]) / budget != (pre[j - 1] - pre[p0]) / budget;
+    }
+    flag[j] = f;
+  }
+}
+
+// Items from their first entries: owner, partner range, the sort key (class,
+// decreasing partner count: the largest items of a class start first), and
+// the per-class item counts.
+__global__ void plan_items(const uint32_t* __restrict__ start, int64_t nitems,
+                           const uint32_t* __restrict__ work_off, int64_t n,
+                           const uint32_t* __restrict__ in_off, uint32_t wave_max,
+                           Item* __restrict__ items, unsigned long long* __restrict__ skey,
+                           uint32_t* __restrict__ sidx, uint32_t* __restrict__ class_count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nitems;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t j = start[i];
+    const uint32_t x = owner_of(work_off, n, j);
+    uint32_t end = work_off[x + 1];
+    if (i + 1 < nitems && start[i + 1] < end) end = start[i + 1];
+    const int c = tc_class(in_off[x + 1] - in_off[x], wave_max);
+    items[i] = Item{(int32_t)x, j, end, 0};
+    skey[i] = ((unsigned long long)c << 32) | (0xFFFFFFFFu - (end - j));
+    sidx[i] = (uint32_t)i;
+    atomicAdd(&class_count[c], 1u);
+  }
+}
+
+template <class T>
+__global__ void plan_gather(const T* __restrict__ src, const uint32_t* __restrict__ idx, int64_t n,
+                            T* __restrict__ dst) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[idx[i]];
+}
+
+// Owners whose in-list is cut into pieces (class kSplitTable) and have partners.
+__global__ void plan_split_flags(const uint32_t* __restrict__ in_off,
+                                 const uint32_t* __restrict__ work_off, int64_t n,
+                                 uint32_t wave_max, uint8_t* __restrict__ flag) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+       x += (int64_t)gridDim.x * blockDim.x)
+    flag[x] = kTcClass[tc_class(in_off[x + 1] - in_off[x], wave_max)].kind == kSplitTable &&
+              work_off[x + 1] > work_off[x];
+}
+
+// One piece of a split owner: in(x) positions [tb, te) (absolute), ids
+// [lo, hi), partners [p0, p0 + np); its (partner, piece) pairs start at base.
+struct PieceSeg {
+  int32_t owner;
+  uint32_t tb, te;
+  int32_t lo, hi;
+  uint32_t p0, np;
+  uint32_t base;
+};
+
+__global__ void plan_seg_bounds(PieceSeg* __restrict__ seg, int64_t nseg,
+                                const uint32_t* __restrict__ in_off,
+                                const int32_t* __restrict__ in_idx) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nseg;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    PieceSeg s = seg[i];
+    s.lo = in_idx[s.tb];
+    s.hi = s.te < in_off[s.owner + 1] ? in_idx[s.te] : s.owner;
+    seg[i] = s;
+  }
+}
+
+__device__ inline uint32_t seg_of(const PieceSeg* __restrict__ seg, int64_t nseg, uint32_t p) {
+  int64_t lo = 0, hi = nseg;  // the last segment with base <= p
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (seg[mid].base <= p)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return (uint32_t)lo;
+}
+
+// One thread per (piece, partner) pair: where the partner's in-list enters
+// the piece's id range [lo, hi) and how many of its elements lie in it.
+__global__ void plan_pairs(const PieceSeg* __restrict__ seg, int64_t nseg, int64_t npairs,
+                           const uint32_t* __restrict__ work, const uint32_t* __restrict__ in_off,
+                           const int32_t* __restrict__ in_idx, uint32_t* __restrict__ pstart,
+                           uint32_t* __restrict__ plen) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npairs;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const PieceSeg s = seg[seg_of(seg, nseg, (uint32_t)p)];
+    const uint32_t y = work[s.p0 + ((uint32_t)p - s.base)] & ~kCreditPartner;
+    const uint32_t b = in_off[y], e = in_off[y + 1];
+    const uint32_t f = lower_pos(in_idx, b, e, s.lo);
+    pstart[p] = f;
+    plen[p] = lower_pos(in_idx, f, e, s.hi) - f;
+  }
+}
+
+__global__ void plan_piece_flags(const PieceSeg* __restrict__ seg, int64_t nseg, int64_t npairs,
+                                 const unsigned long long* __restrict__ pre, uint32_t budget,
+                                 uint8_t* __restrict__ flag) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npairs;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t b = seg[seg_of(seg, nseg, (uint32_t)p)].base;
+    flag[p] = (uint32_t)p == b || (pre[p] - pre[b]) / budget != (pre[p - 1] - pre[b]) / budget;
+  }
+}
+
+__global__ void plan_piece_items(const uint32_t* __restrict__ start, int64_t nitems,
+                                 const PieceSeg* __restrict__ seg, int64_t nseg,
+                                 PieceItem* __restrict__ items,
+                                 unsigned long long* __restrict__ skey,
+                                 uint32_t* __restrict__ sidx) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nitems;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t p = start[i];
+    const PieceSeg s = seg[seg_of(seg, nseg, p)];
+    uint32_t end = s.base + s.np;
+    if (i + 1 < nitems && start[i + 1] < end) end = start[i + 1];
+    items[i] = PieceItem{s.owner, s.p0 + (p - s.base), s.p0 + (end - s.base), s.tb, s.te, s.hi,
+                         p, 0};
+    skey[i] = 0xFFFFFFFFu - (end - p);
+    sidx[i] = (uint32_t)i;
+  }
+}
+
 TcPlan* plan(gm_graph g) { return static_cast<TcPlan*>(g->tc_plan); }
+
+// Device scratch freed at scope exit.
+struct Scratch {
+  void* p = nullptr;
+  Scratch() = default;
+  explicit Scratch(size_t bytes) : p(dmalloc(bytes)) {}
+  Scratch(const Scratch&) = delete;
+  Scratch& operator=(const Scratch&) = delete;
+  ~Scratch() { dfree(p); }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// rocPRIM calls: query the temporary storage, allocate it, run.
+template <class F>
+void with_temp(F&& f, hipStream_t s) {
+  size_t bytes = 0;
+  GM_HIP(f(nullptr, bytes));
+  Scratch tmp(bytes ? bytes : 16);
+  const hipError_t e = f(tmp.p, bytes);
+  if (e == hipSuccess) (void)hipStreamSynchronize(s);  // tmp is freed on return
+  GM_HIP(e);
+}
+
+// Stable sort of (key, index) pairs on the low `bits` bits; returns the
+// buffers holding the result.
+void sort_pairs(Scratch& k1, Scratch& k2, Scratch& v1, Scratch& v2, int64_t n, int bits,
+                hipStream_t s, unsigned long long** kout, uint32_t** vout) {
+  rocprim::double_buffer<unsigned long long> kb(k1.as<unsigned long long>(),
+                                                k2.as<unsigned long long>());
+  rocprim::double_buffer<uint32_t> vb(v1.as<uint32_t>(), v2.as<uint32_t>());
+  if (n > 0)
+    with_temp([&](void* t, size_t& b) {
+      return rocprim::radix_sort_pairs(t, b, kb, vb, (size_t)n, 0, bits, s);
+    }, s);
+  *kout = kb.current();
+  *vout = vb.current();
+}
+
+// Exclusive prefix sums of n uint32 values into uint64.
+void exclusive_u64(const uint32_t* in, unsigned long long* out, int64_t n, hipStream_t s) {
+  if (n == 0) return;
+  with_temp([&](void* t, size_t& b) {
+    return rocprim::exclusive_scan(t, b, in, out, 0ull, (size_t)n,
+                                   rocprim::plus<unsigned long long>(), s);
+  }, s);
+}
+
+// Positions i < n with flag[i] != 0, in order, into out; returns their count
+// (synchronises s).
+int64_t select_flagged(const uint8_t* flag, int64_t n, uint32_t* out, hipStream_t s) {
+  if (n == 0) return 0;
+  Scratch cnt(sizeof(unsigned long long));
+  with_temp([&](void* t, size_t& b) {
+    return rocprim::select(t, b, rocprim::counting_iterator<uint32_t>(0u), flag, out,
+                           cnt.as<unsigned long long>(), (size_t)n, s);
+  }, s);
+  unsigned long long h = 0;
+  GM_HIP(hipMemcpyAsync(&h, cnt.p, sizeof(h), hipMemcpyDeviceToHost, s));
+  GM_HIP(hipStreamSynchronize(s));
+  return (int64_t)h;
+}
 
 }  // namespace
 
@@ -508,188 +846,149 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
     free_tc_plan(g);
   }
   const int64_t n = g->n, m = g->m;
-  std::vector<uint32_t> in_off(n + 1), out_off(n + 1);
-  std::vector<int32_t> out_idx(m), in_idx(m);
-  GM_HIP(hipMemcpyAsync(in_off.data(), g->in_off, (n + 1) * 4, hipMemcpyDeviceToHost, s));
-  GM_HIP(hipMemcpyAsync(out_off.data(), g->out_off, (n + 1) * 4, hipMemcpyDeviceToHost, s));
-  if (m > 0) {
-    GM_HIP(hipMemcpyAsync(out_idx.data(), g->out_idx, m * 4, hipMemcpyDeviceToHost, s));
-    GM_HIP(hipMemcpyAsync(in_idx.data(), g->in_idx, m * 4, hipMemcpyDeviceToHost, s));
-  }
-  GM_HIP(hipStreamSynchronize(s));
-  auto din = [&](int64_t v) { return in_off[v + 1] - in_off[v]; };
-  // For DAG edge (u -> v), u < v: in(u) ∩ in(v) = in(u) ∩ (in(v) ∩ [0, u)).
-  // Either v owns it (its table holds in(v); lanes stream in(u), |in(u)|
-  // elements, credit to v = the owner) or u owns it (table in(u); lanes stream
-  // the prefix of in(v) below u, credit to the partner v). The cheaper stream
-  // decides; an edge with nothing to stream closes no triangle. Streams stop
-  // at the owner's id in both cases, since in(x) holds only ids below x.
-  std::vector<uint32_t> cost(m, 0);  // streamed elements per DAG edge (0: skipped)
-  std::vector<uint8_t> by_u(m, 0);   // 1: u owns the edge
-  std::vector<uint32_t> work_off(n + 1, 0);
-  for (int64_t u = 0; u < n; ++u)
-    for (uint32_t e = out_off[u]; e < out_off[u + 1]; ++e) {
-      const int32_t v = out_idx[e];
-      const uint32_t a = din(u);
-      const int32_t* vb = in_idx.data() + in_off[v];
-      const uint32_t b = (uint32_t)(std::lower_bound(vb, vb + din(v), (int32_t)u) - vb);
-      if (a == 0 || b == 0) continue;
-      by_u[e] = b < a ? 1 : 0;
-      cost[e] = b < a ? b : a;
-      ++work_off[(by_u[e] ? u : v) + 1];
-    }
-  for (int64_t v = 0; v < n; ++v) work_off[v + 1] += work_off[v];
-  std::vector<uint32_t> work(work_off[n]), wcost(work_off[n]);
-  std::vector<uint32_t> cur(work_off.begin(), work_off.end() - 1);
-  for (int64_t u = 0; u < n; ++u)
-    for (uint32_t e = out_off[u]; e < out_off[u + 1]; ++e) {
-      if (cost[e] == 0) continue;
-      const int32_t v = out_idx[e];
-      const uint32_t j = by_u[e] ? cur[u]++ : cur[v]++;
-      work[j] = by_u[e] ? ((uint32_t)v | kCreditPartner) : (uint32_t)u;
-      wcost[j] = cost[e];
-    }
-  // Each owner's partners by decreasing stream length (lanes of a window then
-  // walk lists of similar length).
-  {
-    std::vector<uint64_t> tmp;
-    for (int64_t x = 0; x < n; ++x) {
-      const uint32_t p0 = work_off[x], p1 = work_off[x + 1];
-      if (p1 - p0 < 2) continue;
-      tmp.resize(p1 - p0);
-      for (uint32_t j = p0; j < p1; ++j)
-        tmp[j - p0] = ((uint64_t)(UINT32_MAX - wcost[j]) << 32) | work[j];
-      std::sort(tmp.begin(), tmp.end());
-      for (uint32_t j = p0; j < p1; ++j) {
-        work[j] = (uint32_t)tmp[j - p0];
-        wcost[j] = UINT32_MAX - (uint32_t)(tmp[j - p0] >> 32);
-      }
-    }
-  }
-  // Work items: each owner's partners cut where the scanned elements reach
-  // the class's budget (a partner longer than the budget is an item alone).
-  // The wavefronts of a workgroup item take its 64-partner windows in turn,
-  // however many there are, so that the owner's table is built once per
-  // budget's worth of elements.
-  std::vector<Item> items[kClassesTc];
-  std::vector<PieceItem> pieces;
-  std::vector<uint32_t> pstart, plen;
-  for (int64_t x = 0; x < n; ++x) {
-    const uint32_t p0 = work_off[x], p1 = work_off[x + 1];
-    if (p0 == p1) continue;
-    const uint32_t d = din(x);
-    int cls = 0;
-    if (d <= wave_max) {
-      cls = d <= kTcClass[0].max_d ? 0 : 1;
-    } else {
-      cls = 2;
-      while (d > kTcClass[cls].max_d) ++cls;
-    }
-    const TcClass& tcl = kTcClass[cls];
-    const uint32_t budget = tcl.kind == kWaveTable ? wave_work : block_work;
-    if (tcl.kind == kSplitTable) {
-      // pieces of kPieceMax in-list entries; a partner streams the part of its
-      // list in the piece's id range [lo, hi)
-      const uint32_t xb = in_off[x];
-      for (uint32_t tb = 0; tb < d; tb += kPieceMax) {
-        const uint32_t te = std::min(d, tb + kPieceMax);
-        const int32_t lo = in_idx[xb + tb];
-        const int32_t hi = te < d ? in_idx[xb + te] : (int32_t)x;
-        uint32_t start = p0;
-        uint64_t acc = 0;
-        std::vector<uint32_t> first(p1 - p0);
-        std::vector<uint32_t> len(p1 - p0);
-        for (uint32_t j = p0; j < p1; ++j) {
-          const uint32_t y = work[j] & ~kCreditPartner;
-          const int32_t* yb = in_idx.data() + in_off[y];
-          const int32_t* ye = yb + din(y);
-          const int32_t* f = std::lower_bound(yb, ye, lo);
-          first[j - p0] = (uint32_t)(f - in_idx.data());
-          len[j - p0] = (uint32_t)(std::lower_bound(f, ye, hi) - f);
-        }
-        auto flush = [&](uint32_t a, uint32_t b) {
-          PieceItem pi{(int32_t)x, a, b, xb + tb, xb + te, hi, (uint32_t)pstart.size(), 0};
-          for (uint32_t j = a; j < b; ++j) {
-            pstart.push_back(first[j - p0]);
-            plen.push_back(len[j - p0]);
-          }
-          pieces.push_back(pi);
-        };
-        for (uint32_t j = p0; j < p1; ++j) {
-          if (acc > 0 && acc + len[j - p0] > budget) {
-            flush(start, j);
-            start = j;
-            acc = 0;
-          }
-          acc += len[j - p0];
-        }
-        flush(start, p1);
-      }
-      continue;
-    }
-    uint32_t start = p0;
-    uint64_t acc = 0;
-    for (uint32_t j = p0; j < p1; ++j) {
-      const uint64_t len = wcost[j];
-      if (acc > 0 && acc + len > budget) {
-        items[cls].push_back({(int32_t)x, start, j, 0});
-        start = j;
-        acc = 0;
-      }
-      acc += len;
-    }
-    items[cls].push_back({(int32_t)x, start, p1, 0});
-  }
-  // Largest items first so the long ones start early.
-  for (int c = 0; c < kClassesTc; ++c)
-    std::stable_sort(items[c].begin(), items[c].end(), [&](const Item& a, const Item& b) {
-      return a.p_end - a.p_begin > b.p_end - b.p_begin;
-    });
   TcPlan* p = new TcPlan();
   g->tc_plan = p;
   p->wave_max = wave_max;
   p->wave_work = wave_work;
   p->block_work = block_work;
   try {
-    for (int c = 0; c < kClassesTc; ++c) {
-      p->nitems[c] = (int64_t)items[c].size();
-      p->items[c] = dalloc<Item>(items[c].size());
-      if (!items[c].empty())
-        GM_HIP(hipMemcpyAsync(p->items[c], items[c].data(), items[c].size() * sizeof(Item),
-                              hipMemcpyHostToDevice, s));
-    }
     p->keys = dalloc<int32_t>(m + kIdxPad);
-    if (m > 0) {
-      int64_t kb = (m + kThreads - 1) / kThreads;
-      if (kb > 65536) kb = 65536;
-      make_keys<<<(unsigned)kb, kThreads, 0, s>>>(g->in_idx, m, p->keys);
-      GM_HIP(hipGetLastError());
-    }
-    p->work = dalloc<uint32_t>(work.size());
-    if (!work.empty())
-      GM_HIP(hipMemcpyAsync(p->work, work.data(), work.size() * 4, hipMemcpyHostToDevice, s));
-    std::stable_sort(pieces.begin(), pieces.end(), [&](const PieceItem& a, const PieceItem& b) {
-      return a.p_end - a.p_begin > b.p_end - b.p_begin;
-    });
-    p->npieces = (int64_t)pieces.size();
-    p->pieces = dalloc<PieceItem>(pieces.size());
-    p->pstart = dalloc<uint32_t>(pstart.size());
-    p->plen = dalloc<uint32_t>(plen.size());
-    if (!pieces.empty()) {
-      GM_HIP(hipMemcpyAsync(p->pieces, pieces.data(), pieces.size() * sizeof(PieceItem),
-                            hipMemcpyHostToDevice, s));
-      GM_HIP(hipMemcpyAsync(p->pstart, pstart.data(), pstart.size() * 4, hipMemcpyHostToDevice, s));
-      GM_HIP(hipMemcpyAsync(p->plen, plen.data(), plen.size() * 4, hipMemcpyHostToDevice, s));
-    }
-    p->wlen = dalloc<uint32_t>(wcost.size());
-    if (!wcost.empty())
-      GM_HIP(hipMemcpyAsync(p->wlen, wcost.data(), wcost.size() * 4, hipMemcpyHostToDevice, s));
     p->total = dalloc<unsigned long long>(1);
     GM_HIP(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming));
     for (int c = 0; c < kClassesTc; ++c) {
       GM_HIP(hipStreamCreateWithFlags(&p->lanes[c], hipStreamNonBlocking));
       GM_HIP(hipEventCreateWithFlags(&p->done[c], hipEventDisableTiming));
     }
+    if (m > 0) {
+      make_keys<<<plan_grid(m), kPlanThreads, 0, s>>>(g->in_idx, m, p->keys);
+      GM_HIP(hipGetLastError());
+      // owners, partners and stream lengths, sorted by (owner, decreasing length)
+      const int cb = bits_for((uint64_t)g->max_in + 1);
+      const int ob = bits_for((uint64_t)n + 1);
+      Scratch k1(m * 8), k2(m * 8), v1(m * 4), v2(m * 4);
+      plan_edges<<<plan_grid(m), kPlanThreads, 0, s>>>(g->in_off, g->in_idx, n, m, cb,
+                                                       k1.as<unsigned long long>(),
+                                                       v1.as<uint32_t>());
+      GM_HIP(hipGetLastError());
+      unsigned long long* key = nullptr;
+      uint32_t* val = nullptr;
+      sort_pairs(k1, k2, v1, v2, m, ob + cb, s, &key, &val);
+      Scratch woff((n + 1) * 4);
+      uint32_t* work_off = woff.as<uint32_t>();
+      plan_owner_offsets<<<plan_grid(n + 1), kPlanThreads, 0, s>>>(key, m, cb, n, work_off);
+      GM_HIP(hipGetLastError());
+      uint32_t wh = 0;
+      GM_HIP(hipMemcpyAsync(&wh, work_off + n, 4, hipMemcpyDeviceToHost, s));
+      GM_HIP(hipStreamSynchronize(s));
+      const int64_t w = wh;
+      p->work = dalloc<uint32_t>(w);
+      p->wlen = dalloc<uint32_t>(w);
+      if (w > 0) {
+        plan_work<<<plan_grid(w), kPlanThreads, 0, s>>>(key, val, w, cb, p->work, p->wlen);
+        GM_HIP(hipGetLastError());
+        // work items of owners with a table in LDS, grouped by class, largest first
+        Scratch pre(w * 8), flag(w), start(w * 4);
+        exclusive_u64(p->wlen, pre.as<unsigned long long>(), w, s);
+        plan_item_flags<<<plan_grid(w), kPlanThreads, 0, s>>>(
+            work_off, n, w, g->in_off, pre.as<unsigned long long>(), wave_max, wave_work,
+            block_work, flag.as<uint8_t>());
+        GM_HIP(hipGetLastError());
+        const int64_t ni = select_flagged(flag.as<uint8_t>(), w, start.as<uint32_t>(), s);
+        if (ni > 0) {
+          Scratch it(ni * sizeof(Item)), sk1(ni * 8), sk2(ni * 8), si1(ni * 4), si2(ni * 4),
+              ccnt(kClassesTc * 4);
+          fill_u32(ccnt.as<uint32_t>(), kClassesTc, 0u, s);
+          plan_items<<<plan_grid(ni), kPlanThreads, 0, s>>>(
+              start.as<uint32_t>(), ni, work_off, n, g->in_off, wave_max, it.as<Item>(),
+              sk1.as<unsigned long long>(), si1.as<uint32_t>(), ccnt.as<uint32_t>());
+          GM_HIP(hipGetLastError());
+          unsigned long long* sk = nullptr;
+          uint32_t* si = nullptr;
+          sort_pairs(sk1, sk2, si1, si2, ni, 35, s, &sk, &si);
+          uint32_t cnt[kClassesTc] = {};
+          GM_HIP(hipMemcpyAsync(cnt, ccnt.p, sizeof(cnt), hipMemcpyDeviceToHost, s));
+          GM_HIP(hipStreamSynchronize(s));
+          int64_t off = 0;
+          for (int c = 0; c < kClassesTc; ++c) {
+            p->nitems[c] = cnt[c];
+            p->items[c] = dalloc<Item>(cnt[c]);
+            if (cnt[c] > 0) {
+              plan_gather<Item><<<plan_grid(cnt[c]), kPlanThreads, 0, s>>>(it.as<Item>(), si + off,
+                                                                         cnt[c], p->items[c]);
+              GM_HIP(hipGetLastError());
+            }
+            off += cnt[c];
+          }
+          GM_HIP(hipStreamSynchronize(s));
+        }
+        // owners cut into pieces: one segment per piece, one pair per (piece, partner)
+        Scratch sflag(n), sown(n * 4);
+        plan_split_flags<<<plan_grid(n), kPlanThreads, 0, s>>>(g->in_off, work_off, n, wave_max,
+                                                               sflag.as<uint8_t>());
+        GM_HIP(hipGetLastError());
+        const int64_t nsplit = select_flagged(sflag.as<uint8_t>(), n, sown.as<uint32_t>(), s);
+        if (nsplit > 0) {
+          std::vector<uint32_t> owners(nsplit), io(2 * nsplit), wo(2 * nsplit);
+          GM_HIP(hipMemcpyAsync(owners.data(), sown.p, nsplit * 4, hipMemcpyDeviceToHost, s));
+          GM_HIP(hipStreamSynchronize(s));
+          for (int64_t i = 0; i < nsplit; ++i) {
+            GM_HIP(hipMemcpyAsync(&io[2 * i], g->in_off + owners[i], 8, hipMemcpyDeviceToHost, s));
+            GM_HIP(hipMemcpyAsync(&wo[2 * i], work_off + owners[i], 8, hipMemcpyDeviceToHost, s));
+          }
+          GM_HIP(hipStreamSynchronize(s));
+          std::vector<PieceSeg> segs;
+          uint32_t base = 0;
+          for (int64_t i = 0; i < nsplit; ++i) {
+            const uint32_t xb = io[2 * i], d = io[2 * i + 1] - xb;
+            const uint32_t p0 = wo[2 * i], np = wo[2 * i + 1] - p0;
+            for (uint32_t tb = 0; tb < d; tb += kPieceMax) {
+              const uint32_t te = std::min(d, tb + kPieceMax);
+              if ((uint64_t)base + np > UINT32_MAX)
+                throw Unsupported{"triangle count: too many (piece, partner) pairs"};
+              segs.push_back(PieceSeg{(int32_t)owners[i], xb + tb, xb + te, 0, 0, p0, np, base});
+              base += np;
+            }
+          }
+          const int64_t nseg = (int64_t)segs.size(), npairs = base;
+          Scratch dseg(nseg * sizeof(PieceSeg));
+          GM_HIP(hipMemcpyAsync(dseg.p, segs.data(), nseg * sizeof(PieceSeg),
+                                hipMemcpyHostToDevice, s));
+          plan_seg_bounds<<<plan_grid(nseg), kPlanThreads, 0, s>>>(dseg.as<PieceSeg>(), nseg,
+                                                                   g->in_off, g->in_idx);
+          p->pstart = dalloc<uint32_t>(npairs);
+          p->plen = dalloc<uint32_t>(npairs);
+          plan_pairs<<<plan_grid(npairs), kPlanThreads, 0, s>>>(
+              dseg.as<PieceSeg>(), nseg, npairs, p->work, g->in_off, g->in_idx, p->pstart,
+              p->plen);
+          GM_HIP(hipGetLastError());
+          Scratch ppre(npairs * 8), pflag(npairs), pstarts(npairs * 4);
+          exclusive_u64(p->plen, ppre.as<unsigned long long>(), npairs, s);
+          plan_piece_flags<<<plan_grid(npairs), kPlanThreads, 0, s>>>(
+              dseg.as<PieceSeg>(), nseg, npairs, ppre.as<unsigned long long>(), block_work,
+              pflag.as<uint8_t>());
+          GM_HIP(hipGetLastError());
+          const int64_t np = select_flagged(pflag.as<uint8_t>(), npairs,
+                                            pstarts.as<uint32_t>(), s);
+          Scratch pit(np * sizeof(PieceItem)), pk1(np * 8), pk2(np * 8), pi1(np * 4),
+              pi2(np * 4);
+          plan_piece_items<<<plan_grid(np), kPlanThreads, 0, s>>>(
+              pstarts.as<uint32_t>(), np, dseg.as<PieceSeg>(), nseg, pit.as<PieceItem>(),
+              pk1.as<unsigned long long>(), pi1.as<uint32_t>());
+          GM_HIP(hipGetLastError());
+          unsigned long long* pk = nullptr;
+          uint32_t* pi = nullptr;
+          sort_pairs(pk1, pk2, pi1, pi2, np, 32, s, &pk, &pi);
+          p->npieces = np;
+          p->pieces = dalloc<PieceItem>(np);
+          plan_gather<PieceItem><<<plan_grid(np), kPlanThreads, 0, s>>>(pit.as<PieceItem>(), pi,
+                                                                        np, p->pieces);
+          GM_HIP(hipGetLastError());
+          GM_HIP(hipStreamSynchronize(s));
+        }
+      }
+    }
+    for (int c = 0; c < kClassesTc; ++c)
+      if (!p->items[c]) p->items[c] = dalloc<Item>(0);
     GM_HIP(hipStreamSynchronize(s));
   } catch (...) {
     free_tc_plan(g);

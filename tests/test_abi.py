@@ -134,7 +134,33 @@ def test_union_plan_tuning_validation_without_device(lib):
     assert lib.gm_graph_get_tuning(bogus, ctypes.byref(t)) == _lib.GM_ESTATE
     assert lib.gm_graph_set_tuning(bogus, ctypes.byref(t)) == _lib.GM_ESTATE
     prog = _lib.gm_program(_lib.GM_PROG_BFS, _lib.GM_ORDER_OUT, 0.15, 0)
-    assert lib.gm_autotune(bogus, ctypes.byref(prog), 0, None, 0, -1, 3, None, None) == _lib.GM_ESTATE
+    assert lib.gm_autotune(bogus, ctypes.byref(prog), 0, None, 0, -1, 3, None, None,
+                           None) == _lib.GM_ESTATE
+    assert lib.gm_autotune(bogus, ctypes.byref(prog), 0, None, 0, -1, 3, b"/tmp/x.json", None,
+                           None) == _lib.GM_ESTATE
+
+
+def test_prepare_release_multi_graph_validation_without_device(lib):
+    bogus = ctypes.c_void_p(0x1234)
+    prog = _lib.gm_program(_lib.GM_PROG_BFS, _lib.GM_ORDER_OUT, 0.15, 0)
+    assert lib.gm_graph_prepare(bogus, ctypes.byref(prog), None) == _lib.GM_ESTATE
+    assert lib.gm_graph_release(bogus) == _lib.GM_ESTATE
+    graphs = (ctypes.c_void_p * 2)(0x1234, 0x5678)
+    vprops = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    src = (ctypes.c_int32 * 2)(0, 0)
+    it = ctypes.c_int32(0)
+    run = lib.gm_run_multi_graph
+    assert run(None, 2, ctypes.byref(prog), src, vprops, -1, ctypes.byref(it), None) == _lib.GM_EINVAL
+    assert run(graphs, 0, ctypes.byref(prog), src, vprops, -1, None, None) == _lib.GM_EINVAL
+    assert run(graphs, 2, ctypes.byref(prog), None, vprops, -1, None, None) == _lib.GM_EINVAL
+    assert run(graphs, 2, ctypes.byref(prog), src, vprops, -1, None, None) == _lib.GM_ESTATE
+    ppr = _lib.gm_program(_lib.GM_PROG_PPR, _lib.GM_ORDER_OUT, 0.15, 0)
+    assert run(graphs, 2, ctypes.byref(ppr), src, vprops, 20, None, None) == _lib.GM_EUNSUPPORTED
+    pr = _lib.gm_program(_lib.GM_PROG_PAGERANK, _lib.GM_ORDER_OUT, 0.15, 0)
+    assert run(graphs, 2, ctypes.byref(pr), src, vprops, 20, None, None) == _lib.GM_EINVAL
+    # a bitmap frontier and ids together are refused before the graph is read
+    fr = _lib.gm_frontier(0x1000, 1, 0x2000)
+    assert fr.bitmap == 0x2000
 
 
 def test_binding_refuses_host_tensors():

@@ -146,8 +146,11 @@ def gpu_pr_grad(g, n, w, c, T, r=0.15):
     return hist.cpu().numpy(), gw.cpu().numpy()
 
 
-@pytest.mark.parametrize("scale,T", [(12, 20), (W.SMALL_SCALE, 20), (10, 1), (W.SMALL_SCALE, 3)])
+@pytest.mark.parametrize("scale,T", [(12, 20), (W.SMALL_SCALE, 20), (10, 1), (W.SMALL_SCALE, 3),
+                                     (W.FULL_SCALE, 20)])
 def test_pagerank_weight_gradient(scale, T):
+    """Every edge's gradient against the FP64 oracle (2-norm relative <= 1e-5),
+    up to the full-size scale-22 graph (65.2M edges) at T = 20."""
     n, s, d = W.raw(scale)
     og, w, c, g = pr_setup(n, s, d)
     hist, gw = gpu_pr_grad(g, n, w, c, T)

@@ -133,6 +133,18 @@ def test_ppr_batched_full_size_and_linearity():
     for j in (0, 64, 127):
         ref = oracle.personalized_pagerank(og, int(S[j]), 0.15, 20, g_in=ogin)
         assert l1_rel(pr[:, j], ref) <= 1e-5
+    # every column against the plain single-seed GPU run from its seed (each
+    # within 1e-5 of the FP64 result, so within 2e-5 of each other); the
+    # plain path is the one checked against the oracle above and in
+    # test_gpu_pagerank.py
+    col = torch.empty(n, dtype=torch.float32, device=DEV)
+    worst = 0.0
+    for j, seed in enumerate(S):
+        col.zero_()
+        col[int(seed)] = 1.0
+        gm.run_vertex_program(g, gm.GM_PROG_PPR, dev([int(seed)]), 20, col)
+        worst = max(worst, l1_rel(pr[:, j], col.cpu().numpy()))
+    assert worst <= 2e-5, worst
     # every vertex as a seed: the columns sum to PageRank (teleports sum to 1)
     n2 = 200
     s2, d2 = gg.rmat(8, seed=5)[1:]

@@ -195,3 +195,17 @@ def test_sssp_saturating_weights():
     og = oracle.prepare(6, s, d, w=SAT_W)
     assert out[:, 0].tolist() == SAT_DIST
     assert np.array_equal(out[:, 1], oracle.sssp(og, 5))
+
+
+def test_sssp_superstep_trace_hand_worked():
+    """The hand-worked trace of golden/sssp_supersteps_hand.txt: after k
+    supersteps (a run capped at k, from the initial state) the GPU holds the
+    hand-derived distances and active set; the full run takes exactly 5."""
+    n, s, d, w, src, trace, steps = W.sssp_hand_trace()
+    g = gm.Graph.from_coo(n, s, d, w=w, prep=P_DIR)
+    for k, (dist_k, act_k) in enumerate(trace, start=1):
+        dist, it, active = run_sssp(g, n, src, max_iters=k)
+        assert it == k and np.array_equal(dist, dist_k), k
+        assert np.array_equal(active.astype(bool), act_k), k
+    dist, it, active = run_sssp(g, n, src)
+    assert it == steps and np.array_equal(dist, trace[-1][0]) and not active.any()

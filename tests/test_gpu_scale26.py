@@ -16,9 +16,14 @@ any size:
   batched BFS: column 0 equals the certified plain run, sampled columns equal
     plain runs from their sources, one more column certified;
   weight gradient: the T = 1 closed form (1 - r) c_v / outdeg(u) on every
-    edge, and linearity in the upstream gradient at T = 20.
+    edge; at T = 20, c . PR^T and the gradient's component along a fixed
+    direction against the oracle's FP64 values (golden/pr_grad_rmat26.txt,
+    written by golden/make_pr_grad26.py: a central difference of the
+    oracle's forward, since a full oracle reverse pass at this size does not
+    fit a test run), and linearity in the upstream gradient.
 """
 import gc
+import os
 
 import numpy as np
 import pytest
@@ -32,6 +37,17 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 SCALE = 26
 R = 0.15
+
+
+def read_golden():
+    out = {}
+    for line in open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                  "pr_grad_rmat26.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, v = line.split()
+        out[k] = float(v) if ("." in v or "e" in v) else int(v)
+    return out
 
 
 @pytest.fixture(scope="module")
@@ -113,14 +129,30 @@ def test_pagerank_weight_gradient_scale26(raw, gdir):
         worst = max(worst, float(np.max(np.abs(g1[lo:hi] - ref) / ref)))
     assert worst <= 1e-6, worst
     del hist, g1, src, dst
-    # T = 20: linear in the upstream gradient
+    # T = 20: c . PR^T and the gradient's component along a direction d
+    # against the FP64 oracle (golden/pr_grad_rmat26.txt: a central difference
+    # of the oracle's forward), then linearity in the upstream gradient
+    ref = read_golden()
+    assert ref["n"] == n and ref["m"] == m and ref["T"] == 20
     T = 20
     hist = torch.empty((T + 1, n), dtype=torch.float32, device=DEV)
     hist[0].fill_(1.0)
     gm.pagerank_forward_w(gdir, w, R, T, hist)
-    c2 = torch.tensor(gg.uniform_f32(n, gg.SEED_PR_UPSTREAM + 1), device=DEV)
-    ga, gb, gab = torch.empty_like(w), torch.empty_like(w), torch.empty_like(w)
+    L = float(torch.dot(hist[T].double(), c.double()))
+    assert abs(L - ref["L_w1"]) <= 1e-5 * abs(ref["L_w1"]), (L, ref["L_w1"])
+    ga = torch.empty_like(w)
     gm.pagerank_vjp_w(gdir, w, R, T, hist, c, ga)
+    src, dst = gdir.edges()
+    dd = 0.0
+    for lo in range(0, m, 1 << 27):
+        hi = min(m, lo + (1 << 27))
+        dvec = torch.tensor(gg.weights_f32(src[lo:hi], dst[lo:hi], int(ref["seed_dir"]), 0.5, 1.5),
+                            device=DEV)
+        dd += float(torch.dot(ga[lo:hi].double(), dvec.double()))
+    del src, dst, dvec
+    assert abs(dd - ref["dir_deriv"]) <= 1e-5 * abs(ref["dir_deriv"]), (dd, ref["dir_deriv"])
+    c2 = torch.tensor(gg.uniform_f32(n, gg.SEED_PR_UPSTREAM + 1), device=DEV)
+    gb, gab = torch.empty_like(w), torch.empty_like(w)
     gm.pagerank_vjp_w(gdir, w, R, T, hist, c2, gb)
     gm.pagerank_vjp_w(gdir, w, R, T, hist, c + c2, gab)
     assert bool(torch.isfinite(gab).all())

@@ -1,14 +1,17 @@
 """GPU triangle counting (Sec. 3 IV, Eq. (7); two-program form of Sec. 4.2) against
 the oracle: exact totals and exact per-vertex counts (APPLY output)."""
+import hashlib
 import itertools
 
 import numpy as np
 import pytest
 import torch
 
+import graphgen as gg
 import oracle
 import paper_1503_07241_amd as gm
 from tests import workloads as W
+from tests.golden import make_tc_goldens
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -73,12 +76,24 @@ def test_hub_receivers_large_lists():
     assert np.array_equal(counts, oracle.triangles_at(dag_in, np.arange(n)))
 
 
+def golden_check(name, total, counts):
+    """Total and every receiver's count against the oracle-written golden file
+    (total and SHA-256 of the whole per-vertex uint64 array)."""
+    ref = make_tc_goldens.read(name)
+    assert len(counts) == ref["n"]
+    assert total == ref["total"]
+    digest = hashlib.sha256(np.ascontiguousarray(counts, dtype="<u8").tobytes()).hexdigest()
+    assert digest == ref["counts_sha256"]
+
+
 def test_full_size_sampled_vertices():
-    """RMAT scale 22: per-vertex counts of sampled receivers, computed one by
-    one by the oracle; the total equals the sum of the per-vertex counts."""
+    """RMAT scale 22: the exact total and every receiver's count against the
+    oracle's (golden/tc_rmat22.txt), plus sampled receivers computed one by
+    one by the oracle here."""
     n, s, d = W.raw(W.FULL_SCALE)
     _, total, counts = gpu_tc(n, s, d)
     assert int(counts.sum()) == total
+    golden_check("tc_rmat22", total, counts)
     dag_in = oracle.dag_in_lists(W.ograph(W.FULL_SCALE, "dag"))
     indeg = np.diff(dag_in.off)
     rng = np.random.default_rng(11)
@@ -113,3 +128,16 @@ def test_edgeless_dag():
     tri = torch.full((9,), 3, dtype=torch.int64, device=DEV)  # APPLY adds nothing
     assert gm.run_vertex_program(g, gm.GM_PROG_TC, None, 1, tri) == 1
     assert np.array_equal(tri.cpu().numpy(), np.full(9, 3))
+
+
+def test_paper_tc_workload_rmat20_a45():
+    """The paper's triangle-counting graph (Sec. 5.1, Table 1): RMAT scale 20
+    with a = .45, b = c = .15; exact total and every receiver's count against
+    the oracle (golden/tc_rmat20_a45.txt), sampled receivers recomputed here."""
+    n, s, d = gg.rmat(20, a=0.45, b=0.15, c=0.15)
+    g, total, counts = gpu_tc(n, s, d)
+    assert g.m == make_tc_goldens.read("tc_rmat20_a45")["m_dag"]
+    golden_check("tc_rmat20_a45", total, counts)
+    dag_in = oracle.dag_in_lists(oracle.prepare(n, s, d, mode="dag"))
+    verts = np.random.default_rng(45).choice(n, 200, replace=False).astype(np.int32)
+    assert np.array_equal(counts[verts], oracle.triangles_at(dag_in, verts))
