@@ -123,6 +123,11 @@ def main():
                          "hardware-counter runs")
     ap.add_argument("--tc-only", type=int, default=0, metavar="K",
                     help="only run K triangle counts, for hardware-counter runs")
+    ap.add_argument("--tc-cold", action="store_true",
+                    help="with --tc-only: free the work plan before each count (cold calls)")
+    ap.add_argument("--cf-only", type=int, default=0, metavar="K",
+                    help="only run K CF forward + backward passes on the 100M-rating graph, "
+                         "for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -138,6 +143,19 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.cf_only:
+        R = gg.cf_ratings()
+        PU, PV = gg.cf_point(R.n_users, R.n_items)
+        rg = gm.RatingGraph.from_coo(R.n_users, R.n_items, R.user, R.item, R.rating)
+        pu, pv = torch.tensor(PU, device=dev), torch.tensor(PV, device=dev)
+        loss = torch.empty(1, dtype=torch.float64, device=dev)
+        gu, gv = torch.empty_like(pu), torch.empty_like(pv)
+        for _ in range(args.cf_only):
+            gm.cf_forward(rg, pu, pv, 0.05, loss)
+            gm.cf_backward(rg, pu, pv, 0.05, 1.0, gu, gv)
+        torch.cuda.synchronize()
+        print(json.dumps({"cf_runs": args.cf_only, "ratings": int(R.m)}), flush=True)
+        return
     scale = args.scale
     t0 = time.time()
     n, s, d = gg.rmat(scale)
@@ -150,6 +168,8 @@ def main():
         g = gm.Graph.from_coo(n, s, d, prep=gm.GM_PREP_UPPER_DAG)
         tri = torch.empty(n, dtype=torch.int64, device=dev)
         for _ in range(args.tc_only):
+            if args.tc_cold:
+                g.release()
             tri.zero_()
             gm.run_vertex_program(g, gm.GM_PROG_TC, None, 1, tri)
         torch.cuda.synchronize()

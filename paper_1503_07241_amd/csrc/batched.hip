@@ -723,18 +723,29 @@ void ensure_ppr_items(gm_graph g, Batch* b, hipStream_t s) {
   }
   for (int64_t v = 0; v < n; ++v)
     if (!split[v]) items.push_back({(uint32_t)v, off[v], off[v + 1], -1});
+  // b->items marks complete work items: set last (a failure leaves none)
+  PprItem* it = nullptr;
+  PprSplit* sp = nullptr;
+  try {
+    it = dalloc<PprItem>(items.size());
+    sp = dalloc<PprSplit>(splits.size());
+    GM_HIP(hipMemcpyAsync(it, items.data(), items.size() * sizeof(PprItem),
+                          hipMemcpyHostToDevice, s));
+    if (!splits.empty())
+      GM_HIP(hipMemcpyAsync(sp, splits.data(), splits.size() * sizeof(PprSplit),
+                            hipMemcpyHostToDevice, s));
+    GM_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    dfree(it);
+    dfree(sp);
+    throw;
+  }
   b->nitems = (int64_t)items.size();
   b->nsplit = (int64_t)splits.size();
   b->npartial = np;
   b->items_chunk = chunk;
-  b->items = dalloc<PprItem>(items.size());
-  b->splits = dalloc<PprSplit>(splits.size());
-  GM_HIP(hipMemcpyAsync(b->items, items.data(), items.size() * sizeof(PprItem),
-                        hipMemcpyHostToDevice, s));
-  if (!splits.empty())
-    GM_HIP(hipMemcpyAsync(b->splits, splits.data(), splits.size() * sizeof(PprSplit),
-                          hipMemcpyHostToDevice, s));
-  GM_HIP(hipStreamSynchronize(s));
+  b->items = it;
+  b->splits = sp;
 }
 
 // Pull adjacency of batched BFS: the out-lists of a symmetrised graph, else
@@ -784,35 +795,63 @@ void ensure_bfs_ws(gm_graph g, Batch* b, hipStream_t s) {
     }
   }
   bins.nunits = unit;
-  b->vis = dalloc<unsigned long long>(n);
-  b->fr[0] = dalloc<unsigned long long>(n);
-  b->fr[1] = dalloc<unsigned long long>(n);
-  b->bctl = dalloc<BfsCtl>(kMaxPlanSteps + 1);
-  b->bstat = dalloc<unsigned long long>(2 * kBfsStatBlocks);
-  b->border = dalloc<int32_t>(n);
-  b->bq = dalloc<int32_t>(n);
-  b->bqbeg = dalloc<uint32_t>(n);
-  b->bqest = dalloc<uint32_t>(n);
-  b->bqctl = dalloc<BCtl>(kMaxPlanSteps);
-  void* h = nullptr;
-  GM_HIP(hipHostMalloc(&h, sizeof(BfsCtl), hipHostMallocDefault));
-  b->host_bctl = static_cast<BfsCtl*>(h);
-  GM_HIP(hipMemcpyAsync(b->border, order.data(), n * 4, hipMemcpyHostToDevice, s));
-  GM_HIP(hipStreamSynchronize(s));
+  // b->vis marks a complete workspace: it is set last, and a failed
+  // allocation frees what was taken, so the next call starts over
+  unsigned long long* vis = nullptr;
+  try {
+    b->fr[0] = dalloc<unsigned long long>(n);
+    b->fr[1] = dalloc<unsigned long long>(n);
+    b->bctl = dalloc<BfsCtl>(kMaxPlanSteps + 1);
+    b->bstat = dalloc<unsigned long long>(2 * kBfsStatBlocks);
+    b->border = dalloc<int32_t>(n);
+    b->bq = dalloc<int32_t>(n);
+    b->bqbeg = dalloc<uint32_t>(n);
+    b->bqest = dalloc<uint32_t>(n);
+    b->bqctl = dalloc<BCtl>(kMaxPlanSteps);
+    void* h = nullptr;
+    GM_HIP(hipHostMalloc(&h, sizeof(BfsCtl), hipHostMallocDefault));
+    b->host_bctl = static_cast<BfsCtl*>(h);
+    GM_HIP(hipMemcpyAsync(b->border, order.data(), n * 4, hipMemcpyHostToDevice, s));
+    GM_HIP(hipStreamSynchronize(s));
+    vis = dalloc<unsigned long long>(n);
+  } catch (...) {
+    for (void** p : {(void**)&b->fr[0], (void**)&b->fr[1], (void**)&b->bctl, (void**)&b->bstat,
+                     (void**)&b->border, (void**)&b->bq, (void**)&b->bqbeg, (void**)&b->bqest,
+                     (void**)&b->bqctl}) {
+      dfree(*p);
+      *p = nullptr;
+    }
+    if (b->host_bctl) (void)hipHostFree(b->host_bctl);
+    b->host_bctl = nullptr;
+    throw;
+  }
+  b->vis = vis;
 }
 
 void ensure_sssp_ws(gm_graph g, Batch* b, int k) {
   const int64_t n = g->n;
-  if (!b->act[0]) {
-    b->act[0] = dalloc<unsigned long long>(2 * n);  // both masks in one buffer
-    b->act[1] = b->act[0] + n;
-    b->q = dalloc<int32_t>(n);
-    b->qbeg = dalloc<uint32_t>(n);
-    b->qest = dalloc<uint32_t>(n);
-    b->ctl = dalloc<BCtl>(kMaxPlanSteps);
-    void* h = nullptr;
-    GM_HIP(hipHostMalloc(&h, sizeof(BCtl), hipHostMallocDefault));
-    b->host_ctl = static_cast<BCtl*>(h);
+  if (!b->act[0]) {  // act[0] marks a complete workspace: set last
+    unsigned long long* act = nullptr;
+    try {
+      b->q = dalloc<int32_t>(n);
+      b->qbeg = dalloc<uint32_t>(n);
+      b->qest = dalloc<uint32_t>(n);
+      b->ctl = dalloc<BCtl>(kMaxPlanSteps);
+      void* h = nullptr;
+      GM_HIP(hipHostMalloc(&h, sizeof(BCtl), hipHostMallocDefault));
+      b->host_ctl = static_cast<BCtl*>(h);
+      act = dalloc<unsigned long long>(2 * n);  // both masks in one buffer
+    } catch (...) {
+      for (void** p : {(void**)&b->q, (void**)&b->qbeg, (void**)&b->qest, (void**)&b->ctl}) {
+        dfree(*p);
+        *p = nullptr;
+      }
+      if (b->host_ctl) (void)hipHostFree(b->host_ctl);
+      b->host_ctl = nullptr;
+      throw;
+    }
+    b->act[0] = act;
+    b->act[1] = act + n;
   }
   if (b->qrow_k < k) {
     dfree(b->qrow);

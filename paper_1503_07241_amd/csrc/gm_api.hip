@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <mutex>
 #include <new>
+#include <string>
 #include <unordered_set>
 #include <vector>
 
@@ -18,8 +19,8 @@ thread_local char g_msg[512] = "";
 std::mutex g_reg_mu;
 std::unordered_set<gm_graph>* g_reg = nullptr;
 std::mutex g_fault_mu;
-long g_alloc_count = 0;
-long g_fault_at = -2;  // -2: not read yet, -1: disabled
+long g_alloc_count = 0;     // allocations since GM_FAULT_ALLOC last changed
+std::string* g_fault_env = nullptr;  // its value when last read
 }  // namespace
 
 gm_status fail(gm_status st, const char* fmt, ...) {
@@ -36,16 +37,22 @@ gm_status ok() {
 }
 
 // Device allocations go through here. GM_FAULT_ALLOC=k makes the k-th
-// allocation of the process fail (fault injection for the error paths).
+// allocation after the variable was set (or changed) fail, for tests of the
+// error paths; it is read at every allocation, so a process can set, change
+// and clear it between calls.
 void* dmalloc(size_t bytes) {
   {
     std::lock_guard<std::mutex> lk(g_fault_mu);
-    if (g_fault_at == -2) {
-      const char* e = getenv("GM_FAULT_ALLOC");
-      g_fault_at = e ? atol(e) : -1;
+    const char* e = getenv("GM_FAULT_ALLOC");
+    const std::string now = e ? e : "";
+    if (!g_fault_env) g_fault_env = new std::string();
+    if (now != *g_fault_env) {
+      *g_fault_env = now;
+      g_alloc_count = 0;
     }
+    const long at = e ? atol(e) : -1;
     ++g_alloc_count;
-    if (g_fault_at > 0 && g_alloc_count == g_fault_at) throw OutOfMemory{bytes};
+    if (at > 0 && g_alloc_count == at) throw OutOfMemory{bytes};
   }
   void* p = nullptr;
   const hipError_t e = hipMalloc(&p, bytes ? bytes : 16);

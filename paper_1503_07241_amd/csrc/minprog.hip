@@ -360,22 +360,27 @@ Workspace* ensure_ws(gm_graph g, hipStream_t s) {
   if (ws) return ws;
   ws = new Workspace();
   g->min_ws = ws;
-  const int64_t n = g->n;
-  const int64_t words = (n + 31) / 32;
-  ws->n = n;
-  ws->q = dalloc<int32_t>(n);
-  ws->qmsg = dalloc<uint32_t>(n);
-  ws->qbeg = dalloc<uint32_t>(n);
-  ws->qest = dalloc<uint32_t>(n);
-  ws->bits[0] = dalloc<uint32_t>(words);
-  ws->bits[1] = dalloc<uint32_t>(words);
-  ws->ctl = dalloc<Ctl>(kMaxCtl);
-  void* h = nullptr;
-  GM_HIP(hipHostMalloc(&h, kMaxCtl * sizeof(Ctl), hipHostMallocDefault));
-  ws->host_ctl = static_cast<Ctl*>(h);
-  fill_kernel<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[0], words, 0);
-  fill_kernel<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[1], words, 0);
-  GM_HIP(hipGetLastError());
+  try {
+    const int64_t n = g->n;
+    const int64_t words = (n + 31) / 32;
+    ws->n = n;
+    ws->q = dalloc<int32_t>(n);
+    ws->qmsg = dalloc<uint32_t>(n);
+    ws->qbeg = dalloc<uint32_t>(n);
+    ws->qest = dalloc<uint32_t>(n);
+    ws->bits[0] = dalloc<uint32_t>(words);
+    ws->bits[1] = dalloc<uint32_t>(words);
+    ws->ctl = dalloc<Ctl>(kMaxCtl);
+    void* h = nullptr;
+    GM_HIP(hipHostMalloc(&h, kMaxCtl * sizeof(Ctl), hipHostMallocDefault));
+    ws->host_ctl = static_cast<Ctl*>(h);
+    fill_kernel<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[0], words, 0);
+    fill_kernel<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[1], words, 0);
+    GM_HIP(hipGetLastError());
+  } catch (...) {
+    free_min_workspace(g);  // a failed build leaves no workspace behind
+    throw;
+  }
   return ws;
 }
 

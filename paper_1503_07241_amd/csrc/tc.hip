@@ -510,19 +510,6 @@ __device__ __host__ inline int tc_class(uint32_t d, uint32_t wave_max) {
   return c;
 }
 
-// Row of in-edge j: the last v with off[v] <= j.
-__device__ inline uint32_t row_of(const uint32_t* __restrict__ off, int64_t n, uint32_t j) {
-  int64_t lo = 0, hi = n;
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (off[mid] <= j)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return (uint32_t)lo;
-}
-
 // First position in [b, e) of a sorted id array holding a value >= x.
 __device__ inline uint32_t lower_pos(const int32_t* __restrict__ a, uint32_t b, uint32_t e,
                                      int32_t x) {
@@ -536,17 +523,29 @@ __device__ inline uint32_t lower_pos(const int32_t* __restrict__ a, uint32_t b, 
   return b;
 }
 
+// rowid[j] = v for every in-edge j of row v: one wavefront per row, its
+// lanes storing consecutive entries.
+__global__ void plan_row_ids(const uint32_t* __restrict__ in_off, int64_t n,
+                             uint32_t* __restrict__ rowid) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t v = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; v < n; v += waves) {
+    const uint32_t b = in_off[v], e = in_off[v + 1];
+    for (uint32_t j = b + lane; j < e; j += 64) rowid[j] = (uint32_t)v;
+  }
+}
+
 // One thread per in-edge j (u = in_idx[j] -> v = row of j): the sort key
 // (owner, decreasing stream length) and the work entry (partner, with the
 // credit flag when the partner receives the count). Edges with nothing to
 // stream get a key past every owner.
 __global__ void plan_edges(const uint32_t* __restrict__ in_off, const int32_t* __restrict__ in_idx,
-                           int64_t n, int64_t m, int cb, unsigned long long* __restrict__ key,
-                           uint32_t* __restrict__ val) {
+                           const uint32_t* __restrict__ rowid, int64_t n, int64_t m, int cb,
+                           unsigned long long* __restrict__ key, uint32_t* __restrict__ val) {
   const unsigned long long cmask = (1ull << cb) - 1;
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < m;
        j += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t v = row_of(in_off, n, (uint32_t)j);
+    const uint32_t v = rowid[j];
     const int32_t u = in_idx[j];
     const uint32_t a = in_off[u + 1] - in_off[u];  // |in(u)|
     const uint32_t b = (uint32_t)j - in_off[v];    // |in(v) ∩ [0, u)|
@@ -593,23 +592,20 @@ __global__ void plan_work(const unsigned long long* __restrict__ key,
   }
 }
 
-// Owner of every work entry (binary search over the offsets).
-__device__ inline uint32_t owner_of(const uint32_t* __restrict__ work_off, int64_t n, uint32_t j) {
-  return row_of(work_off, n, j);
-}
 
 // Work items of the owners with a table in LDS: an owner's partners are cut
 // where the streamed elements before a partner cross a multiple of the
 // class's budget (so an item streams at most budget + its last partner's
 // length). flag[j] = 1 where an item starts.
-__global__ void plan_item_flags(const uint32_t* __restrict__ work_off, int64_t n, int64_t w,
+__global__ void plan_item_flags(const unsigned long long* __restrict__ key, int cb,
+                                const uint32_t* __restrict__ work_off, int64_t w,
                                 const uint32_t* __restrict__ in_off,
                                 const unsigned long long* __restrict__ pre, uint32_t wave_max,
                                 uint32_t wave_work, uint32_t block_work,
                                 uint8_t* __restrict__ flag) {
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < w;
        j += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t x = owner_of(work_off, n, (uint32_t)j);
+    const uint32_t x = (uint32_t)(key[j] >> cb);
     const int c = tc_class(in_off[x + 1] - in_off[x], wave_max);
     uint8_t f = 0;
     if (kTcClass[c].kind != kSplitTable) {
@@ -626,22 +622,40 @@ __global__ void plan_item_flags(const uint32_t* __restrict__ work_off, int64_t n
 // decreasing partner count: the largest items of a class start first), and
 // the per-class item counts.
 __global__ void plan_items(const uint32_t* __restrict__ start, int64_t nitems,
-                           const uint32_t* __restrict__ work_off, int64_t n,
+                           const unsigned long long* __restrict__ key, int cb,
+                           const uint32_t* __restrict__ work_off,
                            const uint32_t* __restrict__ in_off, uint32_t wave_max,
                            Item* __restrict__ items, unsigned long long* __restrict__ skey,
-                           uint32_t* __restrict__ sidx, uint32_t* __restrict__ class_count) {
+                           uint32_t* __restrict__ sidx) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nitems;
        i += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t j = start[i];
-    const uint32_t x = owner_of(work_off, n, j);
+    const uint32_t x = (uint32_t)(key[j] >> cb);
     uint32_t end = work_off[x + 1];
     if (i + 1 < nitems && start[i + 1] < end) end = start[i + 1];
     const int c = tc_class(in_off[x + 1] - in_off[x], wave_max);
     items[i] = Item{(int32_t)x, j, end, 0};
     skey[i] = ((unsigned long long)c << 32) | (0xFFFFFFFFu - (end - j));
     sidx[i] = (uint32_t)i;
-    atomicAdd(&class_count[c], 1u);
   }
+}
+
+// first[c] = the first item of class c in the items sorted by class
+// (c = 0..kClassesTc; first[kClassesTc] = nitems).
+__global__ void plan_class_bounds(const unsigned long long* __restrict__ skey, int64_t nitems,
+                                  uint32_t* __restrict__ first) {
+  const int c = threadIdx.x;
+  if (c > kClassesTc) return;
+  const unsigned long long t = (unsigned long long)c << 32;
+  int64_t lo = 0, hi = nitems;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (skey[mid] < t)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  first[c] = (uint32_t)lo;
 }
 
 template <class T>
@@ -743,64 +757,93 @@ __global__ void plan_piece_items(const uint32_t* __restrict__ start, int64_t nit
 
 TcPlan* plan(gm_graph g) { return static_cast<TcPlan*>(g->tc_plan); }
 
-// Device scratch freed at scope exit.
+// Device memory for the temporaries of one plan build: taken in order from
+// a few large chunks and released together when the build ends (after the
+// stream has drained), so that the build makes a handful of allocations
+// rather than one per temporary.
+struct Pool {
+  hipStream_t s;
+  std::vector<void*> chunks;
+  char* cur = nullptr;
+  size_t left = 0;
+  explicit Pool(hipStream_t st) : s(st) {}
+  Pool(const Pool&) = delete;
+  Pool& operator=(const Pool&) = delete;
+  ~Pool() {
+    (void)hipStreamSynchronize(s);
+    for (void* c : chunks) dfree(c);
+  }
+  void* take(size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (bytes == 0) bytes = 256;
+    if (bytes > left) {
+      const size_t cb = std::max(bytes, (size_t)256 << 20);
+      void* c = dmalloc(cb);
+      chunks.push_back(c);
+      cur = static_cast<char*>(c);
+      left = cb;
+    }
+    void* p = cur;
+    cur += bytes;
+    left -= bytes;
+    return p;
+  }
+};
+
+// A temporary of the plan build.
 struct Scratch {
   void* p = nullptr;
-  Scratch() = default;
-  explicit Scratch(size_t bytes) : p(dmalloc(bytes)) {}
-  Scratch(const Scratch&) = delete;
-  Scratch& operator=(const Scratch&) = delete;
-  ~Scratch() { dfree(p); }
+  Scratch(Pool& pool, size_t bytes) : p(pool.take(bytes)) {}
   template <class T>
   T* as() const {
     return static_cast<T*>(p);
   }
 };
 
-// rocPRIM calls: query the temporary storage, allocate it, run.
+// rocPRIM calls: query the temporary storage, take it from the pool, run.
 template <class F>
-void with_temp(F&& f, hipStream_t s) {
+void with_temp(Pool& pool, F&& f) {
   size_t bytes = 0;
   GM_HIP(f(nullptr, bytes));
-  Scratch tmp(bytes ? bytes : 16);
-  const hipError_t e = f(tmp.p, bytes);
-  if (e == hipSuccess) (void)hipStreamSynchronize(s);  // tmp is freed on return
-  GM_HIP(e);
+  void* tmp = pool.take(bytes);
+  GM_HIP(f(tmp, bytes));
 }
 
 // Stable sort of (key, index) pairs on the low `bits` bits; returns the
 // buffers holding the result.
-void sort_pairs(Scratch& k1, Scratch& k2, Scratch& v1, Scratch& v2, int64_t n, int bits,
-                hipStream_t s, unsigned long long** kout, uint32_t** vout) {
+void sort_pairs(Pool& pool, Scratch& k1, Scratch& k2, Scratch& v1, Scratch& v2, int64_t n,
+                int bits, hipStream_t s, unsigned long long** kout, uint32_t** vout) {
   rocprim::double_buffer<unsigned long long> kb(k1.as<unsigned long long>(),
                                                 k2.as<unsigned long long>());
   rocprim::double_buffer<uint32_t> vb(v1.as<uint32_t>(), v2.as<uint32_t>());
   if (n > 0)
-    with_temp([&](void* t, size_t& b) {
+    with_temp(pool, [&](void* t, size_t& b) {
       return rocprim::radix_sort_pairs(t, b, kb, vb, (size_t)n, 0, bits, s);
-    }, s);
+    });
   *kout = kb.current();
   *vout = vb.current();
 }
 
 // Exclusive prefix sums of n uint32 values into uint64.
-void exclusive_u64(const uint32_t* in, unsigned long long* out, int64_t n, hipStream_t s) {
+void exclusive_u64(Pool& pool, const uint32_t* in, unsigned long long* out, int64_t n,
+                   hipStream_t s) {
   if (n == 0) return;
-  with_temp([&](void* t, size_t& b) {
+  with_temp(pool, [&](void* t, size_t& b) {
     return rocprim::exclusive_scan(t, b, in, out, 0ull, (size_t)n,
                                    rocprim::plus<unsigned long long>(), s);
-  }, s);
+  });
 }
 
 // Positions i < n with flag[i] != 0, in order, into out; returns their count
 // (synchronises s).
-int64_t select_flagged(const uint8_t* flag, int64_t n, uint32_t* out, hipStream_t s) {
+int64_t select_flagged(Pool& pool, const uint8_t* flag, int64_t n, uint32_t* out,
+                       hipStream_t s) {
   if (n == 0) return 0;
-  Scratch cnt(sizeof(unsigned long long));
-  with_temp([&](void* t, size_t& b) {
+  Scratch cnt(pool, sizeof(unsigned long long));
+  with_temp(pool, [&](void* t, size_t& b) {
     return rocprim::select(t, b, rocprim::counting_iterator<uint32_t>(0u), flag, out,
                            cnt.as<unsigned long long>(), (size_t)n, s);
-  }, s);
+  });
   unsigned long long h = 0;
   GM_HIP(hipMemcpyAsync(&h, cnt.p, sizeof(h), hipMemcpyDeviceToHost, s));
   GM_HIP(hipStreamSynchronize(s));
@@ -860,20 +903,22 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
       GM_HIP(hipEventCreateWithFlags(&p->done[c], hipEventDisableTiming));
     }
     if (m > 0) {
+      Pool pool(s);
       make_keys<<<plan_grid(m), kPlanThreads, 0, s>>>(g->in_idx, m, p->keys);
       GM_HIP(hipGetLastError());
       // owners, partners and stream lengths, sorted by (owner, decreasing length)
       const int cb = bits_for((uint64_t)g->max_in + 1);
       const int ob = bits_for((uint64_t)n + 1);
-      Scratch k1(m * 8), k2(m * 8), v1(m * 4), v2(m * 4);
-      plan_edges<<<plan_grid(m), kPlanThreads, 0, s>>>(g->in_off, g->in_idx, n, m, cb,
-                                                       k1.as<unsigned long long>(),
+      Scratch k1(pool, m * 8), k2(pool, m * 8), v1(pool, m * 4), v2(pool, m * 4);
+      plan_row_ids<<<plan_grid(n), kPlanThreads, 0, s>>>(g->in_off, n, v2.as<uint32_t>());
+      plan_edges<<<plan_grid(m), kPlanThreads, 0, s>>>(g->in_off, g->in_idx, v2.as<uint32_t>(),
+                                                       n, m, cb, k1.as<unsigned long long>(),
                                                        v1.as<uint32_t>());
       GM_HIP(hipGetLastError());
       unsigned long long* key = nullptr;
       uint32_t* val = nullptr;
-      sort_pairs(k1, k2, v1, v2, m, ob + cb, s, &key, &val);
-      Scratch woff((n + 1) * 4);
+      sort_pairs(pool, k1, k2, v1, v2, m, ob + cb, s, &key, &val);
+      Scratch woff(pool, (n + 1) * 4);
       uint32_t* work_off = woff.as<uint32_t>();
       plan_owner_offsets<<<plan_grid(n + 1), kPlanThreads, 0, s>>>(key, m, cb, n, work_off);
       GM_HIP(hipGetLastError());
@@ -887,46 +932,49 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
         plan_work<<<plan_grid(w), kPlanThreads, 0, s>>>(key, val, w, cb, p->work, p->wlen);
         GM_HIP(hipGetLastError());
         // work items of owners with a table in LDS, grouped by class, largest first
-        Scratch pre(w * 8), flag(w), start(w * 4);
-        exclusive_u64(p->wlen, pre.as<unsigned long long>(), w, s);
+        Scratch pre(pool, w * 8), flag(pool, w), start(pool, w * 4);
+        exclusive_u64(pool, p->wlen, pre.as<unsigned long long>(), w, s);
         plan_item_flags<<<plan_grid(w), kPlanThreads, 0, s>>>(
-            work_off, n, w, g->in_off, pre.as<unsigned long long>(), wave_max, wave_work,
+            key, cb, work_off, w, g->in_off, pre.as<unsigned long long>(), wave_max, wave_work,
             block_work, flag.as<uint8_t>());
         GM_HIP(hipGetLastError());
-        const int64_t ni = select_flagged(flag.as<uint8_t>(), w, start.as<uint32_t>(), s);
+        const int64_t ni =
+            select_flagged(pool, flag.as<uint8_t>(), w, start.as<uint32_t>(), s);
         if (ni > 0) {
-          Scratch it(ni * sizeof(Item)), sk1(ni * 8), sk2(ni * 8), si1(ni * 4), si2(ni * 4),
-              ccnt(kClassesTc * 4);
-          fill_u32(ccnt.as<uint32_t>(), kClassesTc, 0u, s);
+          Scratch it(pool, ni * sizeof(Item)), sk1(pool, ni * 8), sk2(pool, ni * 8),
+              si1(pool, ni * 4), si2(pool, ni * 4), cfirst(pool, (kClassesTc + 1) * 4);
           plan_items<<<plan_grid(ni), kPlanThreads, 0, s>>>(
-              start.as<uint32_t>(), ni, work_off, n, g->in_off, wave_max, it.as<Item>(),
-              sk1.as<unsigned long long>(), si1.as<uint32_t>(), ccnt.as<uint32_t>());
+              start.as<uint32_t>(), ni, key, cb, work_off, g->in_off, wave_max, it.as<Item>(),
+              sk1.as<unsigned long long>(), si1.as<uint32_t>());
           GM_HIP(hipGetLastError());
           unsigned long long* sk = nullptr;
           uint32_t* si = nullptr;
-          sort_pairs(sk1, sk2, si1, si2, ni, 35, s, &sk, &si);
-          uint32_t cnt[kClassesTc] = {};
-          GM_HIP(hipMemcpyAsync(cnt, ccnt.p, sizeof(cnt), hipMemcpyDeviceToHost, s));
+          sort_pairs(pool, sk1, sk2, si1, si2, ni, 35, s, &sk, &si);
+          plan_class_bounds<<<1, 64, 0, s>>>(sk, ni, cfirst.as<uint32_t>());
+          GM_HIP(hipGetLastError());
+          uint32_t first[kClassesTc + 1] = {};
+          GM_HIP(hipMemcpyAsync(first, cfirst.p, sizeof(first), hipMemcpyDeviceToHost, s));
           GM_HIP(hipStreamSynchronize(s));
-          int64_t off = 0;
           for (int c = 0; c < kClassesTc; ++c) {
-            p->nitems[c] = cnt[c];
-            p->items[c] = dalloc<Item>(cnt[c]);
-            if (cnt[c] > 0) {
-              plan_gather<Item><<<plan_grid(cnt[c]), kPlanThreads, 0, s>>>(it.as<Item>(), si + off,
-                                                                         cnt[c], p->items[c]);
+            const uint32_t cnt = first[c + 1] - first[c];
+            p->nitems[c] = cnt;
+            p->items[c] = dalloc<Item>(cnt);
+            if (cnt > 0) {
+              plan_gather<Item><<<plan_grid(cnt), kPlanThreads, 0, s>>>(it.as<Item>(),
+                                                                        si + first[c], cnt,
+                                                                        p->items[c]);
               GM_HIP(hipGetLastError());
             }
-            off += cnt[c];
           }
           GM_HIP(hipStreamSynchronize(s));
         }
         // owners cut into pieces: one segment per piece, one pair per (piece, partner)
-        Scratch sflag(n), sown(n * 4);
+        Scratch sflag(pool, n), sown(pool, n * 4);
         plan_split_flags<<<plan_grid(n), kPlanThreads, 0, s>>>(g->in_off, work_off, n, wave_max,
                                                                sflag.as<uint8_t>());
         GM_HIP(hipGetLastError());
-        const int64_t nsplit = select_flagged(sflag.as<uint8_t>(), n, sown.as<uint32_t>(), s);
+        const int64_t nsplit =
+            select_flagged(pool, sflag.as<uint8_t>(), n, sown.as<uint32_t>(), s);
         if (nsplit > 0) {
           std::vector<uint32_t> owners(nsplit), io(2 * nsplit), wo(2 * nsplit);
           GM_HIP(hipMemcpyAsync(owners.data(), sown.p, nsplit * 4, hipMemcpyDeviceToHost, s));
@@ -950,7 +998,7 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
             }
           }
           const int64_t nseg = (int64_t)segs.size(), npairs = base;
-          Scratch dseg(nseg * sizeof(PieceSeg));
+          Scratch dseg(pool, nseg * sizeof(PieceSeg));
           GM_HIP(hipMemcpyAsync(dseg.p, segs.data(), nseg * sizeof(PieceSeg),
                                 hipMemcpyHostToDevice, s));
           plan_seg_bounds<<<plan_grid(nseg), kPlanThreads, 0, s>>>(dseg.as<PieceSeg>(), nseg,
@@ -961,23 +1009,23 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
               dseg.as<PieceSeg>(), nseg, npairs, p->work, g->in_off, g->in_idx, p->pstart,
               p->plen);
           GM_HIP(hipGetLastError());
-          Scratch ppre(npairs * 8), pflag(npairs), pstarts(npairs * 4);
-          exclusive_u64(p->plen, ppre.as<unsigned long long>(), npairs, s);
+          Scratch ppre(pool, npairs * 8), pflag(pool, npairs), pstarts(pool, npairs * 4);
+          exclusive_u64(pool, p->plen, ppre.as<unsigned long long>(), npairs, s);
           plan_piece_flags<<<plan_grid(npairs), kPlanThreads, 0, s>>>(
               dseg.as<PieceSeg>(), nseg, npairs, ppre.as<unsigned long long>(), block_work,
               pflag.as<uint8_t>());
           GM_HIP(hipGetLastError());
-          const int64_t np = select_flagged(pflag.as<uint8_t>(), npairs,
+          const int64_t np = select_flagged(pool, pflag.as<uint8_t>(), npairs,
                                             pstarts.as<uint32_t>(), s);
-          Scratch pit(np * sizeof(PieceItem)), pk1(np * 8), pk2(np * 8), pi1(np * 4),
-              pi2(np * 4);
+          Scratch pit(pool, np * sizeof(PieceItem)), pk1(pool, np * 8), pk2(pool, np * 8),
+              pi1(pool, np * 4), pi2(pool, np * 4);
           plan_piece_items<<<plan_grid(np), kPlanThreads, 0, s>>>(
               pstarts.as<uint32_t>(), np, dseg.as<PieceSeg>(), nseg, pit.as<PieceItem>(),
               pk1.as<unsigned long long>(), pi1.as<uint32_t>());
           GM_HIP(hipGetLastError());
           unsigned long long* pk = nullptr;
           uint32_t* pi = nullptr;
-          sort_pairs(pk1, pk2, pi1, pi2, np, 32, s, &pk, &pi);
+          sort_pairs(pool, pk1, pk2, pi1, pi2, np, 32, s, &pk, &pi);
           p->npieces = np;
           p->pieces = dalloc<PieceItem>(np);
           plan_gather<PieceItem><<<plan_grid(np), kPlanThreads, 0, s>>>(pit.as<PieceItem>(), pi,
