@@ -503,6 +503,33 @@ gm_status gm_autotune(gm_graph g, const gm_program* prog, int32_t batched, const
                       int64_t count, int32_t max_iters, int32_t trials, const char* cache_path,
                       gm_tuning* chosen, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Allocation-free entry point                                              */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): PageRank
+ * exactly as gm_run_vertex_program with GM_PROG_PAGERANK (rank: device float
+ * n, PR^0 in, PR^iters out; iters > 0 supersteps; r as there), but the
+ * per-run vectors (two message buffers and PR in the layout's labels, n
+ * floats each) and the per-tile partial sums live in a fixed device array of
+ * the library, GM_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, allocated with the
+ * code object and held until the process ends. A run on g needs
+ * 3 * align256(4 n) + 2 * align256(8 * ceil(m / 1024)) bytes of it (n up to
+ * about 5.5 million vertices). The call allocates nothing: the graph's pull
+ * layout must have been built (gm_graph_prepare with GM_PROG_PAGERANK, or an
+ * earlier PageRank run). All calls on one GPU share its array, so calls that
+ * overlap on one GPU (on different streams or threads) race; calls on one
+ * stream are ordered and safe. Asynchronous.
+ * Errors: GM_ESTATE (graph not live, or its pull layout not built);
+ * GM_EINVAL (rank NULL, iters <= 0, r outside [0, 1]); GM_EUNSUPPORTED
+ * (rating graph, no GM_LAYOUT_IN, more scratch needed than the array holds);
+ * GM_EHIP.
+ */
+#define GM_NOALLOC_SCRATCH_BYTES (64u << 20)
+gm_status gm_pagerank_noalloc(gm_graph g, float r, int32_t iters, float* rank, void* stream);
+
 /* Counters of the last gm_run_vertex_program call on a graph. */
 typedef struct gm_run_stats {
   int32_t supersteps;      /* supersteps run (as *iters_done) */

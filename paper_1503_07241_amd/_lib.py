@@ -111,6 +111,7 @@ def load():
                          ctypes.c_char_p, ctypes.POINTER(gm_tuning), vp], i32),
         "gm_graph_prepare": ([vp, ctypes.POINTER(gm_program), vp], i32),
         "gm_graph_release": ([vp], i32),
+        "gm_pagerank_noalloc": ([vp, ctypes.c_float, i32, vp, vp], i32),
         "gm_run_multi_graph": ([ctypes.POINTER(vp), i32, ctypes.POINTER(gm_program),
                                 ctypes.POINTER(i32), ctypes.POINTER(vp), i32,
                                 ctypes.POINTER(i32), vp], i32),

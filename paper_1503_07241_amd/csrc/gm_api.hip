@@ -589,6 +589,29 @@ gm_status gm_run_multi_graph(const gm_graph* graphs, int32_t count, const gm_pro
   return st == GM_OK ? ok() : fail(st, "%s", msg);
 }
 
+static_assert(kNoallocScratchBytes == GM_NOALLOC_SCRATCH_BYTES,
+              "the header states the array's size");
+
+gm_status gm_pagerank_noalloc(gm_graph g, float r, int32_t iters, float* rank, void* stream) {
+  if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
+  if (!rank) return fail(GM_EINVAL, "rank is NULL");
+  if (g->bipartite) return fail(GM_EUNSUPPORTED, "rating graphs take the CF calls only");
+  if (!(g->layouts & GM_LAYOUT_IN)) return fail(GM_EUNSUPPORTED, "PageRank needs GM_LAYOUT_IN");
+  if (iters <= 0) return fail(GM_EINVAL, "PageRank needs iters > 0");
+  if (!(r >= 0.0f && r <= 1.0f)) return fail(GM_EINVAL, "r outside [0, 1]");
+  return guarded([&]() -> gm_status {
+    if (const gm_status st = check_device(g)) return st;
+    if (!pull_schedule_ready(g))
+      return fail(GM_ESTATE, "the pull layout is not built: call gm_graph_prepare first");
+    const size_t need = pagerank_noalloc_bytes(g);
+    if (need > kNoallocScratchBytes)
+      return fail(GM_EUNSUPPORTED, "a run on this graph needs %zu bytes of scratch; the "
+                  "allocation-free array holds %zu", need, kNoallocScratchBytes);
+    run_pagerank_noalloc(g, r, iters, rank, static_cast<hipStream_t>(stream));
+    return ok();
+  });
+}
+
 gm_status gm_last_run_stats(gm_graph g, gm_run_stats* out) {
   if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
   if (!out) return fail(GM_EINVAL, "out is NULL");

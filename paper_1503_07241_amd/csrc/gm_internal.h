@@ -174,6 +174,12 @@ void free_graph_memory(gm_graph g);
 
 // PageRank family (pagerank.hip).
 void ensure_pull_schedule(gm_graph g, hipStream_t s);
+// Allocation-free PageRank: size of its fixed device array, whether g's pull
+// layout exists, the bytes a run on g needs from the array, and the run.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+bool pull_schedule_ready(gm_graph g);
+size_t pagerank_noalloc_bytes(gm_graph g);
+void run_pagerank_noalloc(gm_graph g, float r, int32_t iters, float* rank, hipStream_t s);
 void run_pagerank(gm_graph g, float r, int32_t iters, float* rank, int32_t seed, hipStream_t s);
 
 // Min programs (minprog.hip). Returns supersteps done.

@@ -25,12 +25,17 @@
 // last APPLY.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "gm_internal.h"
 #include "tiles.h"
+
+// Scratch of the allocation-free PageRank entry point (gm_pagerank_noalloc):
+// the two message buffers, PR and the per-tile partial sums of one run.
+static __device__ __align__(256) unsigned char scratch[gm::kNoallocScratchBytes];
 
 namespace gm {
 namespace {
@@ -482,17 +487,33 @@ static unsigned pull_grid(Dense* d, size_t lds, bool weighted, bool personal) {
   return (unsigned)std::max<int64_t>(1, std::min(fit, want));
 }
 
+namespace {
+
+// The per-run vectors of a PageRank run: the two message buffers, PR in the
+// new labels and the per-tile partial sums (the graph's own, or the fixed
+// scratch array of the allocation-free entry point).
+struct Vecs {
+  float* x[2];
+  float* pr;
+  double* head;
+  double* tail;
+};
+
+Vecs own_vecs(Dense* d) { return Vecs{{d->x[0], d->x[1]}, d->pr, d->head, d->tail}; }
+
+}  // namespace
+
 // Supersteps of (personalised, optionally weighted) PageRank from the rank
 // vector `rank0` (caller labels). w: relabelled edge values or NULL. After
 // the last superstep the ranks go to `rank_out`; with `hist` (T + 1 rows),
 // PR^t is also written to row t for t = 1..iters.
-static void pagerank_driver(gm_graph g, Dense* d, float r, int32_t iters, const float* rank0,
-                            int32_t seed_new, const float* w, float* hist, float* rank_out,
-                            hipStream_t st) {
+static void pagerank_driver(gm_graph g, Dense* d, const Vecs& v, float r, int32_t iters,
+                            const float* rank0, int32_t seed_new, const float* w, float* hist,
+                            float* rank_out, hipStream_t st) {
   const int64_t n = g->n;
   const bool weighted = w != nullptr;
   const bool personal = seed_new >= 0;
-  pr_send0<<<blocks_for(n), kThreads, 0, st>>>(rank0, d->old_of, d->inv_outdeg, n, d->x[0]);
+  pr_send0<<<blocks_for(n), kThreads, 0, st>>>(rank0, d->old_of, d->inv_outdeg, n, v.x[0]);
   GM_HIP(hipGetLastError());
   const int64_t c0 = d->rows, n0 = n - d->rows;
   auto const_rows = [&](float* xo, float* po) {
@@ -509,16 +530,16 @@ static void pagerank_driver(gm_graph g, Dense* d, float r, int32_t iters, const 
   const int hot_n = (int)std::min<int64_t>(std::min<int64_t>(g->tune.pr_hot, hot_cap), n);
   const size_t lds = (size_t)hot_n * sizeof(float);
   const unsigned grid = pull_grid(d, lds, weighted, personal);
-  const_rows(d->x[1], d->pr);
+  const_rows(v.x[1], v.pr);
   for (int32_t it = 0; it < iters; ++it) {
-    const float* xin = d->x[it & 1];
-    float* xout = d->x[(it + 1) & 1];
-    float* pout = (hist || it == iters - 1) ? d->pr : nullptr;
+    const float* xin = v.x[it & 1];
+    float* xout = v.x[(it + 1) & 1];
+    float* pout = (hist || it == iters - 1) ? v.pr : nullptr;
     auto launch = [&](auto kern) {
       if (d->ntiles > 0)
         kern<<<grid, kPullThreads, lds, st>>>(d->idx, w, d->starts, d->tile_row, d->ntiles, xin,
-                                              d->inv_outdeg, r, seed_new, xout, pout, d->head,
-                                              d->tail, hot_n);
+                                              d->inv_outdeg, r, seed_new, xout, pout, v.head,
+                                              v.tail, hot_n);
     };
     if (weighted && personal)
       launch(pr_pull<true, true>);
@@ -531,21 +552,21 @@ static void pagerank_driver(gm_graph g, Dense* d, float r, int32_t iters, const 
     if (d->ncross > 0) {
       const unsigned fb = (unsigned)((d->ncross * kCrossLanes + kThreads - 1) / kThreads);
       if (personal)
-        pr_cross<true><<<fb, kThreads, 0, st>>>(d->cross, d->ncross, d->head, d->tail,
+        pr_cross<true><<<fb, kThreads, 0, st>>>(d->cross, d->ncross, v.head, v.tail,
                                                  d->inv_outdeg, r, seed_new, xout, pout);
       else
-        pr_cross<false><<<fb, kThreads, 0, st>>>(d->cross, d->ncross, d->head, d->tail,
+        pr_cross<false><<<fb, kThreads, 0, st>>>(d->cross, d->ncross, v.head, v.tail,
                                                   d->inv_outdeg, r, seed_new, xout, pout);
     }
     GM_HIP(hipGetLastError());
-    if (it == 0) const_rows(d->x[0], nullptr);  // x[0] held PR^0 messages until now
+    if (it == 0) const_rows(v.x[0], nullptr);  // x[0] held PR^0 messages until now
     if (hist) {
-      pr_unpermute<<<blocks_for(n), kThreads, 0, st>>>(d->pr, d->new_of, n, hist + (it + 1) * n);
+      pr_unpermute<<<blocks_for(n), kThreads, 0, st>>>(v.pr, d->new_of, n, hist + (it + 1) * n);
       GM_HIP(hipGetLastError());
     }
   }
   if (rank_out) {
-    pr_unpermute<<<blocks_for(n), kThreads, 0, st>>>(d->pr, d->new_of, n, rank_out);
+    pr_unpermute<<<blocks_for(n), kThreads, 0, st>>>(v.pr, d->new_of, n, rank_out);
     GM_HIP(hipGetLastError());
   }
 }
@@ -558,8 +579,8 @@ void run_pagerank(gm_graph g, float r, int32_t iters, float* rank, int32_t seed,
     GM_HIP(hipMemcpyAsync(&seed_new, d->new_of + seed, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     GM_HIP(hipStreamSynchronize(st));
   }
-  pagerank_driver(g, d, r, iters, rank, seed_new, g->wtype == GM_W_F32 ? d->w : nullptr, nullptr,
-                  rank, st);
+  pagerank_driver(g, d, own_vecs(d), r, iters, rank, seed_new,
+                  g->wtype == GM_W_F32 ? d->w : nullptr, nullptr, rank, st);
 }
 
 // PR^0 = 1 for every vertex, then `iters` supersteps (no allocation and no
@@ -568,8 +589,8 @@ void enqueue_pagerank(gm_graph g, float r, int32_t iters, float* rank, hipStream
   Dense* d = dense(g);
   if (!d) throw Unsupported{"captured run not prepared"};
   fill_f32(rank, g->n, 1.0f, st);
-  pagerank_driver(g, d, r, iters, rank, -1, g->wtype == GM_W_F32 ? d->w : nullptr, nullptr, rank,
-                  st);
+  pagerank_driver(g, d, own_vecs(d), r, iters, rank, -1, g->wtype == GM_W_F32 ? d->w : nullptr,
+                  nullptr, rank, st);
 }
 
 void run_pagerank_history(gm_graph g, const float* w, float r, int32_t T, float* hist,
@@ -585,7 +606,56 @@ void run_pagerank_history(gm_graph g, const float* w, float r, int32_t T, float*
     gather_w<<<blocks_for(g->m), kThreads, 0, st>>>(w, d->ceid, g->m, d->wdyn);
     GM_HIP(hipGetLastError());
   }
-  pagerank_driver(g, d, r, T, hist, -1, d->wdyn, hist, nullptr, st);
+  pagerank_driver(g, d, own_vecs(d), r, T, hist, -1, d->wdyn, hist, nullptr, st);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free PageRank: the per-run vectors live in `scratch` (one copy
+// per device, held until the process ends) instead of the graph's workspace.
+// Host code reaches the array only through the address hipGetSymbolAddress
+// returns for the current device, kept per device.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+bool pull_schedule_ready(gm_graph g) { return dense(g) != nullptr; }
+
+size_t pagerank_noalloc_bytes(gm_graph g) {
+  const Dense* d = dense(g);
+  return 3 * align256((size_t)g->n * 4) + 2 * align256((size_t)std::max<int64_t>(d->ntiles, 1) * 8);
+}
+
+void run_pagerank_noalloc(gm_graph g, float r, int32_t iters, float* rank, hipStream_t st) {
+  Dense* d = dense(g);
+  if (!d) throw Unsupported{"pull layout not built"};
+  if (g->device < 0 || g->device >= kMaxDevices) throw Unsupported{"device ordinal out of range"};
+  char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[g->device]) {
+      void* ptr = nullptr;
+      GM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));  // the current device's copy
+      g_scratch_ptr[g->device] = ptr;
+    }
+    base = static_cast<char*>(g_scratch_ptr[g->device]);
+  }
+  const size_t xv = align256((size_t)g->n * 4);
+  const size_t tv = align256((size_t)std::max<int64_t>(d->ntiles, 1) * 8);
+  Vecs v;
+  v.x[0] = reinterpret_cast<float*>(base);
+  v.x[1] = reinterpret_cast<float*>(base + xv);
+  v.pr = reinterpret_cast<float*>(base + 2 * xv);
+  v.head = reinterpret_cast<double*>(base + 3 * xv);
+  v.tail = reinterpret_cast<double*>(base + 3 * xv + tv);
+  pagerank_driver(g, d, v, r, iters, rank, -1, g->wtype == GM_W_F32 ? d->w : nullptr, nullptr,
+                  rank, st);
 }
 
 }  // namespace gm
