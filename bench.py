@@ -16,7 +16,9 @@ counters, PageRank traverses all m edges per superstep, triangle counting
 sends one message along each of the m_dag DAG edges.
 
 After the timed steps (and outside them) the batched and adjoint forms are
-measured against the plain runs they replace, on the same GPU:
+measured against the plain runs they replace, on the same GPU, together
+with the paper's own triangle-counting and SSSP graphs (RMAT scale 20 with
+a = .45 and RMAT scale 24 with a = .50, Table 1) and a 2048 x 2048 grid:
   RMAT scale 20: 64-source BFS and SSSP, 128-seed personalised PageRank
   (20 supersteps) against 64 / 128 plain runs; the mixed batch of 32 RMAT
   graphs of scales 12-18 (BFS from each vertex 0 + 20 PageRank supersteps)
@@ -312,6 +314,8 @@ def main():
     forms = None
     if not args.no_forms:
         forms = measure_forms(gm, gg, torch, np, tm, g_dir, n, m_dir)
+    if not args.no_forms:
+        forms["paper_workloads"] = measure_paper_workloads(gm, gg, torch, np, tm)
     if not args.no_scale26:
         for g in (g_sym, g_dir, g_dag):
             g.close()
@@ -520,6 +524,61 @@ def measure_forms(gm, gg, torch, np, tm, g22, n22, m22):
         "forward_gteps": round(T * m22 / (tf * 1e-3) / 1e9, 2),
         "vjp_gteps": round(T * m22 / (tbk * 1e-3) / 1e9, 2)}
     log("pr grad: %s (%.1fs)" % (json.dumps(res["pr_weight_grad_rmat22_T20"]), time.time() - t0))
+    return res
+
+
+def measure_paper_workloads(gm, gg, torch, np, tm):
+    """The paper's own triangle-counting and SSSP graphs (Sec. 5.1, Table 1)
+    and a long-diameter graph: triangle counting on RMAT scale 20 with
+    a = .45, b = c = .15 (cold: work plan built inside the call; warm: plan
+    kept); SSSP from vertex 0 on RMAT scale 24 with a = .50, b = c = .10 and
+    on a 2048 x 2048 grid (thousands of supersteps: the per-superstep cost)."""
+    dev = torch.device("cuda:0")
+    res = {}
+    t0 = time.time()
+    n, s, d = gg.rmat(20, a=0.45, b=0.15, c=0.15)
+    g = gm.Graph.from_coo(n, s, d, prep=gm.GM_PREP_UPPER_DAG)
+    cnt = torch.empty(n, dtype=torch.int64, device=dev)
+
+    def tc_cold():
+        g.release()
+        cnt.zero_()
+        gm.run_vertex_program(g, gm.GM_PROG_TC, None, 1, cnt)
+
+    def tc_warm():
+        cnt.zero_()
+        gm.run_vertex_program(g, gm.GM_PROG_TC, None, 1, cnt)
+
+    tcold, twarm = tm.ms(tc_cold, 3), tm.ms(tc_warm, 5)
+    res["tc_rmat20_a45"] = {"m_dag": g.m, "cold_ms": round(tcold, 3), "warm_ms": round(twarm, 3),
+                            "gteps_warm": round(g.m / (twarm * 1e-3) / 1e9, 2),
+                            "gteps_cold": round(g.m / (tcold * 1e-3) / 1e9, 2)}
+    g.close()
+    root = torch.zeros(1, dtype=torch.int32, device=dev)
+    for name, (n, s, d) in (("sssp_rmat24_a50", gg.rmat(24, a=0.50, b=0.10, c=0.10)),
+                            ("sssp_grid2048", gg.grid2d(2048, 2048))):
+        w = gg.weights_u32(s, d)
+        g = gm.Graph.from_coo(n, s, d, w=w, prep=gm.GM_PREP_DROP_SELF_LOOPS,
+                              layouts=gm.GM_LAYOUT_OUT)
+        dist = torch.empty(n, dtype=torch.int32, device=dev)
+        info = {}
+
+        def run():
+            dist.fill_(-1)
+            dist[0] = 0
+            info["it"] = gm.run_vertex_program(g, gm.GM_PROG_SSSP, root, -1, dist)
+            info["edges"] = g.last_run_stats().edges_scanned
+
+        ms = tm.ms(run, 3)
+        res[name] = {"n": n, "m": g.m, "ms": round(ms, 3), "supersteps": info["it"],
+                     "us_per_superstep": round(1e3 * ms / max(info["it"], 1), 2),
+                     "edges_relaxed": int(info["edges"]),
+                     "gteps": round(info["edges"] / (ms * 1e-3) / 1e9, 2),
+                     "m_per_s_gteps": round(g.m / (ms * 1e-3) / 1e9, 2)}
+        g.close()
+        del dist
+    torch.cuda.empty_cache()
+    log("paper workloads: %s (%.1fs)" % (json.dumps(res), time.time() - t0))
     return res
 
 

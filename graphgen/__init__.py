@@ -210,6 +210,22 @@ def cf_point(n_users: int, n_items: int, k: int = CF_K, seed: int = SEED_CF_POIN
     return pu, pv
 
 
+def grid2d(rows: int, cols: int):
+    """A rows x cols 4-neighbour grid as a directed edge list with both
+    directions of every grid edge: vertex (i, j) is i * cols + j. Returns
+    (n, src, dst), int32 arrays. A long-diameter graph (rows + cols - 2
+    hops corner to corner), the shape of road networks' long paths."""
+    n = rows * cols
+    v = np.arange(n, dtype=np.int64).reshape(rows, cols)
+    right = (v[:, :-1].ravel(), v[:, 1:].ravel())
+    down = (v[:-1, :].ravel(), v[1:, :].ravel())
+    a = np.concatenate([right[0], down[0]])
+    b = np.concatenate([right[1], down[1]])
+    src = np.concatenate([a, b]).astype(np.int32)
+    dst = np.concatenate([b, a]).astype(np.int32)
+    return n, src, dst
+
+
 def mixed_batch_specs(count: int = 32, base_scale: int = 12, span: int = 7):
     """(scale, seed) of the graphs of the mixed batch: scale 12 + (i mod 7)."""
     return [(base_scale + (i % span), SEED_MIXED_BASE + i) for i in range(count)]

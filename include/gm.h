@@ -99,6 +99,30 @@ gm_status gm_graph_from_coo(int64_t n, int64_t m, const int32_t* src, const int3
                             const void* w, int32_t wtype, uint32_t prep, uint32_t layouts,
                             void* stream, gm_graph* out);
 
+/*
+ * Read a Matrix Market file, the graph format of the paper's API (App. A,
+ * ReadMTX): a "coordinate" matrix with field pattern, integer or real and
+ * symmetry general or symmetric. Entry (i, j) is the edge i-1 -> j-1 (the
+ * off-diagonal entries of a symmetric file also give j-1 -> i-1) and its
+ * value the edge value: integer -> GM_W_U32 (values in [0, 2^32 - 1]),
+ * real -> GM_W_F32, pattern -> GM_W_NONE. n = max(rows, cols).
+ * Two-call use: with src, dst and w all NULL, *n, *m and *wtype receive the
+ * sizes; then host arrays of *m entries (src, dst int32; w uint32 or float
+ * per *wtype; any of them may be NULL) are filled, *m on input being their
+ * length. Host only: no device work.
+ * Errors: GM_EINVAL (path/n/m/wtype NULL, file unreadable or malformed, an
+ * entry outside the matrix, arrays shorter than the edge count);
+ * GM_EUNSUPPORTED (another field or symmetry, an integer outside uint32).
+ */
+gm_status gm_mtx_read(const char* path, int64_t* n, int64_t* m, int32_t* src, int32_t* dst,
+                      void* w, int32_t* wtype);
+
+/* gm_mtx_read, then gm_graph_from_coo with the file's edges and values
+ * (App. A's ReadMTX followed by the preprocessing `prep`). Errors: as those
+ * two calls. Synchronises `stream`. */
+gm_status gm_graph_from_mtx(const char* path, uint32_t prep, uint32_t layouts, void* stream,
+                            gm_graph* out);
+
 typedef struct gm_graph_info {
   int64_t n;          /* vertices */
   int64_t m;          /* stored directed edges after preprocessing */
@@ -158,15 +182,27 @@ enum {
    * program 1's output. Property uint64 count; every vertex u sends its
    * in-neighbour list along its out-edges; PROCESS |in(u) ∩ in(v)|;
    * REDUCE +; APPLY count(v) += y. One superstep; frontier must be NULL. */
-  GM_PROG_TC = 5
+  GM_PROG_TC = 5,
+  /* Vertex degree as a generalized SpMV with a ones vector (Fig. 1 of the
+   * paper): every vertex sends; PROCESS gives 1 per edge; REDUCE +; APPLY
+   * sets the property (uint32, written from 0 by the call) to the sum. With
+   * GM_ORDER_OUT a vertex counts its in-edges, with GM_ORDER_IN its
+   * out-edges (needs GM_LAYOUT_IN), with GM_ORDER_ALL both. One superstep;
+   * frontier must be NULL. */
+  GM_PROG_DEGREE = 6
 };
 
-/* Edge direction messages travel along (App. A, `order`). */
+/* Edges messages travel along (App. A, `order`; Sec. 4.1): out-edges (the
+ * receivers of u are its out-neighbours), in-edges (its in-neighbours, i.e.
+ * the transposed graph), or both. BFS, SSSP and the degree program take all
+ * three (IN and ALL need GM_LAYOUT_IN, SSSP's weights then come with either
+ * direction's edge); the other programs and the batched, captured and
+ * multi-graph forms take GM_ORDER_OUT. */
 enum { GM_ORDER_OUT = 1, GM_ORDER_IN = 2, GM_ORDER_ALL = 3 };
 
 typedef struct gm_program {
   int32_t kind;   /* GM_PROG_* */
-  int32_t order;  /* GM_ORDER_*; only GM_ORDER_OUT is supported */
+  int32_t order;  /* GM_ORDER_* */
   float r;        /* PageRank random-surf probability (Eq. (1)); 0.15 */
   uint32_t flags; /* reserved, must be 0 */
 } gm_program;
@@ -220,13 +256,16 @@ gm_status gm_graph_release(gm_graph g);
  * (vprop, active) exactly.
  * BFS and SSSP accept either frontier form (ids or bitmap); PPR takes its
  * seed from ids only.
- * Errors: GM_ESTATE; GM_EINVAL (prog/vprop NULL, unknown kind, order not
- * OUT, flags != 0, frontier missing or count < 0 or ids NULL with
+ * Errors: GM_ESTATE; GM_EINVAL (prog/vprop NULL, unknown kind or order,
+ * flags != 0, frontier missing or count < 0 or ids NULL with
  * count > 0, both ids and bitmap given, a bitmap for PPR, an id out of
- * range, PageRank with max_iters <= 0, r outside [0, 1]); GM_EUNSUPPORTED
- * (program needs a layout or weight type the graph lacks); GM_ENOMEM;
- * GM_EHIP.
- * BFS and SSSP synchronise `stream` once per superstep; PageRank is
+ * range, PageRank with max_iters <= 0, r outside [0, 1], a frontier for
+ * the degree program); GM_EUNSUPPORTED (program needs a layout or weight
+ * type the graph lacks, an order the program does not take, GM_ORDER_ALL
+ * beyond 2^32 - 1 edges in both directions); GM_ENOMEM; GM_EHIP.
+ * BFS and SSSP synchronise `stream` after batches of supersteps (the
+ * first of superstep_batch, each later one twice as long, at most 64; the
+ * supersteps after the frontier empties do nothing); PageRank is
  * asynchronous.
  */
 gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_frontier* frontier,
@@ -448,8 +487,9 @@ gm_status gm_plan_destroy(gm_plan p);
 typedef struct gm_tuning {
   uint32_t pull_div;        /* BFS: pull superstep when more than n / pull_div
                                vertices are active (1..65536; 128) */
-  uint32_t superstep_batch; /* BFS/SSSP: supersteps enqueued between two host
-                               checks of the frontier (1..64; 4) */
+  uint32_t superstep_batch; /* BFS/SSSP: supersteps enqueued before the first
+                               host check of the frontier; each later batch is
+                               twice as long, up to 64 (1..64; 4) */
   uint32_t push_blocks;     /* workgroups of the push kernels, plain and batched
                                SSSP (64..65536; 2048) */
   uint32_t ppr_chunk;       /* batched PPR: in-edges per work item (64..65536; 128) */

@@ -292,6 +292,16 @@ def pagerank_step_rows(prev: np.ndarray, outdeg: np.ndarray, src: np.ndarray, ds
     return r + (1.0 - r) * y
 
 
+def degree(g: Graph, order: str = "out") -> np.ndarray:
+    """The degree program of Fig. 1 (an SpMV of the adjacency with a ones
+    vector) by counting: messages along out-edges reach each vertex once per
+    in-edge, so order 'out' gives in-degrees; 'in' gives out-degrees; 'all'
+    their sum (int64)."""
+    indeg = np.bincount(g.idx, minlength=g.n).astype(np.int64)
+    outdeg = np.diff(g.off).astype(np.int64)
+    return {"out": indeg, "in": outdeg, "all": indeg + outdeg}[order]
+
+
 def dag_in_lists(dag: Graph) -> Graph:
     """Program 1 of the triangle count (Sec. 4.2): sorted in-neighbour lists."""
     return dag.transpose()

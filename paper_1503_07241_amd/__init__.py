@@ -18,7 +18,8 @@ import numpy as np
 from . import _lib
 from ._lib import (GM_LAYOUT_IN, GM_LAYOUT_OUT, GM_ORDER_ALL, GM_ORDER_IN, GM_ORDER_OUT,  # noqa: F401
                    GM_PREP_DROP_SELF_LOOPS, GM_PREP_SYMMETRIZE, GM_PREP_UPPER_DAG, GM_PROG_BFS,
-                   GM_PROG_PAGERANK, GM_PROG_PPR, GM_PROG_SSSP, GM_PROG_TC, GM_W_F32, GM_W_NONE,
+                   GM_PROG_DEGREE, GM_PROG_PAGERANK, GM_PROG_PPR, GM_PROG_SSSP, GM_PROG_TC,
+                   GM_W_F32, GM_W_NONE,
                    GM_W_U32,
                    GmError)
 
@@ -77,6 +78,27 @@ def _host(a, dtype):
     return a, a.ctypes.data
 
 
+def read_mtx(path: str):
+    """gm_mtx_read: (n, src, dst, w) host arrays of a Matrix Market file; w is
+    None, uint32 or float32 by the file's field."""
+    lib = _lib.load()
+    n, m, wt = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int32(0)
+    p = str(path).encode()
+    _lib.check(lib.gm_mtx_read(p, ctypes.byref(n), ctypes.byref(m), None, None, None,
+                               ctypes.byref(wt)), "gm_mtx_read")
+    src = np.empty(m.value, dtype=np.int32)
+    dst = np.empty(m.value, dtype=np.int32)
+    w = None
+    if wt.value == GM_W_U32:
+        w = np.empty(m.value, dtype=np.uint32)
+    elif wt.value == GM_W_F32:
+        w = np.empty(m.value, dtype=np.float32)
+    _lib.check(lib.gm_mtx_read(p, ctypes.byref(n), ctypes.byref(m), src.ctypes.data,
+                               dst.ctypes.data, None if w is None else w.ctypes.data,
+                               ctypes.byref(wt)), "gm_mtx_read")
+    return int(n.value), src, dst, w
+
+
 def version() -> str:
     return _lib.load().gm_version().decode()
 
@@ -119,6 +141,16 @@ class Graph:
         out = ctypes.c_void_p()
         _lib.check(lib.gm_graph_from_coo(n, len(s), sp, dp, wp, wtype, prep, layouts,
                                          _stream(stream), ctypes.byref(out)), "gm_graph_from_coo")
+        return cls(out.value)
+
+    @classmethod
+    def from_mtx(cls, path: str, prep: int = GM_PREP_DROP_SELF_LOOPS,
+                 layouts: int = GM_LAYOUT_OUT | GM_LAYOUT_IN, stream=None) -> "Graph":
+        """gm_graph_from_mtx: a Matrix Market file (App. A, ReadMTX)."""
+        out = ctypes.c_void_p()
+        _lib.check(_lib.load().gm_graph_from_mtx(str(path).encode(), prep, layouts,
+                                                 _stream(stream), ctypes.byref(out)),
+                   "gm_graph_from_mtx")
         return cls(out.value)
 
     def info(self) -> _lib.gm_graph_info:
@@ -210,13 +242,14 @@ class Graph:
 
 
 def run_vertex_program(g: Graph, kind: int, frontier, max_iters: int, vprop, active_out=None,
-                       r: float = 0.15, stream=None, bitmap=None) -> int:
+                       r: float = 0.15, stream=None, bitmap=None, order: int = GM_ORDER_OUT) -> int:
     """gm_run_vertex_program. frontier: device int32 tensor of active ids (or
     None for PageRank); bitmap: instead of ids, a device int32/uint32 tensor
     of ceil(n / 32) words with bit v set for an active v; vprop: device
     property tensor (int32 levels, uint32 distances as int32 storage, float32
-    ranks). Returns supersteps done."""
-    prog = _lib.gm_program(kind, GM_ORDER_OUT, r, 0)
+    ranks); order: GM_ORDER_OUT / IN / ALL, the edges messages travel
+    along. Returns supersteps done."""
+    prog = _lib.gm_program(kind, order, r, 0)
     n = g.n
     fr = None
     if bitmap is not None:

@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "GM_OK", 1: "GM_EINVAL", 2: "GM_ENOMEM", 3: "GM_EHIP", 4: "GM
 GM_PREP_DROP_SELF_LOOPS, GM_PREP_SYMMETRIZE, GM_PREP_UPPER_DAG = 1, 2, 4
 GM_W_NONE, GM_W_U32, GM_W_F32 = 0, 1, 2
 GM_LAYOUT_OUT, GM_LAYOUT_IN = 1, 2
-GM_PROG_BFS, GM_PROG_SSSP, GM_PROG_PAGERANK, GM_PROG_PPR, GM_PROG_TC = 1, 2, 3, 4, 5
+GM_PROG_BFS, GM_PROG_SSSP, GM_PROG_PAGERANK, GM_PROG_PPR, GM_PROG_TC, GM_PROG_DEGREE = range(1, 7)
 GM_ORDER_OUT, GM_ORDER_IN, GM_ORDER_ALL = 1, 2, 3
 
 
@@ -110,6 +110,9 @@ def load():
         "gm_autotune": ([vp, ctypes.POINTER(gm_program), i32, vp, i64, i32, i32,
                          ctypes.c_char_p, ctypes.POINTER(gm_tuning), vp], i32),
         "gm_graph_prepare": ([vp, ctypes.POINTER(gm_program), vp], i32),
+        "gm_mtx_read": ([ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp, vp,
+                         ctypes.POINTER(i32)], i32),
+        "gm_graph_from_mtx": ([ctypes.c_char_p, u32, u32, vp, ctypes.POINTER(vp)], i32),
         "gm_graph_release": ([vp], i32),
         "gm_pagerank_noalloc": ([vp, ctypes.c_float, i32, vp, vp], i32),
         "gm_run_multi_graph": ([ctypes.POINTER(vp), i32, ctypes.POINTER(gm_program),

@@ -216,6 +216,7 @@ gm_status gm_graph_prepare(gm_graph g, const gm_program* prog, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   switch (kind) {
     case GM_PROG_BFS:
+    case GM_PROG_DEGREE:
       break;
     case GM_PROG_SSSP:
       if (g->wtype != GM_W_U32) return fail(GM_EUNSUPPORTED, "SSSP needs uint32 edge weights");
@@ -233,7 +234,7 @@ gm_status gm_graph_prepare(gm_graph g, const gm_program* prog, void* stream) {
   }
   return guarded([&]() -> gm_status {
     if (const gm_status st = check_device(g)) return st;
-    if (kind == GM_PROG_BFS || kind == GM_PROG_SSSP) {
+    if (kind == GM_PROG_BFS || kind == GM_PROG_SSSP || kind == GM_PROG_DEGREE) {
       prepare_min_program(g, s);
     } else if (kind == GM_PROG_TC) {
       prepare_triangle_count(g, s);
@@ -269,11 +270,30 @@ gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_fro
   if (g->bipartite) return fail(GM_EUNSUPPORTED, "rating graphs take the CF calls only");
   const int kind = prog->kind;
   if (kind != GM_PROG_BFS && kind != GM_PROG_SSSP && kind != GM_PROG_PAGERANK &&
-      kind != GM_PROG_PPR && kind != GM_PROG_TC)
+      kind != GM_PROG_PPR && kind != GM_PROG_TC && kind != GM_PROG_DEGREE)
     return fail(GM_EINVAL, "unknown program kind %d", kind);
-  if (prog->order != GM_ORDER_OUT)
-    return fail(GM_EINVAL, "order %d: only GM_ORDER_OUT is supported", prog->order);
+  const int order = prog->order;
+  if (order != GM_ORDER_OUT && order != GM_ORDER_IN && order != GM_ORDER_ALL)
+    return fail(GM_EINVAL, "unknown order %d", order);
+  const bool frontier_prog = kind == GM_PROG_BFS || kind == GM_PROG_SSSP || kind == GM_PROG_DEGREE;
+  if (order != GM_ORDER_OUT && !frontier_prog)
+    return fail(GM_EUNSUPPORTED, "order %d: this program runs along out-edges only", order);
+  if (order != GM_ORDER_OUT && !(g->layouts & GM_LAYOUT_IN))
+    return fail(GM_EUNSUPPORTED, "GM_ORDER_IN / GM_ORDER_ALL need GM_LAYOUT_IN");
   if (prog->flags != 0) return fail(GM_EINVAL, "flags must be 0");
+  if (kind == GM_PROG_DEGREE) {
+    if (frontier) return fail(GM_EINVAL, "the degree program takes no frontier (all vertices send)");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return guarded([&]() -> gm_status {
+      if (const gm_status st = check_device(g)) return st;
+      // one superstep: every vertex sends once, nobody changes afterwards
+      const int32_t it = run_min_program(g, kind, order, nullptr, 0, nullptr, 1,
+                                         static_cast<uint32_t*>(vprop), active_out, s,
+                                         &g->last_stats);
+      if (iters_done) *iters_done = it;
+      return ok();
+    });
+  }
   if (kind == GM_PROG_TC) {
     if (frontier) return fail(GM_EINVAL, "triangle counting takes no frontier (all vertices send)");
     if (!(g->prep & GM_PREP_UPPER_DAG) || !(g->layouts & GM_LAYOUT_IN))
@@ -339,7 +359,7 @@ gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_fro
       g->last_stats.pull_supersteps = it;
       g->last_stats.edges_scanned = (unsigned long long)g->m * it;
     } else {
-      it = run_min_program(g, kind, bitmap ? nullptr : frontier->ids,
+      it = run_min_program(g, kind, order, bitmap ? nullptr : frontier->ids,
                            bitmap ? 0 : frontier->count, bitmap, max_iters,
                            static_cast<uint32_t*>(vprop), active_out, s, &g->last_stats);
     }

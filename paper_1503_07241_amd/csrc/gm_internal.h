@@ -63,7 +63,8 @@ struct RunStats {
 struct Tuning {
   // BFS: pull superstep when the frontier holds more than n / pull_div vertices
   uint32_t pull_div = 128;
-  // supersteps launched between two host checks of the frontier size
+  // supersteps launched before the first host check of the frontier size;
+  // each later batch doubles, up to 64
   uint32_t superstep_batch = 4;
   // workgroups of the push kernels (plain and batched SSSP)
   uint32_t push_blocks = 2048;
@@ -184,7 +185,8 @@ void run_pagerank(gm_graph g, float r, int32_t iters, float* rank, int32_t seed,
 
 // Min programs (minprog.hip). Returns supersteps done.
 // The first frontier is `bitmap` (n bits) when non-NULL, else the ids.
-int32_t run_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count,
+// order: GM_ORDER_* (the edges messages travel along).
+int32_t run_min_program(gm_graph g, int kind, int order, const int32_t* ids, int64_t count,
                         const uint32_t* bitmap, int32_t max_iters, uint32_t* prop,
                         int32_t* active_out, hipStream_t s, RunStats* stats);
 void free_min_workspace(gm_graph g);

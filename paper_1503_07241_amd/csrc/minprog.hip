@@ -27,6 +27,7 @@
 // Messages are snapshotted before the product and min is exact and
 // order-free, so every superstep leaves exactly the state of Alg. 2. Only
 // non-returning atomics are used on the hot path.
+#include <algorithm>
 #include <cstring>
 
 #include "gm_internal.h"
@@ -38,7 +39,8 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kUnroll = 4;  // edge rounds in flight per wavefront
 constexpr uint32_t kInfBfs = 0x7FFFFFFFu;
-constexpr int kMaxCtl = 64;  // control records per launch batch
+constexpr int kMaxCtl = 64;  // control records per launch batch (one more is allocated)
+constexpr uint64_t kMinWaveEdges = 512;  // push: fewest edges per working wavefront
 
 struct Ctl {
   unsigned long long packed;  // (queued vertices << 32) | their out-edges
@@ -55,6 +57,20 @@ struct Workspace {
   uint32_t* bits[2] = {nullptr, nullptr};
   Ctl* ctl = nullptr;         // kMaxCtl records
   Ctl* host_ctl = nullptr;    // pinned mirror
+  // GM_ORDER_ALL adjacency (built on first use): off = out_off + in_off,
+  // each vertex's out-list followed by its in-list (values alike)
+  uint32_t* all_off = nullptr;
+  int32_t* all_idx = nullptr;
+  uint32_t* all_w = nullptr;
+};
+
+// The adjacency a superstep pushes messages along: out-edges (GM_ORDER_OUT),
+// in-edges (GM_ORDER_IN), or both (GM_ORDER_ALL: each vertex's out-list
+// followed by its in-list, built once per graph).
+struct Adj {
+  const uint32_t* off;
+  const int32_t* idx;
+  const uint32_t* w;
 };
 
 __device__ inline bool use_pull(const Ctl& c, int kind, bool pull_ok, int64_t n,
@@ -66,7 +82,9 @@ __device__ inline bool use_pull(const Ctl& c, int kind, bool pull_ok, int64_t n,
 
 template <int kKind>
 __device__ inline uint32_t process(uint32_t msg, uint32_t w) {
-  if constexpr (kKind == GM_PROG_SSSP) {
+  if constexpr (kKind == GM_PROG_DEGREE) {
+    return 1u;  // every edge carries a one (Fig. 1: degree as an SpMV with a ones vector)
+  } else if constexpr (kKind == GM_PROG_SSSP) {
     const uint32_t s = msg + w;
     return s < msg ? 0xFFFFFFFFu : s;  // saturating add
   } else {
@@ -119,22 +137,40 @@ __global__ __launch_bounds__(kThreads) void seed_bitmap(const uint32_t* __restri
   }
 }
 
+// Every vertex active (the first frontier of the degree program).
+__global__ __launch_bounds__(kThreads) void seed_all(int64_t words, int64_t n, uint32_t* bits) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t left = n - 32 * i;
+    bits[i] = left >= 32 ? 0xFFFFFFFFu : (1u << left) - 1u;
+  }
+}
+
 // SEND: frontier bitvector -> queue (vertex, message, first edge, edge prefix).
 // A thread takes one 32-bit word; for a nonzero word it reads the 33
 // offsets around its 32 vertices at once (independent loads, unrolled), so
 // that a dense word costs one memory round trip, not one per set bit.
+// The same pass clears the other bitvector (the frontier before this one,
+// read by nobody any more), into which this superstep's product writes the
+// next frontier, and resets the next superstep's control record.
 __global__ __launch_bounds__(kThreads) void send_kernel(
-    const uint32_t* __restrict__ bits, int64_t words, int64_t n,
+    const uint32_t* __restrict__ bits, uint32_t* __restrict__ other, int64_t words, int64_t n,
     const uint32_t* __restrict__ prop, const uint32_t* __restrict__ off, int32_t* __restrict__ q,
     uint32_t* __restrict__ qmsg, uint32_t* __restrict__ qbeg, uint32_t* __restrict__ qest,
-    Ctl* __restrict__ ctl) {
+    Ctl* __restrict__ ctl, Ctl* __restrict__ next_ctl) {
   __shared__ uint32_t sh[2 * kWaves];
   __shared__ unsigned long long base_packed;
+  if (next_ctl && blockIdx.x == 0 && threadIdx.x == 0) {
+    next_ctl->packed = 0;
+    next_ctl->msg_min = 0xFFFFFFFFu;
+    next_ctl->msg_max = 0;
+  }
   uint32_t mn = 0xFFFFFFFFu, mx = 0;
   for (int64_t w0 = (int64_t)blockIdx.x * kThreads; w0 < words;
        w0 += (int64_t)gridDim.x * kThreads) {
     const int64_t wi = w0 + threadIdx.x;
     const uint32_t word = wi < words ? bits[wi] : 0u;
+    if (wi < words) other[wi] = 0u;
     if (!__syncthreads_or(word != 0u)) continue;  // no active vertex in the block's words
     const uint32_t cnt = __popc(word);
     const int64_t v0 = wi * 32;
@@ -212,8 +248,12 @@ __global__ __launch_bounds__(kThreads) void push_kernel(
   const uint64_t E = (uint32_t)c.packed;
   if (count == 0 || E == 0) return;
   const int lane = threadIdx.x & 63;
-  const uint64_t nw = (uint64_t)gridDim.x * kWaves;
+  // at least kMinWaveEdges edges per working wavefront: a small frontier
+  // keeps the others idle instead of spreading a few edges over all of them
+  const uint64_t nw = std::min<uint64_t>((uint64_t)gridDim.x * kWaves,
+                                         (E + kMinWaveEdges - 1) / kMinWaveEdges);
   const uint64_t wid = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (wid >= nw) return;
   const uint32_t e_begin = (uint32_t)(E * wid / nw);
   const uint32_t e_end = (uint32_t)(E * (wid + 1) / nw);
   if (e_begin >= e_end) return;
@@ -275,9 +315,17 @@ __global__ __launch_bounds__(kThreads) void push_kernel(
 #pragma unroll
         for (int k = 0; k < kUnroll; ++k) cand[k] = process<kKind>(cand[k], 0u);
       }
+      if constexpr (kKind == GM_PROG_DEGREE) {  // REDUCE + (APPLY: the sum itself)
 #pragma unroll
-      for (int k = 0; k < kUnroll; ++k)
-        if (act[k]) relax(cand[k], dst[k], prop, next);
+        for (int k = 0; k < kUnroll; ++k)
+          if (act[k])
+            __hip_atomic_fetch_add(&prop[dst[k]], cand[k], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k)
+          if (act[k]) relax(cand[k], dst[k], prop, next);
+      }
     }
     e = stop;
   }
@@ -355,6 +403,35 @@ inline unsigned blocks_for(int64_t n, int64_t cap = 8192) {
   return (unsigned)b;
 }
 
+__global__ void all_offsets(const uint32_t* __restrict__ out_off, const uint32_t* __restrict__ in_off,
+                            int64_t n, uint32_t* __restrict__ all_off) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    all_off[v] = out_off[v] + in_off[v];
+}
+
+// One wavefront per vertex: its out-list, then its in-list.
+__global__ void all_lists(const uint32_t* __restrict__ out_off, const int32_t* __restrict__ out_idx,
+                          const uint32_t* __restrict__ out_w, const uint32_t* __restrict__ in_off,
+                          const int32_t* __restrict__ in_idx, const uint32_t* __restrict__ in_w,
+                          int64_t n, const uint32_t* __restrict__ all_off,
+                          int32_t* __restrict__ all_idx, uint32_t* __restrict__ all_w) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t v = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; v < n; v += waves) {
+    const uint32_t ob = out_off[v], oe = out_off[v + 1], ib = in_off[v], ie = in_off[v + 1];
+    const uint32_t base = all_off[v], mid = base + (oe - ob);
+    for (uint32_t j = lane; j < oe - ob; j += 64) {
+      all_idx[base + j] = out_idx[ob + j];
+      if (all_w) all_w[base + j] = out_w[ob + j];
+    }
+    for (uint32_t j = lane; j < ie - ib; j += 64) {
+      all_idx[mid + j] = in_idx[ib + j];
+      if (all_w) all_w[mid + j] = in_w[ib + j];
+    }
+  }
+}
+
 Workspace* ensure_ws(gm_graph g, hipStream_t s) {
   Workspace* ws = static_cast<Workspace*>(g->min_ws);
   if (ws) return ws;
@@ -370,7 +447,7 @@ Workspace* ensure_ws(gm_graph g, hipStream_t s) {
     ws->qest = dalloc<uint32_t>(n);
     ws->bits[0] = dalloc<uint32_t>(words);
     ws->bits[1] = dalloc<uint32_t>(words);
-    ws->ctl = dalloc<Ctl>(kMaxCtl);
+    ws->ctl = dalloc<Ctl>(kMaxCtl + 1);
     void* h = nullptr;
     GM_HIP(hipHostMalloc(&h, kMaxCtl * sizeof(Ctl), hipHostMallocDefault));
     ws->host_ctl = static_cast<Ctl*>(h);
@@ -382,6 +459,43 @@ Workspace* ensure_ws(gm_graph g, hipStream_t s) {
     throw;
   }
   return ws;
+}
+
+// The adjacency messages travel along for `order` (the in-layout is needed
+// for GM_ORDER_IN and GM_ORDER_ALL).
+Adj adjacency(gm_graph g, Workspace* ws, int order, hipStream_t s) {
+  if (order == GM_ORDER_IN)
+    return Adj{g->in_off, g->in_idx, static_cast<const uint32_t*>(g->in_w)};
+  if (order != GM_ORDER_ALL)
+    return Adj{g->out_off, g->out_idx, static_cast<const uint32_t*>(g->out_w)};
+  if (!ws->all_off) {
+    const int64_t n = g->n, m = g->m;
+    if (2 * m > (int64_t)UINT32_MAX) throw Unsupported{"GM_ORDER_ALL: more than 2^32 - 1 edges"};
+    const bool weighted = g->wtype == GM_W_U32;
+    uint32_t* off = nullptr;
+    int32_t* idx = nullptr;
+    uint32_t* w = nullptr;
+    try {
+      off = dalloc<uint32_t>(n + 1);
+      idx = dalloc<int32_t>(2 * m + kIdxPad);
+      if (weighted) w = dalloc<uint32_t>(2 * m);
+      all_offsets<<<blocks_for(n + 1), kThreads, 0, s>>>(g->out_off, g->in_off, n, off);
+      all_lists<<<blocks_for(64 * n), kThreads, 0, s>>>(
+          g->out_off, g->out_idx, static_cast<const uint32_t*>(g->out_w), g->in_off, g->in_idx,
+          static_cast<const uint32_t*>(g->in_w), n, off, idx, w);
+      GM_HIP(hipGetLastError());
+      GM_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      dfree(off);
+      dfree(idx);
+      dfree(w);
+      throw;
+    }
+    ws->all_idx = idx;
+    ws->all_w = w;
+    ws->all_off = off;
+  }
+  return Adj{ws->all_off, ws->all_idx, ws->all_w};
 }
 
 }  // namespace
@@ -402,6 +516,9 @@ void free_min_workspace(gm_graph g) {
   dfree(ws->bits[0]);
   dfree(ws->bits[1]);
   dfree(ws->ctl);
+  dfree(ws->all_off);
+  dfree(ws->all_idx);
+  dfree(ws->all_w);
   if (ws->host_ctl) (void)hipHostFree(ws->host_ctl);
   delete ws;
   g->min_ws = nullptr;
@@ -428,36 +545,49 @@ bool ids_in_range(const int32_t* ids, int64_t count, int64_t n, hipStream_t s) {
 
 namespace {
 
-// One superstep on control record c: SEND from bits[cur], then the push or
-// the pull product into bits[cur ^ 1]; bits[cur] is cleared afterwards.
-void enqueue_superstep(gm_graph g, Workspace* ws, int kind, Ctl* c, int cur, uint32_t* prop,
-                       hipStream_t s) {
+// One superstep on control record c (reset beforehand): SEND from bits[cur]
+// (which also clears bits[cur ^ 1] and resets the record c + 1 of the next
+// superstep), then the push or the pull product into bits[cur ^ 1]. After
+// the last superstep of a run, bits[cur] of that superstep holds a stale
+// frontier, which the run's epilogue clears.
+void enqueue_superstep(gm_graph g, Workspace* ws, int kind, const Adj& a, Ctl* c, int cur,
+                       uint32_t* prop, hipStream_t s) {
   const int64_t n = g->n;
   const int64_t words = (n + 31) / 32;
   const bool sym = (g->prep & (GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG)) == GM_PREP_SYMMETRIZE;
   const uint32_t* pull_off = sym ? g->out_off : g->in_off;
   const int32_t* pull_idx = sym ? g->out_idx : g->in_idx;
-  const bool pull_ok = kind == GM_PROG_BFS && pull_off != nullptr;
+  // pull supersteps only for BFS along out-edges
+  const bool pull_ok = kind == GM_PROG_BFS && a.off == g->out_off && pull_off != nullptr;
   const uint32_t pull_div = g->tune.pull_div;
   const unsigned push_blocks = g->tune.push_blocks;
-  reset_ctl<<<1, 1, 0, s>>>(c);
-  send_kernel<<<blocks_for(words, 4096), kThreads, 0, s>>>(ws->bits[cur], words, g->n, prop,
-                                                           g->out_off,
-                                                           ws->q, ws->qmsg, ws->qbeg, ws->qest, c);
+  send_kernel<<<blocks_for(words, 4096), kThreads, 0, s>>>(
+      ws->bits[cur], ws->bits[cur ^ 1], words, g->n, prop, a.off, ws->q, ws->qmsg, ws->qbeg,
+      ws->qest, c, c + 1);
   if (kind == GM_PROG_SSSP)
     push_kernel<GM_PROG_SSSP><<<push_blocks, kThreads, 0, s>>>(
-        c, n, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, g->out_idx,
-        static_cast<const uint32_t*>(g->out_w), prop, ws->bits[cur ^ 1]);
+        c, n, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, a.idx, a.w, prop,
+        ws->bits[cur ^ 1]);
+  else if (kind == GM_PROG_DEGREE)
+    push_kernel<GM_PROG_DEGREE><<<push_blocks, kThreads, 0, s>>>(
+        c, n, false, pull_div, ws->qmsg, ws->qbeg, ws->qest, a.idx, nullptr, prop,
+        ws->bits[cur ^ 1]);
   else
     push_kernel<GM_PROG_BFS><<<push_blocks, kThreads, 0, s>>>(
-        c, n, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, g->out_idx, nullptr, prop,
+        c, n, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, a.idx, nullptr, prop,
         ws->bits[cur ^ 1]);
   if (pull_ok)
     pull_kernel<<<blocks_for(n, 8192), kThreads, 0, s>>>(c, n, pull_ok, pull_div, pull_off, pull_idx,
                                                          ws->bits[cur], prop, ws->bits[cur ^ 1]);
-  fill_kernel<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[cur], words, 0);
   GM_HIP(hipGetLastError());
 }
+
+// Zero a control record (the first of a batch of supersteps).
+void start_batch(Workspace* ws, hipStream_t s) {
+  reset_ctl<<<1, 1, 0, s>>>(ws->ctl);
+  GM_HIP(hipGetLastError());
+}
+
 
 // prop[v] = 0 and v active, for every id.
 __global__ void seed_sources(const int32_t* __restrict__ ids, int64_t count, uint32_t* prop,
@@ -521,12 +651,15 @@ void enqueue_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count
     seed_sources<<<blocks_for(count), kThreads, 0, s>>>(ids, count, prop, ws->bits[0]);
   GM_HIP(hipGetLastError());
   int cur = 0;
+  const Adj out{g->out_off, g->out_idx, static_cast<const uint32_t*>(g->out_w)};
+  start_batch(ws, s);
   for (int32_t b = 0; b < steps; ++b) {
-    enqueue_superstep(g, ws, kind, ws->ctl + b, cur, prop, s);
+    enqueue_superstep(g, ws, kind, out, ws->ctl + b, cur, prop, s);
     cur ^= 1;
   }
   min_summary<<<1, 1, 0, s>>>(ws->ctl, steps, res);
   bits_finish<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[cur], words, &res->converged);
+  fill_kernel<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[cur ^ 1], words, 0);  // stale
   GM_HIP(hipGetLastError());
 }
 
@@ -541,10 +674,11 @@ void init_min_prop(gm_graph g, int kind, const int32_t* ids, int64_t count, uint
   GM_HIP(hipGetLastError());
 }
 
-int32_t run_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count,
+int32_t run_min_program(gm_graph g, int kind, int order, const int32_t* ids, int64_t count,
                         const uint32_t* bitmap, int32_t max_iters, uint32_t* prop,
                         int32_t* active_out, hipStream_t s, RunStats* stats) {
   Workspace* ws = ensure_ws(g, s);
+  const Adj adj = adjacency(g, ws, order, s);
   const int64_t n = g->n;
   const int64_t words = (n + 31) / 32;
   const bool sym = (g->prep & (GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG)) == GM_PREP_SYMMETRIZE;
@@ -553,7 +687,11 @@ int32_t run_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count,
   int32_t batch = (int32_t)g->tune.superstep_batch;
   if (batch < 1) batch = 1;
   int cur = 0;
-  if (bitmap) {
+  if (kind == GM_PROG_DEGREE) {  // every vertex sends; the property starts at 0
+    fill_kernel<<<blocks_for(n), kThreads, 0, s>>>(prop, n, 0u);
+    seed_all<<<blocks_for(words), kThreads, 0, s>>>(words, n, ws->bits[0]);
+    GM_HIP(hipGetLastError());
+  } else if (bitmap) {
     seed_bitmap<<<blocks_for(words), kThreads, 0, s>>>(bitmap, words, n, ws->bits[0]);
     GM_HIP(hipGetLastError());
   } else if (count > 0) {
@@ -562,13 +700,14 @@ int32_t run_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count,
   }
   int32_t iters = 0;
   RunStats st{};
-  bool done = count == 0 && !bitmap;  // an empty bitmap ends after one SEND
+  bool done = count == 0 && !bitmap && kind != GM_PROG_DEGREE;  // an empty bitmap: one SEND
   while (!done) {
     int32_t nb = batch;
     if (max_iters > 0 && max_iters - iters < nb) nb = max_iters - iters;
     if (nb > kMaxCtl) nb = kMaxCtl;
+    start_batch(ws, s);
     for (int32_t b = 0; b < nb; ++b) {
-      enqueue_superstep(g, ws, kind, ws->ctl + b, cur, prop, s);
+      enqueue_superstep(g, ws, kind, adj, ws->ctl + b, cur, prop, s);
       cur ^= 1;
     }
     GM_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, nb * sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -590,10 +729,16 @@ int32_t run_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count,
         ++st.push_supersteps;
     }
     if (max_iters > 0 && iters >= max_iters) done = true;
+    // a run that goes on is long: each further batch is twice as long (the
+    // supersteps after the frontier empties do nothing), so a run of S
+    // supersteps waits for the host about log2(S) times, not S / batch
+    batch = std::min<int32_t>(2 * batch, kMaxCtl);
   }
   // bits[cur] holds the frontier left after the last superstep (empty when
-  // the program converged); report it and leave the workspace cleared.
+  // the program converged); report it and leave the workspace cleared (the
+  // other vector holds a stale frontier).
   bits_epilogue<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[cur], words, n, active_out);
+  fill_kernel<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[cur ^ 1], words, 0);
   GM_HIP(hipGetLastError());
   GM_HIP(hipStreamSynchronize(s));
   st.supersteps = iters;

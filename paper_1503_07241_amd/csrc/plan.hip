@@ -394,7 +394,8 @@ struct Trial {
       uint32_t* prop = static_cast<uint32_t*>(out);
       init_min_prop(g, kind, ids, count, prop, s);
       RunStats st{};
-      run_min_program(g, kind, ids, count, nullptr, max_iters, prop, nullptr, s, &st);
+      run_min_program(g, kind, GM_ORDER_OUT, ids, count, nullptr, max_iters, prop, nullptr, s,
+                      &st);
     } else if (kind == GM_PROG_PAGERANK) {
       fill_f32(static_cast<float*>(out), g->n, 1.0f, s);
       run_pagerank(g, r, max_iters, static_cast<float*>(out), -1, s);

@@ -2,6 +2,7 @@
 (Sec. 5.1): canonical edge lists must be identical, values included."""
 import numpy as np
 import pytest
+import torch
 
 import graphgen as gg
 import oracle
@@ -9,6 +10,7 @@ import paper_1503_07241_amd as gm
 from tests import workloads as W
 
 pytestmark = pytest.mark.gpu
+DEV = "cuda"
 
 P_DIR = gm.GM_PREP_DROP_SELF_LOOPS
 P_SYM = gm.GM_PREP_DROP_SELF_LOOPS | gm.GM_PREP_SYMMETRIZE
@@ -101,3 +103,37 @@ def test_rating_graph_edges():
     assert np.array_equal(s, row[order]) and np.array_equal(d, col[order])
     with pytest.raises(gm.GmError):
         g.edges(with_weights=True)
+
+
+def test_graph_from_matrix_market(tmp_path):
+    """App. A's ReadMTX path: an RMAT scale-12 weighted digraph written as an
+    integer Matrix Market file, loaded by gm_graph_from_mtx, gives the
+    oracle's SSSP distances; a symmetric pattern file gives BFS levels."""
+    n, s, d = gg.rmat(12)
+    w = gg.weights_u32(s, d)
+    p = tmp_path / "g.mtx"
+    with open(p, "w") as f:
+        f.write("%%MatrixMarket matrix coordinate integer general\n")
+        f.write("%d %d %d\n" % (n, n, len(s)))
+        for a, b, c in zip(s.tolist(), d.tolist(), w.tolist()):
+            f.write("%d %d %d\n" % (a + 1, b + 1, c))
+    g = gm.Graph.from_mtx(str(p), layouts=gm.GM_LAYOUT_OUT)
+    dist = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+    dist[0] = 0
+    gm.run_vertex_program(g, gm.GM_PROG_SSSP, torch.zeros(1, dtype=torch.int32, device=DEV), -1,
+                          dist)
+    ref = oracle.sssp(oracle.prepare(n, s, d, w=w), 0)
+    assert np.array_equal(dist.cpu().numpy().view(np.uint32), ref)
+    q = tmp_path / "sym.mtx"
+    keep = s > d
+    with open(q, "w") as f:
+        f.write("%%MatrixMarket matrix coordinate pattern symmetric\n")
+        f.write("%d %d %d\n" % (n, n, int(keep.sum())))
+        for a, b in zip(s[keep].tolist(), d[keep].tolist()):
+            f.write("%d %d\n" % (a + 1, b + 1))
+    gs = gm.Graph.from_mtx(str(q), layouts=gm.GM_LAYOUT_OUT)
+    lv = torch.full((n,), gm.INF_LEVEL, dtype=torch.int32, device=DEV)
+    lv[0] = 0
+    gm.run_vertex_program(gs, gm.GM_PROG_BFS, torch.zeros(1, dtype=torch.int32, device=DEV), -1, lv)
+    sym = oracle.prepare(n, s[keep], d[keep], mode="symmetric")
+    assert np.array_equal(lv.cpu().numpy(), oracle.bfs(sym, 0))

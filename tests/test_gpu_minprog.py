@@ -209,3 +209,83 @@ def test_sssp_superstep_trace_hand_worked():
         assert np.array_equal(active.astype(bool), act_k), k
     dist, it, active = run_sssp(g, n, src)
     assert it == steps and np.array_equal(dist, trace[-1][0]) and not active.any()
+
+
+@pytest.mark.parametrize("name", ["sssp_rmat24_a50", "sssp_grid2048"])
+def test_paper_sssp_workloads(name):
+    """The paper's SSSP graphs (f3): RMAT scale 24 with a = .50, b = c = .10
+    (Sec. 5.1, Table 1) and a long-diameter 2048 x 2048 grid; every distance
+    against the oracle's Dijkstra (SHA-256 of the whole array in the
+    oracle-written golden file) and the superstep count of its Alg. 2 loop."""
+    from tests.golden import make_sssp_goldens as G
+    ref = G.read(name)
+    n, s, d, w, _ = G.workload(name)
+    g = gm.Graph.from_coo(n, s, d, w=w, prep=P_DIR)
+    assert g.m == ref["m"]
+    dist, it, active = run_sssp(g, n, 0)
+    assert it == ref["supersteps"] and not active.any()
+    reached = dist != oracle.INF_U32
+    assert int(reached.sum()) == ref["reached"] and int(dist[reached].max()) == ref["max_dist"]
+    import hashlib
+    assert hashlib.sha256(np.ascontiguousarray(dist, dtype="<u4").tobytes()).hexdigest() == \
+        ref["dist_sha256"]
+
+
+def test_orders_in_and_all():
+    """Messages along in-edges (GM_ORDER_IN) equal the run on the transposed
+    graph; along both (GM_ORDER_ALL) the run on the union of the graph and its
+    transpose (a pair in both directions keeps the smaller weight): BFS and
+    SSSP from several sources against the oracle."""
+    scale = 12
+    n, s, d = W.raw(scale)
+    w = W.weights(scale)
+    g = gm.Graph.from_coo(n, s, d, w=w, prep=P_DIR)
+    og_in = oracle.prepare(n, d, s, w=w)                      # transposed
+    og_all = oracle.prepare(n, np.concatenate([s, d]), np.concatenate([d, s]),
+                            w=np.concatenate([w, w]))          # both directions
+    for src in (0, 7, 1234):
+        for order, og in ((gm.GM_ORDER_IN, og_in), (gm.GM_ORDER_ALL, og_all)):
+            lv = torch.full((n,), gm.INF_LEVEL, dtype=torch.int32, device=DEV)
+            lv[src] = 0
+            gm.run_vertex_program(g, gm.GM_PROG_BFS, ids(src), -1, lv, order=order)
+            assert np.array_equal(lv.cpu().numpy(), oracle.bfs(og, src)), (order, src)
+            dist = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+            dist[src] = 0
+            gm.run_vertex_program(g, gm.GM_PROG_SSSP, ids(src), -1, dist, order=order)
+            assert np.array_equal(dist.cpu().numpy().view(np.uint32), oracle.sssp(og, src))
+
+
+def test_degree_program_all_orders():
+    """Fig. 1: degree as one generalized SpMV with a ones vector, along out-,
+    in- and both directions, against the oracle's counts (RMAT scale 14 and
+    a graph with isolated and edgeless vertices)."""
+    for n, s, d in (W.raw(W.SMALL_SCALE), (50, np.array([3, 3, 4], np.int32),
+                                           np.array([4, 5, 3], np.int32))):
+        g = gm.Graph.from_coo(n, s, d)
+        og = oracle.prepare(n, s, d)
+        for order, name in ((gm.GM_ORDER_OUT, "out"), (gm.GM_ORDER_IN, "in"),
+                            (gm.GM_ORDER_ALL, "all")):
+            deg = torch.full((n,), 77, dtype=torch.int32, device=DEV)  # overwritten from 0
+            it = gm.run_vertex_program(g, gm.GM_PROG_DEGREE, None, 1, deg, order=order)
+            assert it == (1 if n > 0 else 0)
+            assert np.array_equal(deg.cpu().numpy().astype(np.int64), oracle.degree(og, name))
+
+
+def test_order_errors():
+    n, s, d = W.raw(8)
+    g = gm.Graph.from_coo(n, s, d, layouts=gm.GM_LAYOUT_OUT)
+    lv = torch.zeros(n, dtype=torch.int32, device=DEV)
+    with pytest.raises(gm.GmError) as e:  # IN needs the in-layout
+        gm.run_vertex_program(g, gm.GM_PROG_BFS, ids(0), -1, lv, order=gm.GM_ORDER_IN)
+    assert e.value.status == gm._lib.GM_EUNSUPPORTED
+    g2 = gm.Graph.from_coo(n, s, d)
+    pr = torch.ones(n, dtype=torch.float32, device=DEV)
+    with pytest.raises(gm.GmError) as e:  # PageRank runs along out-edges only
+        gm.run_vertex_program(g2, gm.GM_PROG_PAGERANK, None, 20, pr, order=gm.GM_ORDER_IN)
+    assert e.value.status == gm._lib.GM_EUNSUPPORTED
+    with pytest.raises(gm.GmError) as e:
+        gm.run_vertex_program(g2, gm.GM_PROG_BFS, ids(0), -1, lv, order=9)
+    assert e.value.status == gm._lib.GM_EINVAL
+    with pytest.raises(gm.GmError) as e:  # the degree program takes no frontier
+        gm.run_vertex_program(g2, gm.GM_PROG_DEGREE, ids(0), 1, lv)
+    assert e.value.status == gm._lib.GM_EINVAL

@@ -268,3 +268,18 @@ def test_sssp_superstep_trace_hand_worked():
     p, a, it = oracle.run_min_program(g, prop, act, weighted=True)
     assert it == steps == 5 and not a.any()
     assert np.array_equal(p, oracle.sssp(g, src)) and np.array_equal(p, trace[-1][0])
+
+
+def test_degree_program_hand_graph_and_closed_forms():
+    """Fig. 1's degree-as-SpMV: on the hand-made digraph 0->1, 0->2, 2->1,
+    1->3 the in-degrees are [0, 2, 1, 1] and out-degrees [2, 1, 1, 0]; on K_n
+    every degree is n - 1 each way; a star's hub has degree n - 1."""
+    g = graph_from_pairs(4, [(0, 1), (0, 2), (2, 1), (1, 3)])
+    assert oracle.degree(g, "out").tolist() == [0, 2, 1, 1]
+    assert oracle.degree(g, "in").tolist() == [2, 1, 1, 0]
+    assert oracle.degree(g, "all").tolist() == [2, 3, 2, 1]
+    n = 7
+    kn = graph_from_pairs(n, [(i, j) for i in range(n) for j in range(n) if i != j])
+    assert (oracle.degree(kn, "out") == n - 1).all() and (oracle.degree(kn, "all") == 2 * n - 2).all()
+    star = graph_from_pairs(n, [(0, j) for j in range(1, n)])
+    assert oracle.degree(star, "in")[0] == n - 1 and oracle.degree(star, "out")[0] == 0
