@@ -125,6 +125,10 @@ def main():
                          "hardware-counter runs")
     ap.add_argument("--tc-only", type=int, default=0, metavar="K",
                     help="only run K triangle counts, for hardware-counter runs")
+    ap.add_argument("--ablation", action="store_true",
+                    help="only the ablation of the paper's design choices (Sec. 5.4, Fig. 7) on "
+                         "RMAT scale 22: frontier as bitvector or sorted list, equal-edge or "
+                         "thread-per-vertex push, push vs pull, PageRank tiles and LDS copy")
     ap.add_argument("--tc-cold", action="store_true",
                     help="with --tc-only: free the work plan before each count (cold calls)")
     ap.add_argument("--cf-only", type=int, default=0, metavar="K",
@@ -165,6 +169,9 @@ def main():
     log("generated RMAT scale %d in %.1fs" % (scale, time.time() - t0))
     if args.pr_only:
         pr_counter_run(gm, torch, n, s, d, args.pr_only)
+        return
+    if args.ablation:
+        print(json.dumps(run_ablation(gm, torch, np, n, s, d, w)), flush=True)
         return
     if args.tc_only:
         g = gm.Graph.from_coo(n, s, d, prep=gm.GM_PREP_UPPER_DAG)
@@ -661,6 +668,91 @@ def measure_scale26(gm, gg, torch, np, tm):
     torch.cuda.empty_cache()
     log("scale 26: %s (%.1fs)" % (json.dumps(res), time.time() - t0))
     return res
+
+
+def run_ablation(gm, torch, np, n, s, d, w):
+    """Each design choice of the paper's Fig. 7 (Sec. 5.4) swapped for its
+    alternative on the scale-22 workload, results asserted equal to the
+    default schedule's (BFS, SSSP bit-exact; PageRank within 2e-5 relative):
+      frontier: bitvector (default) vs sorted list of distinct ids;
+      load balance: equal edge ranges per wavefront (default) vs one thread
+        per active vertex;
+      direction (BFS): push with pull supersteps for large frontiers
+        (default) vs push only;
+      PageRank: edge tiles + LDS copy of the hottest messages (default),
+        tiles without the LDS copy, one thread per row."""
+    dev = torch.device("cuda:0")
+    LIST, VPUSH, ROWPULL = (gm._lib.GM_VARIANT_LIST_FRONTIER, gm._lib.GM_VARIANT_VERTEX_PUSH,
+                            gm._lib.GM_VARIANT_ROW_PULL)
+    tm = Timer()
+    g_sym = gm.Graph.from_coo(n, s, d, prep=gm.GM_PREP_DROP_SELF_LOOPS | gm.GM_PREP_SYMMETRIZE,
+                              layouts=gm.GM_LAYOUT_OUT)
+    g_dir = gm.Graph.from_coo(n, s, d, w=w, prep=gm.GM_PREP_DROP_SELF_LOOPS)
+    root = torch.zeros(1, dtype=torch.int32, device=dev)
+    lv = torch.empty(n, dtype=torch.int32, device=dev)
+    dist = torch.empty(n, dtype=torch.int32, device=dev)
+    rank = torch.empty(n, dtype=torch.float32, device=dev)
+    out, ref = {"bfs": {}, "sssp": {}, "pagerank": {}}, {}
+
+    def bfs():
+        lv.fill_(gm.INF_LEVEL)
+        lv[0] = 0
+        gm.run_vertex_program(g_sym, gm.GM_PROG_BFS, root, -1, lv)
+
+    def sssp():
+        dist.fill_(-1)
+        dist[0] = 0
+        gm.run_vertex_program(g_dir, gm.GM_PROG_SSSP, root, -1, dist)
+
+    def pr(T):
+        def f():
+            rank.fill_(1.0)
+            gm.run_vertex_program(g_dir, gm.GM_PROG_PAGERANK, None, T, rank)
+        return f
+
+    frontier_variants = [("bitvector_frontier+equal_edge_push", 0), ("list_frontier", LIST),
+                         ("thread_per_vertex_push", VPUSH),
+                         ("list_frontier+thread_per_vertex_push", LIST | VPUSH)]
+    for name, var in frontier_variants:
+        # pull supersteps once more than n / pull_div vertices are active: 1
+        # never pulls, 128 is the default switch
+        for dname, pull_div in (("push_pull", 128), ("push_only", 1)):
+            g_sym.set_tuning(variant=var, pull_div=pull_div)
+            ms = tm.ms(bfs, 3)
+            e = g_sym.last_run_stats().edges_scanned
+            got = lv.cpu().numpy()
+            if "bfs" not in ref:
+                ref["bfs"] = got.copy()
+            assert np.array_equal(got, ref["bfs"]), (name, dname)
+            out["bfs"][name + "/" + dname] = {"ms": round(ms, 3), "gteps": round(e / ms / 1e6, 2)}
+        g_dir.set_tuning(variant=var)
+        ms = tm.ms(sssp, 3)
+        e = g_dir.last_run_stats().edges_scanned
+        got = dist.cpu().numpy()
+        if "sssp" not in ref:
+            ref["sssp"] = got.copy()
+        assert np.array_equal(got, ref["sssp"]), name
+        out["sssp"][name] = {"ms": round(ms, 3), "gteps": round(e / ms / 1e6, 2)}
+    g_dir.set_tuning(variant=0)
+    m = g_dir.m
+    for name, var, hot in (("tiles+lds_hot_set", 0, 40960), ("tiles_no_lds", 0, 0),
+                           ("row_per_thread", ROWPULL, 40960)):
+        g_dir.set_tuning(variant=var, pr_hot=hot)
+        per = (tm.ms(pr(21), 3) - tm.ms(pr(1), 3)) / 20
+        pr(20)()
+        torch.cuda.synchronize()
+        got = rank.cpu().numpy().astype(np.float64)
+        if "pr" not in ref:
+            ref["pr"] = got.copy()
+        err = float(np.max(np.abs(got - ref["pr"]) / ref["pr"]))
+        assert err <= 2e-5, (name, err)
+        out["pagerank"][name] = {"ms_per_superstep": round(per, 4),
+                                 "gteps": round(m / per / 1e6, 2),
+                                 "gbs_4m_24n": round((4 * m + 24 * n) / per / 1e6, 1),
+                                 "max_rel_diff_vs_default": err}
+    out["config"] = {"workload": "RMAT scale 22 (BFS symmetrised, SSSP/PageRank directed), "
+                                 "source 0", "n": n, "m_dir": m, "m_sym": g_sym.m}
+    return out
 
 
 def pr_counter_run(gm, torch, n, s, d, K):

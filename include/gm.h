@@ -350,6 +350,21 @@ gm_status gm_cf_backward(gm_graph g, int32_t K, const float* PU, const float* PV
                          float scale, float* gPU, float* gPV, void* stream);
 
 /*
+ * Collaborative filtering by gradient descent (Sec. 3 III, Eqs. (5)-(6)):
+ * `iters` steps, each computing both gradients at the current point (the
+ * row and transpose passes of gm_cf_backward) and then updating both factor
+ * matrices in place, P <- P - (gamma / 2) dL/dP, i.e. the paper's
+ * p <- p + gamma (sum_other e p_other - lambda p). PU, PV: device float
+ * factors as for gm_cf_forward, updated in place. loss_hist (device double,
+ * iters + 1 entries, may be NULL): the loss of Eq. (3) at the point of each
+ * step and after the last. The gradient buffers are kept with the graph.
+ * Errors: as gm_cf_forward; GM_EINVAL (iters < 0, gamma negative or not
+ * finite). Asynchronous.
+ */
+gm_status gm_cf_gd(gm_graph g, int32_t K, float* PU, float* PV, float lambda, float gamma,
+                   int32_t iters, double* loss_hist, void* stream);
+
+/*
  * Weighted PageRank with history: PR^{t+1}(v) = r + (1 - r) *
  * sum_{u -> v} w_uv PR^t(u) / outdeg(u) (Eq. (1) with edge weights w in
  * canonical edge order, device float[m]; outdeg is the unweighted count).
@@ -504,7 +519,24 @@ typedef struct gm_tuning {
                                highest-degree vertices are staged in LDS by
                                every workgroup (0..40960; 40960, capped by the
                                device's LDS per workgroup) */
+  uint32_t variant;         /* alternative schedules of the paper's design
+                               choices, for ablation (Sec. 5.4, Fig. 7); each
+                               bit swaps one in, results are identical:
+                               GM_VARIANT_LIST_FRONTIER, _VERTEX_PUSH,
+                               _ROW_PULL (0..7; 0) */
 } gm_tuning;
+
+/* Bits of gm_tuning.variant (BFS/SSSP supersteps and the PageRank pull):
+ *  GM_VARIANT_LIST_FRONTIER: the next frontier as a sorted, deduplicated
+ *    list of vertex ids (the (index, value) sparse vector the paper's
+ *    bitvector replaces, Sec. 4.4.2) instead of a bitvector: the product
+ *    appends every lowered vertex and the list is sorted and made unique
+ *    between supersteps (the host reads its length each superstep);
+ *  GM_VARIANT_VERTEX_PUSH: one thread per active vertex walks its out-edges
+ *    (no load balancing, Sec. 4.4.3) instead of equal edge ranges;
+ *  GM_VARIANT_ROW_PULL: PageRank pulls one row per thread (no edge tiles,
+ *    no LDS copy of the hottest messages) instead of the tiled kernel. */
+enum { GM_VARIANT_LIST_FRONTIER = 1, GM_VARIANT_VERTEX_PUSH = 2, GM_VARIANT_ROW_PULL = 4 };
 
 /* Read g's parameters. Errors: GM_ESTATE, GM_EINVAL (out NULL). */
 gm_status gm_graph_get_tuning(gm_graph g, gm_tuning* out);

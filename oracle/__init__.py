@@ -302,6 +302,37 @@ def degree(g: Graph, order: str = "out") -> np.ndarray:
     return {"out": indeg, "in": outdeg, "all": indeg + outdeg}[order]
 
 
+def cf_gd(n_users: int, n_items: int, user, item, rating, PU, PV, lam: float, gamma: float,
+          iters: int):
+    """Gradient descent of Eqs. (5)-(6) in float64: both factor matrices
+    updated from the same point, p <- p - (gamma / 2) dL/dp (the paper's
+    p + gamma (sum e p_other - lambda p)), `iters` times. Returns (PU, PV,
+    losses) with losses[t] = L at the point of step t (t = 0..iters)."""
+    pu = np.array(PU, dtype=np.float64)
+    pv = np.array(PV, dtype=np.float64)
+    losses = []
+    for _ in range(iters):
+        L, gu, gv = _cf_loss_grad64(n_users, n_items, user, item, rating, pu, pv, lam)
+        losses.append(L)
+        pu = pu - 0.5 * gamma * gu
+        pv = pv - 0.5 * gamma * gv
+    losses.append(_cf_loss_grad64(n_users, n_items, user, item, rating, pu, pv, lam)[0])
+    return pu, pv, np.array(losses)
+
+
+def _cf_loss_grad64(n_users, n_items, user, item, rating, pu, pv, lam):
+    """Eq. (3) loss and gradients at float64 factors (numpy, one pass)."""
+    user = np.asarray(user, dtype=np.int64)
+    item = np.asarray(item, dtype=np.int64)
+    e = np.asarray(rating, dtype=np.float64) - np.einsum("ij,ij->i", pu[user], pv[item])
+    L = float(e @ e + lam * (np.sum(pu * pu) + np.sum(pv * pv)))
+    gu = 2.0 * lam * pu
+    gv = 2.0 * lam * pv
+    np.add.at(gu, user, -2.0 * e[:, None] * pv[item])
+    np.add.at(gv, item, -2.0 * e[:, None] * pu[user])
+    return L, gu, gv
+
+
 def dag_in_lists(dag: Graph) -> Graph:
     """Program 1 of the triangle count (Sec. 4.2): sorted in-neighbour lists."""
     return dag.transpose()

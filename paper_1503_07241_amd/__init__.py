@@ -446,6 +446,17 @@ def cf_backward(g: RatingGraph, PU, PV, lam: float, scale: float, gPU=None, gPV=
                "gm_cf_backward")
 
 
+def cf_gd(g: RatingGraph, PU, PV, lam: float, gamma: float, iters: int, loss_hist=None,
+          stream=None) -> None:
+    """gm_cf_gd: `iters` gradient-descent steps of Eqs. (5)-(6) on PU, PV in
+    place; loss_hist (device float64[iters + 1]) receives the losses."""
+    K = _factors(g, PU, PV)
+    _lib.check(_lib.load().gm_cf_gd(g.handle, K, _dev(PU, "PU", PU.numel(), _F32),
+                                    _dev(PV, "PV", PV.numel(), _F32), lam, gamma, iters,
+                                    _dev(loss_hist, "loss_hist", iters + 1, _F64),
+                                    _stream(stream)), "gm_cf_gd")
+
+
 def pagerank_forward_w(g: Graph, w, r: float, T: int, hist, stream=None) -> None:
     """gm_pagerank_forward_w: hist[0] holds PR^0; rows 1..T are written."""
     n, m = g.n, g.m

@@ -21,6 +21,7 @@ GM_W_NONE, GM_W_U32, GM_W_F32 = 0, 1, 2
 GM_LAYOUT_OUT, GM_LAYOUT_IN = 1, 2
 GM_PROG_BFS, GM_PROG_SSSP, GM_PROG_PAGERANK, GM_PROG_PPR, GM_PROG_TC, GM_PROG_DEGREE = range(1, 7)
 GM_ORDER_OUT, GM_ORDER_IN, GM_ORDER_ALL = 1, 2, 3
+GM_VARIANT_LIST_FRONTIER, GM_VARIANT_VERTEX_PUSH, GM_VARIANT_ROW_PULL = 1, 2, 4
 
 
 class GmError(RuntimeError):
@@ -63,7 +64,7 @@ class gm_plan_result(ctypes.Structure):
 
 
 TUNING_FIELDS = ("pull_div", "superstep_batch", "push_blocks", "ppr_chunk", "tc_wave_max",
-                 "tc_wave_work", "tc_block_work", "pr_hot")
+                 "tc_wave_work", "tc_block_work", "pr_hot", "variant")
 
 
 class gm_tuning(ctypes.Structure):
@@ -98,6 +99,7 @@ def load():
         "gm_bipartite_from_coo": ([i64, i64, i64, vp, vp, vp, vp, ctypes.POINTER(vp)], i32),
         "gm_cf_forward": ([vp, i32, vp, vp, ctypes.c_float, vp, vp], i32),
         "gm_cf_backward": ([vp, i32, vp, vp, ctypes.c_float, ctypes.c_float, vp, vp, vp], i32),
+        "gm_cf_gd": ([vp, i32, vp, vp, ctypes.c_float, ctypes.c_float, i32, vp, vp], i32),
         "gm_pagerank_forward_w": ([vp, vp, ctypes.c_float, i32, vp, vp], i32),
         "gm_pagerank_vjp_w": ([vp, vp, ctypes.c_float, i32, vp, vp, vp, vp], i32),
         "gm_graph_union": ([vp, i32, vp, ctypes.POINTER(vp)], i32),

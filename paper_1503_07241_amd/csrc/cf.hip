@@ -86,6 +86,8 @@ struct CfPlan {
   CfSide side[2];  // 0: rows (users), 1: columns (items)
   double* partial = nullptr;  // largest npartial * K of the two sides
   int64_t partial_k = 0;
+  float* grad[2] = {nullptr, nullptr};  // gradients of a descent step (grad_k columns)
+  int64_t grad_k = 0;
   double* loss_part = nullptr;  // kGridMax workgroup sums, then 2 x 1024 norm sums
 };
 
@@ -293,6 +295,14 @@ __global__ void finish_loss(const double* __restrict__ a, int64_t na, const doub
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = ws[0][0] + lambda * (ws[1][0] + ws[2][0]);
+}
+
+// One descent step of Eqs. (5)-(6): P <- P - (gamma / 2) dL/dP.
+__global__ void cf_step(float* __restrict__ P, const float* __restrict__ grad, int64_t count,
+                        float half_gamma) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    P[i] = fmaf(-half_gamma, grad[i], P[i]);
 }
 
 // bounds[v * (nb + 1) + b] = first rating of column v whose user is in block
@@ -511,6 +521,8 @@ void free_cf_plan(gm_graph g) {
   }
   dfree(p->partial);
   dfree(p->loss_part);
+  dfree(p->grad[0]);
+  dfree(p->grad[1]);
   delete p;
   g->cf_plan = nullptr;
   ++g->ws_gen;
@@ -692,6 +704,29 @@ void run_cf_backward(gm_graph g, int K, const float* PU, const float* PV, float 
       GM_HIP(hipGetLastError());
     }
   }
+}
+
+void run_cf_gd(gm_graph g, int K, float* PU, float* PV, float lambda, float gamma, int32_t iters,
+               double* loss_hist, hipStream_t s) {
+  CfPlan* p = ensure_plan(g, K, s);
+  const int64_t nu = g->n_rows * K, nv = g->n_cols * K;
+  if (p->grad_k < K) {
+    dfree(p->grad[0]);
+    dfree(p->grad[1]);
+    p->grad[0] = p->grad[1] = nullptr;
+    p->grad_k = 0;
+    p->grad[0] = dalloc<float>(nu);
+    p->grad[1] = dalloc<float>(nv);
+    p->grad_k = K;
+  }
+  for (int32_t t = 0; t < iters; ++t) {
+    if (loss_hist) run_cf_forward(g, K, PU, PV, lambda, loss_hist + t, s);
+    run_cf_backward(g, K, PU, PV, lambda, 1.0f, p->grad[0], p->grad[1], s);
+    cf_step<<<blocks_for(nu), kThreads, 0, s>>>(PU, p->grad[0], nu, 0.5f * gamma);
+    cf_step<<<blocks_for(nv), kThreads, 0, s>>>(PV, p->grad[1], nv, 0.5f * gamma);
+    GM_HIP(hipGetLastError());
+  }
+  if (loss_hist) run_cf_forward(g, K, PU, PV, lambda, loss_hist + iters, s);
 }
 
 }  // namespace gm

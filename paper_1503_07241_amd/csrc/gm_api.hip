@@ -509,6 +509,19 @@ gm_status gm_cf_backward(gm_graph g, int32_t K, const float* PU, const float* PV
   });
 }
 
+gm_status gm_cf_gd(gm_graph g, int32_t K, float* PU, float* PV, float lambda, float gamma,
+                   int32_t iters, double* loss_hist, void* stream) {
+  const gm_status st = check_cf(g, K, PU, PV, lambda);
+  if (st != GM_OK) return st;
+  if (iters < 0) return fail(GM_EINVAL, "iters = %d is negative", iters);
+  if (!(gamma >= 0.0f) || !std::isfinite(gamma)) return fail(GM_EINVAL, "gamma must be >= 0");
+  return guarded([&]() -> gm_status {
+    if (const gm_status st = check_device(g)) return st;
+    run_cf_gd(g, K, PU, PV, lambda, gamma, iters, loss_hist, static_cast<hipStream_t>(stream));
+    return ok();
+  });
+}
+
 static gm_status check_prw(gm_graph g, const float* w, float r, int32_t T) {
   if (!graph_live(g)) return fail(GM_ESTATE, "graph handle is not live");
   if (g->bipartite) return fail(GM_EUNSUPPORTED, "rating graphs take the CF calls only");

@@ -77,6 +77,8 @@ struct Tuning {
   uint32_t tc_block_work = 1u << 23;
   // PageRank / PPR pull: messages of the first pr_hot labels read from LDS
   uint32_t pr_hot = 40960;
+  // GM_VARIANT_* bits: alternative schedules for ablation
+  uint32_t variant = 0;
 };
 
 // Per-run outcome recorded on the device by a captured plan.
@@ -215,6 +217,8 @@ void run_cf_forward(gm_graph g, int K, const float* PU, const float* PV, float l
                     double* loss_dev, hipStream_t s);
 void run_cf_backward(gm_graph g, int K, const float* PU, const float* PV, float lambda, float scale,
                      float* gPU, float* gPV, hipStream_t s);
+void run_cf_gd(gm_graph g, int K, float* PU, float* PV, float lambda, float gamma, int32_t iters,
+               double* loss_hist, hipStream_t s);
 void free_cf_plan(gm_graph g);
 
 // Weighted PageRank with history and its edge-weight VJP (pagerank.hip,

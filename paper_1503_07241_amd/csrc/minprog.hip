@@ -30,6 +30,9 @@
 #include <algorithm>
 #include <cstring>
 
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_select.hpp>
+
 #include "gm_internal.h"
 
 namespace gm {
@@ -222,6 +225,52 @@ __global__ __launch_bounds__(kThreads) void send_kernel(
   }
 }
 
+// SEND of the list-frontier variant: the frontier is a sorted list of count
+// distinct vertices; one thread per entry, queue slots in list order.
+__global__ __launch_bounds__(kThreads) void send_list_kernel(
+    const uint32_t* __restrict__ lst, int64_t count, const uint32_t* __restrict__ prop,
+    const uint32_t* __restrict__ off, int32_t* __restrict__ q, uint32_t* __restrict__ qmsg,
+    uint32_t* __restrict__ qbeg, uint32_t* __restrict__ qest, Ctl* __restrict__ ctl) {
+  __shared__ uint32_t sh[2 * kWaves];
+  __shared__ unsigned long long base_packed;
+  for (int64_t i0 = (int64_t)blockIdx.x * kThreads; i0 < count;
+       i0 += (int64_t)gridDim.x * kThreads) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool live = i < count;
+    const uint32_t v = live ? lst[i] : 0u;
+    const uint32_t b = live ? off[v] : 0u;
+    const uint32_t deg = live ? off[v + 1] - b : 0u;
+    uint32_t ctot, etot;
+    const uint32_t cex = block_excl_scan(live ? 1u : 0u, sh, &ctot);
+    const uint32_t eex = block_excl_scan(deg, sh + kWaves, &etot);
+    if (threadIdx.x == 0)
+      base_packed = atomicAdd(&ctl->packed, ((unsigned long long)ctot << 32) | etot);
+    __syncthreads();
+    const unsigned long long bp = base_packed;
+    __syncthreads();
+    if (live) {
+      const uint32_t slot = (uint32_t)(bp >> 32) + cex;
+      q[slot] = (int32_t)v;
+      qmsg[slot] = prop[v];
+      qbeg[slot] = b;
+      qest[slot] = (uint32_t)bp + eex;
+    }
+  }
+}
+
+__global__ void list_to_active(const uint32_t* __restrict__ lst, int64_t count,
+                               int32_t* __restrict__ active) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    active[lst[i]] = 1;
+}
+
+__global__ void ids_to_u32(const int32_t* __restrict__ ids, int64_t count, uint32_t* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (uint32_t)ids[i];
+}
+
 // PROCESS + REDUCE(min) + APPLY(min) of one edge. A cached read of v's value
 // (the value at kernel start or a later, lower one: values only drop) filters
 // out most edges; the others do an atomic min, and v is marked changed
@@ -236,12 +285,29 @@ __device__ inline void relax(uint32_t cand, int32_t v, uint32_t* prop, uint32_t*
   }
 }
 
+// relax() with the next frontier as a bitvector (list == NULL) or, for the
+// list-frontier variant, as an appended list of lowered vertices (a vertex
+// lowered twice appears twice; the list is sorted and made unique later).
+__device__ inline void relax_to(uint32_t cand, int32_t v, uint32_t* prop, uint32_t* next,
+                                uint32_t* list, unsigned int* list_count) {
+  if (!list) {
+    relax(cand, v, prop, next);
+    return;
+  }
+  if (cand < __hip_atomic_load(&prop[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT)) {
+    const uint32_t old =
+        __hip_atomic_fetch_min(&prop[v], cand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cand < old) list[atomicAdd(list_count, 1u)] = (uint32_t)v;
+  }
+}
+
 template <int kKind>
 __global__ __launch_bounds__(kThreads) void push_kernel(
     const Ctl* __restrict__ ctlp, int64_t n, bool pull_ok, uint32_t pull_div,
     const uint32_t* __restrict__ qmsg, const uint32_t* __restrict__ qbeg,
     const uint32_t* __restrict__ qest, const int32_t* __restrict__ idx,
-    const uint32_t* __restrict__ w, uint32_t* prop, uint32_t* next) {
+    const uint32_t* __restrict__ w, uint32_t* prop, uint32_t* next, uint32_t* list = nullptr,
+    unsigned int* list_count = nullptr) {
   const Ctl c = *ctlp;
   if (use_pull(c, kKind, pull_ok, n, pull_div)) return;
   const uint32_t count = (uint32_t)(c.packed >> 32);
@@ -324,10 +390,36 @@ __global__ __launch_bounds__(kThreads) void push_kernel(
       } else {
 #pragma unroll
         for (int k = 0; k < kUnroll; ++k)
-          if (act[k]) relax(cand[k], dst[k], prop, next);
+          if (act[k]) relax_to(cand[k], dst[k], prop, next, list, list_count);
       }
     }
     e = stop;
+  }
+}
+
+// Ablation variant of the push (GM_VARIANT_VERTEX_PUSH): one thread per
+// queued vertex walks all its out-edges, so a hub's edges are one thread's
+// serial work (no load balancing).
+template <int kKind>
+__global__ __launch_bounds__(kThreads) void push_vertex_kernel(
+    const Ctl* __restrict__ ctlp, int64_t n, bool pull_ok, uint32_t pull_div,
+    const uint32_t* __restrict__ qmsg, const uint32_t* __restrict__ qbeg,
+    const uint32_t* __restrict__ qest, const int32_t* __restrict__ idx,
+    const uint32_t* __restrict__ w, uint32_t* prop, uint32_t* next, uint32_t* list,
+    unsigned int* list_count) {
+  const Ctl c = *ctlp;
+  if (use_pull(c, kKind, pull_ok, n, pull_div)) return;
+  const uint32_t count = (uint32_t)(c.packed >> 32);
+  const uint32_t E = (uint32_t)c.packed;
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < count;
+       s += gridDim.x * blockDim.x) {
+    const uint32_t beg = qbeg[s];
+    const uint32_t deg = (s + 1 < count ? qest[s + 1] : E) - qest[s];
+    const uint32_t msg = qmsg[s];
+    for (uint32_t e = beg; e < beg + deg; ++e) {
+      const uint32_t cand = process<kKind>(msg, kKind == GM_PROG_SSSP ? w[e] : 0u);
+      relax_to(cand, idx[e], prop, next, list, list_count);
+    }
   }
 }
 
@@ -564,7 +656,16 @@ void enqueue_superstep(gm_graph g, Workspace* ws, int kind, const Adj& a, Ctl* c
   send_kernel<<<blocks_for(words, 4096), kThreads, 0, s>>>(
       ws->bits[cur], ws->bits[cur ^ 1], words, g->n, prop, a.off, ws->q, ws->qmsg, ws->qbeg,
       ws->qest, c, c + 1);
-  if (kind == GM_PROG_SSSP)
+  if (kind != GM_PROG_DEGREE && (g->tune.variant & GM_VARIANT_VERTEX_PUSH)) {
+    if (kind == GM_PROG_SSSP)
+      push_vertex_kernel<GM_PROG_SSSP><<<blocks_for(n), kThreads, 0, s>>>(
+          c, n, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, a.idx, a.w, prop,
+          ws->bits[cur ^ 1], nullptr, nullptr);
+    else
+      push_vertex_kernel<GM_PROG_BFS><<<blocks_for(n), kThreads, 0, s>>>(
+          c, n, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, a.idx, nullptr, prop,
+          ws->bits[cur ^ 1], nullptr, nullptr);
+  } else if (kind == GM_PROG_SSSP)
     push_kernel<GM_PROG_SSSP><<<push_blocks, kThreads, 0, s>>>(
         c, n, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, a.idx, a.w, prop,
         ws->bits[cur ^ 1]);
@@ -674,11 +775,134 @@ void init_min_prop(gm_graph g, int kind, const int32_t* ids, int64_t count, uint
   GM_HIP(hipGetLastError());
 }
 
+namespace {
+
+// Device buffers of the list-frontier variant, freed at scope exit.
+struct ListBufs {
+  uint32_t* lst = nullptr;       // current frontier: sorted distinct ids (n)
+  uint32_t* app[2] = {nullptr, nullptr};  // appended lowered vertices, sort buffers (cap)
+  unsigned int* cnt = nullptr;   // [0]: appended count, [1]: distinct count
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
+  ~ListBufs() {
+    dfree(lst);
+    dfree(app[0]);
+    dfree(app[1]);
+    dfree(cnt);
+    dfree(tmp);
+  }
+};
+
+// Sort app[0][0..k) and keep each id once, into lst; returns the number of
+// distinct ids (synchronises s).
+int64_t sort_unique(ListBufs& b, int64_t k, hipStream_t s) {
+  if (k == 0) return 0;
+  rocprim::double_buffer<uint32_t> kb(b.app[0], b.app[1]);
+  size_t need = 0, need2 = 0;
+  GM_HIP(rocprim::radix_sort_keys(nullptr, need, kb, (size_t)k, 0, 32, s));
+  GM_HIP(rocprim::unique(nullptr, need2, kb.current(), b.lst, b.cnt + 1, (size_t)k,
+                         rocprim::equal_to<uint32_t>(), s));
+  need = std::max(need, need2);
+  if (need > b.tmp_bytes) {
+    dfree(b.tmp);
+    b.tmp = nullptr;
+    b.tmp = dmalloc(need);
+    b.tmp_bytes = need;
+  }
+  GM_HIP(rocprim::radix_sort_keys(b.tmp, need, kb, (size_t)k, 0, 32, s));
+  need = b.tmp_bytes;
+  GM_HIP(rocprim::unique(b.tmp, need, kb.current(), b.lst, b.cnt + 1, (size_t)k,
+                         rocprim::equal_to<uint32_t>(), s));
+  unsigned int h = 0;
+  GM_HIP(hipMemcpyAsync(&h, b.cnt + 1, 4, hipMemcpyDeviceToHost, s));
+  GM_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
+}  // namespace
+
+// BFS / SSSP with the frontier as a sorted list of distinct vertex ids (the
+// GM_VARIANT_LIST_FRONTIER ablation): each superstep is SEND from the list,
+// the push product appending every lowered vertex, and a sort + unique that
+// forms the next list (its length read by the host).
+static int32_t run_min_program_list(gm_graph g, Workspace* ws, const Adj& adj, int kind,
+                                    const int32_t* ids, int64_t count, const uint32_t* bitmap,
+                                    int32_t max_iters, uint32_t* prop, int32_t* active_out,
+                                    hipStream_t s, RunStats* stats) {
+  const int64_t n = g->n;
+  if (bitmap) throw Unsupported{"the list-frontier variant takes frontier ids"};
+  uint32_t medges = 0;
+  GM_HIP(hipMemcpyAsync(&medges, adj.off + n, 4, hipMemcpyDeviceToHost, s));
+  GM_HIP(hipStreamSynchronize(s));
+  const int64_t cap = std::max<int64_t>({(int64_t)medges, count, 1});
+  ListBufs b;
+  b.lst = dalloc<uint32_t>(std::max<int64_t>(n, 1));
+  b.app[0] = dalloc<uint32_t>(cap);
+  b.app[1] = dalloc<uint32_t>(cap);
+  b.cnt = dalloc<unsigned int>(2);
+  if (count > 0) {
+    ids_to_u32<<<blocks_for(count), kThreads, 0, s>>>(ids, count, b.app[0]);
+    GM_HIP(hipGetLastError());
+  }
+  int64_t c = sort_unique(b, count, s);
+  const bool vertex_push = (g->tune.variant & GM_VARIANT_VERTEX_PUSH) != 0;
+  int32_t iters = 0;
+  RunStats st{};
+  while (c > 0 && (max_iters <= 0 || iters < max_iters)) {
+    start_batch(ws, s);
+    fill_u32(b.cnt, 1, 0u, s);
+    send_list_kernel<<<blocks_for(c, 4096), kThreads, 0, s>>>(b.lst, c, prop, adj.off, ws->q,
+                                                               ws->qmsg, ws->qbeg, ws->qest,
+                                                               ws->ctl);
+    if (vertex_push) {
+      if (kind == GM_PROG_SSSP)
+        push_vertex_kernel<GM_PROG_SSSP><<<blocks_for(c), kThreads, 0, s>>>(
+            ws->ctl, n, false, 1, ws->qmsg, ws->qbeg, ws->qest, adj.idx, adj.w, prop, nullptr,
+            b.app[0], b.cnt);
+      else
+        push_vertex_kernel<GM_PROG_BFS><<<blocks_for(c), kThreads, 0, s>>>(
+            ws->ctl, n, false, 1, ws->qmsg, ws->qbeg, ws->qest, adj.idx, nullptr, prop, nullptr,
+            b.app[0], b.cnt);
+    } else if (kind == GM_PROG_SSSP) {
+      push_kernel<GM_PROG_SSSP><<<g->tune.push_blocks, kThreads, 0, s>>>(
+          ws->ctl, n, false, 1, ws->qmsg, ws->qbeg, ws->qest, adj.idx, adj.w, prop, nullptr,
+          b.app[0], b.cnt);
+    } else {
+      push_kernel<GM_PROG_BFS><<<g->tune.push_blocks, kThreads, 0, s>>>(
+          ws->ctl, n, false, 1, ws->qmsg, ws->qbeg, ws->qest, adj.idx, nullptr, prop, nullptr,
+          b.app[0], b.cnt);
+    }
+    GM_HIP(hipGetLastError());
+    unsigned int appended = 0;
+    GM_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    GM_HIP(hipMemcpyAsync(&appended, b.cnt, 4, hipMemcpyDeviceToHost, s));
+    GM_HIP(hipStreamSynchronize(s));
+    ++iters;
+    ++st.push_supersteps;
+    st.edges_scanned += (uint32_t)ws->host_ctl[0].packed;
+    c = sort_unique(b, appended, s);
+  }
+  if (active_out) {
+    fill_u32(reinterpret_cast<uint32_t*>(active_out), n, 0u, s);
+    if (c > 0) {
+      list_to_active<<<blocks_for(c), kThreads, 0, s>>>(b.lst, c, active_out);
+      GM_HIP(hipGetLastError());
+    }
+  }
+  GM_HIP(hipStreamSynchronize(s));
+  st.supersteps = iters;
+  if (stats) *stats = st;
+  return iters;
+}
+
 int32_t run_min_program(gm_graph g, int kind, int order, const int32_t* ids, int64_t count,
                         const uint32_t* bitmap, int32_t max_iters, uint32_t* prop,
                         int32_t* active_out, hipStream_t s, RunStats* stats) {
   Workspace* ws = ensure_ws(g, s);
   const Adj adj = adjacency(g, ws, order, s);
+  if ((g->tune.variant & GM_VARIANT_LIST_FRONTIER) && kind != GM_PROG_DEGREE)
+    return run_min_program_list(g, ws, adj, kind, ids, count, bitmap, max_iters, prop,
+                                active_out, s, stats);
   const int64_t n = g->n;
   const int64_t words = (n + 31) / 32;
   const bool sym = (g->prep & (GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG)) == GM_PREP_SYMMETRIZE;

@@ -63,6 +63,7 @@ struct Dense {
   double* head = nullptr;       // per tile: sum of the part of a row begun before the tile
   double* tail = nullptr;       // per tile: sum of the part of a row that goes on after it
   Cross* cross = nullptr;
+  uint32_t* roff = nullptr;     // row offsets of the relabelled in-adjacency (n + 1)
   int64_t ntiles = 0, ncross = 0;
   int64_t rows = 0;             // rows with in-edges: new labels [0, rows)
   int cus = 0;                  // compute units of the device
@@ -242,6 +243,28 @@ __global__ void pr_cross(const Cross* __restrict__ cross, int64_t ncross,
   if (i < ncross && j == 0) apply_row<kPersonal>(c.row, acc, r, seed, inv_outdeg, x_out, pr_out);
 }
 
+// Ablation variant of the superstep (GM_VARIANT_ROW_PULL): one thread per
+// row sums its in-edges in order (no edge tiles, no LDS copy of the hottest
+// messages), then APPLY and the next SEND.
+template <bool kWeighted, bool kPersonal>
+__global__ void pr_rowpull(const uint32_t* __restrict__ roff, const int32_t* __restrict__ idx,
+                           const float* __restrict__ w, int64_t rows,
+                           const float* __restrict__ x_in, const float* __restrict__ inv_outdeg,
+                           float r, int32_t seed, float* __restrict__ x_out,
+                           float* __restrict__ pr_out) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < rows;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    double y = 0.0;
+    const uint32_t e1 = roff[v + 1];
+    for (uint32_t e = roff[v]; e < e1; ++e) {
+      float x = x_in[idx[e]];
+      if constexpr (kWeighted) x *= w[e];
+      y += (double)x;
+    }
+    apply_row<kPersonal>((uint32_t)v, y, r, seed, inv_outdeg, x_out, pr_out);
+  }
+}
+
 // Rows without in-edges: PR = r * tele(v) in every superstep after the first,
 // so their APPLY and next SEND are written once per run instead of per
 // superstep.
@@ -362,6 +385,7 @@ void free_pull_schedule(gm_graph g) {
   dfree(d->head);
   dfree(d->tail);
   dfree(d->cross);
+  dfree(d->roff);
   delete d;
   g->pr_sched = nullptr;
   ++g->ws_gen;
@@ -428,6 +452,8 @@ void ensure_pull_schedule(gm_graph g, hipStream_t st) {
     d->head = dalloc<double>(ntiles);
     d->tail = dalloc<double>(ntiles);
     d->cross = dalloc<Cross>(cross.size());
+    d->roff = dalloc<uint32_t>(n + 1);
+    GM_HIP(hipMemcpyAsync(d->roff, noff.data(), (n + 1) * 4, hipMemcpyHostToDevice, st));
     GM_HIP(hipMemcpyAsync(d->new_of, new_of.data(), n * 4, hipMemcpyHostToDevice, st));
     GM_HIP(hipMemcpyAsync(d->old_of, old_of.data(), n * 4, hipMemcpyHostToDevice, st));
     GM_HIP(hipMemcpyAsync(d->starts, starts.data(), starts.size() * 4, hipMemcpyHostToDevice, st));
@@ -541,7 +567,21 @@ static void pagerank_driver(gm_graph g, Dense* d, const Vecs& v, float r, int32_
                                               d->inv_outdeg, r, seed_new, xout, pout, v.head,
                                               v.tail, hot_n);
     };
-    if (weighted && personal)
+    if (g->tune.variant & GM_VARIANT_ROW_PULL) {
+      auto rows = [&](auto kern) {
+        if (d->rows > 0)
+          kern<<<blocks_for(d->rows), kThreads, 0, st>>>(d->roff, d->idx, w, d->rows, xin,
+                                                         d->inv_outdeg, r, seed_new, xout, pout);
+      };
+      if (weighted && personal)
+        rows(pr_rowpull<true, true>);
+      else if (weighted)
+        rows(pr_rowpull<true, false>);
+      else if (personal)
+        rows(pr_rowpull<false, true>);
+      else
+        rows(pr_rowpull<false, false>);
+    } else if (weighted && personal)
       launch(pr_pull<true, true>);
     else if (weighted)
       launch(pr_pull<true, false>);
@@ -549,7 +589,7 @@ static void pagerank_driver(gm_graph g, Dense* d, const Vecs& v, float r, int32_
       launch(pr_pull<false, true>);
     else
       launch(pr_pull<false, false>);
-    if (d->ncross > 0) {
+    if (d->ncross > 0 && !(g->tune.variant & GM_VARIANT_ROW_PULL)) {
       const unsigned fb = (unsigned)((d->ncross * kCrossLanes + kThreads - 1) / kThreads);
       if (personal)
         pr_cross<true><<<fb, kThreads, 0, st>>>(d->cross, d->ncross, v.head, v.tail,

@@ -191,7 +191,8 @@ gm_status check_tuning(const gm_tuning& t) {
            {"tc_wave_max", t.tc_wave_max, {64, 1024}},
            {"tc_wave_work", t.tc_wave_work, {256, 1u << 24}},
            {"tc_block_work", t.tc_block_work, {256, 1u << 26}},
-           {"pr_hot", t.pr_hot, {0, 40960}}};
+           {"pr_hot", t.pr_hot, {0, 40960}},
+           {"variant", t.variant, {0, 7}}};
   for (const F& x : f)
     if (x.v < x.r.lo || x.v > x.r.hi)
       return fail(GM_EINVAL, "%s = %u outside [%u, %u]", x.name, x.v, x.r.lo, x.r.hi);
@@ -208,6 +209,7 @@ gm_tuning to_abi(const Tuning& t) {
   o.tc_wave_work = t.tc_wave_work;
   o.tc_block_work = t.tc_block_work;
   o.pr_hot = t.pr_hot;
+  o.variant = t.variant;
   return o;
 }
 
@@ -220,6 +222,7 @@ void from_abi(const gm_tuning& o, Tuning* t) {
   t->tc_wave_work = o.tc_wave_work;
   t->tc_block_work = o.tc_block_work;
   t->pr_hot = o.pr_hot;
+  t->variant = o.variant;
 }
 
 // ---------------------------------------------------------------------------
@@ -300,6 +303,7 @@ bool read_cache(const char* path, TuneCache* out) {
         else if (field == "tc_wave_work") t.tc_wave_work = v;
         else if (field == "tc_block_work") t.tc_block_work = v;
         else if (field == "pr_hot") t.pr_hot = v;
+        else if (field == "variant") t.variant = v;
         else p.ok = false;
       } while (p.ok && p.eat(','));
       p.need('}');
@@ -324,7 +328,8 @@ bool write_cache(const char* path, const TuneCache& c) {
         << ", \"superstep_batch\": " << t.superstep_batch << ", \"push_blocks\": " << t.push_blocks
         << ", \"ppr_chunk\": " << t.ppr_chunk << ", \"tc_wave_max\": " << t.tc_wave_max
         << ", \"tc_wave_work\": " << t.tc_wave_work << ", \"tc_block_work\": " << t.tc_block_work
-        << ", \"pr_hot\": " << t.pr_hot << "}" << (++k < c.size() ? "," : "") << "\n";
+        << ", \"pr_hot\": " << t.pr_hot << ", \"variant\": " << t.variant << "}"
+        << (++k < c.size() ? "," : "") << "\n";
     }
     f << "}\n";
     if (!f) return false;

@@ -255,3 +255,32 @@ def test_pagerank_weight_gradient_edgeless_graph():
     assert np.allclose(out.detach().cpu().numpy(), ref, rtol=1e-6, atol=0)
     out.sum().backward()
     assert wt.grad.shape == (0,)
+
+
+def test_cf_gradient_descent_hand_and_oracle():
+    """gm_cf_gd (Eqs. (5)-(6)): the hand-worked two steps of
+    golden/cf_gd_hand.txt, and five steps on a 2,000 x 300 rating graph
+    against the oracle's float64 descent (losses relative <= 1e-5, factors
+    Frobenius relative <= 1e-5)."""
+    kv = {}
+    for line in open(os.path.join(HERE, "golden", "cf_gd_hand.txt")):
+        if line.startswith("#") or not line.strip() or line.startswith("key"):
+            continue
+        k, v = line.split()
+        kv[k] = float(v)
+    g = gm.RatingGraph.from_coo(1, 1, [0], [0], [int(kv["G"])])
+    pu = torch.full((1, 1), kv["p0"], dtype=torch.float32, device=DEV)
+    pv = pu.clone()
+    hist = torch.empty(3, dtype=torch.float64, device=DEV)
+    gm.cf_gd(g, pu, pv, kv["lambda"], kv["gamma"], 2, hist)
+    assert abs(float(pu.item()) - kv["p2"]) < 1e-6 and abs(float(pv.item()) - kv["p2"]) < 1e-6
+    assert abs(float(hist[0]) - kv["L0"]) < 1e-6 and abs(float(hist[1]) - kv["L1"]) < 1e-5
+    R, PU, PV, rg = cf_setup(2000, 300, 60_000)
+    pu, pv = torch.tensor(PU, device=DEV), torch.tensor(PV, device=DEV)
+    hist = torch.empty(6, dtype=torch.float64, device=DEV)
+    gm.cf_gd(rg, pu, pv, LAM, 0.002, 5, hist)
+    rpu, rpv, rL = oracle.cf_gd(R.n_users, R.n_items, R.user, R.item, R.rating, PU, PV, LAM,
+                                0.002, 5)
+    assert np.max(np.abs(hist.cpu().numpy() - rL) / rL) <= 1e-5
+    assert rL[-1] < rL[0]  # descent
+    assert rel(pu.cpu().numpy(), rpu) <= 1e-5 and rel(pv.cpu().numpy(), rpv) <= 1e-5

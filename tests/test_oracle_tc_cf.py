@@ -186,3 +186,30 @@ def test_cf_without_ratings_is_the_l2_term():
     assert L == pytest.approx(0.05 * l2, rel=1e-12)
     assert np.allclose(gU, 0.1 * PU.astype(np.float64), rtol=1e-12, atol=0)
     assert np.allclose(gV, 0.1 * PV.astype(np.float64), rtol=1e-12, atol=0)
+
+
+def test_cf_gd_hand_worked_and_against_one_pass_gradients():
+    """The oracle's GD loop (Eqs. (5)-(6)) on the hand-worked 1 x 1 example of
+    golden/cf_gd_hand.txt (two steps), and each step's gradients against the
+    C oracle's one-pass gradients at the same (float32-representable) point."""
+    import os
+    kv = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "cf_gd_hand.txt")):
+        if line.startswith("#") or not line.strip() or line.startswith("key"):
+            continue
+        k, v = line.split()
+        kv[k] = float(v)
+    P = np.array([[kv["p0"]]])
+    pu, pv, L = oracle.cf_gd(1, 1, [0], [0], [int(kv["G"])], P, P, kv["lambda"], kv["gamma"], 2)
+    assert abs(L[0] - kv["L0"]) < 1e-12 and abs(L[1] - kv["L1"]) < 1e-12
+    assert abs(pu[0, 0] - kv["p2"]) < 1e-12 and abs(pv[0, 0] - kv["p2"]) < 1e-12
+    pu1, _, _ = oracle.cf_gd(1, 1, [0], [0], [int(kv["G"])], P, P, kv["lambda"], kv["gamma"], 1)
+    assert abs(pu1[0, 0] - kv["p1"]) < 1e-12
+    R = gg.cf_ratings(n_users=300, n_items=40, total=6000, dmin=5)
+    PU, PV = gg.cf_point(300, 40, 8)
+    L0, gu, gv = oracle.cf_loss_grad(300, 40, R.user, R.item, R.rating, PU, PV, 0.05)
+    L64, gu64, gv64 = oracle._cf_loss_grad64(300, 40, R.user, R.item, R.rating,
+                                             PU.astype(np.float64), PV.astype(np.float64), 0.05)
+    assert abs(L0 - L64) <= 1e-12 * L0
+    assert np.allclose(gu, gu64, rtol=1e-12, atol=1e-12)
+    assert np.allclose(gv, gv64, rtol=1e-12, atol=1e-12)
