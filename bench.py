@@ -171,7 +171,7 @@ def main():
         pr_counter_run(gm, torch, n, s, d, args.pr_only)
         return
     if args.ablation:
-        print(json.dumps(run_ablation(gm, torch, np, n, s, d, w)), flush=True)
+        print(json.dumps(run_ablation(gm, gg, torch, np, n, s, d, w)), flush=True)
         return
     if args.tc_only:
         g = gm.Graph.from_coo(n, s, d, prep=gm.GM_PREP_UPPER_DAG)
@@ -670,7 +670,7 @@ def measure_scale26(gm, gg, torch, np, tm):
     return res
 
 
-def run_ablation(gm, torch, np, n, s, d, w):
+def run_ablation(gm, gg, torch, np, n, s, d, w):
     """Each design choice of the paper's Fig. 7 (Sec. 5.4) swapped for its
     alternative on the scale-22 workload, results asserted equal to the
     default schedule's (BFS, SSSP bit-exact; PageRank within 2e-5 relative):
@@ -679,11 +679,15 @@ def run_ablation(gm, torch, np, n, s, d, w):
         per active vertex;
       direction (BFS): push with pull supersteps for large frontiers
         (default) vs push only;
+      vertex order (BFS, SSSP): the caller's labels (default) vs a copy
+        relabelled by decreasing in-degree, on the generator's labels and on
+        a seeded random permutation of them (scrambled_labels);
       PageRank: edge tiles + LDS copy of the hottest messages (default),
         tiles without the LDS copy, one thread per row."""
     dev = torch.device("cuda:0")
-    LIST, VPUSH, ROWPULL = (gm._lib.GM_VARIANT_LIST_FRONTIER, gm._lib.GM_VARIANT_VERTEX_PUSH,
-                            gm._lib.GM_VARIANT_ROW_PULL)
+    LIST, VPUSH, ROWPULL, DEG = (gm._lib.GM_VARIANT_LIST_FRONTIER,
+                                  gm._lib.GM_VARIANT_VERTEX_PUSH, gm._lib.GM_VARIANT_ROW_PULL,
+                                  gm._lib.GM_VARIANT_DEGREE_ORDER)
     tm = Timer()
     g_sym = gm.Graph.from_coo(n, s, d, prep=gm.GM_PREP_DROP_SELF_LOOPS | gm.GM_PREP_SYMMETRIZE,
                               layouts=gm.GM_LAYOUT_OUT)
@@ -712,7 +716,8 @@ def run_ablation(gm, torch, np, n, s, d, w):
 
     frontier_variants = [("bitvector_frontier+equal_edge_push", 0), ("list_frontier", LIST),
                          ("thread_per_vertex_push", VPUSH),
-                         ("list_frontier+thread_per_vertex_push", LIST | VPUSH)]
+                         ("list_frontier+thread_per_vertex_push", LIST | VPUSH),
+                         ("degree_ordered_labels", DEG)]
     for name, var in frontier_variants:
         # pull supersteps once more than n / pull_div vertices are active: 1
         # never pulls, 128 is the default switch
@@ -734,6 +739,39 @@ def run_ablation(gm, torch, np, n, s, d, w):
         assert np.array_equal(got, ref["sssp"]), name
         out["sssp"][name] = {"ms": round(ms, 3), "gteps": round(e / ms / 1e6, 2)}
     g_dir.set_tuning(variant=0)
+    # The same graphs with the vertex labels scrambled (seeded permutation):
+    # results are the unscrambled ones, permuted.
+    perm = gg.label_permutation(n)
+    sg_sym = gm.Graph.from_coo(n, perm[s], perm[d],
+                               prep=gm.GM_PREP_DROP_SELF_LOOPS | gm.GM_PREP_SYMMETRIZE,
+                               layouts=gm.GM_LAYOUT_OUT)
+    sg_dir = gm.Graph.from_coo(n, perm[s], perm[d], w=w, prep=gm.GM_PREP_DROP_SELF_LOOPS)
+    sroot = torch.tensor([int(perm[0])], dtype=torch.int32, device=dev)
+    out["scrambled_labels"] = {}
+    for name, var in (("caller_labels", 0), ("degree_ordered_labels", DEG)):
+        sg_sym.set_tuning(variant=var)
+        sg_dir.set_tuning(variant=var)
+
+        def sbfs():
+            lv.fill_(gm.INF_LEVEL)
+            lv[int(perm[0])] = 0
+            gm.run_vertex_program(sg_sym, gm.GM_PROG_BFS, sroot, -1, lv)
+
+        def ssssp():
+            dist.fill_(-1)
+            dist[int(perm[0])] = 0
+            gm.run_vertex_program(sg_dir, gm.GM_PROG_SSSP, sroot, -1, dist)
+        bms = tm.ms(sbfs, 3)
+        be = sg_sym.last_run_stats().edges_scanned
+        assert np.array_equal(lv.cpu().numpy()[perm], ref["bfs"]), name
+        sms = tm.ms(ssssp, 3)
+        se = sg_dir.last_run_stats().edges_scanned
+        assert np.array_equal(dist.cpu().numpy()[perm], ref["sssp"]), name
+        out["scrambled_labels"][name] = {
+            "bfs": {"ms": round(bms, 3), "gteps": round(be / bms / 1e6, 2)},
+            "sssp": {"ms": round(sms, 3), "gteps": round(se / sms / 1e6, 2)}}
+    sg_sym.close()
+    sg_dir.close()
     m = g_dir.m
     for name, var, hot in (("tiles+lds_hot_set", 0, 40960), ("tiles_no_lds", 0, 0),
                            ("row_per_thread", ROWPULL, 40960)):

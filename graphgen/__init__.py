@@ -43,6 +43,7 @@ SEED_CF_TRUE = 7
 SEED_CF_NOISE = 8
 SEED_CF_POINT = 9
 SEED_PR_UPSTREAM = 10
+SEED_SCRAMBLE = 11
 SEED_MIXED_BASE = 100
 
 
@@ -145,6 +146,16 @@ def normal_f32(n: int, seed: int, std: float = 1.0) -> np.ndarray:
     out = np.empty(n, dtype=np.float32)
     _load().gg_normal_f32(n, seed, std, _p(out))
     return out
+
+
+def label_permutation(n: int, seed: int = SEED_SCRAMBLE) -> np.ndarray:
+    """A seeded random permutation of [0, n) (vertex v becomes perm[v]): the
+    vertices ordered by uniform keys of stream (seed, 0), ties by label."""
+    keys = uniform_f32(n, seed)
+    order = np.argsort(keys, kind="stable")  # order[j] = vertex taking label j
+    perm = np.empty(n, dtype=np.int32)
+    perm[order] = np.arange(n, dtype=np.int32)
+    return perm
 
 
 def sources(n: int, src: np.ndarray, dst: np.ndarray, k: int, seed: int,

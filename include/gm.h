@@ -221,8 +221,10 @@ typedef struct gm_frontier {
 
 /*
  * Build, now, the per-graph schedules a program run needs, which a first
- * run would otherwise build: the frontier workspace of BFS and SSSP, the
- * relabelled pull layout of PageRank and PPR (Sec. 4.4.1 stores the matrix
+ * run would otherwise build: the frontier workspace of BFS and SSSP (and,
+ * with GM_VARIANT_DEGREE_ORDER set, their degree-ordered copy of the
+ * out-adjacency; runs along in-edges or both directions build theirs on
+ * first use), the relabelled pull layout of PageRank and PPR (Sec. 4.4.1 stores the matrix
  * once in the layout its SpMV reads; this is that step), the owner/partner
  * work plan of triangle counting (Sec. 4.2, program 2). Lets a caller time
  * preprocessing and runs apart. prog->kind selects the program; the other
@@ -523,7 +525,7 @@ typedef struct gm_tuning {
                                choices, for ablation (Sec. 5.4, Fig. 7); each
                                bit swaps one in, results are identical:
                                GM_VARIANT_LIST_FRONTIER, _VERTEX_PUSH,
-                               _ROW_PULL (0..7; 0) */
+                               _ROW_PULL, _DEGREE_ORDER (0..15; 0) */
 } gm_tuning;
 
 /* Bits of gm_tuning.variant (BFS/SSSP supersteps and the PageRank pull):
@@ -535,8 +537,19 @@ typedef struct gm_tuning {
  *  GM_VARIANT_VERTEX_PUSH: one thread per active vertex walks its out-edges
  *    (no load balancing, Sec. 4.4.3) instead of equal edge ranges;
  *  GM_VARIANT_ROW_PULL: PageRank pulls one row per thread (no edge tiles,
- *    no LDS copy of the hottest messages) instead of the tiled kernel. */
-enum { GM_VARIANT_LIST_FRONTIER = 1, GM_VARIANT_VERTEX_PUSH = 2, GM_VARIANT_ROW_PULL = 4 };
+ *    no LDS copy of the hottest messages) instead of the tiled kernel;
+ *  GM_VARIANT_DEGREE_ORDER: BFS/SSSP/degree supersteps of
+ *    gm_run_vertex_program run on a copy of the adjacency relabelled by
+ *    decreasing in-degree (built on first use, one per order; each run maps
+ *    its values and frontier in and out) instead of the caller's labels, so
+ *    that the values read at random cluster in few cache lines whatever the
+ *    caller's vertex order (the locality Sec. 4.4.1's partitioning seeks). */
+enum {
+  GM_VARIANT_LIST_FRONTIER = 1,
+  GM_VARIANT_VERTEX_PUSH = 2,
+  GM_VARIANT_ROW_PULL = 4,
+  GM_VARIANT_DEGREE_ORDER = 8
+};
 
 /* Read g's parameters. Errors: GM_ESTATE, GM_EINVAL (out NULL). */
 gm_status gm_graph_get_tuning(gm_graph g, gm_tuning* out);

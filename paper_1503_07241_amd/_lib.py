@@ -22,6 +22,7 @@ GM_LAYOUT_OUT, GM_LAYOUT_IN = 1, 2
 GM_PROG_BFS, GM_PROG_SSSP, GM_PROG_PAGERANK, GM_PROG_PPR, GM_PROG_TC, GM_PROG_DEGREE = range(1, 7)
 GM_ORDER_OUT, GM_ORDER_IN, GM_ORDER_ALL = 1, 2, 3
 GM_VARIANT_LIST_FRONTIER, GM_VARIANT_VERTEX_PUSH, GM_VARIANT_ROW_PULL = 1, 2, 4
+GM_VARIANT_DEGREE_ORDER = 8
 
 
 class GmError(RuntimeError):

@@ -235,7 +235,7 @@ gm_status gm_graph_prepare(gm_graph g, const gm_program* prog, void* stream) {
   return guarded([&]() -> gm_status {
     if (const gm_status st = check_device(g)) return st;
     if (kind == GM_PROG_BFS || kind == GM_PROG_SSSP || kind == GM_PROG_DEGREE) {
-      prepare_min_program(g, s);
+      prepare_plain_min_program(g, kind, s);
     } else if (kind == GM_PROG_TC) {
       prepare_triangle_count(g, s);
     } else {

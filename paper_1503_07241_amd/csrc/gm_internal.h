@@ -229,6 +229,11 @@ void run_pagerank_vjp(gm_graph g, const float* w, float r, int32_t T, const floa
                       const float* grad_out, float* grad_w, hipStream_t s);
 void free_vjp_plan(gm_graph g);
 
+// The frontier workspace of the plain BFS/SSSP/degree runs and, when the
+// tuning asks for the degree order, their relabelled adjacency along
+// out-edges (with BFS's pull layout).
+void prepare_plain_min_program(gm_graph g, int kind, hipStream_t s);
+
 // Captured-run building blocks (no allocation, no host synchronisation once
 // the prepare_* call for the same graph and shape has run).
 void prepare_min_program(gm_graph g, hipStream_t s);

@@ -31,6 +31,7 @@
 #include <cstring>
 
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 #include <rocprim/device/device_select.hpp>
 
 #include "gm_internal.h"
@@ -65,6 +66,7 @@ struct Workspace {
   uint32_t* all_off = nullptr;
   int32_t* all_idx = nullptr;
   uint32_t* all_w = nullptr;
+  struct Relab* rl = nullptr;  // degree-ordered copy for the plain runs (built on first use)
 };
 
 // The adjacency a superstep pushes messages along: out-edges (GM_ORDER_OUT),
@@ -75,6 +77,50 @@ struct Adj {
   const int32_t* idx;
   const uint32_t* w;
 };
+
+// What a superstep reads: the adjacency it pushes along and, for BFS along
+// out-edges, the in-adjacency a pull superstep scans (pull_ok false: never
+// pulls).
+struct View {
+  Adj push;
+  const uint32_t* pull_off;
+  const int32_t* pull_idx;
+  bool pull_ok;
+};
+
+// A device-owned adjacency (offsets, targets padded by kIdxPad, values).
+struct OwnedAdj {
+  uint32_t* off = nullptr;
+  int32_t* idx = nullptr;
+  uint32_t* w = nullptr;
+  Adj view() const { return Adj{off, idx, w}; }
+  void release() {
+    dfree(off);
+    dfree(idx);
+    dfree(w);
+    off = nullptr;
+    idx = nullptr;
+    w = nullptr;
+  }
+};
+
+// Degree-ordered relabelling of the plain runs (GM_VARIANT_DEGREE_ORDER):
+// vertices numbered by decreasing in-degree (out-degree without the
+// in-layout), ties by label, and the adjacency rebuilt in the new labels.
+// The values a superstep reads and lowers at random (prop of every edge's
+// target) then cluster at low labels, where the hottest share few cache
+// lines, whatever order the caller's labels come in. Each run maps the
+// caller's values and frontier in and its results back; supersteps,
+// frontiers and results are those of the caller's labels, permuted.
+struct Relab {
+  int32_t* new_of = nullptr;   // caller label -> new label
+  int32_t* old_of = nullptr;   // new label -> caller label
+  uint32_t* prop = nullptr;    // the run's vertex values in new labels
+  int32_t* ids = nullptr;      // the run's frontier ids in new labels (list variant)
+  int32_t* active = nullptr;   // the run's final frontier in new labels
+  OwnedAdj out, in, all;       // each built on first use
+};
+
 
 __device__ inline bool use_pull(const Ctl& c, int kind, bool pull_ok, int64_t n,
                                 uint32_t pull_div) {
@@ -524,6 +570,89 @@ __global__ void all_lists(const uint32_t* __restrict__ out_off, const int32_t* _
   }
 }
 
+// Sort keys of the relabelling: mask - degree (a stable ascending sort puts
+// higher degrees first, ties in label order), the vertex as value.
+__global__ void degree_keys(const uint32_t* __restrict__ off, int64_t n, uint32_t mask,
+                            uint32_t* __restrict__ key, int32_t* __restrict__ val) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    key[v] = mask - (off[v + 1] - off[v]);
+    val[v] = (int32_t)v;
+  }
+}
+
+__global__ void invert_perm(const int32_t* __restrict__ old_of, int64_t n,
+                            int32_t* __restrict__ new_of) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    new_of[old_of[i]] = (int32_t)i;
+}
+
+// len[i] = degree of the vertex with new label i; len[n] = 0 (an exclusive
+// scan of n + 1 lengths gives the offsets, the last one the edge count).
+__global__ void relabel_lengths(const uint32_t* __restrict__ off, const int32_t* __restrict__ old_of,
+                                int64_t n, uint32_t* __restrict__ len) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i == n) {
+      len[i] = 0;
+    } else {
+      const int32_t v = old_of[i];
+      len[i] = off[v + 1] - off[v];
+    }
+  }
+}
+
+// Row i of the relabelled adjacency, one wavefront per row: the row of
+// old_of[i], its targets mapped to new labels, values alike, in the row's
+// own order.
+__global__ void relabel_rows(const uint32_t* __restrict__ off, const int32_t* __restrict__ idx,
+                             const uint32_t* __restrict__ w, const int32_t* __restrict__ old_of,
+                             const int32_t* __restrict__ new_of, int64_t n,
+                             const uint32_t* __restrict__ noff, int32_t* __restrict__ nidx,
+                             uint32_t* __restrict__ nw) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; i < n; i += waves) {
+    const int32_t v = old_of[i];
+    const uint32_t b = off[v], e = off[v + 1], nb = noff[i];
+    for (uint32_t j = lane; j < e - b; j += 64) {
+      nidx[nb + j] = new_of[idx[b + j]];
+      if (nw) nw[nb + j] = w[b + j];
+    }
+  }
+}
+
+// out[i] = src[index[i]]: values between the caller's labels and the new ones.
+__global__ void permute_u32(const uint32_t* __restrict__ src, const int32_t* __restrict__ index,
+                            int64_t n, uint32_t* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = src[index[i]];
+}
+
+// The caller's frontier bitvector (vertices below n) as bits of the new
+// labels, into a cleared bitvector.
+__global__ __launch_bounds__(kThreads) void seed_bitmap_mapped(const uint32_t* __restrict__ in,
+                                                               int64_t n,
+                                                               const int32_t* __restrict__ new_of,
+                                                               uint32_t* bits) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    if ((in[v >> 5] >> (v & 31)) & 1u) {
+      const int32_t u = new_of[v];
+      atomicOr(&bits[u >> 5], 1u << (u & 31));
+    }
+}
+
+// The caller's frontier ids in new labels (list variant).
+__global__ void map_ids(const int32_t* __restrict__ ids, int64_t count,
+                        const int32_t* __restrict__ new_of, int32_t* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = new_of[ids[i]];
+}
+
 Workspace* ensure_ws(gm_graph g, hipStream_t s) {
   Workspace* ws = static_cast<Workspace*>(g->min_ws);
   if (ws) return ws;
@@ -590,6 +719,167 @@ Adj adjacency(gm_graph g, Workspace* ws, int order, hipStream_t s) {
   return Adj{ws->all_off, ws->all_idx, ws->all_w};
 }
 
+void free_relab(Relab* rl) {
+  if (!rl) return;
+  dfree(rl->new_of);
+  dfree(rl->old_of);
+  dfree(rl->prop);
+  dfree(rl->ids);
+  dfree(rl->active);
+  rl->out.release();
+  rl->in.release();
+  rl->all.release();
+  delete rl;
+}
+
+// The permutation and per-run buffers of the relabelling (built once per
+// graph; a failed build leaves none behind).
+Relab* ensure_relab(gm_graph g, Workspace* ws, hipStream_t s) {
+  if (ws->rl) return ws->rl;
+  const int64_t n = g->n;
+  const bool has_in = g->in_off != nullptr;
+  const uint32_t* doff = has_in ? g->in_off : g->out_off;
+  const int64_t maxd = has_in ? g->max_in : g->max_out;
+  int bits = 1;  // 2^bits > every degree
+  while (bits < 32 && ((int64_t)1 << bits) <= maxd) ++bits;
+  const uint32_t mask = bits >= 32 ? 0xFFFFFFFFu : (1u << bits) - 1u;
+  Relab* rl = new Relab();
+  uint32_t* k1 = nullptr;
+  uint32_t* k2 = nullptr;
+  int32_t* v1 = nullptr;
+  void* tmp = nullptr;
+  auto drop_temps = [&]() {
+    dfree(tmp);
+    dfree(k1);
+    dfree(k2);
+    dfree(v1);
+  };
+  try {
+    rl->new_of = dalloc<int32_t>(n);
+    rl->old_of = dalloc<int32_t>(n);
+    rl->prop = dalloc<uint32_t>(n);
+    rl->ids = dalloc<int32_t>(n);
+    rl->active = dalloc<int32_t>(n);
+    k1 = dalloc<uint32_t>(n);
+    k2 = dalloc<uint32_t>(n);
+    v1 = dalloc<int32_t>(n);
+    degree_keys<<<blocks_for(n), kThreads, 0, s>>>(doff, n, mask, k1, v1);
+    GM_HIP(hipGetLastError());
+    size_t bytes = 0;
+    GM_HIP(rocprim::radix_sort_pairs(nullptr, bytes, k1, k2, v1, rl->old_of, (size_t)n, 0, bits, s));
+    tmp = dmalloc(bytes);
+    GM_HIP(rocprim::radix_sort_pairs(tmp, bytes, k1, k2, v1, rl->old_of, (size_t)n, 0, bits, s));
+    invert_perm<<<blocks_for(n), kThreads, 0, s>>>(rl->old_of, n, rl->new_of);
+    GM_HIP(hipGetLastError());
+    GM_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    drop_temps();
+    free_relab(rl);
+    throw;
+  }
+  drop_temps();
+  ws->rl = rl;
+  return rl;
+}
+
+// One adjacency (off, idx, w) rebuilt in the labels of rl.
+OwnedAdj relabel_adj(gm_graph g, const Relab* rl, const uint32_t* off, const int32_t* idx,
+                     const uint32_t* w, hipStream_t s) {
+  const int64_t n = g->n, m = g->m;
+  OwnedAdj a;
+  uint32_t* len = nullptr;
+  void* tmp = nullptr;
+  try {
+    a.off = dalloc<uint32_t>(n + 1);
+    a.idx = dalloc<int32_t>(m + kIdxPad);
+    if (w) a.w = dalloc<uint32_t>(m);
+    len = dalloc<uint32_t>(n + 1);
+    relabel_lengths<<<blocks_for(n + 1), kThreads, 0, s>>>(off, rl->old_of, n, len);
+    GM_HIP(hipGetLastError());
+    size_t bytes = 0;
+    GM_HIP(rocprim::exclusive_scan(nullptr, bytes, len, a.off, 0u, (size_t)(n + 1),
+                                   rocprim::plus<uint32_t>(), s));
+    tmp = dmalloc(bytes);
+    GM_HIP(rocprim::exclusive_scan(tmp, bytes, len, a.off, 0u, (size_t)(n + 1),
+                                   rocprim::plus<uint32_t>(), s));
+    relabel_rows<<<blocks_for(64 * n), kThreads, 0, s>>>(off, idx, w, rl->old_of, rl->new_of, n,
+                                                         a.off, a.idx, a.w);
+    fill_kernel<<<1, kThreads, 0, s>>>(reinterpret_cast<uint32_t*>(a.idx) + m, kIdxPad, 0u);
+    GM_HIP(hipGetLastError());
+    GM_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    dfree(tmp);
+    dfree(len);
+    a.release();
+    throw;
+  }
+  dfree(tmp);
+  dfree(len);
+  return a;
+}
+
+// The relabelled adjacency for `order` (GM_ORDER_ALL: each vertex's
+// relabelled out-list followed by its relabelled in-list).
+Adj relab_adjacency(gm_graph g, Relab* rl, int order, hipStream_t s) {
+  const bool weighted = g->wtype == GM_W_U32;
+  const uint32_t* out_w = weighted ? static_cast<const uint32_t*>(g->out_w) : nullptr;
+  const uint32_t* in_w = weighted ? static_cast<const uint32_t*>(g->in_w) : nullptr;
+  if ((order == GM_ORDER_IN || order == GM_ORDER_ALL) && !rl->in.off)
+    rl->in = relabel_adj(g, rl, g->in_off, g->in_idx, in_w, s);
+  if (order != GM_ORDER_IN && !rl->out.off)
+    rl->out = relabel_adj(g, rl, g->out_off, g->out_idx, out_w, s);
+  if (order == GM_ORDER_IN) return rl->in.view();
+  if (order != GM_ORDER_ALL) return rl->out.view();
+  if (!rl->all.off) {
+    const int64_t n = g->n, m = g->m;
+    if (2 * m > (int64_t)UINT32_MAX) throw Unsupported{"GM_ORDER_ALL: more than 2^32 - 1 edges"};
+    OwnedAdj a;
+    try {
+      a.off = dalloc<uint32_t>(n + 1);
+      a.idx = dalloc<int32_t>(2 * m + kIdxPad);
+      if (weighted) a.w = dalloc<uint32_t>(2 * m);
+      all_offsets<<<blocks_for(n + 1), kThreads, 0, s>>>(rl->out.off, rl->in.off, n, a.off);
+      all_lists<<<blocks_for(64 * n), kThreads, 0, s>>>(rl->out.off, rl->out.idx, rl->out.w,
+                                                        rl->in.off, rl->in.idx, rl->in.w, n,
+                                                        a.off, a.idx, a.w);
+      fill_kernel<<<1, kThreads, 0, s>>>(reinterpret_cast<uint32_t*>(a.idx) + 2 * m, kIdxPad, 0u);
+      GM_HIP(hipGetLastError());
+      GM_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      (void)hipStreamSynchronize(s);
+      a.release();
+      throw;
+    }
+    rl->all = a;
+  }
+  return rl->all.view();
+}
+
+// The view of a plain run: the caller's labels, or the relabelled copy
+// (then rl is set). BFS pulls only when pushing along out-edges, over the
+// in-adjacency (the out-adjacency of a symmetrised graph).
+View run_view(gm_graph g, Workspace* ws, int kind, int order, Relab* rl, hipStream_t s) {
+  const bool sym = (g->prep & (GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG)) == GM_PREP_SYMMETRIZE;
+  const bool pull = kind == GM_PROG_BFS && order == GM_ORDER_OUT && (sym || g->in_off);
+  if (!rl) {
+    View v{adjacency(g, ws, order, s), nullptr, nullptr, pull};
+    if (pull) {
+      v.pull_off = sym ? g->out_off : g->in_off;
+      v.pull_idx = sym ? g->out_idx : g->in_idx;
+    }
+    return v;
+  }
+  View v{relab_adjacency(g, rl, order, s), nullptr, nullptr, pull};
+  if (pull) {
+    const Adj p = sym ? v.push : relab_adjacency(g, rl, GM_ORDER_IN, s);
+    v.pull_off = p.off;
+    v.pull_idx = p.idx;
+  }
+  return v;
+}
+
 }  // namespace
 
 void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
@@ -611,6 +901,7 @@ void free_min_workspace(gm_graph g) {
   dfree(ws->all_off);
   dfree(ws->all_idx);
   dfree(ws->all_w);
+  free_relab(ws->rl);
   if (ws->host_ctl) (void)hipHostFree(ws->host_ctl);
   delete ws;
   g->min_ws = nullptr;
@@ -642,15 +933,14 @@ namespace {
 // superstep), then the push or the pull product into bits[cur ^ 1]. After
 // the last superstep of a run, bits[cur] of that superstep holds a stale
 // frontier, which the run's epilogue clears.
-void enqueue_superstep(gm_graph g, Workspace* ws, int kind, const Adj& a, Ctl* c, int cur,
+void enqueue_superstep(gm_graph g, Workspace* ws, int kind, const View& view, Ctl* c, int cur,
                        uint32_t* prop, hipStream_t s) {
   const int64_t n = g->n;
   const int64_t words = (n + 31) / 32;
-  const bool sym = (g->prep & (GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG)) == GM_PREP_SYMMETRIZE;
-  const uint32_t* pull_off = sym ? g->out_off : g->in_off;
-  const int32_t* pull_idx = sym ? g->out_idx : g->in_idx;
-  // pull supersteps only for BFS along out-edges
-  const bool pull_ok = kind == GM_PROG_BFS && a.off == g->out_off && pull_off != nullptr;
+  const Adj& a = view.push;
+  const uint32_t* pull_off = view.pull_off;
+  const int32_t* pull_idx = view.pull_idx;
+  const bool pull_ok = view.pull_ok;
   const uint32_t pull_div = g->tune.pull_div;
   const unsigned push_blocks = g->tune.push_blocks;
   send_kernel<<<blocks_for(words, 4096), kThreads, 0, s>>>(
@@ -740,6 +1030,13 @@ void prepare_min_program(gm_graph g, hipStream_t s) {
   GM_HIP(hipStreamSynchronize(s));
 }
 
+void prepare_plain_min_program(gm_graph g, int kind, hipStream_t s) {
+  Workspace* ws = ensure_ws(g, s);
+  if (g->n > 0 && (g->tune.variant & GM_VARIANT_DEGREE_ORDER))
+    (void)run_view(g, ws, kind, GM_ORDER_OUT, ensure_relab(g, ws, s), s);
+  GM_HIP(hipStreamSynchronize(s));
+}
+
 void enqueue_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count, int32_t steps,
                          uint32_t* prop, PlanResult* res, hipStream_t s) {
   Workspace* ws = static_cast<Workspace*>(g->min_ws);
@@ -752,10 +1049,13 @@ void enqueue_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count
     seed_sources<<<blocks_for(count), kThreads, 0, s>>>(ids, count, prop, ws->bits[0]);
   GM_HIP(hipGetLastError());
   int cur = 0;
-  const Adj out{g->out_off, g->out_idx, static_cast<const uint32_t*>(g->out_w)};
+  const bool sym = (g->prep & (GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG)) == GM_PREP_SYMMETRIZE;
+  View view{Adj{g->out_off, g->out_idx, static_cast<const uint32_t*>(g->out_w)},
+            sym ? g->out_off : g->in_off, sym ? g->out_idx : g->in_idx, false};
+  view.pull_ok = kind == GM_PROG_BFS && view.pull_off != nullptr;
   start_batch(ws, s);
   for (int32_t b = 0; b < steps; ++b) {
-    enqueue_superstep(g, ws, kind, out, ws->ctl + b, cur, prop, s);
+    enqueue_superstep(g, ws, kind, view, ws->ctl + b, cur, prop, s);
     cur ^= 1;
   }
   min_summary<<<1, 1, 0, s>>>(ws->ctl, steps, res);
@@ -826,11 +1126,10 @@ int64_t sort_unique(ListBufs& b, int64_t k, hipStream_t s) {
 // the push product appending every lowered vertex, and a sort + unique that
 // forms the next list (its length read by the host).
 static int32_t run_min_program_list(gm_graph g, Workspace* ws, const Adj& adj, int kind,
-                                    const int32_t* ids, int64_t count, const uint32_t* bitmap,
-                                    int32_t max_iters, uint32_t* prop, int32_t* active_out,
-                                    hipStream_t s, RunStats* stats) {
+                                    const int32_t* ids, int64_t count, int32_t max_iters,
+                                    uint32_t* prop, int32_t* active_out, hipStream_t s,
+                                    RunStats* stats) {
   const int64_t n = g->n;
-  if (bitmap) throw Unsupported{"the list-frontier variant takes frontier ids"};
   uint32_t medges = 0;
   GM_HIP(hipMemcpyAsync(&medges, adj.off + n, 4, hipMemcpyDeviceToHost, s));
   GM_HIP(hipStreamSynchronize(s));
@@ -895,19 +1194,15 @@ static int32_t run_min_program_list(gm_graph g, Workspace* ws, const Adj& adj, i
   return iters;
 }
 
-int32_t run_min_program(gm_graph g, int kind, int order, const int32_t* ids, int64_t count,
-                        const uint32_t* bitmap, int32_t max_iters, uint32_t* prop,
-                        int32_t* active_out, hipStream_t s, RunStats* stats) {
-  Workspace* ws = ensure_ws(g, s);
-  const Adj adj = adjacency(g, ws, order, s);
-  if ((g->tune.variant & GM_VARIANT_LIST_FRONTIER) && kind != GM_PROG_DEGREE)
-    return run_min_program_list(g, ws, adj, kind, ids, count, bitmap, max_iters, prop,
-                                active_out, s, stats);
+// The supersteps of a plain run on a view (labels of `view`): prop and the
+// first frontier (in bits[0]: the caller's ids or bitmap, already seeded, or
+// every vertex for the degree program) in, prop and the final frontier
+// (active_out, if set) out.
+static int32_t run_supersteps(gm_graph g, Workspace* ws, int kind, const View& view,
+                              bool have_frontier, int32_t max_iters, uint32_t* prop,
+                              int32_t* active_out, hipStream_t s, RunStats* stats) {
   const int64_t n = g->n;
   const int64_t words = (n + 31) / 32;
-  const bool sym = (g->prep & (GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG)) == GM_PREP_SYMMETRIZE;
-  const bool pull_ok = kind == GM_PROG_BFS && (sym ? g->out_off : g->in_off) != nullptr;
-  const uint32_t pull_div = g->tune.pull_div;
   int32_t batch = (int32_t)g->tune.superstep_batch;
   if (batch < 1) batch = 1;
   int cur = 0;
@@ -915,23 +1210,17 @@ int32_t run_min_program(gm_graph g, int kind, int order, const int32_t* ids, int
     fill_kernel<<<blocks_for(n), kThreads, 0, s>>>(prop, n, 0u);
     seed_all<<<blocks_for(words), kThreads, 0, s>>>(words, n, ws->bits[0]);
     GM_HIP(hipGetLastError());
-  } else if (bitmap) {
-    seed_bitmap<<<blocks_for(words), kThreads, 0, s>>>(bitmap, words, n, ws->bits[0]);
-    GM_HIP(hipGetLastError());
-  } else if (count > 0) {
-    seed_bits<<<blocks_for(count), kThreads, 0, s>>>(ids, count, ws->bits[0]);
-    GM_HIP(hipGetLastError());
   }
   int32_t iters = 0;
   RunStats st{};
-  bool done = count == 0 && !bitmap && kind != GM_PROG_DEGREE;  // an empty bitmap: one SEND
+  bool done = !have_frontier && kind != GM_PROG_DEGREE;  // an empty bitmap: one SEND
   while (!done) {
     int32_t nb = batch;
     if (max_iters > 0 && max_iters - iters < nb) nb = max_iters - iters;
     if (nb > kMaxCtl) nb = kMaxCtl;
     start_batch(ws, s);
     for (int32_t b = 0; b < nb; ++b) {
-      enqueue_superstep(g, ws, kind, adj, ws->ctl + b, cur, prop, s);
+      enqueue_superstep(g, ws, kind, view, ws->ctl + b, cur, prop, s);
       cur ^= 1;
     }
     GM_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, nb * sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -945,8 +1234,8 @@ int32_t run_min_program(gm_graph g, int kind, int order, const int32_t* ids, int
       }
       ++iters;
       st.edges_scanned += (uint32_t)c.packed;
-      const bool pulled = kind == GM_PROG_BFS && pull_ok && c.msg_min == c.msg_max &&
-                          (int64_t)cnt > n / (int64_t)pull_div;
+      const bool pulled = kind == GM_PROG_BFS && view.pull_ok && c.msg_min == c.msg_max &&
+                          (int64_t)cnt > n / (int64_t)g->tune.pull_div;
       if (pulled)
         ++st.pull_supersteps;
       else
@@ -964,9 +1253,63 @@ int32_t run_min_program(gm_graph g, int kind, int order, const int32_t* ids, int
   bits_epilogue<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[cur], words, n, active_out);
   fill_kernel<<<blocks_for(words), kThreads, 0, s>>>(ws->bits[cur ^ 1], words, 0);
   GM_HIP(hipGetLastError());
-  GM_HIP(hipStreamSynchronize(s));
   st.supersteps = iters;
   if (stats) *stats = st;
+  return iters;
+}
+
+int32_t run_min_program(gm_graph g, int kind, int order, const int32_t* ids, int64_t count,
+                        const uint32_t* bitmap, int32_t max_iters, uint32_t* prop,
+                        int32_t* active_out, hipStream_t s, RunStats* stats) {
+  Workspace* ws = ensure_ws(g, s);
+  const int64_t n = g->n;
+  const int64_t words = (n + 31) / 32;
+  const bool list = (g->tune.variant & GM_VARIANT_LIST_FRONTIER) && kind != GM_PROG_DEGREE;
+  if (list && bitmap) throw Unsupported{"the list-frontier variant takes frontier ids"};
+  Relab* rl = nullptr;
+  if (n > 0 && (g->tune.variant & GM_VARIANT_DEGREE_ORDER)) rl = ensure_relab(g, ws, s);
+  const View view = run_view(g, ws, kind, order, rl, s);
+  const bool have_frontier = bitmap != nullptr || count > 0;
+  int32_t iters = 0;
+  if (!rl) {
+    if (!list && kind != GM_PROG_DEGREE) {
+      if (bitmap)
+        seed_bitmap<<<blocks_for(words), kThreads, 0, s>>>(bitmap, words, n, ws->bits[0]);
+      else if (count > 0)
+        seed_bits<<<blocks_for(count), kThreads, 0, s>>>(ids, count, ws->bits[0]);
+      GM_HIP(hipGetLastError());
+    }
+    iters = list ? run_min_program_list(g, ws, view.push, kind, ids, count, max_iters, prop,
+                                        active_out, s, stats)
+                 : run_supersteps(g, ws, kind, view, have_frontier, max_iters, prop, active_out,
+                                  s, stats);
+    GM_HIP(hipStreamSynchronize(s));
+    return iters;
+  }
+  // Relabelled run: the caller's values and frontier into the new labels,
+  // the supersteps, the results back.
+  if (kind != GM_PROG_DEGREE)
+    permute_u32<<<blocks_for(n), kThreads, 0, s>>>(prop, rl->old_of, n, rl->prop);
+  if (count > 0) map_ids<<<blocks_for(count), kThreads, 0, s>>>(ids, count, rl->new_of, rl->ids);
+  if (!list && kind != GM_PROG_DEGREE) {
+    if (bitmap)
+      seed_bitmap_mapped<<<blocks_for(n), kThreads, 0, s>>>(bitmap, n, rl->new_of, ws->bits[0]);
+    else if (count > 0)
+      seed_bits<<<blocks_for(count), kThreads, 0, s>>>(rl->ids, count, ws->bits[0]);
+  }
+  GM_HIP(hipGetLastError());
+  int32_t* act = active_out ? rl->active : nullptr;
+  iters = list ? run_min_program_list(g, ws, view.push, kind, rl->ids, count, max_iters, rl->prop,
+                                      act, s, stats)
+               : run_supersteps(g, ws, kind, view, have_frontier, max_iters, rl->prop, act, s,
+                                stats);
+  permute_u32<<<blocks_for(n), kThreads, 0, s>>>(rl->prop, rl->new_of, n, prop);
+  if (active_out)
+    permute_u32<<<blocks_for(n), kThreads, 0, s>>>(reinterpret_cast<const uint32_t*>(rl->active),
+                                                   rl->new_of, n,
+                                                   reinterpret_cast<uint32_t*>(active_out));
+  GM_HIP(hipGetLastError());
+  GM_HIP(hipStreamSynchronize(s));
   return iters;
 }
 

@@ -192,7 +192,7 @@ gm_status check_tuning(const gm_tuning& t) {
            {"tc_wave_work", t.tc_wave_work, {256, 1u << 24}},
            {"tc_block_work", t.tc_block_work, {256, 1u << 26}},
            {"pr_hot", t.pr_hot, {0, 40960}},
-           {"variant", t.variant, {0, 7}}};
+           {"variant", t.variant, {0, 15}}};
   for (const F& x : f)
     if (x.v < x.r.lo || x.v > x.r.hi)
       return fail(GM_EINVAL, "%s = %u outside [%u, %u]", x.name, x.v, x.r.lo, x.r.hi);

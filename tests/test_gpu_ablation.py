@@ -14,9 +14,9 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 P_DIR = gm.GM_PREP_DROP_SELF_LOOPS
 P_SYM = gm.GM_PREP_DROP_SELF_LOOPS | gm.GM_PREP_SYMMETRIZE
-LIST, VPUSH, ROWPULL = (gm._lib.GM_VARIANT_LIST_FRONTIER, gm._lib.GM_VARIANT_VERTEX_PUSH,
-                        gm._lib.GM_VARIANT_ROW_PULL)
-VARIANTS = [0, LIST, VPUSH, LIST | VPUSH]
+LIST, VPUSH, ROWPULL, DEG = (gm._lib.GM_VARIANT_LIST_FRONTIER, gm._lib.GM_VARIANT_VERTEX_PUSH,
+                              gm._lib.GM_VARIANT_ROW_PULL, gm._lib.GM_VARIANT_DEGREE_ORDER)
+VARIANTS = [0, LIST, VPUSH, LIST | VPUSH, DEG, DEG | LIST, DEG | VPUSH]
 
 
 def ids(*v):

@@ -30,14 +30,17 @@ def bitmap_of(n, verts):
     return torch.tensor(words.view(np.int32), device=DEV)
 
 
-def test_bitmap_frontier_equals_ids():
+@pytest.mark.parametrize("labels", [0, gm._lib.GM_VARIANT_DEGREE_ORDER])
+def test_bitmap_frontier_equals_ids(labels):
     """The bitvector sparse vector of Sec. 4.4.2 as the first frontier: BFS and
     SSSP from several sources equal the oracle and the id-list runs; bits at or
-    past n are ignored; an empty bitmap runs no superstep."""
+    past n are ignored; an empty bitmap runs no superstep. On the caller's
+    labels and on the degree-ordered copy of the adjacency."""
     scale = 12
     n, s, d = W.raw(scale)
     srcs = [0, 5, 77, n - 1]
     g = gm.Graph.from_coo(n, s, d, prep=P_SYM)
+    g.set_tuning(variant=labels)
     lv = torch.full((n,), gm.INF_LEVEL, dtype=torch.int32, device=DEV)
     lv[srcs] = 0
     bm = bitmap_of(n + 40, srcs + [n + 3, n + 39])  # stray bits past n
@@ -49,6 +52,7 @@ def test_bitmap_frontier_equals_ids():
     assert gm.run_vertex_program(g, gm.GM_PROG_BFS, dev(srcs), -1, lv2) == it
     assert torch.equal(lv, lv2)
     gw = gm.Graph.from_coo(n, s, d, w=W.weights(scale), prep=P_DIR)
+    gw.set_tuning(variant=labels)
     dist = torch.full((n,), -1, dtype=torch.int32, device=DEV)
     dist[srcs] = 0
     gm.run_vertex_program(gw, gm.GM_PROG_SSSP, None, -1, dist, bitmap=bitmap_of(n, srcs))

@@ -13,6 +13,7 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 P_DIR = gm.GM_PREP_DROP_SELF_LOOPS
 P_SYM = gm.GM_PREP_DROP_SELF_LOOPS | gm.GM_PREP_SYMMETRIZE
+DEG = gm._lib.GM_VARIANT_DEGREE_ORDER
 
 
 def ids(*v):
@@ -231,15 +232,18 @@ def test_paper_sssp_workloads(name):
         ref["dist_sha256"]
 
 
-def test_orders_in_and_all():
+@pytest.mark.parametrize("labels", [0, DEG])
+def test_orders_in_and_all(labels):
     """Messages along in-edges (GM_ORDER_IN) equal the run on the transposed
     graph; along both (GM_ORDER_ALL) the run on the union of the graph and its
     transpose (a pair in both directions keeps the smaller weight): BFS and
-    SSSP from several sources against the oracle."""
+    SSSP from several sources against the oracle, on the caller's labels and on
+    the degree-ordered copy of each adjacency."""
     scale = 12
     n, s, d = W.raw(scale)
     w = W.weights(scale)
     g = gm.Graph.from_coo(n, s, d, w=w, prep=P_DIR)
+    g.set_tuning(variant=labels)
     og_in = oracle.prepare(n, d, s, w=w)                      # transposed
     og_all = oracle.prepare(n, np.concatenate([s, d]), np.concatenate([d, s]),
                             w=np.concatenate([w, w]))          # both directions
@@ -255,13 +259,15 @@ def test_orders_in_and_all():
             assert np.array_equal(dist.cpu().numpy().view(np.uint32), oracle.sssp(og, src))
 
 
-def test_degree_program_all_orders():
+@pytest.mark.parametrize("labels", [0, DEG])
+def test_degree_program_all_orders(labels):
     """Fig. 1: degree as one generalized SpMV with a ones vector, along out-,
     in- and both directions, against the oracle's counts (RMAT scale 14 and
     a graph with isolated and edgeless vertices)."""
     for n, s, d in (W.raw(W.SMALL_SCALE), (50, np.array([3, 3, 4], np.int32),
                                            np.array([4, 5, 3], np.int32))):
         g = gm.Graph.from_coo(n, s, d)
+        g.set_tuning(variant=labels)
         og = oracle.prepare(n, s, d)
         for order, name in ((gm.GM_ORDER_OUT, "out"), (gm.GM_ORDER_IN, "in"),
                             (gm.GM_ORDER_ALL, "all")):
