@@ -131,6 +131,9 @@ def main():
                          "thread-per-vertex push, push vs pull, PageRank tiles and LDS copy")
     ap.add_argument("--tc-cold", action="store_true",
                     help="with --tc-only: free the work plan before each count (cold calls)")
+    ap.add_argument("--sssp-only", type=int, default=0, metavar="K",
+                    help="only run K SSSP runs from vertex 0 on the scale-22 directed graph, "
+                         "for hardware-counter runs")
     ap.add_argument("--cf-only", type=int, default=0, metavar="K",
                     help="only run K CF forward + backward passes on the 100M-rating graph, "
                          "for hardware-counter runs")
@@ -172,6 +175,18 @@ def main():
         return
     if args.ablation:
         print(json.dumps(run_ablation(gm, gg, torch, np, n, s, d, w)), flush=True)
+        return
+    if args.sssp_only:
+        g = gm.Graph.from_coo(n, s, d, w=w, prep=gm.GM_PREP_DROP_SELF_LOOPS)
+        root = torch.zeros(1, dtype=torch.int32, device=dev)
+        dist = torch.empty(n, dtype=torch.int32, device=dev)
+        for _ in range(args.sssp_only):
+            dist.fill_(-1)
+            dist[0] = 0
+            it = gm.run_vertex_program(g, gm.GM_PROG_SSSP, root, -1, dist)
+        torch.cuda.synchronize()
+        print(json.dumps({"sssp_runs": args.sssp_only, "supersteps": it,
+                          "edges": g.last_run_stats().edges_scanned}), flush=True)
         return
     if args.tc_only:
         g = gm.Graph.from_coo(n, s, d, prep=gm.GM_PREP_UPPER_DAG)
