@@ -3,11 +3,12 @@
 //
 // The frontier is a bitvector over the vertices (the sparse-vector layout the
 // paper adopts, Sec. 4.4.2). Superstep t:
-//   send_kernel   compacts the frontier bitvector into a queue of active
-//                 vertices and snapshots each one's message x_u = prop(u)
-//                 (SEND_MESSAGE), its first out-edge, and the exclusive
-//                 prefix sum of out-degrees over the queue. Counts, edge
-//                 totals and the smallest/largest message go to a small
+//   send_count, send_write
+//                 compact the frontier bitvector into a queue of active
+//                 vertices (in vertex order) and snapshot each one's message
+//                 x_u = prop(u) (SEND_MESSAGE), its first out-edge, and the
+//                 exclusive prefix sum of out-degrees over the queue. Counts,
+//                 edge totals and the smallest/largest message go to a small
 //                 per-superstep control record.
 //   push_kernel   walks the out-edges of the queued vertices (the columns of
 //                 G^T present in x, Alg. 1). The concatenated edge lists are
@@ -23,7 +24,7 @@
 //                 look for an in-neighbour in the frontier. Levels are
 //                 unique, so the result is the same as pushing.
 // The push and pull kernels of a superstep are both launched; each reads the
-// control record written by send_kernel and only the selected one works.
+// control record written by send_write and only the selected one works.
 // Messages are snapshotted before the product and min is exact and
 // order-free, so every superstep leaves exactly the state of Alg. 2. Only
 // non-returning atomics are used on the hot path.
@@ -60,6 +61,7 @@ struct Workspace {
   uint32_t* qest = nullptr;   // exclusive prefix sum of out-degrees
   uint32_t* bits[2] = {nullptr, nullptr};
   Ctl* ctl = nullptr;         // kMaxCtl records
+  struct SendInfo* sinfo = nullptr;  // per-workgroup SEND totals (kSendBlocksMax)
   Ctl* host_ctl = nullptr;    // pinned mirror
   // GM_ORDER_ALL adjacency (built on first use): off = out_off + in_off,
   // each vertex's out-list followed by its in-list (values alike)
@@ -195,53 +197,158 @@ __global__ __launch_bounds__(kThreads) void seed_all(int64_t words, int64_t n, u
   }
 }
 
-// SEND: frontier bitvector -> queue (vertex, message, first edge, edge prefix).
-// A thread takes one 32-bit word; for a nonzero word it reads the 33
-// offsets around its 32 vertices at once (independent loads, unrolled), so
-// that a dense word costs one memory round trip, not one per set bit.
-// The same pass clears the other bitvector (the frontier before this one,
-// read by nobody any more), into which this superstep's product writes the
-// next frontier, and resets the next superstep's control record.
-__global__ __launch_bounds__(kThreads) void send_kernel(
+// SEND: frontier bitvector -> queue (vertex, message, first edge, edge prefix),
+// in two launches with no atomics on a shared address (which device-scope
+// atomics, performed past the per-XCD caches, serialise): send_count gives
+// each workgroup's contiguous range of words its totals (active vertices,
+// their out-edges, smallest and largest message) and clears the other
+// bitvector (the frontier before this one, into which this superstep's
+// product writes the next); send_write places each workgroup's vertices
+// after those of the workgroups before it, so the queue is in vertex order,
+// and its first workgroup writes the superstep's control record. A thread
+// takes one 32-bit word; for a nonzero word it reads the 33 offsets around
+// its 32 vertices at once (independent loads, unrolled), so that a dense
+// word costs one memory round trip, not one per set bit.
+constexpr int kSendBlocksMax = 1024;
+
+struct SendInfo {
+  uint32_t cnt, edges, mn, mx;
+};
+
+// Words [w_begin, w_end) of workgroup b when the words are cut into
+// contiguous ranges of `chunk` (a multiple of kThreads).
+__device__ inline void send_range(int64_t words, int64_t chunk, int64_t* w_begin, int64_t* w_end) {
+  *w_begin = (int64_t)blockIdx.x * chunk;
+  *w_end = *w_begin + chunk < words ? *w_begin + chunk : words;
+}
+
+// Out-degree sum of the set bits of `word` (vertices v0..v0+31), with the
+// 33 offsets around them left in o.
+__device__ inline uint32_t word_edges(uint32_t word, int64_t v0, int64_t n,
+                                      const uint32_t* __restrict__ off, uint32_t (&o)[33]) {
+#pragma unroll
+  for (int k = 0; k <= 32; ++k) o[k] = off[v0 + k < n ? v0 + k : n];
+  uint32_t edges = 0;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) edges += (word >> k) & 1u ? o[k + 1] - o[k] : 0u;
+  return edges;
+}
+
+__global__ __launch_bounds__(kThreads) void send_count(
     const uint32_t* __restrict__ bits, uint32_t* __restrict__ other, int64_t words, int64_t n,
-    const uint32_t* __restrict__ prop, const uint32_t* __restrict__ off, int32_t* __restrict__ q,
-    uint32_t* __restrict__ qmsg, uint32_t* __restrict__ qbeg, uint32_t* __restrict__ qest,
-    Ctl* __restrict__ ctl, Ctl* __restrict__ next_ctl) {
-  __shared__ uint32_t sh[2 * kWaves];
-  __shared__ unsigned long long base_packed;
-  if (next_ctl && blockIdx.x == 0 && threadIdx.x == 0) {
-    next_ctl->packed = 0;
-    next_ctl->msg_min = 0xFFFFFFFFu;
-    next_ctl->msg_max = 0;
-  }
-  uint32_t mn = 0xFFFFFFFFu, mx = 0;
-  for (int64_t w0 = (int64_t)blockIdx.x * kThreads; w0 < words;
-       w0 += (int64_t)gridDim.x * kThreads) {
-    const int64_t wi = w0 + threadIdx.x;
-    const uint32_t word = wi < words ? bits[wi] : 0u;
-    if (wi < words) other[wi] = 0u;
-    if (!__syncthreads_or(word != 0u)) continue;  // no active vertex in the block's words
-    const uint32_t cnt = __popc(word);
+    int64_t chunk, const uint32_t* __restrict__ prop, const uint32_t* __restrict__ off,
+    SendInfo* __restrict__ info) {
+  __shared__ uint32_t sh[4 * kWaves];
+  int64_t wb, we;
+  send_range(words, chunk, &wb, &we);
+  uint32_t cnt = 0, edges = 0, mn = 0xFFFFFFFFu, mx = 0;
+  for (int64_t wi = wb + threadIdx.x; wi < we; wi += kThreads) {
+    const uint32_t word = bits[wi];
+    other[wi] = 0u;
+    if (!word) continue;
     const int64_t v0 = wi * 32;
     uint32_t o[33];
-    uint32_t edges = 0;
-    if (word) {
+    cnt += __popc(word);
+    edges += word_edges(word, v0, n, off, o);
+    uint32_t msg[32];
 #pragma unroll
-      for (int k = 0; k <= 32; ++k) o[k] = off[v0 + k < n ? v0 + k : n];
+    for (int k = 0; k < 32; ++k) msg[k] = (word >> k) & 1u ? prop[v0 + k] : 0u;
 #pragma unroll
-      for (int k = 0; k < 32; ++k) edges += (word >> k) & 1u ? o[k + 1] - o[k] : 0u;
+    for (int k = 0; k < 32; ++k)
+      if ((word >> k) & 1u) {
+        mn = msg[k] < mn ? msg[k] : mn;
+        mx = msg[k] > mx ? msg[k] : mx;
+      }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    cnt += __shfl_xor(cnt, o, 64);
+    edges += __shfl_xor(edges, o, 64);
+    const uint32_t a = __shfl_xor(mn, o, 64), c = __shfl_xor(mx, o, 64);
+    mn = a < mn ? a : mn;
+    mx = c > mx ? c : mx;
+  }
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[wave] = cnt;
+    sh[kWaves + wave] = edges;
+    sh[2 * kWaves + wave] = mn;
+    sh[3 * kWaves + wave] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    SendInfo t{0, 0, 0xFFFFFFFFu, 0};
+    for (int i = 0; i < kWaves; ++i) {
+      t.cnt += sh[i];
+      t.edges += sh[kWaves + i];
+      t.mn = sh[2 * kWaves + i] < t.mn ? sh[2 * kWaves + i] : t.mn;
+      t.mx = sh[3 * kWaves + i] > t.mx ? sh[3 * kWaves + i] : t.mx;
     }
-    uint32_t ctot, etot;
-    const uint32_t cex = block_excl_scan(cnt, sh, &ctot);
-    const uint32_t eex = block_excl_scan(edges, sh + kWaves, &etot);
-    if (threadIdx.x == 0)
-      base_packed = atomicAdd(&ctl->packed, ((unsigned long long)ctot << 32) | etot);
+    info[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void send_write(
+    const uint32_t* __restrict__ bits, int64_t words, int64_t n, int64_t chunk,
+    const uint32_t* __restrict__ prop, const uint32_t* __restrict__ off,
+    const SendInfo* __restrict__ info, int32_t* __restrict__ q, uint32_t* __restrict__ qmsg,
+    uint32_t* __restrict__ qbeg, uint32_t* __restrict__ qest, Ctl* __restrict__ ctl) {
+  __shared__ uint32_t sh[2 * kWaves];
+  // This workgroup's place: the totals of the workgroups before it (the
+  // first workgroup also totals all of them for the control record).
+  const int nb = blockIdx.x == 0 ? (int)gridDim.x : (int)blockIdx.x;
+  uint32_t cb = 0, eb = 0, mn = 0xFFFFFFFFu, mx = 0;
+  for (int i = threadIdx.x; i < nb; i += kThreads) {
+    const SendInfo t = info[i];
+    cb += t.cnt;
+    eb += t.edges;
+    mn = t.mn < mn ? t.mn : mn;
+    mx = t.mx > mx ? t.mx : mx;
+  }
+  uint32_t ctot, etot;
+  (void)block_excl_scan(cb, sh, &ctot);
+  (void)block_excl_scan(eb, sh + kWaves, &etot);
+  if (blockIdx.x == 0) {
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint32_t a = __shfl_xor(mn, o, 64), c = __shfl_xor(mx, o, 64);
+      mn = a < mn ? a : mn;
+      mx = c > mx ? c : mx;
+    }
     __syncthreads();
-    const unsigned long long bp = base_packed;
+    if ((threadIdx.x & 63) == 0) {
+      sh[threadIdx.x >> 6] = mn;
+      sh[kWaves + (threadIdx.x >> 6)] = mx;
+    }
     __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t a = 0xFFFFFFFFu, c = 0;
+      for (int i = 0; i < kWaves; ++i) {
+        a = sh[i] < a ? sh[i] : a;
+        c = sh[kWaves + i] > c ? sh[kWaves + i] : c;
+      }
+      ctl->packed = ((unsigned long long)ctot << 32) | etot;
+      ctl->msg_min = a;
+      ctl->msg_max = c;
+    }
+    ctot = 0;  // the first workgroup starts at slot 0
+    etot = 0;
+    __syncthreads();
+  }
+  uint32_t slot0 = ctot, est0 = etot;
+  int64_t wb, we;
+  send_range(words, chunk, &wb, &we);
+  for (int64_t w0 = wb; w0 < we; w0 += kThreads) {
+    const int64_t wi = w0 + threadIdx.x;
+    const uint32_t word = wi < we ? bits[wi] : 0u;
+    if (!__syncthreads_or(word != 0u)) continue;  // no active vertex in these words
+    const int64_t v0 = wi * 32;
+    uint32_t o[33];
+    const uint32_t edges = word ? word_edges(word, v0, n, off, o) : 0u;
+    uint32_t ct, et;
+    const uint32_t cex = block_excl_scan(word ? (uint32_t)__popc(word) : 0u, sh, &ct);
+    const uint32_t eex = block_excl_scan(edges, sh + kWaves, &et);
     if (word) {
-      uint32_t slot = (uint32_t)(bp >> 32) + cex;
-      uint32_t est = (uint32_t)bp + eex;
+      uint32_t slot = slot0 + cex;
+      uint32_t est = est0 + eex;
       uint32_t msg[32];
 #pragma unroll
       for (int k = 0; k < 32; ++k) msg[k] = (word >> k) & 1u ? prop[v0 + k] : 0u;
@@ -254,20 +361,11 @@ __global__ __launch_bounds__(kThreads) void send_kernel(
           qest[slot] = est;
           est += o[k + 1] - o[k];
           ++slot;
-          mn = msg[k] < mn ? msg[k] : mn;
-          mx = msg[k] > mx ? msg[k] : mx;
         }
       }
     }
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    const uint32_t a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
-    mn = a < mn ? a : mn;
-    mx = b > mx ? b : mx;
-  }
-  if ((threadIdx.x & 63) == 0 && mn <= mx) {
-    atomicMin(&ctl->msg_min, mn);
-    atomicMax(&ctl->msg_max, mx);
+    slot0 += ct;
+    est0 += et;
   }
 }
 
@@ -669,6 +767,7 @@ Workspace* ensure_ws(gm_graph g, hipStream_t s) {
     ws->bits[0] = dalloc<uint32_t>(words);
     ws->bits[1] = dalloc<uint32_t>(words);
     ws->ctl = dalloc<Ctl>(kMaxCtl + 1);
+    ws->sinfo = dalloc<SendInfo>(kSendBlocksMax);
     void* h = nullptr;
     GM_HIP(hipHostMalloc(&h, kMaxCtl * sizeof(Ctl), hipHostMallocDefault));
     ws->host_ctl = static_cast<Ctl*>(h);
@@ -898,6 +997,7 @@ void free_min_workspace(gm_graph g) {
   dfree(ws->bits[0]);
   dfree(ws->bits[1]);
   dfree(ws->ctl);
+  dfree(ws->sinfo);
   dfree(ws->all_off);
   dfree(ws->all_idx);
   dfree(ws->all_w);
@@ -943,9 +1043,16 @@ void enqueue_superstep(gm_graph g, Workspace* ws, int kind, const View& view, Ct
   const bool pull_ok = view.pull_ok;
   const uint32_t pull_div = g->tune.pull_div;
   const unsigned push_blocks = g->tune.push_blocks;
-  send_kernel<<<blocks_for(words, 4096), kThreads, 0, s>>>(
-      ws->bits[cur], ws->bits[cur ^ 1], words, g->n, prop, a.off, ws->q, ws->qmsg, ws->qbeg,
-      ws->qest, c, c + 1);
+  // SEND: contiguous ranges of words, at most kSendBlocksMax workgroups
+  int64_t nbk = std::min<int64_t>(std::max<int64_t>((words + kThreads - 1) / kThreads, 1),
+                                  kSendBlocksMax);
+  const int64_t chunk =
+      std::max<int64_t>(((words + nbk - 1) / nbk + kThreads - 1) / kThreads * kThreads, kThreads);
+  nbk = std::max<int64_t>((words + chunk - 1) / chunk, 1);
+  send_count<<<(unsigned)nbk, kThreads, 0, s>>>(ws->bits[cur], ws->bits[cur ^ 1], words, g->n,
+                                                chunk, prop, a.off, ws->sinfo);
+  send_write<<<(unsigned)nbk, kThreads, 0, s>>>(ws->bits[cur], words, g->n, chunk, prop, a.off,
+                                                ws->sinfo, ws->q, ws->qmsg, ws->qbeg, ws->qest, c);
   if (kind != GM_PROG_DEGREE && (g->tune.variant & GM_VARIANT_VERTEX_PUSH)) {
     if (kind == GM_PROG_SSSP)
       push_vertex_kernel<GM_PROG_SSSP><<<blocks_for(n), kThreads, 0, s>>>(
