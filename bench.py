@@ -331,7 +331,8 @@ def main():
     pr_bytes = 4 * m_dir + 24 * n
     layout_bytes = 4 * m_dir + 12 * info.n_dst + 4 * info.n_src
     achieved = pr_bytes / (pr_ms_launch * 1e-3) / 1e9
-    traffic = measured_traffic()
+    # the committed counter summary is of the scale-22 workload's kernel
+    traffic = measured_traffic() if scale == 22 else None
 
     forms = None
     if not args.no_forms:
@@ -896,10 +897,11 @@ def cpu_baseline(n, s, d, w, programs):
     return {"value": round(edges / step_s / 1e9, 4), "unit": "GTEPS", "cores": 1,
             "kind": "oracle", "step_s": round(step_s, 2), "programs": per,
             "host": host_info(),
-            "sample": "scale-22 step on the oracle: queue BFS (%.2fs) + Dijkstra SSSP (%.2fs) "
-                      "+ 2 of 20 PageRank supersteps in FP64 (%.3fs each) + triangle counts of "
-                      "%d receivers stratified by in-degree (%.1fs, scaled to an estimated "
-                      "%.0fs for all)" % (t_bfs, t_sssp, t_pr, sampled, t_tc_sample, t_tc)}
+            "sample": "RMAT scale-%d step on the oracle: queue BFS (%.3fs) + Dijkstra SSSP "
+                      "(%.3fs) + 2 of 20 PageRank supersteps in FP64 (%.4fs each) + triangle "
+                      "counts of %d receivers stratified by in-degree (%.2fs, scaled to an "
+                      "estimated %.1fs for all)" % (int(n).bit_length() - 1, t_bfs, t_sssp, t_pr,
+                                                    sampled, t_tc_sample, t_tc)}
 
 
 if __name__ == "__main__":
