@@ -502,8 +502,12 @@ gm_status gm_plan_destroy(gm_plan p);
 
 /* Per-graph schedule parameters. None changes any result, only time. */
 typedef struct gm_tuning {
-  uint32_t pull_div;        /* BFS: pull superstep when more than n / pull_div
-                               vertices are active (1..65536; 128) */
+  uint32_t pull_div;        /* pull superstep (in-edges of every vertex) instead
+                               of push: BFS when more than n / pull_div
+                               vertices are active, SSSP (weighted, along
+                               out-edges) when the frontier's out-edges
+                               exceed 64 m / pull_div; 1 = push only
+                               (1..65536; 128) */
   uint32_t superstep_batch; /* BFS/SSSP: supersteps enqueued before the first
                                host check of the frontier; each later batch is
                                twice as long, up to 64 (1..64; 4) */

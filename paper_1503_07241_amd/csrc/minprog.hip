@@ -23,6 +23,10 @@
 //                 lets every vertex whose level exceeds the frontier level + 1
 //                 look for an in-neighbour in the frontier. Levels are
 //                 unique, so the result is the same as pushing.
+//   pull_min_tiles (SSSP, frontier with many out-edges) instead lets every
+//                 vertex take the min over all its in-edges of PROCESS applied
+//                 to a dense snapshot of the frontier's messages (the max
+//                 value for inactive sources), with no atomics on the edges.
 // The push and pull kernels of a superstep are both launched; each reads the
 // control record written by send_write and only the selected one works.
 // Messages are snapshotted before the product and min is exact and
@@ -47,6 +51,15 @@ constexpr uint32_t kInfBfs = 0x7FFFFFFFu;
 constexpr int kMaxCtl = 64;  // control records per launch batch (one more is allocated)
 constexpr uint64_t kMinWaveEdges = 512;  // push: fewest edges per working wavefront
 
+template <class T>
+struct DevBuf {  // a temporary device array, freed at scope exit
+  T* p = nullptr;
+  explicit DevBuf(int64_t count) : p(dalloc<T>(count)) {}
+  ~DevBuf() { dfree(p); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+};
+
 struct Ctl {
   unsigned long long packed;  // (queued vertices << 32) | their out-edges
   unsigned int msg_min;       // smallest message of the frontier
@@ -69,6 +82,25 @@ struct Workspace {
   int32_t* all_idx = nullptr;
   uint32_t* all_w = nullptr;
   struct Relab* rl = nullptr;  // degree-ordered copy for the plain runs (built on first use)
+  uint32_t* snap = nullptr;    // SSSP pull: frontier messages, the max value elsewhere (n)
+  struct PullTiles* pt = nullptr;  // SSSP pull: tile layout of the pulled adjacency
+};
+
+// Tile layout of the SSSP pull over one adjacency (built on first use): the
+// row-start bitmap over its edges (and bit m), its rows with edges in order,
+// and for each tile of kPullTile edges the index in that list of the row
+// holding the tile's first edge.
+struct PullTiles {
+  const uint32_t* for_off = nullptr;  // offsets of the adjacency it describes
+  uint32_t* starts = nullptr;
+  uint32_t* rows = nullptr;
+  uint32_t* tile_row = nullptr;
+  int64_t ntiles = 0, nrows = 0;
+  ~PullTiles() {
+    dfree(starts);
+    dfree(rows);
+    dfree(tile_row);
+  }
 };
 
 // The adjacency a superstep pushes messages along: out-edges (GM_ORDER_OUT),
@@ -80,13 +112,12 @@ struct Adj {
   const uint32_t* w;
 };
 
-// What a superstep reads: the adjacency it pushes along and, for BFS along
-// out-edges, the in-adjacency a pull superstep scans (pull_ok false: never
-// pulls).
+// What a superstep reads: the adjacency it pushes along and, for BFS and
+// SSSP along out-edges, the in-adjacency (with its values) a pull superstep
+// scans (pull_ok false: never pulls).
 struct View {
   Adj push;
-  const uint32_t* pull_off;
-  const int32_t* pull_idx;
+  Adj pull;
   bool pull_ok;
 };
 
@@ -124,11 +155,19 @@ struct Relab {
 };
 
 
-__device__ inline bool use_pull(const Ctl& c, int kind, bool pull_ok, int64_t n,
-                                uint32_t pull_div) {
+// Direction of a superstep, from its control record: BFS pulls when more
+// than n / pull_div vertices are active (all at one level), SSSP when the
+// frontier's out-edges exceed 64 m / pull_div (half the edges at the
+// default 128; pull_div 1: never).
+__host__ __device__ inline bool use_pull(const Ctl& c, int kind, bool pull_ok, int64_t n,
+                                         int64_t m, uint32_t pull_div) {
   const uint64_t count = c.packed >> 32;
-  return kind == GM_PROG_BFS && pull_ok && count > 0 && c.msg_min == c.msg_max &&
-         count > (uint64_t)(n / (int64_t)pull_div);
+  if (!pull_ok || count == 0) return false;
+  if (kind == GM_PROG_BFS)
+    return c.msg_min == c.msg_max && count > (uint64_t)(n / (int64_t)pull_div);
+  if (kind == GM_PROG_SSSP)
+    return (uint64_t)(uint32_t)c.packed * pull_div > 64 * (uint64_t)m;
+  return false;
 }
 
 template <int kKind>
@@ -447,13 +486,13 @@ __device__ inline void relax_to(uint32_t cand, int32_t v, uint32_t* prop, uint32
 
 template <int kKind>
 __global__ __launch_bounds__(kThreads) void push_kernel(
-    const Ctl* __restrict__ ctlp, int64_t n, bool pull_ok, uint32_t pull_div,
+    const Ctl* __restrict__ ctlp, int64_t n, int64_t m, bool pull_ok, uint32_t pull_div,
     const uint32_t* __restrict__ qmsg, const uint32_t* __restrict__ qbeg,
     const uint32_t* __restrict__ qest, const int32_t* __restrict__ idx,
     const uint32_t* __restrict__ w, uint32_t* prop, uint32_t* next, uint32_t* list = nullptr,
     unsigned int* list_count = nullptr) {
   const Ctl c = *ctlp;
-  if (use_pull(c, kKind, pull_ok, n, pull_div)) return;
+  if (use_pull(c, kKind, pull_ok, n, m, pull_div)) return;
   const uint32_t count = (uint32_t)(c.packed >> 32);
   const uint64_t E = (uint32_t)c.packed;
   if (count == 0 || E == 0) return;
@@ -546,13 +585,13 @@ __global__ __launch_bounds__(kThreads) void push_kernel(
 // serial work (no load balancing).
 template <int kKind>
 __global__ __launch_bounds__(kThreads) void push_vertex_kernel(
-    const Ctl* __restrict__ ctlp, int64_t n, bool pull_ok, uint32_t pull_div,
+    const Ctl* __restrict__ ctlp, int64_t n, int64_t m, bool pull_ok, uint32_t pull_div,
     const uint32_t* __restrict__ qmsg, const uint32_t* __restrict__ qbeg,
     const uint32_t* __restrict__ qest, const int32_t* __restrict__ idx,
     const uint32_t* __restrict__ w, uint32_t* prop, uint32_t* next, uint32_t* list,
     unsigned int* list_count) {
   const Ctl c = *ctlp;
-  if (use_pull(c, kKind, pull_ok, n, pull_div)) return;
+  if (use_pull(c, kKind, pull_ok, n, m, pull_div)) return;
   const uint32_t count = (uint32_t)(c.packed >> 32);
   const uint32_t E = (uint32_t)c.packed;
   for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < count;
@@ -569,11 +608,11 @@ __global__ __launch_bounds__(kThreads) void push_vertex_kernel(
 
 // BFS pull superstep over all vertices (frontier levels uniform).
 __global__ __launch_bounds__(kThreads) void pull_kernel(
-    const Ctl* __restrict__ ctlp, int64_t n, bool pull_ok, uint32_t pull_div,
+    const Ctl* __restrict__ ctlp, int64_t n, int64_t m, bool pull_ok, uint32_t pull_div,
     const uint32_t* __restrict__ off, const int32_t* __restrict__ idx,
     const uint32_t* __restrict__ cur, uint32_t* prop, uint32_t* next) {
   const Ctl c = *ctlp;
-  if (!use_pull(c, GM_PROG_BFS, pull_ok, n, pull_div)) return;
+  if (!use_pull(c, GM_PROG_BFS, pull_ok, n, m, pull_div)) return;
   const uint32_t cand = c.msg_min >= kInfBfs ? kInfBfs : c.msg_min + 1;
   const int lane = threadIdx.x & 63;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -596,6 +635,216 @@ __global__ __launch_bounds__(kThreads) void pull_kernel(
     const int64_t word0 = (base + (threadIdx.x & ~63)) >> 5;
     if (lane == 0 && (uint32_t)m) atomicOr(&next[word0], (uint32_t)m);
     if (lane == 32 && (uint32_t)(m >> 32)) atomicOr(&next[word0 + 1], (uint32_t)(m >> 32));
+  }
+}
+
+// SSSP pull superstep, first part: snap[v] = x_v = prop(v) for a frontier
+// vertex, the max value (kept by PROCESS) for every other vertex.
+__global__ __launch_bounds__(kThreads) void pull_snapshot(
+    const Ctl* __restrict__ ctlp, int64_t n, int64_t m, bool pull_ok, uint32_t pull_div,
+    const uint32_t* __restrict__ cur, const uint32_t* __restrict__ prop,
+    uint32_t* __restrict__ snap) {
+  if (!use_pull(*ctlp, GM_PROG_SSSP, pull_ok, n, m, pull_div)) return;
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    snap[v] = (cur[v >> 5] >> (v & 31)) & 1u ? prop[v] : 0xFFFFFFFFu;
+}
+
+// Segmented-min state of a run of in-edges: c = row starts in it, s = min of
+// the candidates after the last of them (of all, if c = 0). Joining an
+// earlier run with a later one is associative.
+struct MinSeg {
+  int c;
+  uint32_t s;
+};
+
+__device__ inline MinSeg mseg_join(MinSeg a, MinSeg b) {
+  return {a.c + b.c, b.c > 0 ? b.s : min(a.s, b.s)};
+}
+
+template <int kCtrl>
+__device__ inline MinSeg mseg_dpp(MinSeg old, MinSeg v) {
+  return {__builtin_amdgcn_update_dpp(old.c, v.c, kCtrl, 0xF, 0xF, false),
+          (uint32_t)__builtin_amdgcn_update_dpp((int)old.s, (int)v.s, kCtrl, 0xF, 0xF, false)};
+}
+
+__device__ inline MinSeg mseg_lane(MinSeg v, int lane) {
+  return {__builtin_amdgcn_readlane(v.c, lane),
+          (uint32_t)__builtin_amdgcn_readlane((int)v.s, lane)};
+}
+
+// Wavefront scan of one round: each lane's exclusive prefix (earlier lanes
+// and the carry of the earlier rounds); carry moves on to the round's end.
+__device__ inline MinSeg mseg_scan(MinSeg own, MinSeg& carry, int lane) {
+  constexpr MinSeg id{0, 0xFFFFFFFFu};
+  MinSeg x = own;  // inclusive within rows of 16 lanes (row_shr 1, 2, 4, 8)
+  x = mseg_join(mseg_dpp<0x111>(id, x), x);
+  x = mseg_join(mseg_dpp<0x112>(id, x), x);
+  x = mseg_join(mseg_dpp<0x114>(id, x), x);
+  x = mseg_join(mseg_dpp<0x118>(id, x), x);
+  const MinSeg p1 = mseg_join(carry, mseg_lane(x, 15));
+  const MinSeg p2 = mseg_join(p1, mseg_lane(x, 31));
+  const MinSeg p3 = mseg_join(p2, mseg_lane(x, 47));
+  const int row = lane >> 4;
+  const MinSeg before = row == 0 ? carry : row == 1 ? p1 : row == 2 ? p2 : p3;
+  const MinSeg incl = mseg_join(before, x);
+  carry = mseg_lane(incl, 63);
+  return mseg_dpp<0x111>(before, incl);  // the row's first lane takes `before`
+}
+
+// APPLY of a row's minimum y: lower prop(v) and put v in the next frontier.
+// kOwned: no other wavefront touches v in this superstep (plain store).
+template <bool kOwned>
+__device__ inline void apply_min(uint32_t v, uint32_t y, uint32_t* prop, uint32_t* next) {
+  if (y >= prop[v]) return;
+  if constexpr (kOwned) {
+    prop[v] = y;
+  } else {
+    if (y >= __hip_atomic_fetch_min(&prop[v], y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return;
+  }
+  atomicOr(&next[v >> 5], 1u << (v & 31));
+}
+
+// SSSP pull superstep: every vertex v takes the min of PROCESS(snap[u], w)
+// over its in-edges (u, v, w) and APPLYs it: the state the push superstep
+// leaves, since the messages are the same snapshot and min is exact and
+// order-free. The in-adjacency is cut into tiles of kPullTile edges
+// whatever the rows (a bitmap marks each row's first edge; rows without
+// in-edges are skipped by a list of the rows that have some); a wavefront
+// takes a tile in four rounds of 256 edges, four consecutive ones per lane
+// (16-byte index and weight loads, all sixteen gathers in flight at once).
+// Each lane takes the min of its edges per row, a segmented scan over the
+// wavefront joins the lanes, and the lane holding a row's last edge applies
+// it: with a plain store if the row began in the tile (no other wavefront
+// touches it), with an atomic min if it began in an earlier tile; the part
+// of a row that goes on past the tile is applied with an atomic min too.
+constexpr int64_t kPullTile = 1024;
+__global__ __launch_bounds__(kThreads) void pull_min_tiles(
+    const Ctl* __restrict__ ctlp, int64_t n, int64_t m, bool pull_ok, uint32_t pull_div,
+    const int32_t* __restrict__ idx, const uint32_t* __restrict__ w,
+    const uint32_t* __restrict__ starts, const uint32_t* __restrict__ rows,
+    const uint32_t* __restrict__ tile_row, int64_t ntiles, int64_t nrows,
+    const uint32_t* __restrict__ snap, uint32_t* prop, uint32_t* next) {
+  if (!use_pull(*ctlp, GM_PROG_SSSP, pull_ok, n, m, pull_div)) return;
+  typedef int v4i __attribute__((ext_vector_type(4)));
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * kWaves;
+  const int sh = (lane & 7) * 4;  // this lane's 4 bits in its word of `starts`
+  for (int64_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
+       t < ntiles; t += stride) {
+    const int64_t e0 = t * kPullTile;
+    const bool whole = e0 + kPullTile <= m;  // the last tile may be partial
+    v4i src[4];
+    v4u wt[4];
+    uint32_t fa[4], fb[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t ev = e0 + v * 256 + lane * 4;
+      if (whole) {
+        src[v] = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(idx + ev));
+        wt[v] = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(w + ev));
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          src[v][q] = ev + q < m ? idx[ev + q] : 0;
+          wt[v][q] = ev + q < m ? w[ev + q] : 0u;
+        }
+      }
+      fa[v] = starts[ev >> 5];
+      fb[v] = starts[(ev >> 5) + 1];
+    }
+    uint32_t cand[4][4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cand[v][q] = snap[(uint32_t)src[v][q]];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool real = whole || e0 + v * 256 + lane * 4 + q < m;
+        cand[v][q] = real ? process<GM_PROG_SSSP>(cand[v][q], wt[v][q]) : 0xFFFFFFFFu;
+      }
+    const uint32_t r0 = tile_row[t];  // index in `rows` of the row holding edge e0
+    // A start at the tile's first edge opens row r0 itself, not the next.
+    const int f0 = __builtin_amdgcn_readfirstlane((int)((fa[0] >> sh) & 1u));
+    MinSeg carry{0, 0xFFFFFFFFu};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const uint32_t nib = (fa[v] >> sh) & 0xFu;  // bit q: edge q of the lane starts a row
+      const uint32_t nx = sh == 28 ? (fb[v] & 1u) : (fa[v] >> (sh + 4)) & 1u;
+      const uint32_t ends = (nib >> 1) | (nx << 3);  // bit q: edge q ends its row
+      uint32_t sm[4];
+      sm[0] = cand[v][0];
+#pragma unroll
+      for (int q = 1; q < 4; ++q) sm[q] = (nib >> q) & 1u ? cand[v][q] : min(sm[q - 1], cand[v][q]);
+      const MinSeg ex = mseg_scan(MinSeg{(int)__popc(nib), sm[3]}, carry, lane);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (!((ends >> q) & 1u)) continue;
+        const int lc = (int)__popc(nib & ((2u << q) - 1u));  // starts at or before edge q
+        const int c = ex.c + lc;                              // ... since the tile's first edge
+        const uint32_t y = lc > 0 ? sm[q] : min(ex.s, sm[q]);
+        if (y == 0xFFFFFFFFu) continue;
+        if (c > 0) {
+          const int64_t ri = (int64_t)r0 + c - f0;
+          if (ri < nrows) apply_min<true>(rows[ri], y, prop, next);
+        } else {
+          apply_min<false>(rows[r0], y, prop, next);  // begun in an earlier tile
+        }
+      }
+      if (v == 3 && lane == 63 && !(ends >> 3)) {  // goes on past the tile
+        const int c = ex.c + (int)__popc(nib);
+        const uint32_t y = nib ? sm[3] : min(ex.s, sm[3]);
+        const int64_t ri = (int64_t)r0 + c - f0;
+        if (y != 0xFFFFFFFFu && ri < nrows) apply_min<false>(rows[ri], y, prop, next);
+      }
+    }
+  }
+}
+
+// Layout of a pull over the adjacency off/idx/w (n rows, m edges): the
+// row-start bitmap (bit off[v] of every row with edges, and bit m), the
+// rows with edges in order, and for each tile the index in that list of the
+// row holding its first edge.
+__global__ void pull_rows(const uint32_t* __restrict__ off, int64_t n,
+                          const uint32_t* __restrict__ cidx, uint32_t* __restrict__ rows,
+                          uint32_t* __restrict__ starts) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t b = off[v];
+    if (off[v + 1] > b) {
+      rows[cidx[v]] = (uint32_t)v;
+      atomicOr(&starts[b >> 5], 1u << (b & 31));
+    }
+  }
+}
+
+__global__ void pull_flags(const uint32_t* __restrict__ off, int64_t n, uint32_t* __restrict__ f,
+                           uint32_t* __restrict__ starts, int64_t m) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v <= n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    f[v] = v < n && off[v + 1] > off[v] ? 1u : 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&starts[m >> 5], 1u << (m & 31));
+}
+
+__global__ void pull_tile_rows(const uint32_t* __restrict__ off, int64_t n,
+                               const uint32_t* __restrict__ cidx, int64_t ntiles,
+                               uint32_t* __restrict__ tile_row) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntiles;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t e = (uint32_t)(t * kPullTile);
+    int64_t lo = 0, hi = n;  // the last v with off[v] <= e: the row holding edge e
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (off[mid] <= e)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    tile_row[t] = cidx[lo];
   }
 }
 
@@ -956,25 +1205,75 @@ Adj relab_adjacency(gm_graph g, Relab* rl, int order, hipStream_t s) {
   return rl->all.view();
 }
 
+// The SSSP pull's tile layout of the adjacency with offsets `off` (g->m
+// edges), kept in the workspace; another adjacency replaces it.
+void ensure_pull_tiles(gm_graph g, Workspace* ws, const uint32_t* off, hipStream_t s) {
+  if (ws->pt && ws->pt->for_off == off) return;
+  delete ws->pt;
+  ws->pt = nullptr;
+  ++g->ws_gen;
+  const int64_t n = g->n, m = g->m;
+  PullTiles* pt = new PullTiles();
+  void* tmp = nullptr;
+  try {
+    pt->ntiles = (m + kPullTile - 1) / kPullTile;
+    const int64_t words = pt->ntiles * (kPullTile / 32) + 1;
+    pt->starts = dalloc<uint32_t>(words);
+    fill_kernel<<<blocks_for(words), kThreads, 0, s>>>(pt->starts, words, 0u);
+    DevBuf<uint32_t> f(n + 1), cidx(n + 1);
+    pull_flags<<<blocks_for(n + 1), kThreads, 0, s>>>(off, n, f.p, pt->starts, m);
+    GM_HIP(hipGetLastError());
+    size_t bytes = 0;
+    GM_HIP(rocprim::exclusive_scan(nullptr, bytes, f.p, cidx.p, 0u, (size_t)(n + 1),
+                                   rocprim::plus<uint32_t>(), s));
+    tmp = dmalloc(bytes);
+    GM_HIP(rocprim::exclusive_scan(tmp, bytes, f.p, cidx.p, 0u, (size_t)(n + 1),
+                                   rocprim::plus<uint32_t>(), s));
+    uint32_t nrows = 0;
+    GM_HIP(hipMemcpyAsync(&nrows, cidx.p + n, 4, hipMemcpyDeviceToHost, s));
+    GM_HIP(hipStreamSynchronize(s));
+    dfree(tmp);
+    tmp = nullptr;
+    pt->nrows = nrows;
+    pt->rows = dalloc<uint32_t>(std::max<int64_t>(nrows, 1));
+    pt->tile_row = dalloc<uint32_t>(std::max<int64_t>(pt->ntiles, 1));
+    pull_rows<<<blocks_for(n), kThreads, 0, s>>>(off, n, cidx.p, pt->rows, pt->starts);
+    if (pt->ntiles > 0)
+      pull_tile_rows<<<blocks_for(pt->ntiles), kThreads, 0, s>>>(off, n, cidx.p, pt->ntiles,
+                                                                 pt->tile_row);
+    GM_HIP(hipGetLastError());
+    GM_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    dfree(tmp);
+    delete pt;
+    throw;
+  }
+  pt->for_off = off;
+  ws->pt = pt;
+}
+
 // The view of a plain run: the caller's labels, or the relabelled copy
 // (then rl is set). BFS pulls only when pushing along out-edges, over the
 // in-adjacency (the out-adjacency of a symmetrised graph).
 View run_view(gm_graph g, Workspace* ws, int kind, int order, Relab* rl, hipStream_t s) {
   const bool sym = (g->prep & (GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG)) == GM_PREP_SYMMETRIZE;
-  const bool pull = kind == GM_PROG_BFS && order == GM_ORDER_OUT && (sym || g->in_off);
+  const bool pull = (kind == GM_PROG_BFS || (kind == GM_PROG_SSSP && g->wtype == GM_W_U32 &&
+                                              g->m > 0)) &&
+                    order == GM_ORDER_OUT && (sym || g->in_off) && g->n > 0;
+  View v{Adj{nullptr, nullptr, nullptr}, Adj{nullptr, nullptr, nullptr}, pull};
   if (!rl) {
-    View v{adjacency(g, ws, order, s), nullptr, nullptr, pull};
-    if (pull) {
-      v.pull_off = sym ? g->out_off : g->in_off;
-      v.pull_idx = sym ? g->out_idx : g->in_idx;
-    }
-    return v;
+    v.push = adjacency(g, ws, order, s);
+    if (pull)
+      v.pull = sym ? v.push
+                   : Adj{g->in_off, g->in_idx, static_cast<const uint32_t*>(g->in_w)};
+  } else {
+    v.push = relab_adjacency(g, rl, order, s);
+    if (pull) v.pull = sym ? v.push : relab_adjacency(g, rl, GM_ORDER_IN, s);
   }
-  View v{relab_adjacency(g, rl, order, s), nullptr, nullptr, pull};
-  if (pull) {
-    const Adj p = sym ? v.push : relab_adjacency(g, rl, GM_ORDER_IN, s);
-    v.pull_off = p.off;
-    v.pull_idx = p.idx;
+  if (pull && kind == GM_PROG_SSSP) {
+    if (!ws->snap) ws->snap = dalloc<uint32_t>(g->n);
+    ensure_pull_tiles(g, ws, v.pull.off, s);
   }
   return v;
 }
@@ -1002,6 +1301,8 @@ void free_min_workspace(gm_graph g) {
   dfree(ws->all_idx);
   dfree(ws->all_w);
   free_relab(ws->rl);
+  dfree(ws->snap);
+  delete ws->pt;
   if (ws->host_ctl) (void)hipHostFree(ws->host_ctl);
   delete ws;
   g->min_ws = nullptr;
@@ -1037,9 +1338,9 @@ void enqueue_superstep(gm_graph g, Workspace* ws, int kind, const View& view, Ct
                        uint32_t* prop, hipStream_t s) {
   const int64_t n = g->n;
   const int64_t words = (n + 31) / 32;
+  const int64_t m = g->m;
   const Adj& a = view.push;
-  const uint32_t* pull_off = view.pull_off;
-  const int32_t* pull_idx = view.pull_idx;
+  const Adj& pl = view.pull;
   const bool pull_ok = view.pull_ok;
   const uint32_t pull_div = g->tune.pull_div;
   const unsigned push_blocks = g->tune.push_blocks;
@@ -1056,27 +1357,37 @@ void enqueue_superstep(gm_graph g, Workspace* ws, int kind, const View& view, Ct
   if (kind != GM_PROG_DEGREE && (g->tune.variant & GM_VARIANT_VERTEX_PUSH)) {
     if (kind == GM_PROG_SSSP)
       push_vertex_kernel<GM_PROG_SSSP><<<blocks_for(n), kThreads, 0, s>>>(
-          c, n, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, a.idx, a.w, prop,
+          c, n, m, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, a.idx, a.w, prop,
           ws->bits[cur ^ 1], nullptr, nullptr);
     else
       push_vertex_kernel<GM_PROG_BFS><<<blocks_for(n), kThreads, 0, s>>>(
-          c, n, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, a.idx, nullptr, prop,
+          c, n, m, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, a.idx, nullptr, prop,
           ws->bits[cur ^ 1], nullptr, nullptr);
   } else if (kind == GM_PROG_SSSP)
     push_kernel<GM_PROG_SSSP><<<push_blocks, kThreads, 0, s>>>(
-        c, n, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, a.idx, a.w, prop,
+        c, n, m, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, a.idx, a.w, prop,
         ws->bits[cur ^ 1]);
   else if (kind == GM_PROG_DEGREE)
     push_kernel<GM_PROG_DEGREE><<<push_blocks, kThreads, 0, s>>>(
-        c, n, false, pull_div, ws->qmsg, ws->qbeg, ws->qest, a.idx, nullptr, prop,
+        c, n, m, false, pull_div, ws->qmsg, ws->qbeg, ws->qest, a.idx, nullptr, prop,
         ws->bits[cur ^ 1]);
   else
     push_kernel<GM_PROG_BFS><<<push_blocks, kThreads, 0, s>>>(
-        c, n, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, a.idx, nullptr, prop,
+        c, n, m, pull_ok, pull_div, ws->qmsg, ws->qbeg, ws->qest, a.idx, nullptr, prop,
         ws->bits[cur ^ 1]);
-  if (pull_ok)
-    pull_kernel<<<blocks_for(n, 8192), kThreads, 0, s>>>(c, n, pull_ok, pull_div, pull_off, pull_idx,
-                                                         ws->bits[cur], prop, ws->bits[cur ^ 1]);
+  if (pull_ok && kind == GM_PROG_BFS)
+    pull_kernel<<<blocks_for(n, 8192), kThreads, 0, s>>>(c, n, m, pull_ok, pull_div, pl.off,
+                                                         pl.idx, ws->bits[cur], prop,
+                                                         ws->bits[cur ^ 1]);
+  if (pull_ok && kind == GM_PROG_SSSP) {
+    pull_snapshot<<<blocks_for(n, 8192), kThreads, 0, s>>>(c, n, m, pull_ok, pull_div,
+                                                           ws->bits[cur], prop, ws->snap);
+    const PullTiles* pt = ws->pt;
+    pull_min_tiles<<<push_blocks, kThreads, 0, s>>>(c, n, m, pull_ok, pull_div, pl.idx, pl.w,
+                                                    pt->starts, pt->rows, pt->tile_row,
+                                                    pt->ntiles, pt->nrows, ws->snap, prop,
+                                                    ws->bits[cur ^ 1]);
+  }
   GM_HIP(hipGetLastError());
 }
 
@@ -1157,9 +1468,10 @@ void enqueue_min_program(gm_graph g, int kind, const int32_t* ids, int64_t count
   GM_HIP(hipGetLastError());
   int cur = 0;
   const bool sym = (g->prep & (GM_PREP_SYMMETRIZE | GM_PREP_UPPER_DAG)) == GM_PREP_SYMMETRIZE;
+  // captured SSSP runs push only (no snapshot buffer is prepared for them)
   View view{Adj{g->out_off, g->out_idx, static_cast<const uint32_t*>(g->out_w)},
-            sym ? g->out_off : g->in_off, sym ? g->out_idx : g->in_idx, false};
-  view.pull_ok = kind == GM_PROG_BFS && view.pull_off != nullptr;
+            Adj{sym ? g->out_off : g->in_off, sym ? g->out_idx : g->in_idx, nullptr}, false};
+  view.pull_ok = kind == GM_PROG_BFS && view.pull.off != nullptr;
   start_batch(ws, s);
   for (int32_t b = 0; b < steps; ++b) {
     enqueue_superstep(g, ws, kind, view, ws->ctl + b, cur, prop, s);
@@ -1263,19 +1575,19 @@ static int32_t run_min_program_list(gm_graph g, Workspace* ws, const Adj& adj, i
     if (vertex_push) {
       if (kind == GM_PROG_SSSP)
         push_vertex_kernel<GM_PROG_SSSP><<<blocks_for(c), kThreads, 0, s>>>(
-            ws->ctl, n, false, 1, ws->qmsg, ws->qbeg, ws->qest, adj.idx, adj.w, prop, nullptr,
+            ws->ctl, n, g->m, false, 1, ws->qmsg, ws->qbeg, ws->qest, adj.idx, adj.w, prop, nullptr,
             b.app[0], b.cnt);
       else
         push_vertex_kernel<GM_PROG_BFS><<<blocks_for(c), kThreads, 0, s>>>(
-            ws->ctl, n, false, 1, ws->qmsg, ws->qbeg, ws->qest, adj.idx, nullptr, prop, nullptr,
+            ws->ctl, n, g->m, false, 1, ws->qmsg, ws->qbeg, ws->qest, adj.idx, nullptr, prop, nullptr,
             b.app[0], b.cnt);
     } else if (kind == GM_PROG_SSSP) {
       push_kernel<GM_PROG_SSSP><<<g->tune.push_blocks, kThreads, 0, s>>>(
-          ws->ctl, n, false, 1, ws->qmsg, ws->qbeg, ws->qest, adj.idx, adj.w, prop, nullptr,
+          ws->ctl, n, g->m, false, 1, ws->qmsg, ws->qbeg, ws->qest, adj.idx, adj.w, prop, nullptr,
           b.app[0], b.cnt);
     } else {
       push_kernel<GM_PROG_BFS><<<g->tune.push_blocks, kThreads, 0, s>>>(
-          ws->ctl, n, false, 1, ws->qmsg, ws->qbeg, ws->qest, adj.idx, nullptr, prop, nullptr,
+          ws->ctl, n, g->m, false, 1, ws->qmsg, ws->qbeg, ws->qest, adj.idx, nullptr, prop, nullptr,
           b.app[0], b.cnt);
     }
     GM_HIP(hipGetLastError());
@@ -1341,8 +1653,7 @@ static int32_t run_supersteps(gm_graph g, Workspace* ws, int kind, const View& v
       }
       ++iters;
       st.edges_scanned += (uint32_t)c.packed;
-      const bool pulled = kind == GM_PROG_BFS && view.pull_ok && c.msg_min == c.msg_max &&
-                          (int64_t)cnt > n / (int64_t)g->tune.pull_div;
+      const bool pulled = use_pull(c, kind, view.pull_ok, n, g->m, g->tune.pull_div);
       if (pulled)
         ++st.pull_supersteps;
       else

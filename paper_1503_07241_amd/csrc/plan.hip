@@ -670,6 +670,8 @@ gm_status gm_autotune(gm_graph g, const gm_program* prog, int32_t batched, const
       params.push_back({&Tuning::push_blocks, {512, 1024, 2048, 4096, 8192}});
       params.push_back({&Tuning::superstep_batch, {1, 2, 4, 8, 16}});
     } else if (!batched && kind == GM_PROG_SSSP) {
+      // pull once the frontier's out-edges exceed m (never), m/2, m/4, m/8, m/16
+      params.push_back({&Tuning::pull_div, {64, 128, 256, 512, 1024}});
       params.push_back({&Tuning::push_blocks, {512, 1024, 2048, 4096, 8192}});
       params.push_back({&Tuning::superstep_batch, {1, 2, 4, 8, 16}});
     } else if (batched && kind == GM_PROG_SSSP) {

@@ -37,19 +37,21 @@ def test_min_program_variants(scale, variant):
         it = gm.run_vertex_program(gs, gm.GM_PROG_BFS, ids(0), -1, lv)
         assert np.array_equal(lv.cpu().numpy(), ref_lv)
         assert it == int(ref_lv[ref_lv != oracle.INF_I32].max()) + 1
-    gd.set_tuning(variant=variant)
-    dist = torch.full((n,), -1, dtype=torch.int32, device=DEV)
-    dist[0] = 0
-    it = gm.run_vertex_program(gd, gm.GM_PROG_SSSP, ids(0), -1, dist)
-    assert np.array_equal(dist.cpu().numpy().view(np.uint32), ref_d)
-    assert it == W.sssp_supersteps(scale)
+    for pull_div in (128, 1, 65536):  # pull supersteps for frontiers with many edges,
+        gd.set_tuning(variant=variant, pull_div=pull_div)  # push only, pull almost always
+        dist = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+        dist[0] = 0
+        it = gm.run_vertex_program(gd, gm.GM_PROG_SSSP, ids(0), -1, dist)
+        assert np.array_equal(dist.cpu().numpy().view(np.uint32), ref_d)
+        assert it == W.sssp_supersteps(scale)
 
 
+@pytest.mark.parametrize("pull_div", [128, 65536])
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_min_program_variants_resume_and_hand_trace(variant):
+def test_min_program_variants_resume_and_hand_trace(variant, pull_div):
     n, s, d, w, src, trace, steps = W.sssp_hand_trace()
     g = gm.Graph.from_coo(n, s, d, w=w, prep=P_DIR)
-    g.set_tuning(variant=variant)
+    g.set_tuning(variant=variant, pull_div=pull_div)
     for k, (dist_k, act_k) in enumerate(trace, start=1):
         dist = torch.full((n,), -1, dtype=torch.int32, device=DEV)
         dist[src] = 0

@@ -289,6 +289,12 @@ def test_autotune_keeps_results_and_sets_values():
     og, ogin = W.ograph(sc, "directed"), W.otranspose(sc, "directed")
     ref = oracle.personalized_pagerank(og, int(P[5]), 0.15, 20, g_in=ogin)
     assert l1_rel(bp.cpu().numpy()[:, 5], ref) <= 1e-5
+    t = gm.autotune(gdir, gm.GM_PROG_SSSP, dev([0]), trials=2)
+    assert t["pull_div"] in (64, 128, 256, 512, 1024)
+    dist = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+    dist[0] = 0
+    assert gm.run_vertex_program(gdir, gm.GM_PROG_SSSP, dev([0]), -1, dist) == W.sssp_supersteps(sc)
+    assert np.array_equal(dist.cpu().numpy().view(np.uint32), W.sssp_dist(sc))
     gdag = gm.Graph.from_coo(n, s, d, prep=P_DAG)
     t = gm.autotune(gdag, gm.GM_PROG_TC, trials=1)
     assert gm.triangle_count(gdag) == oracle.triangle_count(W.ograph(sc, "dag"))
