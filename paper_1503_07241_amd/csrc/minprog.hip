@@ -330,48 +330,53 @@ __global__ __launch_bounds__(kThreads) void send_write(
     const uint32_t* __restrict__ bits, int64_t words, int64_t n, int64_t chunk,
     const uint32_t* __restrict__ prop, const uint32_t* __restrict__ off,
     const SendInfo* __restrict__ info, int32_t* __restrict__ q, uint32_t* __restrict__ qmsg,
-    uint32_t* __restrict__ qbeg, uint32_t* __restrict__ qest, Ctl* __restrict__ ctl) {
+    uint32_t* __restrict__ qbeg, uint32_t* __restrict__ qest, Ctl* __restrict__ ctl, int kind,
+    int64_t m, bool pull_ok, uint32_t pull_div) {
   __shared__ uint32_t sh[2 * kWaves];
-  // This workgroup's place: the totals of the workgroups before it (the
-  // first workgroup also totals all of them for the control record).
-  const int nb = blockIdx.x == 0 ? (int)gridDim.x : (int)blockIdx.x;
-  uint32_t cb = 0, eb = 0, mn = 0xFFFFFFFFu, mx = 0;
-  for (int i = threadIdx.x; i < nb; i += kThreads) {
+  __shared__ uint32_t red[4][kWaves];
+  // The superstep's totals (all workgroups: the control record and the
+  // direction) and this workgroup's place (the workgroups before it).
+  uint32_t cb = 0, eb = 0, ca = 0, ea = 0, mn = 0xFFFFFFFFu, mx = 0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += kThreads) {
     const SendInfo t = info[i];
-    cb += t.cnt;
-    eb += t.edges;
+    ca += t.cnt;
+    ea += t.edges;
     mn = t.mn < mn ? t.mn : mn;
     mx = t.mx > mx ? t.mx : mx;
+    if (i < (int)blockIdx.x) {
+      cb += t.cnt;
+      eb += t.edges;
+    }
   }
   uint32_t ctot, etot;
   (void)block_excl_scan(cb, sh, &ctot);
   (void)block_excl_scan(eb, sh + kWaves, &etot);
-  if (blockIdx.x == 0) {
-    for (int o = 32; o > 0; o >>= 1) {
-      const uint32_t a = __shfl_xor(mn, o, 64), c = __shfl_xor(mx, o, 64);
-      mn = a < mn ? a : mn;
-      mx = c > mx ? c : mx;
-    }
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) {
-      sh[threadIdx.x >> 6] = mn;
-      sh[kWaves + (threadIdx.x >> 6)] = mx;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t a = 0xFFFFFFFFu, c = 0;
-      for (int i = 0; i < kWaves; ++i) {
-        a = sh[i] < a ? sh[i] : a;
-        c = sh[kWaves + i] > c ? sh[kWaves + i] : c;
-      }
-      ctl->packed = ((unsigned long long)ctot << 32) | etot;
-      ctl->msg_min = a;
-      ctl->msg_max = c;
-    }
-    ctot = 0;  // the first workgroup starts at slot 0
-    etot = 0;
-    __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    ca += __shfl_xor(ca, o, 64);
+    ea += __shfl_xor(ea, o, 64);
+    const uint32_t a = __shfl_xor(mn, o, 64), c = __shfl_xor(mx, o, 64);
+    mn = a < mn ? a : mn;
+    mx = c > mx ? c : mx;
   }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = ca;
+    red[1][threadIdx.x >> 6] = ea;
+    red[2][threadIdx.x >> 6] = mn;
+    red[3][threadIdx.x >> 6] = mx;
+  }
+  __syncthreads();
+  Ctl c{0, 0xFFFFFFFFu, 0};
+  uint32_t call = 0, eall = 0;
+  for (int i = 0; i < kWaves; ++i) {
+    call += red[0][i];
+    eall += red[1][i];
+    c.msg_min = red[2][i] < c.msg_min ? red[2][i] : c.msg_min;
+    c.msg_max = red[3][i] > c.msg_max ? red[3][i] : c.msg_max;
+  }
+  c.packed = ((unsigned long long)call << 32) | eall;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ctl = c;
+  // a pull superstep reads the frontier bits and the control record only
+  if (use_pull(c, kind, pull_ok, n, m, pull_div)) return;
   uint32_t slot0 = ctot, est0 = etot;
   int64_t wb, we;
   send_range(words, chunk, &wb, &we);
@@ -1353,7 +1358,8 @@ void enqueue_superstep(gm_graph g, Workspace* ws, int kind, const View& view, Ct
   send_count<<<(unsigned)nbk, kThreads, 0, s>>>(ws->bits[cur], ws->bits[cur ^ 1], words, g->n,
                                                 chunk, prop, a.off, ws->sinfo);
   send_write<<<(unsigned)nbk, kThreads, 0, s>>>(ws->bits[cur], words, g->n, chunk, prop, a.off,
-                                                ws->sinfo, ws->q, ws->qmsg, ws->qbeg, ws->qest, c);
+                                                ws->sinfo, ws->q, ws->qmsg, ws->qbeg, ws->qest, c,
+                                                kind, m, pull_ok, pull_div);
   if (kind != GM_PROG_DEGREE && (g->tune.variant & GM_VARIANT_VERTEX_PUSH)) {
     if (kind == GM_PROG_SSSP)
       push_vertex_kernel<GM_PROG_SSSP><<<blocks_for(n), kThreads, 0, s>>>(
