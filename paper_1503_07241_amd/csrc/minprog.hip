@@ -96,10 +96,21 @@ struct PullTiles {
   uint32_t* rows = nullptr;
   uint32_t* tile_row = nullptr;
   int64_t ntiles = 0, nrows = 0;
+  // LDS hot set: the hot_n sources with the most out-edges (hot_ids); tidx is
+  // the adjacency's index array with each of their entries replaced by
+  // (slot | kHotTag), padded to whole tiles
+  int32_t* tidx = nullptr;
+  int32_t* hot_ids = nullptr;
+  uint32_t* hot_snap = nullptr;  // per pull superstep: their messages
+  int hot_n = 0;
+  int cus = 0;  // compute units (one 1,024-lane workgroup each)
   ~PullTiles() {
     dfree(starts);
     dfree(rows);
     dfree(tile_row);
+    dfree(tidx);
+    dfree(hot_ids);
+    dfree(hot_snap);
   }
 };
 
@@ -645,14 +656,22 @@ __global__ __launch_bounds__(kThreads) void pull_kernel(
 
 // SSSP pull superstep, first part: snap[v] = x_v = prop(v) for a frontier
 // vertex, the max value (kept by PROCESS) for every other vertex.
+// The same for the hot set, contiguous: hot_snap[i] = the message of
+// hot_ids[i].
 __global__ __launch_bounds__(kThreads) void pull_snapshot(
     const Ctl* __restrict__ ctlp, int64_t n, int64_t m, bool pull_ok, uint32_t pull_div,
     const uint32_t* __restrict__ cur, const uint32_t* __restrict__ prop,
-    uint32_t* __restrict__ snap) {
+    uint32_t* __restrict__ snap, const int32_t* __restrict__ hot_ids, int hot_n,
+    uint32_t* __restrict__ hot_snap) {
   if (!use_pull(*ctlp, GM_PROG_SSSP, pull_ok, n, m, pull_div)) return;
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x)
     snap[v] = (cur[v >> 5] >> (v & 31)) & 1u ? prop[v] : 0xFFFFFFFFu;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < hot_n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = hot_ids[i];
+    hot_snap[i] = (cur[v >> 5] >> (v & 31)) & 1u ? prop[v] : 0xFFFFFFFFu;
+  }
 }
 
 // Segmented-min state of a run of in-edges: c = row starts in it, s = min of
@@ -719,25 +738,42 @@ __device__ inline void apply_min(uint32_t v, uint32_t y, uint32_t* prop, uint32_
 // in-edges are skipped by a list of the rows that have some); a wavefront
 // takes a tile in four rounds of 256 edges, four consecutive ones per lane
 // (16-byte index and weight loads, all sixteen gathers in flight at once).
+// Each workgroup (one per compute unit) first copies the messages of the
+// hot set (the sources with the most out-edges, which most in-edges name)
+// to LDS; an edge whose index carries kHotTag reads its message there (its
+// global gather is redirected to snap[0], one line for all such lanes).
 // Each lane takes the min of its edges per row, a segmented scan over the
 // wavefront joins the lanes, and the lane holding a row's last edge applies
 // it: with a plain store if the row began in the tile (no other wavefront
 // touches it), with an atomic min if it began in an earlier tile; the part
 // of a row that goes on past the tile is applied with an atomic min too.
 constexpr int64_t kPullTile = 1024;
-__global__ __launch_bounds__(kThreads) void pull_min_tiles(
+constexpr int kPullThreads = 1024;
+constexpr int kPullWaves = kPullThreads / 64;
+constexpr int kPullHotMax = 40960;  // hot messages in LDS (160 KB)
+constexpr uint32_t kHotTag = 0x80000000u;
+__global__ __launch_bounds__(kPullThreads) void pull_min_tiles(
     const Ctl* __restrict__ ctlp, int64_t n, int64_t m, bool pull_ok, uint32_t pull_div,
     const int32_t* __restrict__ idx, const uint32_t* __restrict__ w,
     const uint32_t* __restrict__ starts, const uint32_t* __restrict__ rows,
     const uint32_t* __restrict__ tile_row, int64_t ntiles, int64_t nrows,
-    const uint32_t* __restrict__ snap, uint32_t* prop, uint32_t* next) {
+    const uint32_t* __restrict__ snap, const uint32_t* __restrict__ hot_snap, int hot_n,
+    uint32_t* prop, uint32_t* next) {
+  extern __shared__ uint32_t hot[];  // hot_n messages
   if (!use_pull(*ctlp, GM_PROG_SSSP, pull_ok, n, m, pull_div)) return;
   typedef int v4i __attribute__((ext_vector_type(4)));
   typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  {
+    const int n4 = hot_n >> 2;
+    for (int i = threadIdx.x; i < n4; i += kPullThreads)
+      reinterpret_cast<v4u*>(hot)[i] = reinterpret_cast<const v4u*>(hot_snap)[i];
+    for (int i = 4 * n4 + threadIdx.x; i < hot_n; i += kPullThreads) hot[i] = hot_snap[i];
+    __syncthreads();
+  }
   const int lane = threadIdx.x & 63;
-  const int64_t stride = (int64_t)gridDim.x * kWaves;
+  const int64_t stride = (int64_t)gridDim.x * kPullWaves;
   const int sh = (lane & 7) * 4;  // this lane's 4 bits in its word of `starts`
-  for (int64_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
+  for (int64_t t = __builtin_amdgcn_readfirstlane(blockIdx.x * kPullWaves + (threadIdx.x >> 6));
        t < ntiles; t += stride) {
     const int64_t e0 = t * kPullTile;
     const bool whole = e0 + kPullTile <= m;  // the last tile may be partial
@@ -747,15 +783,12 @@ __global__ __launch_bounds__(kThreads) void pull_min_tiles(
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t ev = e0 + v * 256 + lane * 4;
+      src[v] = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(idx + ev));  // padded
       if (whole) {
-        src[v] = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(idx + ev));
         wt[v] = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(w + ev));
       } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          src[v][q] = ev + q < m ? idx[ev + q] : 0;
-          wt[v][q] = ev + q < m ? w[ev + q] : 0u;
-        }
+        for (int q = 0; q < 4; ++q) wt[v][q] = ev + q < m ? w[ev + q] : 0u;
       }
       fa[v] = starts[ev >> 5];
       fb[v] = starts[(ev >> 5) + 1];
@@ -764,7 +797,13 @@ __global__ __launch_bounds__(kThreads) void pull_min_tiles(
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) cand[v][q] = snap[(uint32_t)src[v][q]];
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t sv = (uint32_t)src[v][q];
+        const bool in_lds = (sv & kHotTag) != 0u;
+        const uint32_t g = snap[in_lds ? 0u : sv];
+        const uint32_t l = hot[in_lds ? sv & ~kHotTag : 0u];
+        cand[v][q] = in_lds ? l : g;
+      }
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -808,6 +847,44 @@ __global__ __launch_bounds__(kThreads) void pull_min_tiles(
       }
     }
   }
+}
+
+// Tagged index array of the pull: tidx[e] = slot | kHotTag for a hot source,
+// the source otherwise; 0 past m (to the end of the last tile).
+__global__ void pull_tag(const int32_t* __restrict__ idx, int64_t m, int64_t mpad,
+                         const int32_t* __restrict__ slot_of, int32_t* __restrict__ tidx) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < mpad;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int32_t v = 0;
+    if (e < m) {
+      const int32_t u = idx[e];
+      const int32_t sl = slot_of[u];
+      v = sl >= 0 ? (int32_t)((uint32_t)sl | kHotTag) : u;
+    }
+    tidx[e] = v;
+  }
+}
+
+__global__ void pull_slots(const int32_t* __restrict__ hot_ids, int hot_n,
+                           int32_t* __restrict__ slot_of) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < hot_n; i += gridDim.x * blockDim.x)
+    slot_of[hot_ids[i]] = i;
+}
+
+// Sort key of a vertex for the hot set: most out-edges first, ties by id.
+__global__ void pull_hot_keys(const uint32_t* __restrict__ push_off, int64_t n,
+                              unsigned long long* __restrict__ key) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t d = push_off[v + 1] - push_off[v];
+    key[v] = ((unsigned long long)(0xFFFFFFFFu - d) << 32) | (uint32_t)v;
+  }
+}
+
+__global__ void pull_hot_ids(const unsigned long long* __restrict__ key, int hot_n,
+                             int32_t* __restrict__ hot_ids) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < hot_n; i += gridDim.x * blockDim.x)
+    hot_ids[i] = (int32_t)(uint32_t)key[i];
 }
 
 // Layout of a pull over the adjacency off/idx/w (n rows, m edges): the
@@ -1210,9 +1287,12 @@ Adj relab_adjacency(gm_graph g, Relab* rl, int order, hipStream_t s) {
   return rl->all.view();
 }
 
-// The SSSP pull's tile layout of the adjacency with offsets `off` (g->m
-// edges), kept in the workspace; another adjacency replaces it.
-void ensure_pull_tiles(gm_graph g, Workspace* ws, const uint32_t* off, hipStream_t s) {
+// The SSSP pull's tile layout of the adjacency `pl` (g->m edges; push_off:
+// the offsets of the pushed adjacency in the same labels, whose degrees
+// pick the hot set), kept in the workspace; another adjacency replaces it.
+void ensure_pull_tiles(gm_graph g, Workspace* ws, const Adj& pl, const uint32_t* push_off,
+                       hipStream_t s) {
+  const uint32_t* off = pl.off;
   if (ws->pt && ws->pt->for_off == off) return;
   delete ws->pt;
   ws->pt = nullptr;
@@ -1247,7 +1327,41 @@ void ensure_pull_tiles(gm_graph g, Workspace* ws, const uint32_t* off, hipStream
       pull_tile_rows<<<blocks_for(pt->ntiles), kThreads, 0, s>>>(off, n, cidx.p, pt->ntiles,
                                                                  pt->tile_row);
     GM_HIP(hipGetLastError());
-    GM_HIP(hipStreamSynchronize(s));
+    // hot set: the sources with the most out-edges, as many as LDS holds
+    int dev = 0, lds_max = 0;
+    GM_HIP(hipGetDevice(&dev));
+    GM_HIP(hipDeviceGetAttribute(&pt->cus, hipDeviceAttributeMultiprocessorCount, dev));
+    GM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    pt->hot_n = (int)std::min<int64_t>({(int64_t)kPullHotMax, n, (int64_t)lds_max / 4});
+    pt->hot_ids = dalloc<int32_t>(std::max(pt->hot_n, 1));
+    pt->hot_snap = dalloc<uint32_t>(std::max(pt->hot_n, 1));
+    {
+      DevBuf<unsigned long long> k1(n), k2(n);
+      pull_hot_keys<<<blocks_for(n), kThreads, 0, s>>>(push_off, n, k1.p);
+      GM_HIP(hipGetLastError());
+      rocprim::double_buffer<unsigned long long> kb(k1.p, k2.p);
+      size_t sb = 0;
+      GM_HIP(rocprim::radix_sort_keys(nullptr, sb, kb, (size_t)n, 0, 64, s));
+      tmp = dmalloc(sb);
+      GM_HIP(rocprim::radix_sort_keys(tmp, sb, kb, (size_t)n, 0, 64, s));
+      pull_hot_ids<<<blocks_for(pt->hot_n), kThreads, 0, s>>>(kb.current(), pt->hot_n,
+                                                              pt->hot_ids);
+      GM_HIP(hipGetLastError());
+      GM_HIP(hipStreamSynchronize(s));
+      dfree(tmp);
+      tmp = nullptr;
+    }
+    {
+      DevBuf<int32_t> slot_of(n);
+      fill_kernel<<<blocks_for(n), kThreads, 0, s>>>(reinterpret_cast<uint32_t*>(slot_of.p), n,
+                                                     0xFFFFFFFFu);
+      pull_slots<<<blocks_for(pt->hot_n), kThreads, 0, s>>>(pt->hot_ids, pt->hot_n, slot_of.p);
+      const int64_t mpad = pt->ntiles * kPullTile;
+      pt->tidx = dalloc<int32_t>(std::max<int64_t>(mpad, 1));
+      pull_tag<<<blocks_for(mpad), kThreads, 0, s>>>(pl.idx, m, mpad, slot_of.p, pt->tidx);
+      GM_HIP(hipGetLastError());
+      GM_HIP(hipStreamSynchronize(s));
+    }
   } catch (...) {
     (void)hipStreamSynchronize(s);
     dfree(tmp);
@@ -1278,7 +1392,7 @@ View run_view(gm_graph g, Workspace* ws, int kind, int order, Relab* rl, hipStre
   }
   if (pull && kind == GM_PROG_SSSP) {
     if (!ws->snap) ws->snap = dalloc<uint32_t>(g->n);
-    ensure_pull_tiles(g, ws, v.pull.off, s);
+    ensure_pull_tiles(g, ws, v.pull, v.push.off, s);
   }
   return v;
 }
@@ -1386,13 +1500,14 @@ void enqueue_superstep(gm_graph g, Workspace* ws, int kind, const View& view, Ct
                                                          pl.idx, ws->bits[cur], prop,
                                                          ws->bits[cur ^ 1]);
   if (pull_ok && kind == GM_PROG_SSSP) {
-    pull_snapshot<<<blocks_for(n, 8192), kThreads, 0, s>>>(c, n, m, pull_ok, pull_div,
-                                                           ws->bits[cur], prop, ws->snap);
     const PullTiles* pt = ws->pt;
-    pull_min_tiles<<<push_blocks, kThreads, 0, s>>>(c, n, m, pull_ok, pull_div, pl.idx, pl.w,
-                                                    pt->starts, pt->rows, pt->tile_row,
-                                                    pt->ntiles, pt->nrows, ws->snap, prop,
-                                                    ws->bits[cur ^ 1]);
+    pull_snapshot<<<blocks_for(n, 8192), kThreads, 0, s>>>(c, n, m, pull_ok, pull_div,
+                                                           ws->bits[cur], prop, ws->snap,
+                                                           pt->hot_ids, pt->hot_n, pt->hot_snap);
+    pull_min_tiles<<<(unsigned)std::max(pt->cus, 1), kPullThreads,
+                     (size_t)pt->hot_n * sizeof(uint32_t), s>>>(
+        c, n, m, pull_ok, pull_div, pt->tidx, pl.w, pt->starts, pt->rows, pt->tile_row,
+        pt->ntiles, pt->nrows, ws->snap, pt->hot_snap, pt->hot_n, prop, ws->bits[cur ^ 1]);
   }
   GM_HIP(hipGetLastError());
 }
