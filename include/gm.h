@@ -266,9 +266,10 @@ gm_status gm_graph_release(gm_graph g);
  * type the graph lacks, an order the program does not take, GM_ORDER_ALL
  * beyond 2^32 - 1 edges in both directions); GM_ENOMEM; GM_EHIP.
  * BFS and SSSP synchronise `stream` after batches of supersteps (the
- * first of superstep_batch, each later one twice as long, at most 64; the
- * supersteps after the frontier empties do nothing); PageRank is
- * asynchronous.
+ * first of superstep_batch; each later one twice as long, at most 64, while
+ * the frontier holds up, back to superstep_batch once it fell below half
+ * of its size during a batch; the supersteps after the frontier empties do
+ * nothing); PageRank is asynchronous.
  */
 gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_frontier* frontier,
                                 int32_t max_iters, void* vprop, int32_t* active_out,
@@ -510,7 +511,8 @@ typedef struct gm_tuning {
                                (1..65536; 128) */
   uint32_t superstep_batch; /* BFS/SSSP: supersteps enqueued before the first
                                host check of the frontier; each later batch is
-                               twice as long, up to 64 (1..64; 4) */
+                               twice as long, up to 64, unless the frontier
+                               fell below half during the last (1..64; 4) */
   uint32_t push_blocks;     /* workgroups of the push kernels, plain and batched
                                SSSP (64..65536; 2048) */
   uint32_t ppr_chunk;       /* batched PPR: in-edges per work item (64..65536; 128) */
@@ -566,8 +568,8 @@ gm_status gm_graph_set_tuning(gm_graph g, const gm_tuning* t);
  * Autotuner: times `prog` on g for candidate values of the parameters that
  * schedule it and keeps the fastest, one parameter at a time (coordinate
  * descent; median of `trials` timed runs per candidate after a warm-up run):
- *   BFS: pull_div, superstep_batch, push_blocks; SSSP: superstep_batch,
- *   push_blocks; batched SSSP: push_blocks; batched PPR: ppr_chunk;
+ *   BFS: pull_div, superstep_batch, push_blocks; SSSP: pull_div,
+ *   push_blocks, superstep_batch; batched SSSP: push_blocks; batched PPR: ppr_chunk;
  *   TC: tc_wave_max, tc_wave_work, tc_block_work; PageRank: pr_hot;
  *   batched BFS has no parameters (the current values are returned).
  * batched selects gm_run_batched semantics with `count` = k sources; ids are

@@ -342,7 +342,8 @@ __global__ __launch_bounds__(kThreads) void send_write(
     const uint32_t* __restrict__ prop, const uint32_t* __restrict__ off,
     const SendInfo* __restrict__ info, int32_t* __restrict__ q, uint32_t* __restrict__ qmsg,
     uint32_t* __restrict__ qbeg, uint32_t* __restrict__ qest, Ctl* __restrict__ ctl, int kind,
-    int64_t m, bool pull_ok, uint32_t pull_div) {
+    int64_t m, bool pull_ok, uint32_t pull_div, uint32_t* __restrict__ snap,
+    const int32_t* __restrict__ hot_ids, int hot_n, uint32_t* __restrict__ hot_snap) {
   __shared__ uint32_t sh[2 * kWaves];
   __shared__ uint32_t red[4][kWaves];
   // The superstep's totals (all workgroups: the control record and the
@@ -386,8 +387,25 @@ __global__ __launch_bounds__(kThreads) void send_write(
   }
   c.packed = ((unsigned long long)call << 32) | eall;
   if (blockIdx.x == 0 && threadIdx.x == 0) *ctl = c;
-  // a pull superstep reads the frontier bits and the control record only
-  if (use_pull(c, kind, pull_ok, n, m, pull_div)) return;
+  // A pull superstep reads no queue: the frontier bits, the control record
+  // and, for SSSP, the message snapshot (snap[v] = x_v for a frontier vertex,
+  // the max value, which PROCESS keeps, for any other; hot_snap the same for
+  // the hot set, contiguous), written here instead.
+  if (use_pull(c, kind, pull_ok, n, m, pull_div)) {
+    if (snap) {
+      int64_t wb, we;
+      send_range(words, chunk, &wb, &we);
+      const int64_t ve = we * 32 < n ? we * 32 : n;
+      for (int64_t v = wb * 32 + threadIdx.x; v < ve; v += kThreads)
+        snap[v] = (bits[v >> 5] >> (v & 31)) & 1u ? prop[v] : 0xFFFFFFFFu;
+      for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < hot_n;
+           i += (int64_t)gridDim.x * kThreads) {
+        const int32_t v = hot_ids[i];
+        hot_snap[i] = (bits[v >> 5] >> (v & 31)) & 1u ? prop[v] : 0xFFFFFFFFu;
+      }
+    }
+    return;
+  }
   uint32_t slot0 = ctot, est0 = etot;
   int64_t wb, we;
   send_range(words, chunk, &wb, &we);
@@ -651,26 +669,6 @@ __global__ __launch_bounds__(kThreads) void pull_kernel(
     const int64_t word0 = (base + (threadIdx.x & ~63)) >> 5;
     if (lane == 0 && (uint32_t)m) atomicOr(&next[word0], (uint32_t)m);
     if (lane == 32 && (uint32_t)(m >> 32)) atomicOr(&next[word0 + 1], (uint32_t)(m >> 32));
-  }
-}
-
-// SSSP pull superstep, first part: snap[v] = x_v = prop(v) for a frontier
-// vertex, the max value (kept by PROCESS) for every other vertex.
-// The same for the hot set, contiguous: hot_snap[i] = the message of
-// hot_ids[i].
-__global__ __launch_bounds__(kThreads) void pull_snapshot(
-    const Ctl* __restrict__ ctlp, int64_t n, int64_t m, bool pull_ok, uint32_t pull_div,
-    const uint32_t* __restrict__ cur, const uint32_t* __restrict__ prop,
-    uint32_t* __restrict__ snap, const int32_t* __restrict__ hot_ids, int hot_n,
-    uint32_t* __restrict__ hot_snap) {
-  if (!use_pull(*ctlp, GM_PROG_SSSP, pull_ok, n, m, pull_div)) return;
-  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * blockDim.x)
-    snap[v] = (cur[v >> 5] >> (v & 31)) & 1u ? prop[v] : 0xFFFFFFFFu;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < hot_n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t v = hot_ids[i];
-    hot_snap[i] = (cur[v >> 5] >> (v & 31)) & 1u ? prop[v] : 0xFFFFFFFFu;
   }
 }
 
@@ -1471,9 +1469,11 @@ void enqueue_superstep(gm_graph g, Workspace* ws, int kind, const View& view, Ct
   nbk = std::max<int64_t>((words + chunk - 1) / chunk, 1);
   send_count<<<(unsigned)nbk, kThreads, 0, s>>>(ws->bits[cur], ws->bits[cur ^ 1], words, g->n,
                                                 chunk, prop, a.off, ws->sinfo);
-  send_write<<<(unsigned)nbk, kThreads, 0, s>>>(ws->bits[cur], words, g->n, chunk, prop, a.off,
-                                                ws->sinfo, ws->q, ws->qmsg, ws->qbeg, ws->qest, c,
-                                                kind, m, pull_ok, pull_div);
+  const PullTiles* pt = kind == GM_PROG_SSSP && pull_ok ? ws->pt : nullptr;
+  send_write<<<(unsigned)nbk, kThreads, 0, s>>>(
+      ws->bits[cur], words, g->n, chunk, prop, a.off, ws->sinfo, ws->q, ws->qmsg, ws->qbeg,
+      ws->qest, c, kind, m, pull_ok, pull_div, pt ? ws->snap : nullptr,
+      pt ? pt->hot_ids : nullptr, pt ? pt->hot_n : 0, pt ? pt->hot_snap : nullptr);
   if (kind != GM_PROG_DEGREE && (g->tune.variant & GM_VARIANT_VERTEX_PUSH)) {
     if (kind == GM_PROG_SSSP)
       push_vertex_kernel<GM_PROG_SSSP><<<blocks_for(n), kThreads, 0, s>>>(
@@ -1500,10 +1500,6 @@ void enqueue_superstep(gm_graph g, Workspace* ws, int kind, const View& view, Ct
                                                          pl.idx, ws->bits[cur], prop,
                                                          ws->bits[cur ^ 1]);
   if (pull_ok && kind == GM_PROG_SSSP) {
-    const PullTiles* pt = ws->pt;
-    pull_snapshot<<<blocks_for(n, 8192), kThreads, 0, s>>>(c, n, m, pull_ok, pull_div,
-                                                           ws->bits[cur], prop, ws->snap,
-                                                           pt->hot_ids, pt->hot_n, pt->hot_snap);
     pull_min_tiles<<<(unsigned)std::max(pt->cus, 1), kPullThreads,
                      (size_t)pt->hot_n * sizeof(uint32_t), s>>>(
         c, n, m, pull_ok, pull_div, pt->tidx, pl.w, pt->starts, pt->rows, pt->tile_row,
@@ -1765,6 +1761,7 @@ static int32_t run_supersteps(gm_graph g, Workspace* ws, int kind, const View& v
     }
     GM_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, nb * sizeof(Ctl), hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
+    uint64_t first_cnt = 0, last_cnt = 0;  // frontier sizes at the batch's ends
     for (int32_t b = 0; b < nb; ++b) {
       const Ctl& c = ws->host_ctl[b];
       const uint64_t cnt = c.packed >> 32;
@@ -1772,6 +1769,8 @@ static int32_t run_supersteps(gm_graph g, Workspace* ws, int kind, const View& v
         done = true;
         break;
       }
+      if (b == 0) first_cnt = cnt;
+      last_cnt = cnt;
       ++iters;
       st.edges_scanned += (uint32_t)c.packed;
       const bool pulled = use_pull(c, kind, view.pull_ok, n, g->m, g->tune.pull_div);
@@ -1781,10 +1780,13 @@ static int32_t run_supersteps(gm_graph g, Workspace* ws, int kind, const View& v
         ++st.push_supersteps;
     }
     if (max_iters > 0 && iters >= max_iters) done = true;
-    // a run that goes on is long: each further batch is twice as long (the
-    // supersteps after the frontier empties do nothing), so a run of S
-    // supersteps waits for the host about log2(S) times, not S / batch
-    batch = std::min<int32_t>(2 * batch, kMaxCtl);
+    // A run whose frontier holds up is long: each further batch is twice as
+    // long, so a run of S supersteps waits for the host about log2(S) times,
+    // not S / batch. One whose frontier fell below half during the batch is
+    // ending: the next batch goes back to the first length, since every
+    // superstep enqueued after the frontier empties still costs its launches.
+    const int32_t batch0 = std::max<int32_t>(1, (int32_t)g->tune.superstep_batch);
+    batch = 2 * last_cnt < first_cnt ? batch0 : std::min<int32_t>(2 * batch, kMaxCtl);
   }
   // bits[cur] holds the frontier left after the last superstep (empty when
   // the program converged); report it and leave the workspace cleared (the
