@@ -282,7 +282,7 @@ def main():
     # and the PageRank pull layout, each from a released graph, next to the
     # warm per-call times above.
     ea, eb, ec = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-    tc_plan, tc_cold, pr_layout = [], [], []
+    tc_plan, tc_cold, pr_layout, sssp_layout = [], [], [], []
     for _ in range(3):
         g_dag.release()
         ea.record()
@@ -298,12 +298,16 @@ def main():
         ea.record()
         g_dir.prepare(gm.GM_PROG_PAGERANK)
         eb.record()
+        g_dir.prepare(gm.GM_PROG_SSSP)
+        ec.record()
         torch.cuda.synchronize()
         pr_layout.append(ea.elapsed_time(eb))
+        sssp_layout.append(eb.elapsed_time(ec))
     med = lambda a: sorted(a)[len(a) // 2]  # noqa: E731
     programs["tc"].update({"warm_ms": programs["tc"]["ms"], "plan_ms": round(med(tc_plan), 3),
                            "cold_ms": round(med(tc_cold), 3)})
     programs["pr"]["layout_ms"] = round(med(pr_layout), 3)
+    programs["sssp"]["layout_ms"] = round(med(sssp_layout), 3)
     step(False)  # rebuild the released schedules before anything else is timed
     torch.cuda.synchronize()
     log("programs: %s" % json.dumps(programs))
@@ -368,14 +372,15 @@ def main():
                    "scale": scale, "n": n, "m_dir": m_dir, "m_sym": m_sym, "m_dag": m_dag,
                    "edges_per_step": int(edges_step),
                    "schedules": "warm: per-graph schedules (triangle-count work plan, PageRank "
-                                "pull layout) are built by the warm-up steps; their first-call "
-                                "costs are programs.tc.plan_ms / cold_ms and "
-                                "programs.pr.layout_ms, and value_cold_schedules counts them in "
-                                "every step"},
+                                "pull layout, SSSP pull layout) are built by the warm-up steps; "
+                                "their first-call costs are programs.tc.plan_ms / cold_ms, "
+                                "programs.pr.layout_ms and programs.sssp.layout_ms, and "
+                                "value_cold_schedules counts them in every step"},
         "value_cold_schedules": round(edges_step / ((ms_step - programs["tc"]["warm_ms"]
                                                      + programs["tc"]["cold_ms"]
-                                                     + programs["pr"]["layout_ms"]) * 1e-3) / 1e9,
-                                      3),
+                                                     + programs["pr"]["layout_ms"]
+                                                     + programs["sssp"]["layout_ms"]) * 1e-3)
+                                      / 1e9, 3),
         "programs": programs,
         "roofline": {"kernel": "pr_pull (PageRank superstep)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -224,7 +224,8 @@ typedef struct gm_frontier {
  * run would otherwise build: the frontier workspace of BFS and SSSP (and,
  * with GM_VARIANT_DEGREE_ORDER set, their degree-ordered copy of the
  * out-adjacency; runs along in-edges or both directions build theirs on
- * first use), the relabelled pull layout of PageRank and PPR (Sec. 4.4.1 stores the matrix
+ * first use), the tiled pull layout of weighted SSSP (row-start bitmap, row
+ * list, hot set), the relabelled pull layout of PageRank and PPR (Sec. 4.4.1 stores the matrix
  * once in the layout its SpMV reads; this is that step), the owner/partner
  * work plan of triangle counting (Sec. 4.2, program 2). Lets a caller time
  * preprocessing and runs apart. prog->kind selects the program; the other

@@ -1567,8 +1567,10 @@ void prepare_min_program(gm_graph g, hipStream_t s) {
 
 void prepare_plain_min_program(gm_graph g, int kind, hipStream_t s) {
   Workspace* ws = ensure_ws(g, s);
-  if (g->n > 0 && (g->tune.variant & GM_VARIANT_DEGREE_ORDER))
-    (void)run_view(g, ws, kind, GM_ORDER_OUT, ensure_relab(g, ws, s), s);
+  if (g->n > 0) {  // the relabelled copy and the SSSP pull layout, where they apply
+    Relab* rl = (g->tune.variant & GM_VARIANT_DEGREE_ORDER) ? ensure_relab(g, ws, s) : nullptr;
+    (void)run_view(g, ws, kind, GM_ORDER_OUT, rl, s);
+  }
   GM_HIP(hipStreamSynchronize(s));
 }
 
