@@ -131,6 +131,8 @@ def main():
                          "thread-per-vertex push, push vs pull, PageRank tiles and LDS copy")
     ap.add_argument("--tc-cold", action="store_true",
                     help="with --tc-only: free the work plan before each count (cold calls)")
+    ap.add_argument("--sssp-pull-div", type=int, default=0, metavar="D",
+                    help="with --sssp-only: the pull_div tuning value (1: push only)")
     ap.add_argument("--sssp-only", type=int, default=0, metavar="K",
                     help="only run K SSSP runs from vertex 0 on the scale-22 directed graph, "
                          "for hardware-counter runs")
@@ -178,6 +180,8 @@ def main():
         return
     if args.sssp_only:
         g = gm.Graph.from_coo(n, s, d, w=w, prep=gm.GM_PREP_DROP_SELF_LOOPS)
+        if args.sssp_pull_div:
+            g.set_tuning(pull_div=args.sssp_pull_div)
         root = torch.zeros(1, dtype=torch.int32, device=dev)
         dist = torch.empty(n, dtype=torch.int32, device=dev)
         for _ in range(args.sssp_only):
