@@ -212,6 +212,65 @@ def test_sssp_superstep_trace_hand_worked():
     assert it == steps and np.array_equal(dist, trace[-1][0]) and not active.any()
 
 
+def tile_edge_graph():
+    """A graph for the SSSP pull's tile layout: vertex 0 has an edge to every
+    vertex with in-edges; in-degrees are picked so that rows end one edge
+    before, on and one edge after multiples of the 1,024-edge tile, one row
+    has 5,001 in-edges (spanning several tiles), every third vertex has no
+    in-edge at all (interspersed empty rows), and the edge count is not a
+    multiple of the tile. No duplicate edges and no self-loops, so the
+    in-offsets are the cumulative sums of the in-degrees below."""
+    rng = np.random.default_rng(1234)
+    n = 6000
+    empty = np.arange(n) % 3 == 2
+    empty[0] = True
+    targets = np.flatnonzero(~empty)
+    deg = rng.integers(0, 40, size=len(targets))  # in-edges besides the one from 0
+    deg[1500] = 5000
+    for t, delta in ((2048, -1), (6144, 0), (9216, 1)):
+        off = np.cumsum(deg + 1)
+        i = int(np.searchsorted(off, t))
+        deg[i] -= off[i] - (t + delta)  # row i now ends at t + delta
+        assert deg[i] >= 0
+    src, dst = [], []
+    pool = np.arange(1, n)
+    for v, k in zip(targets, deg):
+        u = rng.choice(pool[pool != v], size=int(k), replace=False)
+        src.append(np.concatenate([[0], u]))
+        dst.append(np.full(int(k) + 1, v))
+    return n, np.concatenate(src).astype(np.int32), np.concatenate(dst).astype(np.int32)
+
+
+@pytest.mark.parametrize("pull_div", [1, 128, 65536])
+def test_sssp_pull_tile_layout_cases(pull_div):
+    """Every superstep's distances and frontier against the oracle's Alg. 2
+    superstep loop, pushing only, by default, and pulling almost always."""
+    n, s, d = tile_edge_graph()
+    w = gg.weights_u32(s, d)
+    g = gm.Graph.from_coo(n, s, d, w=w, prep=P_DIR)
+    g.set_tuning(pull_div=pull_div)
+    og = oracle.prepare(n, s, d, w=w)
+    m = og.off[-1]
+    assert m % 1024 != 0 and g.m == m
+    prop0 = np.full(n, oracle.INF_U32, np.uint32)
+    prop0[0] = 0
+    act0 = np.zeros(n, bool)
+    act0[0] = True
+    _, _, steps = oracle.run_min_program(og, prop0, act0, True)
+    for k in range(1, steps + 1):
+        ref_p, ref_a, it = oracle.run_min_program(og, prop0, act0, True, max_iters=k)
+        dist, it_g, active = run_sssp(g, n, 0, max_iters=k)
+        assert it_g == it and np.array_equal(dist, ref_p), k
+        assert np.array_equal(active.astype(bool), ref_a), k
+    dist, it_g, _ = run_sssp(g, n, 0)
+    assert it_g == steps and np.array_equal(dist, oracle.sssp(og, 0))
+    st = g.last_run_stats()
+    if pull_div == 1:
+        assert st.pull_supersteps == 0
+    if pull_div == 65536:
+        assert st.pull_supersteps > 0
+
+
 @pytest.mark.parametrize("name", ["sssp_rmat24_a50", "sssp_grid2048"])
 def test_paper_sssp_workloads(name):
     """The paper's SSSP graphs (f3): RMAT scale 24 with a = .50, b = c = .10
