@@ -702,7 +702,7 @@ def run_ablation(gm, gg, torch, np, n, s, d, w):
       frontier: bitvector (default) vs sorted list of distinct ids;
       load balance: equal edge ranges per wavefront (default) vs one thread
         per active vertex;
-      direction (BFS): push with pull supersteps for large frontiers
+      direction (BFS, SSSP): push with pull supersteps for large frontiers
         (default) vs push only;
       vertex order (BFS, SSSP): the caller's labels (default) vs a copy
         relabelled by decreasing in-degree, on the generator's labels and on
@@ -755,15 +755,17 @@ def run_ablation(gm, gg, torch, np, n, s, d, w):
                 ref["bfs"] = got.copy()
             assert np.array_equal(got, ref["bfs"]), (name, dname)
             out["bfs"][name + "/" + dname] = {"ms": round(ms, 3), "gteps": round(e / ms / 1e6, 2)}
-        g_dir.set_tuning(variant=var)
-        ms = tm.ms(sssp, 3)
-        e = g_dir.last_run_stats().edges_scanned
-        got = dist.cpu().numpy()
-        if "sssp" not in ref:
-            ref["sssp"] = got.copy()
-        assert np.array_equal(got, ref["sssp"]), name
-        out["sssp"][name] = {"ms": round(ms, 3), "gteps": round(e / ms / 1e6, 2)}
-    g_dir.set_tuning(variant=0)
+        for dname, pull_div in (("push_pull", 128), ("push_only", 1)):
+            g_dir.set_tuning(variant=var, pull_div=pull_div)
+            ms = tm.ms(sssp, 3)
+            e = g_dir.last_run_stats().edges_scanned
+            got = dist.cpu().numpy()
+            if "sssp" not in ref:
+                ref["sssp"] = got.copy()
+            assert np.array_equal(got, ref["sssp"]), (name, dname)
+            out["sssp"][name + "/" + dname] = {"ms": round(ms, 3),
+                                               "gteps": round(e / ms / 1e6, 2)}
+    g_dir.set_tuning(variant=0, pull_div=128)
     # The same graphs with the vertex labels scrambled (seeded permutation):
     # results are the unscrambled ones, permuted.
     perm = gg.label_permutation(n)
