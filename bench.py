@@ -224,6 +224,7 @@ def main():
           for k in ("bfs", "sssp", "pr", "tc")}
     acc = {k: 0.0 for k in ev}
     edges = {}
+    steps_sssp = [0]
 
     def step(record: bool):
         e = ev["bfs"]
@@ -244,6 +245,7 @@ def main():
         if record:
             e[1].record()
         edges["sssp"] = g_dir.last_run_stats().edges_scanned
+        steps_sssp[0] = g_dir.last_run_stats().supersteps
         e = ev["pr"]
         if record:
             e[0].record()
@@ -282,6 +284,15 @@ def main():
         ms = acc[k] / args.steps
         programs[k] = {"ms": round(ms, 4), "edges": int(edges[k]),
                        "gteps": round(edges[k] / (ms * 1e-3) / 1e9, 2)}
+    # algorithmic bytes of the BFS and SSSP runs (the survey's formulas):
+    # BFS 4 m_sym + 20 N; SSSP 8 B per relaxed edge (index + weight) plus
+    # 12 B per vertex and superstep
+    alg = {"bfs": 4 * m_sym + 20 * n,
+           "sssp": 8 * edges["sssp"] + 12 * n * steps_sssp[0]}
+    for k, b in alg.items():
+        gbs = b / (acc[k] / args.steps * 1e-3) / 1e9
+        programs[k].update({"algorithmic_bytes": int(b), "algorithmic_gbs": round(gbs, 1),
+                            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
     # First-call costs: the triangle count's work plan (built on the device)
     # and the PageRank pull layout, each from a released graph, next to the
     # warm per-call times above.
@@ -590,8 +601,7 @@ def measure_paper_workloads(gm, gg, torch, np, tm):
     for name, (n, s, d) in (("sssp_rmat24_a50", gg.rmat(24, a=0.50, b=0.10, c=0.10)),
                             ("sssp_grid2048", gg.grid2d(2048, 2048))):
         w = gg.weights_u32(s, d)
-        g = gm.Graph.from_coo(n, s, d, w=w, prep=gm.GM_PREP_DROP_SELF_LOOPS,
-                              layouts=gm.GM_LAYOUT_OUT)
+        g = gm.Graph.from_coo(n, s, d, w=w, prep=gm.GM_PREP_DROP_SELF_LOOPS)
         dist = torch.empty(n, dtype=torch.int32, device=dev)
         info = {}
 
@@ -600,9 +610,11 @@ def measure_paper_workloads(gm, gg, torch, np, tm):
             dist[0] = 0
             info["it"] = gm.run_vertex_program(g, gm.GM_PROG_SSSP, root, -1, dist)
             info["edges"] = g.last_run_stats().edges_scanned
+            info["pull"] = g.last_run_stats().pull_supersteps
 
         ms = tm.ms(run, 3)
         res[name] = {"n": n, "m": g.m, "ms": round(ms, 3), "supersteps": info["it"],
+                     "pull_supersteps": info["pull"],
                      "us_per_superstep": round(1e3 * ms / max(info["it"], 1), 2),
                      "edges_relaxed": int(info["edges"]),
                      "gteps": round(info["edges"] / (ms * 1e-3) / 1e9, 2),

@@ -269,8 +269,9 @@ gm_status gm_graph_release(gm_graph g);
  * BFS and SSSP synchronise `stream` after batches of supersteps (the
  * first of superstep_batch; each later one twice as long, at most 64, while
  * the frontier holds up, back to superstep_batch once it fell below half
- * of its size during a batch; the supersteps after the frontier empties do
- * nothing); PageRank is asynchronous.
+ * of its size from one superstep to the next at the end of a batch; the
+ * supersteps after the frontier empties do nothing); PageRank is
+ * asynchronous.
  */
 gm_status gm_run_vertex_program(gm_graph g, const gm_program* prog, const gm_frontier* frontier,
                                 int32_t max_iters, void* vprop, int32_t* active_out,
@@ -513,7 +514,8 @@ typedef struct gm_tuning {
   uint32_t superstep_batch; /* BFS/SSSP: supersteps enqueued before the first
                                host check of the frontier; each later batch is
                                twice as long, up to 64, unless the frontier
-                               fell below half during the last (1..64; 4) */
+                               fell below half at the end of the last
+                               (1..64; 4) */
   uint32_t push_blocks;     /* workgroups of the push kernels, plain and batched
                                SSSP (64..65536; 2048) */
   uint32_t ppr_chunk;       /* batched PPR: in-edges per work item (64..65536; 128) */

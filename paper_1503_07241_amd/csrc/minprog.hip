@@ -181,6 +181,30 @@ __host__ __device__ inline bool use_pull(const Ctl& c, int kind, bool pull_ok, i
   return false;
 }
 
+// Whether the batch after superstep `c` (preceded by `p`) may pull: its
+// frontier (vertices for BFS, out-edges for SSSP) is within a factor 8 of
+// the pull threshold, or within 64 and still growing by more than a
+// quarter per superstep. A batch that may not pull is enqueued without pull
+// kernels (every superstep of it pushes, with the same results).
+inline bool near_pull(const Ctl& c, const Ctl& p, int kind, int64_t n, int64_t m,
+                      uint32_t pull_div) {
+  uint64_t x, xp;
+  double thr;
+  if (kind == GM_PROG_BFS) {
+    x = c.packed >> 32;
+    xp = p.packed >> 32;
+    thr = (double)(n / (int64_t)pull_div);
+  } else if (kind == GM_PROG_SSSP) {
+    x = (uint32_t)c.packed;
+    xp = (uint32_t)p.packed;
+    thr = 64.0 * (double)m / (double)pull_div;
+  } else {
+    return false;
+  }
+  const bool growing = 4 * x > 5 * xp;
+  return 8.0 * (double)x > thr || (growing && 64.0 * (double)x > thr);
+}
+
 template <int kKind>
 __device__ inline uint32_t process(uint32_t msg, uint32_t w) {
   if constexpr (kKind == GM_PROG_DEGREE) {
@@ -1752,18 +1776,22 @@ static int32_t run_supersteps(gm_graph g, Workspace* ws, int kind, const View& v
   int32_t iters = 0;
   RunStats st{};
   bool done = !have_frontier && kind != GM_PROG_DEGREE;  // an empty bitmap: one SEND
+  uint64_t prev_cnt = 0, last_cnt = 0;  // frontier sizes of the last two supersteps
+  bool near = false;  // the next batch may pull (near_pull of its last two supersteps)
+  Ctl prev_ctl{0, 0, 0}, last_ctl{0, 0, 0};
   while (!done) {
     int32_t nb = batch;
     if (max_iters > 0 && max_iters - iters < nb) nb = max_iters - iters;
     if (nb > kMaxCtl) nb = kMaxCtl;
     start_batch(ws, s);
+    View bv = view;
+    bv.pull_ok = view.pull_ok && (iters == 0 || near);
     for (int32_t b = 0; b < nb; ++b) {
-      enqueue_superstep(g, ws, kind, view, ws->ctl + b, cur, prop, s);
+      enqueue_superstep(g, ws, kind, bv, ws->ctl + b, cur, prop, s);
       cur ^= 1;
     }
     GM_HIP(hipMemcpyAsync(ws->host_ctl, ws->ctl, nb * sizeof(Ctl), hipMemcpyDeviceToHost, s));
     GM_HIP(hipStreamSynchronize(s));
-    uint64_t first_cnt = 0, last_cnt = 0;  // frontier sizes at the batch's ends
     for (int32_t b = 0; b < nb; ++b) {
       const Ctl& c = ws->host_ctl[b];
       const uint64_t cnt = c.packed >> 32;
@@ -1771,24 +1799,28 @@ static int32_t run_supersteps(gm_graph g, Workspace* ws, int kind, const View& v
         done = true;
         break;
       }
-      if (b == 0) first_cnt = cnt;
+      prev_cnt = last_cnt;
       last_cnt = cnt;
       ++iters;
       st.edges_scanned += (uint32_t)c.packed;
-      const bool pulled = use_pull(c, kind, view.pull_ok, n, g->m, g->tune.pull_div);
+      prev_ctl = last_ctl;
+      last_ctl = c;
+      const bool pulled = use_pull(c, kind, bv.pull_ok, n, g->m, g->tune.pull_div);
       if (pulled)
         ++st.pull_supersteps;
       else
         ++st.push_supersteps;
     }
     if (max_iters > 0 && iters >= max_iters) done = true;
+    near = near_pull(last_ctl, prev_ctl, kind, n, g->m, g->tune.pull_div);
     // A run whose frontier holds up is long: each further batch is twice as
     // long, so a run of S supersteps waits for the host about log2(S) times,
-    // not S / batch. One whose frontier fell below half during the batch is
-    // ending: the next batch goes back to the first length, since every
-    // superstep enqueued after the frontier empties still costs its launches.
+    // not S / batch. One whose frontier fell below half from one superstep to
+    // the next at the end of the batch is ending: the next batch goes back to
+    // the first length, since every superstep enqueued after the frontier
+    // empties still costs its launches.
     const int32_t batch0 = std::max<int32_t>(1, (int32_t)g->tune.superstep_batch);
-    batch = 2 * last_cnt < first_cnt ? batch0 : std::min<int32_t>(2 * batch, kMaxCtl);
+    batch = 2 * last_cnt < prev_cnt ? batch0 : std::min<int32_t>(2 * batch, kMaxCtl);
   }
   // bits[cur] holds the frontier left after the last superstep (empty when
   // the program converged); report it and leave the workspace cleared (the
