@@ -96,12 +96,12 @@ struct PullTiles {
   uint32_t* rows = nullptr;
   uint32_t* tile_row = nullptr;
   int64_t ntiles = 0, nrows = 0;
-  // LDS hot set: the hot_n sources with the most out-edges (hot_ids); tidx is
-  // the adjacency's index array with each of their entries replaced by
-  // (slot | kHotTag), padded to whole tiles
+  // The message snapshot is kept in rank order: vertices by decreasing
+  // out-degree (vert_of[rank] = vertex), so that the most gathered messages
+  // share cache lines and the hot_n first ranks are the LDS hot set; tidx is
+  // the adjacency's index array in ranks, padded to whole tiles with 0
+  uint32_t* vert_of = nullptr;
   int32_t* tidx = nullptr;
-  int32_t* hot_ids = nullptr;
-  uint32_t* hot_snap = nullptr;  // per pull superstep: their messages
   int hot_n = 0;
   int cus = 0;  // compute units (one 1,024-lane workgroup each)
   ~PullTiles() {
@@ -109,8 +109,7 @@ struct PullTiles {
     dfree(rows);
     dfree(tile_row);
     dfree(tidx);
-    dfree(hot_ids);
-    dfree(hot_snap);
+    dfree(vert_of);
   }
 };
 
@@ -367,7 +366,7 @@ __global__ __launch_bounds__(kThreads) void send_write(
     const SendInfo* __restrict__ info, int32_t* __restrict__ q, uint32_t* __restrict__ qmsg,
     uint32_t* __restrict__ qbeg, uint32_t* __restrict__ qest, Ctl* __restrict__ ctl, int kind,
     int64_t m, bool pull_ok, uint32_t pull_div, uint32_t* __restrict__ snap,
-    const int32_t* __restrict__ hot_ids, int hot_n, uint32_t* __restrict__ hot_snap) {
+    const uint32_t* __restrict__ vert_of) {
   __shared__ uint32_t sh[2 * kWaves];
   __shared__ uint32_t red[4][kWaves];
   // The superstep's totals (all workgroups: the control record and the
@@ -412,20 +411,18 @@ __global__ __launch_bounds__(kThreads) void send_write(
   c.packed = ((unsigned long long)call << 32) | eall;
   if (blockIdx.x == 0 && threadIdx.x == 0) *ctl = c;
   // A pull superstep reads no queue: the frontier bits, the control record
-  // and, for SSSP, the message snapshot (snap[v] = x_v for a frontier vertex,
-  // the max value, which PROCESS keeps, for any other; hot_snap the same for
-  // the hot set, contiguous), written here instead.
+  // and, for SSSP, the message snapshot in rank order (snap[r] = x_v of
+  // v = vert_of[r] for a frontier vertex, the max value, which PROCESS keeps,
+  // for any other), written here instead (this workgroup: the ranks of its
+  // range of words).
   if (use_pull(c, kind, pull_ok, n, m, pull_div)) {
     if (snap) {
       int64_t wb, we;
       send_range(words, chunk, &wb, &we);
-      const int64_t ve = we * 32 < n ? we * 32 : n;
-      for (int64_t v = wb * 32 + threadIdx.x; v < ve; v += kThreads)
-        snap[v] = (bits[v >> 5] >> (v & 31)) & 1u ? prop[v] : 0xFFFFFFFFu;
-      for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < hot_n;
-           i += (int64_t)gridDim.x * kThreads) {
-        const int32_t v = hot_ids[i];
-        hot_snap[i] = (bits[v >> 5] >> (v & 31)) & 1u ? prop[v] : 0xFFFFFFFFu;
+      const int64_t re = we * 32 < n ? we * 32 : n;
+      for (int64_t r = wb * 32 + threadIdx.x; r < re; r += kThreads) {
+        const uint32_t v = vert_of[r];
+        snap[r] = (bits[v >> 5] >> (v & 31)) & 1u ? prop[v] : 0xFFFFFFFFu;
       }
     }
     return;
@@ -760,10 +757,12 @@ __device__ inline void apply_min(uint32_t v, uint32_t y, uint32_t* prop, uint32_
 // in-edges are skipped by a list of the rows that have some); a wavefront
 // takes a tile in four rounds of 256 edges, four consecutive ones per lane
 // (16-byte index and weight loads, all sixteen gathers in flight at once).
-// Each workgroup (one per compute unit) first copies the messages of the
-// hot set (the sources with the most out-edges, which most in-edges name)
-// to LDS; an edge whose index carries kHotTag reads its message there (its
-// global gather is redirected to snap[0], one line for all such lanes).
+// Sources are numbered by rank (decreasing out-degree), the snapshot held in
+// that order: each workgroup (one per compute unit) first copies the
+// messages of the first hot_n ranks, which most in-edges name, to LDS; an
+// edge from such a source reads its message there (its global gather is
+// redirected to snap[0], one line for all such lanes), and the next most
+// gathered messages share cache lines.
 // Each lane takes the min of its edges per row, a segmented scan over the
 // wavefront joins the lanes, and the lane holding a row's last edge applies
 // it: with a plain store if the row began in the tile (no other wavefront
@@ -773,13 +772,12 @@ constexpr int64_t kPullTile = 1024;
 constexpr int kPullThreads = 1024;
 constexpr int kPullWaves = kPullThreads / 64;
 constexpr int kPullHotMax = 40960;  // hot messages in LDS (160 KB)
-constexpr uint32_t kHotTag = 0x80000000u;
 __global__ __launch_bounds__(kPullThreads) void pull_min_tiles(
     const Ctl* __restrict__ ctlp, int64_t n, int64_t m, bool pull_ok, uint32_t pull_div,
     const int32_t* __restrict__ idx, const uint32_t* __restrict__ w,
     const uint32_t* __restrict__ starts, const uint32_t* __restrict__ rows,
     const uint32_t* __restrict__ tile_row, int64_t ntiles, int64_t nrows,
-    const uint32_t* __restrict__ snap, const uint32_t* __restrict__ hot_snap, int hot_n,
+    const uint32_t* __restrict__ snap, int hot_n,
     uint32_t* prop, uint32_t* next) {
   extern __shared__ uint32_t hot[];  // hot_n messages
   if (!use_pull(*ctlp, GM_PROG_SSSP, pull_ok, n, m, pull_div)) return;
@@ -788,8 +786,8 @@ __global__ __launch_bounds__(kPullThreads) void pull_min_tiles(
   {
     const int n4 = hot_n >> 2;
     for (int i = threadIdx.x; i < n4; i += kPullThreads)
-      reinterpret_cast<v4u*>(hot)[i] = reinterpret_cast<const v4u*>(hot_snap)[i];
-    for (int i = 4 * n4 + threadIdx.x; i < hot_n; i += kPullThreads) hot[i] = hot_snap[i];
+      reinterpret_cast<v4u*>(hot)[i] = reinterpret_cast<const v4u*>(snap)[i];
+    for (int i = 4 * n4 + threadIdx.x; i < hot_n; i += kPullThreads) hot[i] = snap[i];
     __syncthreads();
   }
   const int lane = threadIdx.x & 63;
@@ -821,9 +819,9 @@ __global__ __launch_bounds__(kPullThreads) void pull_min_tiles(
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const uint32_t sv = (uint32_t)src[v][q];
-        const bool in_lds = (sv & kHotTag) != 0u;
+        const bool in_lds = sv < (uint32_t)hot_n;
         const uint32_t g = snap[in_lds ? 0u : sv];
-        const uint32_t l = hot[in_lds ? sv & ~kHotTag : 0u];
+        const uint32_t l = hot[in_lds ? sv : 0u];
         cand[v][q] = in_lds ? l : g;
       }
 #pragma unroll
@@ -871,29 +869,16 @@ __global__ __launch_bounds__(kPullThreads) void pull_min_tiles(
   }
 }
 
-// Tagged index array of the pull: tidx[e] = slot | kHotTag for a hot source,
-// the source otherwise; 0 past m (to the end of the last tile).
+// Index array of the pull in ranks: tidx[e] = rank_of[idx[e]]; 0 past m (to
+// the end of the last tile).
 __global__ void pull_tag(const int32_t* __restrict__ idx, int64_t m, int64_t mpad,
-                         const int32_t* __restrict__ slot_of, int32_t* __restrict__ tidx) {
+                         const uint32_t* __restrict__ rank_of, int32_t* __restrict__ tidx) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < mpad;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int32_t v = 0;
-    if (e < m) {
-      const int32_t u = idx[e];
-      const int32_t sl = slot_of[u];
-      v = sl >= 0 ? (int32_t)((uint32_t)sl | kHotTag) : u;
-    }
-    tidx[e] = v;
-  }
+       e += (int64_t)gridDim.x * blockDim.x)
+    tidx[e] = e < m ? (int32_t)rank_of[idx[e]] : 0;
 }
 
-__global__ void pull_slots(const int32_t* __restrict__ hot_ids, int hot_n,
-                           int32_t* __restrict__ slot_of) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < hot_n; i += gridDim.x * blockDim.x)
-    slot_of[hot_ids[i]] = i;
-}
-
-// Sort key of a vertex for the hot set: most out-edges first, ties by id.
+// Sort key of a vertex for its rank: most out-edges first, ties by id.
 __global__ void pull_hot_keys(const uint32_t* __restrict__ push_off, int64_t n,
                               unsigned long long* __restrict__ key) {
   for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
@@ -903,10 +888,14 @@ __global__ void pull_hot_keys(const uint32_t* __restrict__ push_off, int64_t n,
   }
 }
 
-__global__ void pull_hot_ids(const unsigned long long* __restrict__ key, int hot_n,
-                             int32_t* __restrict__ hot_ids) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < hot_n; i += gridDim.x * blockDim.x)
-    hot_ids[i] = (int32_t)(uint32_t)key[i];
+__global__ void pull_ranks(const unsigned long long* __restrict__ key, int64_t n,
+                           uint32_t* __restrict__ vert_of, uint32_t* __restrict__ rank_of) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t v = (uint32_t)key[i];
+    vert_of[i] = v;
+    rank_of[v] = (uint32_t)i;
+  }
 }
 
 // Layout of a pull over the adjacency off/idx/w (n rows, m edges): the
@@ -1355,8 +1344,8 @@ void ensure_pull_tiles(gm_graph g, Workspace* ws, const Adj& pl, const uint32_t*
     GM_HIP(hipDeviceGetAttribute(&pt->cus, hipDeviceAttributeMultiprocessorCount, dev));
     GM_HIP(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     pt->hot_n = (int)std::min<int64_t>({(int64_t)kPullHotMax, n, (int64_t)lds_max / 4});
-    pt->hot_ids = dalloc<int32_t>(std::max(pt->hot_n, 1));
-    pt->hot_snap = dalloc<uint32_t>(std::max(pt->hot_n, 1));
+    pt->vert_of = dalloc<uint32_t>(n);
+    DevBuf<uint32_t> rank_of(n);
     {
       DevBuf<unsigned long long> k1(n), k2(n);
       pull_hot_keys<<<blocks_for(n), kThreads, 0, s>>>(push_off, n, k1.p);
@@ -1366,21 +1355,16 @@ void ensure_pull_tiles(gm_graph g, Workspace* ws, const Adj& pl, const uint32_t*
       GM_HIP(rocprim::radix_sort_keys(nullptr, sb, kb, (size_t)n, 0, 64, s));
       tmp = dmalloc(sb);
       GM_HIP(rocprim::radix_sort_keys(tmp, sb, kb, (size_t)n, 0, 64, s));
-      pull_hot_ids<<<blocks_for(pt->hot_n), kThreads, 0, s>>>(kb.current(), pt->hot_n,
-                                                              pt->hot_ids);
+      pull_ranks<<<blocks_for(n), kThreads, 0, s>>>(kb.current(), n, pt->vert_of, rank_of.p);
       GM_HIP(hipGetLastError());
       GM_HIP(hipStreamSynchronize(s));
       dfree(tmp);
       tmp = nullptr;
     }
     {
-      DevBuf<int32_t> slot_of(n);
-      fill_kernel<<<blocks_for(n), kThreads, 0, s>>>(reinterpret_cast<uint32_t*>(slot_of.p), n,
-                                                     0xFFFFFFFFu);
-      pull_slots<<<blocks_for(pt->hot_n), kThreads, 0, s>>>(pt->hot_ids, pt->hot_n, slot_of.p);
       const int64_t mpad = pt->ntiles * kPullTile;
       pt->tidx = dalloc<int32_t>(std::max<int64_t>(mpad, 1));
-      pull_tag<<<blocks_for(mpad), kThreads, 0, s>>>(pl.idx, m, mpad, slot_of.p, pt->tidx);
+      pull_tag<<<blocks_for(mpad), kThreads, 0, s>>>(pl.idx, m, mpad, rank_of.p, pt->tidx);
       GM_HIP(hipGetLastError());
       GM_HIP(hipStreamSynchronize(s));
     }
@@ -1497,7 +1481,7 @@ void enqueue_superstep(gm_graph g, Workspace* ws, int kind, const View& view, Ct
   send_write<<<(unsigned)nbk, kThreads, 0, s>>>(
       ws->bits[cur], words, g->n, chunk, prop, a.off, ws->sinfo, ws->q, ws->qmsg, ws->qbeg,
       ws->qest, c, kind, m, pull_ok, pull_div, pt ? ws->snap : nullptr,
-      pt ? pt->hot_ids : nullptr, pt ? pt->hot_n : 0, pt ? pt->hot_snap : nullptr);
+      pt ? pt->vert_of : nullptr);
   if (kind != GM_PROG_DEGREE && (g->tune.variant & GM_VARIANT_VERTEX_PUSH)) {
     if (kind == GM_PROG_SSSP)
       push_vertex_kernel<GM_PROG_SSSP><<<blocks_for(n), kThreads, 0, s>>>(
@@ -1527,7 +1511,7 @@ void enqueue_superstep(gm_graph g, Workspace* ws, int kind, const View& view, Ct
     pull_min_tiles<<<(unsigned)std::max(pt->cus, 1), kPullThreads,
                      (size_t)pt->hot_n * sizeof(uint32_t), s>>>(
         c, n, m, pull_ok, pull_div, pt->tidx, pl.w, pt->starts, pt->rows, pt->tile_row,
-        pt->ntiles, pt->nrows, ws->snap, pt->hot_snap, pt->hot_n, prop, ws->bits[cur ^ 1]);
+        pt->ntiles, pt->nrows, ws->snap, pt->hot_n, prop, ws->bits[cur ^ 1]);
   }
   GM_HIP(hipGetLastError());
 }
