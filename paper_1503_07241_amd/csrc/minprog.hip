@@ -9,7 +9,9 @@
 //                 x_u = prop(u) (SEND_MESSAGE), its first out-edge, and the
 //                 exclusive prefix sum of out-degrees over the queue. Counts,
 //                 edge totals and the smallest/largest message go to a small
-//                 per-superstep control record.
+//                 per-superstep control record, which also decides the
+//                 superstep's direction; a pull superstep needs no queue (an
+//                 SSSP pull gets a dense message snapshot instead).
 //   push_kernel   walks the out-edges of the queued vertices (the columns of
 //                 G^T present in x, Alg. 1). The concatenated edge lists are
 //                 cut into equal ranges, one per wavefront, so hubs and
@@ -28,10 +30,13 @@
 //                 to a dense snapshot of the frontier's messages (the max
 //                 value for inactive sources), with no atomics on the edges.
 // The push and pull kernels of a superstep are both launched; each reads the
-// control record written by send_write and only the selected one works.
-// Messages are snapshotted before the product and min is exact and
-// order-free, so every superstep leaves exactly the state of Alg. 2. Only
-// non-returning atomics are used on the hot path.
+// control record written by send_write and only the selected one works (a
+// batch of supersteps the host expects to push only launches no pull
+// kernel). Messages are snapshotted before the product and min is exact and
+// order-free, so every superstep leaves exactly the state of Alg. 2. The
+// push's atomic min returns the old value, which tells whether the target
+// changed; the pull applies a row with a plain store when one wavefront
+// holds all of its in-edges.
 #include <algorithm>
 #include <cstring>
 
