@@ -520,7 +520,7 @@ typedef struct gm_tuning {
                                SSSP (64..65536; 2048) */
   uint32_t ppr_chunk;       /* batched PPR: in-edges per work item (64..65536; 128) */
   uint32_t tc_wave_max;     /* TC: owners with at most this many in-neighbours
-                               use a per-wavefront table (64..1024; 1024) */
+                               use a per-wavefront table (64..512; 512) */
   uint32_t tc_wave_work;    /* TC: partner elements per wavefront work item
                                (256..2^24; 2^14) */
   uint32_t tc_block_work;   /* TC: partner elements per workgroup work item

@@ -71,7 +71,7 @@ struct Tuning {
   // batched PPR: in-edges per work item
   uint32_t ppr_chunk = 128;
   // TC: owners whose in-list is at most this long use a per-wavefront table
-  uint32_t tc_wave_max = 1024;
+  uint32_t tc_wave_max = 512;
   // TC: partner-list elements per wavefront / workgroup work item
   uint32_t tc_wave_work = 1u << 14;
   uint32_t tc_block_work = 1u << 23;

@@ -188,7 +188,7 @@ gm_status check_tuning(const gm_tuning& t) {
            {"superstep_batch", t.superstep_batch, {1, 64}},
            {"push_blocks", t.push_blocks, {64, 65536}},
            {"ppr_chunk", t.ppr_chunk, {64, 65536}},
-           {"tc_wave_max", t.tc_wave_max, {64, 1024}},
+           {"tc_wave_max", t.tc_wave_max, {64, 512}},
            {"tc_wave_work", t.tc_wave_work, {256, 1u << 24}},
            {"tc_block_work", t.tc_block_work, {256, 1u << 26}},
            {"pr_hot", t.pr_hot, {0, 40960}},
@@ -681,7 +681,7 @@ gm_status gm_autotune(gm_graph g, const gm_program* prog, int32_t batched, const
     } else if (!batched && kind == GM_PROG_PAGERANK) {
       params.push_back({&Tuning::pr_hot, {0, 8192, 16384, 32768, 40960}});
     } else if (kind == GM_PROG_TC) {
-      params.push_back({&Tuning::tc_wave_max, {256, 512, 1024}});
+      params.push_back({&Tuning::tc_wave_max, {128, 256, 512}});
       params.push_back({&Tuning::tc_wave_work, {1u << 12, 1u << 14, 1u << 16}});
       params.push_back({&Tuning::tc_block_work, {1u << 21, 1u << 23, 1u << 25}});
     }

@@ -36,7 +36,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr uint32_t kWaveMax = 1024;          // owners with |in(x)| <= this: LDS table per wavefront
+constexpr uint32_t kWaveMax = 512;          // owners with |in(x)| <= this: LDS table per wavefront
 constexpr uint32_t kCreditPartner = 0x80000000u;  // partner entry flag: credit goes to it
 constexpr int32_t kEmpty = -1;
 
@@ -44,7 +44,7 @@ constexpr int32_t kEmpty = -1;
 // LDS tables per workgroup of growing size (small tables leave room for
 // more resident wavefronts); longer in-lists are cut into pieces of the
 // largest table size, each piece an owner of its own whose partners stream
-// only their elements in the piece's id range. A table has at least 2 d
+// only their elements in the piece's id range. A table has at least 4 d
 // slots.
 enum TcKind { kWaveTable, kBlockTable, kSplitTable };
 struct TcClass {
@@ -54,14 +54,14 @@ struct TcClass {
   TcKind kind;
 };
 constexpr int kClassesTc = 7;
-constexpr TcClass kTcClass[kClassesTc] = {{256, 512, 256, kWaveTable},          // 2 KB per wavefront
+constexpr TcClass kTcClass[kClassesTc] = {{128, 512, 256, kWaveTable},          // 2 KB per wavefront
                                           {kWaveMax, 2048, 256, kWaveTable},    // 8 KB per wavefront
-                                          {2048, 4096, 512, kBlockTable},       // 16 KB
-                                          {4096, 8192, 512, kBlockTable},       // 32 KB
-                                          {8192, 16384, 512, kBlockTable},      // 64 KB
-                                          {16384, 32768, 1024, kBlockTable},    // 128 KB
+                                          {1024, 4096, 512, kBlockTable},       // 16 KB
+                                          {2048, 8192, 512, kBlockTable},       // 32 KB
+                                          {4096, 16384, 512, kBlockTable},      // 64 KB
+                                          {8192, 32768, 1024, kBlockTable},     // 128 KB
                                           {UINT32_MAX, 32768, 1024, kSplitTable}};
-constexpr uint32_t kPieceMax = 16384;  // in-list entries per piece of a split owner
+constexpr uint32_t kPieceMax = 8192;  // in-list entries per piece of a split owner
 
 // A work item: owner x and a range of its partner list.
 struct Item {
@@ -127,8 +127,9 @@ __device__ inline uint32_t bucket_shift(uint32_t bmask) { return 32u - (uint32_t
 
 // Tables are buckets of 4 slots (one 16-byte LDS read); a key lives in its
 // home bucket or, when that is full, in the next buckets (linear probing
-// over buckets). At most half of the slots are used, so most lookups read
-// one bucket.
+// over buckets). At most a quarter of the slots are used, so that a home
+// bucket is full in about 2% of lookups (in up to 16% at half the slots
+// used, where the overflow walk cost a quarter of all vector instructions).
 __device__ inline void table_insert(int32_t* T, uint32_t bmask, int32_t key) {
   uint32_t b = home_bucket(key, bucket_shift(bmask));
   for (;;) {
@@ -341,11 +342,11 @@ __device__ __forceinline__ unsigned long long walk_partners(const int4* T4, uint
   return own;
 }
 
-// Bucket mask of the table of an owner with d in-neighbours: at least twice
-// as many slots as keys, at least 16 buckets.
+// Bucket mask of the table of an owner with d in-neighbours: at least four
+// times as many slots as keys, at least 16 buckets.
 __device__ __host__ inline uint32_t table_buckets(uint32_t d) {
   uint32_t slots = 64;
-  while (slots < 2 * d) slots <<= 1;
+  while (slots < 4 * d) slots <<= 1;
   return slots / 4;
 }
 
@@ -1053,7 +1054,7 @@ void run_triangle_count(gm_graph g, unsigned long long* counts, unsigned long lo
                     kTcClass[4].slots == 16384 && kTcClass[5].slots == 32768 &&
                     kTcClass[5].threads == 1024 && kTcClass[6].kind == kSplitTable &&
                     kTcClass[6].slots == 32768 && kTcClass[6].threads == 1024 &&
-                    2 * kPieceMax <= kTcClass[6].slots,
+                    4 * kPieceMax <= kTcClass[6].slots,
                 "kernel instances below follow the class table");
   // Each class on its own stream, forked from s and joined back: the
   // launches run side by side (counts are only added to, atomically).
