@@ -395,74 +395,36 @@ void ensure_pull_schedule(gm_graph g, hipStream_t st) {
   if (dense(g)) return;
   const int64_t n = g->n, m = g->m;
   if (n >= (int64_t)1 << 30) throw Unsupported{"PageRank pull takes fewer than 2^30 vertices"};
-  // Counting sort of the vertices by decreasing in-degree (ties by label).
-  std::vector<uint32_t> off(n + 1);
-  GM_HIP(hipMemcpyAsync(off.data(), g->in_off, (n + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                        st));
-  GM_HIP(hipStreamSynchronize(st));
-  const uint32_t maxd = (uint32_t)g->max_in;
-  std::vector<int64_t> cnt((size_t)maxd + 2, 0);
-  for (int64_t v = 0; v < n; ++v) ++cnt[maxd - (off[v + 1] - off[v])];
-  int64_t acc = 0;
-  for (size_t i = 0; i < cnt.size(); ++i) {
-    const int64_t c = cnt[i];
-    cnt[i] = acc;
-    acc += c;
-  }
-  std::vector<int32_t> old_of(n), new_of(n);
-  for (int64_t v = 0; v < n; ++v) {
-    const int64_t pos = cnt[maxd - (off[v + 1] - off[v])]++;
-    old_of[pos] = (int32_t)v;
-    new_of[v] = (int32_t)pos;
-  }
-  std::vector<uint32_t> noff(n + 1);
-  noff[0] = 0;
-  for (int64_t i = 0; i < n; ++i) {
-    const int32_t v = old_of[i];
-    noff[i + 1] = noff[i] + (off[v + 1] - off[v]);
-  }
   Dense* d = new Dense();
   g->pr_sched = d;
   try {
     d->n = n;
     d->m = m;
-    // Rows with in-edges come first (decreasing in-degree); tiles of kTile
-    // edges, the index stream padded to whole tiles.
-    const TileLayout L = tile_layout(noff, n, m);
+    // Vertices relabelled by decreasing in-degree (ties by label): rows with
+    // in-edges come first; tiles of kTile edges, the index stream padded to
+    // whole tiles.
+    const DeviceLayout L = build_device_layout(g->in_off, n, m, (uint32_t)g->max_in, st);
+    d->new_of = L.new_of;
+    d->old_of = L.old_of;
+    d->roff = L.noff;
+    d->starts = L.starts;
+    d->tile_row = L.tile_row;
+    d->cross = L.cross;
     d->rows = L.rows;
     d->ntiles = L.ntiles;
-    d->ncross = (int64_t)L.cross.size();
+    d->ncross = L.ncross;
     const int64_t ntiles = L.ntiles, mpad = L.mpad;
-    const std::vector<uint32_t>& starts = L.starts;
-    const std::vector<uint32_t>& tile_row = L.tile_row;
-    const std::vector<Cross>& cross = L.cross;
     int dev = 0;
     GM_HIP(hipGetDevice(&dev));
     GM_HIP(hipDeviceGetAttribute(&d->cus, hipDeviceAttributeMultiprocessorCount, dev));
     GM_HIP(hipDeviceGetAttribute(&d->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    d->new_of = dalloc<int32_t>(n);
-    d->old_of = dalloc<int32_t>(n);
     d->idx = dalloc<int32_t>(mpad);
     d->inv_outdeg = dalloc<float>(n);
     d->x[0] = dalloc<float>(n);
     d->x[1] = dalloc<float>(n);
     d->pr = dalloc<float>(n);
-    d->starts = dalloc<uint32_t>(starts.size());
-    d->tile_row = dalloc<uint32_t>(tile_row.size());
     d->head = dalloc<double>(ntiles);
     d->tail = dalloc<double>(ntiles);
-    d->cross = dalloc<Cross>(cross.size());
-    d->roff = dalloc<uint32_t>(n + 1);
-    GM_HIP(hipMemcpyAsync(d->roff, noff.data(), (n + 1) * 4, hipMemcpyHostToDevice, st));
-    GM_HIP(hipMemcpyAsync(d->new_of, new_of.data(), n * 4, hipMemcpyHostToDevice, st));
-    GM_HIP(hipMemcpyAsync(d->old_of, old_of.data(), n * 4, hipMemcpyHostToDevice, st));
-    GM_HIP(hipMemcpyAsync(d->starts, starts.data(), starts.size() * 4, hipMemcpyHostToDevice, st));
-    if (ntiles > 0)
-      GM_HIP(hipMemcpyAsync(d->tile_row, tile_row.data(), tile_row.size() * 4,
-                            hipMemcpyHostToDevice, st));
-    if (!cross.empty())
-      GM_HIP(hipMemcpyAsync(d->cross, cross.data(), cross.size() * sizeof(Cross),
-                            hipMemcpyHostToDevice, st));
     if (mpad > m) GM_HIP(hipMemsetAsync(d->idx + m, 0, (mpad - m) * 4, st));
     gather_f32<<<blocks_for(n), kThreads, 0, st>>>(g->inv_outdeg, d->old_of, n, d->inv_outdeg);
     GM_HIP(hipGetLastError());

@@ -251,62 +251,40 @@ inline unsigned blocks_for(int64_t n) {
   return (unsigned)b;
 }
 
-template <class T>
-struct DevBuf {
-  T* p = nullptr;
-  explicit DevBuf(size_t n) : p(dalloc<T>(n)) {}
-  ~DevBuf() { dfree(p); }
-};
-
 VjpPlan* plan(gm_graph g) { return static_cast<VjpPlan*>(g->vjp_plan); }
 
 VjpPlan* ensure_plan(gm_graph g, hipStream_t st) {
   if (plan(g)) return plan(g);
   const int64_t n = g->n, m = g->m;
   if (n >= (int64_t)1 << 30) throw Unsupported{"PageRank reverse pass takes fewer than 2^30 vertices"};
-  std::vector<uint32_t> off(n + 1);
-  GM_HIP(hipMemcpyAsync(off.data(), g->out_off, (n + 1) * 4, hipMemcpyDeviceToHost, st));
-  GM_HIP(hipStreamSynchronize(st));
-  // Counting sort of the vertices by decreasing out-degree (ties by label).
-  const uint32_t maxd = (uint32_t)g->max_out;
-  std::vector<int64_t> cnt((size_t)maxd + 2, 0);
-  for (int64_t v = 0; v < n; ++v) ++cnt[maxd - (off[v + 1] - off[v])];
-  int64_t acc = 0;
-  for (auto& c : cnt) {
-    const int64_t t = c;
-    c = acc;
-    acc += t;
-  }
-  std::vector<int32_t> old_of(n), new_of(n);
-  for (int64_t v = 0; v < n; ++v) {
-    const int64_t pos = cnt[maxd - (off[v + 1] - off[v])]++;
-    old_of[pos] = (int32_t)v;
-    new_of[v] = (int32_t)pos;
-  }
-  std::vector<uint32_t> noff(n + 1);
-  noff[0] = 0;
-  for (int64_t i = 0; i < n; ++i) noff[i + 1] = noff[i] + (off[old_of[i] + 1] - off[old_of[i]]);
-  const TileLayout L = tile_layout(noff, n, m);
   VjpPlan* p = new VjpPlan();
   g->vjp_plan = p;
+  DeviceLayout L;
   try {
+    // Vertices relabelled by decreasing out-degree (ties by label), tiles of
+    // the relabelled out-adjacency.
+    L = build_device_layout(g->out_off, n, m, (uint32_t)g->max_out, st);
     p->n = n;
     p->m = m;
+    p->old_of = L.old_of;
+    p->starts = L.starts;
+    p->tile_row = L.tile_row;
+    p->cross = L.cross;
+    L.old_of = nullptr;  // owned by the plan from here on
+    L.starts = nullptr;
+    L.tile_row = nullptr;
+    L.cross = nullptr;
     p->rows = L.rows;
     p->ntiles = L.ntiles;
-    p->ncross = (int64_t)L.cross.size();
+    p->ncross = L.ncross;
     p->mpad = L.mpad;
     int dev = 0;
     GM_HIP(hipGetDevice(&dev));
     GM_HIP(hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, dev));
     GM_HIP(hipDeviceGetAttribute(&p->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    p->old_of = dalloc<int32_t>(n);
     p->idx = dalloc<int32_t>(L.mpad);
     p->ceid = dalloc<uint32_t>(m);
     p->inv_outdeg = dalloc<float>(n);
-    p->starts = dalloc<uint32_t>(L.starts.size());
-    p->tile_row = dalloc<uint32_t>(L.tile_row.size());
-    p->cross = dalloc<Cross>(L.cross.size());
     p->head = dalloc<double>(L.ntiles);
     p->tail = dalloc<double>(L.ntiles);
     p->wv = dalloc<float>(L.mpad);
@@ -314,19 +292,6 @@ VjpPlan* ensure_plan(gm_graph g, hipStream_t st) {
     p->cu = dalloc<float>(n + 1);
     p->abar[0] = dalloc<float>(n);
     p->abar[1] = dalloc<float>(n);
-    DevBuf<int32_t> dnew(n);
-    DevBuf<uint32_t> dnoff(n + 1);
-    GM_HIP(hipMemcpyAsync(p->old_of, old_of.data(), n * 4, hipMemcpyHostToDevice, st));
-    GM_HIP(hipMemcpyAsync(dnew.p, new_of.data(), n * 4, hipMemcpyHostToDevice, st));
-    GM_HIP(hipMemcpyAsync(dnoff.p, noff.data(), (n + 1) * 4, hipMemcpyHostToDevice, st));
-    GM_HIP(hipMemcpyAsync(p->starts, L.starts.data(), L.starts.size() * 4, hipMemcpyHostToDevice,
-                          st));
-    if (L.ntiles > 0)
-      GM_HIP(hipMemcpyAsync(p->tile_row, L.tile_row.data(), L.tile_row.size() * 4,
-                            hipMemcpyHostToDevice, st));
-    if (!L.cross.empty())
-      GM_HIP(hipMemcpyAsync(p->cross, L.cross.data(), L.cross.size() * sizeof(Cross),
-                            hipMemcpyHostToDevice, st));
     if (L.mpad > m) {
       GM_HIP(hipMemsetAsync(p->idx + m, 0, (L.mpad - m) * 4, st));
       GM_HIP(hipMemsetAsync(p->wv + m, 0, (L.mpad - m) * 4, st));
@@ -334,14 +299,17 @@ VjpPlan* ensure_plan(gm_graph g, hipStream_t st) {
     GM_HIP(hipMemsetAsync(p->cu, 0, (n + 1) * 4, st));
     gather_f32<<<blocks_for(n), kThreads, 0, st>>>(g->inv_outdeg, p->old_of, n, p->inv_outdeg);
     if (L.rows > 0)
-      build_edges<<<blocks_for(m), kThreads, 0, st>>>(g->out_off, g->out_idx, p->old_of, dnew.p,
-                                                       dnoff.p, L.rows, m, p->idx, p->ceid);
+      build_edges<<<blocks_for(m), kThreads, 0, st>>>(g->out_off, g->out_idx, p->old_of, L.new_of,
+                                                       L.noff, L.rows, m, p->idx, p->ceid);
     GM_HIP(hipGetLastError());
     GM_HIP(hipStreamSynchronize(st));
   } catch (...) {
+    (void)hipStreamSynchronize(st);
+    free_device_layout(&L);
     free_vjp_plan(g);
     throw;
   }
+  free_device_layout(&L);  // the new labels and offsets were only needed for the edges
   return p;
 }
 

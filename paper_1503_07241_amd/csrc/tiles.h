@@ -6,7 +6,6 @@
 #pragma once
 
 #include <cstdint>
-#include <vector>
 
 #include <hip/hip_runtime.h>
 
@@ -32,36 +31,27 @@ struct Cross {
   uint32_t pad;
 };
 
-// Host side of a tile layout, from the row offsets noff (n + 1 entries,
-// rows with edges first): the row-start bitmap (bit e for each row's first
-// edge, and bit m), the row holding each tile's first edge, the rows that
-// span tiles.
-struct TileLayout {
-  int64_t rows = 0, ntiles = 0, mpad = 0;
-  std::vector<uint32_t> starts, tile_row;
-  std::vector<Cross> cross;
+// A tile layout built on the device from the row offsets off (n + 1
+// entries) of an adjacency whose degrees are at most maxd: the vertices
+// relabelled by decreasing degree (ties by label), so that rows with edges
+// are the new labels [0, rows); their offsets noff (n + 1); the row-start
+// bitmap starts (bit noff[u] for every row with edges, and bit m; mpad / 32
+// + 1 words); the row holding each tile's first edge; the rows that span
+// tiles, in increasing order. The caller owns the arrays:
+// free_device_layout releases those still set.
+struct DeviceLayout {
+  int64_t rows = 0, ntiles = 0, mpad = 0, ncross = 0;
+  int32_t* old_of = nullptr;     // new label -> old label
+  int32_t* new_of = nullptr;     // old label -> new label
+  uint32_t* noff = nullptr;
+  uint32_t* starts = nullptr;
+  uint32_t* tile_row = nullptr;  // ntiles entries
+  Cross* cross = nullptr;        // ncross entries
 };
 
-inline TileLayout tile_layout(const std::vector<uint32_t>& noff, int64_t n, int64_t m) {
-  TileLayout L;
-  while (L.rows < n && noff[L.rows + 1] > noff[L.rows]) ++L.rows;
-  L.ntiles = (m + kTile - 1) / kTile;
-  L.mpad = L.ntiles * kTile;
-  L.starts.assign((size_t)(L.mpad / 32 + 1), 0u);
-  for (int64_t v = 0; v < L.rows; ++v) L.starts[noff[v] >> 5] |= 1u << (noff[v] & 31);
-  L.starts[(size_t)(m >> 5)] |= 1u << (m & 31);
-  L.tile_row.resize((size_t)L.ntiles);
-  int64_t v = 0;
-  for (int64_t t = 0; t < L.ntiles; ++t) {
-    while (noff[v + 1] <= (uint64_t)(t * kTile)) ++v;
-    L.tile_row[(size_t)t] = (uint32_t)v;
-  }
-  for (int64_t u = 0; u < L.rows; ++u) {
-    const uint32_t ta = (uint32_t)(noff[u] / kTile), tb = (uint32_t)((noff[u + 1] - 1) / kTile);
-    if (ta != tb) L.cross.push_back({(uint32_t)u, ta, tb, 0});
-  }
-  return L;
-}
+DeviceLayout build_device_layout(const uint32_t* off, int64_t n, int64_t m, uint32_t maxd,
+                                 hipStream_t st);
+void free_device_layout(DeviceLayout* L);
 
 // Copy of the first hot_n messages to LDS: all of a thread's 16-byte loads
 // are issued before the first store.

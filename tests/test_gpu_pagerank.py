@@ -83,13 +83,19 @@ TILE_CASES = [
     [1024],
     [5] * 3 + [1] * 7,
     [700, 324] + [3] * 341 + [1],
+    [5 * 1024 + 17],
+    [512] * 4,
+    list(np.sort(np.minimum((np.random.default_rng(3).pareto(1.2, 3000) * 3 + 1).astype(int),
+                            9000))[::-1]),
 ]
 
 
 @pytest.mark.parametrize("case", range(len(TILE_CASES)))
 def test_pagerank_tile_boundaries(case):
+    """The device-built layout (degree relabelling, row-start bitmap, first
+    row of each tile, rows spanning tiles) through the pull superstep."""
     degrees = TILE_CASES[case]
-    n, s, d = _rows_graph(degrees, 4000, seed=100 + case)
+    n, s, d = _rows_graph(degrees, max(4000, max(degrees) + 1), seed=100 + case)
     g = gm.Graph.from_coo(n, s, d)
     og = oracle.prepare(n, s, d)
     assert W.max_rel_err(run_pr(g, n), oracle.pagerank(og, 0.15, 20)) <= TOL
