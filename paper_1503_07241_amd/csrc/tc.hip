@@ -677,6 +677,22 @@ __global__ void plan_split_flags(const uint32_t* __restrict__ in_off,
               work_off[x + 1] > work_off[x];
 }
 
+// In-list and partner-list bounds of each split owner: in_off[x], in_off[x +
+// 1], work_off[x], work_off[x + 1] for owner x = owners[i], at out[4 i].
+__global__ void plan_split_bounds(const uint32_t* __restrict__ owners, int64_t nsplit,
+                                  const uint32_t* __restrict__ in_off,
+                                  const uint32_t* __restrict__ work_off,
+                                  uint32_t* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nsplit;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t x = owners[i];
+    out[4 * i] = in_off[x];
+    out[4 * i + 1] = in_off[x + 1];
+    out[4 * i + 2] = work_off[x];
+    out[4 * i + 3] = work_off[x + 1];
+  }
+}
+
 // One piece of a split owner: in(x) positions [tb, te) (absolute), ids
 // [lo, hi), partners [p0, p0 + np); its (partner, piece) pairs start at base.
 struct PieceSeg {
@@ -977,19 +993,19 @@ static TcPlan* ensure_plan(gm_graph g, hipStream_t s) {
         const int64_t nsplit =
             select_flagged(pool, sflag.as<uint8_t>(), n, sown.as<uint32_t>(), s);
         if (nsplit > 0) {
-          std::vector<uint32_t> owners(nsplit), io(2 * nsplit), wo(2 * nsplit);
+          std::vector<uint32_t> owners(nsplit), bnd(4 * nsplit);
+          Scratch sbnd(pool, nsplit * 16);
+          plan_split_bounds<<<plan_grid(nsplit), kPlanThreads, 0, s>>>(
+              sown.as<uint32_t>(), nsplit, g->in_off, work_off, sbnd.as<uint32_t>());
+          GM_HIP(hipGetLastError());
           GM_HIP(hipMemcpyAsync(owners.data(), sown.p, nsplit * 4, hipMemcpyDeviceToHost, s));
-          GM_HIP(hipStreamSynchronize(s));
-          for (int64_t i = 0; i < nsplit; ++i) {
-            GM_HIP(hipMemcpyAsync(&io[2 * i], g->in_off + owners[i], 8, hipMemcpyDeviceToHost, s));
-            GM_HIP(hipMemcpyAsync(&wo[2 * i], work_off + owners[i], 8, hipMemcpyDeviceToHost, s));
-          }
+          GM_HIP(hipMemcpyAsync(bnd.data(), sbnd.p, nsplit * 16, hipMemcpyDeviceToHost, s));
           GM_HIP(hipStreamSynchronize(s));
           std::vector<PieceSeg> segs;
           uint32_t base = 0;
           for (int64_t i = 0; i < nsplit; ++i) {
-            const uint32_t xb = io[2 * i], d = io[2 * i + 1] - xb;
-            const uint32_t p0 = wo[2 * i], np = wo[2 * i + 1] - p0;
+            const uint32_t xb = bnd[4 * i], d = bnd[4 * i + 1] - xb;
+            const uint32_t p0 = bnd[4 * i + 2], np = bnd[4 * i + 3] - p0;
             for (uint32_t tb = 0; tb < d; tb += kPieceMax) {
               const uint32_t te = std::min(d, tb + kPieceMax);
               if ((uint64_t)base + np > UINT32_MAX)
