@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cctype>
 #include <cerrno>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -92,7 +93,7 @@ gm_status read_entries(FILE* f, const char* path, const MtxHeader& h, std::vecto
     if (i < 1 || i > h.rows || j < 1 || j > h.cols)
       return fail(GM_EINVAL, "%s: entry %lld (%lld, %lld) outside the %lld x %lld matrix", path,
                   (long long)got + 1, i, j, (long long)h.rows, (long long)h.cols);
-    if (h.field == 1 && (v < 0 || v > 4294967295.0 || v != (double)(long long)v))
+    if (h.field == 1 && !(v >= 0 && v <= 4294967295.0 && v == std::floor(v)))  // NaN fails
       return fail(GM_EUNSUPPORTED, "%s: entry %lld: integer value %g is not a uint32", path,
                   (long long)got + 1, v);
     src->push_back((int32_t)(i - 1));
