@@ -284,9 +284,10 @@ def main():
         ms = acc[k] / args.steps
         programs[k] = {"ms": round(ms, 4), "edges": int(edges[k]),
                        "gteps": round(edges[k] / (ms * 1e-3) / 1e9, 2)}
-    # algorithmic bytes of the BFS and SSSP runs (the survey's formulas):
-    # BFS 4 m_sym + 20 N; SSSP 8 B per relaxed edge (index + weight) plus
-    # 12 B per vertex and superstep
+    # algorithmic bytes of the BFS and SSSP runs: BFS reads each symmetric
+    # edge's index once (4 m_sym) and 20 B per vertex (offsets, level,
+    # frontier bits); SSSP 8 B per relaxed edge (index + weight) plus 12 B
+    # per vertex and superstep
     alg = {"bfs": 4 * m_sym + 20 * n,
            "sssp": 8 * edges["sssp"] + 12 * n * steps_sssp[0]}
     for k, b in alg.items():
