@@ -141,3 +141,24 @@ def test_paper_tc_workload_rmat20_a45():
     dag_in = oracle.dag_in_lists(oracle.prepare(n, s, d, mode="dag"))
     verts = np.random.default_rng(45).choice(n, 200, replace=False).astype(np.int32)
     assert np.array_equal(counts[verts], oracle.triangles_at(dag_in, verts))
+
+
+@pytest.mark.parametrize("tuning", [
+    {"tc_wave_max": 64},                                   # per-wavefront tables up to 64 keys only
+    {"tc_wave_max": 128, "tc_wave_work": 256},             # class 0 only, tiny wavefront items
+    {"tc_wave_max": 300, "tc_block_work": 4096},           # class 1 boundary off a power of two
+    {"tc_wave_max": 512, "tc_wave_work": 1 << 20, "tc_block_work": 256},
+])
+def test_tuning_keeps_counts_exact(tuning):
+    """Table classes, work-item sizes and the split into pieces move with the
+    tuning; the total and every receiver's count stay exact (Eq. (7))."""
+    n, s, d = W.raw(16)
+    g = gm.Graph.from_coo(n, s, d, prep=gm.GM_PREP_UPPER_DAG,
+                          layouts=gm.GM_LAYOUT_OUT | gm.GM_LAYOUT_IN)
+    g.set_tuning(**tuning)
+    counts = torch.zeros(n, dtype=torch.int64, device=DEV)
+    total = gm.triangle_count(g, counts)
+    dag_in = oracle.dag_in_lists(W.ograph(16, "dag"))
+    assert total == oracle.triangle_count(W.ograph(16, "dag"), dag_in)
+    assert np.array_equal(counts.cpu().numpy().view(np.uint64),
+                          oracle.triangles_at(dag_in, np.arange(n)))
